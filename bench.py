@@ -1,0 +1,209 @@
+#!/usr/bin/env python3
+"""Benchmark of the non-Fourier SENSE hot path on one MI355X.
+
+One step = one full CG solve (setup, E^H m, n_iter iterations of E^H E with
+the FP64 scalar updates) on the 2D 128x128 / 16-coil / 4 x 15000-sample /
+16-field-term workload (30 iterations), inputs resident in HBM.
+
+Reported value: E^H E voxel*sample*coil per second over the solve, i.e.
+(n_iter + 1/2) * L * K * G / (solve time), the initial E^H m counting as half
+an application.  ms_per_step is the CG solve time.  The result is checked
+against the stored FP64 oracle solve of the same workload.
+
+Also reported: the same for the FP32 operand form, one E^H E application
+timed alone, the fused encode kernel's average duration (HIP events on its
+launch stream, over the timed region) with its roofline, and the FP64 CPU
+oracle timed on a bounded sample of the workload on this host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+# MI355X published / derived peaks
+HBM_PEAK_GBS = 8000.0
+MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
+N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--trans-rate", type=float, default=0.25,
+                    help="v_sin/v_cos issue rate as a fraction of the FP32 FMA rate (for the ALU peak)")
+    return ap.parse_args()
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def cpu_baseline(d):
+    """FP64 oracle E^H E on every 8th sample (all voxels, all coils), repeated
+    for at least 10 s of wall time; returns v*s*c/s."""
+    import oracle
+
+    ks = np.arange(0, d["K"], 8)
+    a = (d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
+    x = d["rho_true"]
+    work = 0.0
+    t0 = time.perf_counter()
+    while True:
+        oracle.apply_EHE(x, *a)
+        work += d["L"] * len(ks) * d["n_coil"]
+        el = time.perf_counter() - t0
+        if el >= 10.0:
+            break
+    return dict(value=work / el, unit="voxel*sample*coil/s", cores=os.cpu_count(), kind="oracle",
+                sample=f"FP64 E^H E on every 8th sample ({len(ks)} of {d['K']}) x {d['L']} voxels x "
+                       f"{d['n_coil']} coils, repeated {work / (d['L'] * len(ks) * d['n_coil']):.0f}x "
+                       f"in {el:.1f} s, numpy with {os.cpu_count()} threads")
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (multi-GPU sharding over samples "
+                                   "is a design note only)"}))
+        sys.exit(2)
+    import torch
+
+    import synth
+    from paper_2604_09233_amd import nfs
+
+    dev = torch.device("cuda:0")
+    d = synth.make_config(args.config)
+    L, K, G, n_iter = d["L"], d["K"], d["n_coil"], d["n_iter"]
+    prob = nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev)
+    # synthetic data: m = E rho_phantom + complex noise at SNR 30
+    clean = nfs.apply_E(prob, torch.from_numpy(d["rho_true"]), "fp32")
+    rms = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2)))
+    sigma = rms / (30 * np.sqrt(2))
+    m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
+    torch.cuda.synchronize()
+
+    def solve(prec, out, hist, info):
+        return nfs.cg_solve(prob, m, n_iter, precision=prec, out=out, hist=hist, info=info)
+
+    def time_solves(prec, steps, warmup, profile=False):
+        out = torch.empty(L, dtype=torch.complex64, device=dev)
+        hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
+        info = torch.zeros(2, dtype=torch.int32, device=dev)
+        for _ in range(warmup):
+            solve(prec, out, hist, info)
+        torch.cuda.synchronize()
+        if profile:
+            nfs.profile_enable(0, True)
+            nfs.profile_read(0, "E")
+            nfs.profile_read(0, "EH")
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        for _ in range(steps):
+            solve(prec, out, hist, info)
+        ev1.record()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        ms = ev0.elapsed_time(ev1) / steps
+        kt = None
+        if profile:
+            kt = {k: nfs.profile_read(0, k) for k in ("E", "EH")}
+            nfs.profile_enable(0, False)
+        return out, hist, info, ms, wall, kt
+
+    rho, hist, info, ms, wall, kt = time_solves(args.precision, args.steps, args.warmup, profile=True)
+    vsc = L * K * G
+    value = (n_iter + 0.5) * vsc / (ms * 1e-3)
+
+    # accuracy against the stored FP64 oracle solve of this workload
+    err = None
+    gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}_cg.npz")
+    if os.path.exists(gpath):
+        g = np.load(gpath)
+        err = rel(rho.cpu().numpy(), g["rho"])
+
+    # one E^H E application alone (median of 20 after 3 warm-ups)
+    p = torch.from_numpy(d["rho_true"]).to(dev)
+    q = torch.empty_like(p)
+    for _ in range(3):
+        nfs.apply_EHE(prob, p, args.precision, out=q)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(20):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        nfs.apply_EHE(prob, p, args.precision, out=q)
+        e1.record()
+        torch.cuda.synchronize()
+        times.append(e0.elapsed_time(e1))
+    ehe_ms = float(np.median(times))
+
+    # FP32 operand form for comparison
+    fp32 = None
+    if not args.no_fp32_form and args.precision != "fp32":
+        rho32, _, _, ms32, _, _ = time_solves("fp32", max(1, args.steps // 2), 1)
+        fp32 = dict(ms_per_step=ms32, value=(n_iter + 0.5) * vsc / (ms32 * 1e-3),
+                    rel_err_vs_oracle=rel(rho32.cpu().numpy(), g["rho"]) if err is not None else None)
+
+    # roofline of the dominant kernel (the fused encode kernel, E or E^H)
+    n_e, ms_e = kt["E"]
+    n_h, ms_h = kt["EH"]
+    kind, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
+    avg_ms = ms_k / max(n_k, 1)
+    pairs = L * K  # voxel-sample pairs per launch
+    # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
+    trans_peak = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 * args.trans_rate  # ops/s
+    achieved = 2 * pairs / (avg_ms * 1e-3)
+    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=trans_peak / 1e12, unit="Tsincos-ops/s",
+                    frac=achieved / trans_peak, traffic=None, kernel=f"encode_kernel ({kind})",
+                    avg_launch_ms=avg_ms, launches=n_k,
+                    mfma_frac=(8 * G * pairs / (avg_ms * 1e-3)) / (MFMA_PEAK_TFLOPS[args.precision] * 1e12))
+
+    st = info.cpu().tolist()
+    out = {
+        "metric": "E^H·E voxel·sample·coil/s (over the CG solve); CG solve time at rel.err <=2e-3 vs FP64 oracle",
+        "value": value,
+        "unit": "voxel*sample*coil/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.precision,
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: 2D 128x128, 16 coils, 4x15000-sample R=4 spiral, 16 field terms, "
+                               f"B0 +-100 Hz, {n_iter} CG iterations (one step = one CG solve)",
+                   "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision},
+        "rel_err_vs_oracle": err,
+        "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
+        "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
+        "fp32_form": fp32,
+        "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
+        "roofline": roofline,
+        "wall_s_timed": wall,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(d)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,173 @@
+/*
+ * nfs.h -- C ABI of the MI355X (gfx950) non-Fourier SENSE library.
+ *
+ * The library evaluates the encoding operator E of higher-order ("non-Fourier")
+ * SENSE, its adjoint E^H, the normal operator E^H E, and solves
+ * E^H E rho = E^H sigma with conjugate gradients, as defined in the paper's
+ * Methods section ("Implementation of the higher-order SENSE reconstruction":
+ * the signal-model equations P = exp(i K R), E p = P (S o (p 1^T)),
+ * E^H sigma = (S* o (P^H Sigma)) 1, and the CG listings of the
+ * reconstruction-algorithm figure).
+ *
+ * Model.  For voxel l (0 <= l < L), sample k (0 <= k < K) and coil c
+ * (0 <= c < G), with P field-basis terms,
+ *     phi(k, l)  = sum_{b<P} kcoef[k][b] * fields[b][l] + t[k] * b0[l]      (radians)
+ *     (E rho)[c][k] = sum_l sens[c][l] * exp(+i phi(k, l)) * rho[l]
+ *     (E^H m)[l]    = sum_c conj(sens[c][l]) * sum_k exp(-i phi(k, l)) * m[c][k]
+ * kcoef holds the dynamic field terms k_b(t_k) and t the sample times
+ * (columns of the paper's temporal basis K); fields holds the spatial basis
+ * h_b(r_l) and b0 the off-resonance map in rad/s (rows of the spatial basis R).
+ *
+ * Conventions for every call.
+ *  - Every array argument is a DEVICE pointer owned by the caller; the library
+ *    never allocates, frees or retains device memory.  Scratch space is the
+ *    caller's workspace `ws` of at least nfs_workspace_bytes() bytes,
+ *    256-byte aligned; its contents on entry are ignored and on exit undefined.
+ *  - Complex arrays are interleaved (re, im) float pairs (complex64), 8-byte
+ *    aligned; real arrays are float32, 4-byte aligned.  Multi-index arrays are
+ *    row-major, last index contiguous, with the shapes given in brackets.
+ *  - Work is enqueued on `stream` (a hipStream_t; NULL = the null stream) and
+ *    is asynchronous: the call returns once the work is enqueued.  Inputs are
+ *    read-only and must not alias outputs or the workspace.
+ *  - Return value: NFS_OK, or a negative status.  All argument checks run on
+ *    the host before anything is enqueued, so an error leaves every output
+ *    untouched.  A failed launch returns NFS_EHIP; device faults surface at
+ *    the caller's next synchronisation.  nfs_last_error() gives a message for
+ *    the last non-OK status of the calling thread.
+ *  - Limits: 1 <= G <= 64; 0 <= P <= 31; 0 <= L, K <= 2^26.
+ */
+#ifndef NFS_H
+#define NFS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum nfs_status {
+  NFS_OK = 0,
+  NFS_EINVAL = -1,       /* null pointer, bad enum, misaligned pointer, non-finite scalar */
+  NFS_ESHAPE = -2,       /* size out of the supported range */
+  NFS_EHIP = -3,         /* HIP runtime error (device query or launch) */
+  NFS_EWORKSPACE = -4,   /* workspace missing, misaligned or too small */
+  NFS_EUNSUPPORTED = -6  /* device is not gfx950 */
+};
+
+/* Operand precision of the two complex contractions (the phase and its
+ * sin/cos are always float32; accumulation is always float32).
+ *  NFS_FP32: float32 operands on the FP32 matrix cores.
+ *  NFS_BF16: bfloat16 operands (round to nearest even).
+ *  NFS_FP16: float16 operands; the data operand is scaled by a power of two
+ *            chosen on the device from its maximum magnitude, and unscaled
+ *            after the contraction (exact).                                  */
+enum nfs_precision { NFS_FP32 = 0, NFS_BF16 = 1, NFS_FP16 = 2 };
+
+/* Operation selector for nfs_workspace_bytes. */
+enum nfs_op { NFS_OP_E = 0, NFS_OP_EH = 1, NFS_OP_EHE = 2, NFS_OP_CG = 3 };
+
+/* Values of info[1] written by nfs_cg_solve. */
+enum nfs_cg_status {
+  NFS_CG_MAXITER = 1,    /* ran n_iter iterations */
+  NFS_CG_TOL = 2,        /* ||r_n|| <= tol * ||r_0|| */
+  NFS_CG_EXACT = 3,      /* r_n^H r_n == 0 (includes E^H sigma == 0) */
+  NFS_CG_BREAKDOWN = 4   /* p^H E^H E p <= 0 or a non-finite CG scalar */
+};
+
+/* The reconstruction problem: sizes and the model arrays (all device). */
+typedef struct nfs_problem {
+  int64_t n_vox;        /* L: number of voxels (entries of rho) */
+  int64_t n_samp;       /* K: number of samples, all shots concatenated */
+  int32_t n_coil;       /* G: number of receive coils */
+  int32_t n_basis;      /* P: number of dynamic field terms */
+  const float* sens;    /* [G][L] complex: S_c(r_l) (the paper's S, stored transposed) */
+  const float* fields;  /* [P][L] real: h_b(r_l) (rows 2..P+1 of the spatial basis R) */
+  const float* b0;      /* [L] real, rad/s: B0(r_l) (row 1 of R, gamma folded in) */
+  const float* kcoef;   /* [K][P] real, rad: k_b(t_k) (columns 2..P+1 of K, row-major) */
+  const float* t;       /* [K] real, s: t_k (column 1 of K) */
+  const float* icorr;   /* [L] real or NULL: intensity correction j (used by nfs_cg_solve only) */
+} nfs_problem;
+
+typedef struct nfs_ctx nfs_ctx;
+
+/* Bind a context to HIP device `device` (checks that it is gfx950 and reads
+ * its compute-unit count, used to size launch grids).  The context holds no
+ * device memory.  Returns NFS_EHIP if the device cannot be queried and
+ * NFS_EUNSUPPORTED if it is not gfx950; *ctx is NULL on error.            */
+int nfs_create(nfs_ctx** ctx, int device);
+int nfs_destroy(nfs_ctx* ctx);
+
+/* Workspace bytes needed by `op` (enum nfs_op) at `precision` for problem
+ * sizes `prob` (only the sizes and whether icorr is NULL are read; array
+ * pointers may be NULL here).  For NFS_OP_CG the size also depends on
+ * n_iter and reorth (both ignored for the other ops).  Host-only; never
+ * touches the device.                                                    */
+int nfs_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, int op, int precision,
+                        int n_iter, int reorth, size_t* bytes);
+
+/* m = E rho (signal-model equation for E).  rho: [L] complex; m: [G][K]
+ * complex (coil-major, the paper's Sigma transposed).                     */
+int nfs_apply_E(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, float* m,
+                int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* x = E^H m (adjoint equation, evaluated as sum_c conj(S_c) o (P^H m_c)
+ * without forming P^H).  m: [G][K] complex; x: [L] complex.               */
+int nfs_apply_EH(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* x,
+                 int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* q = E^H E p (the normal operator applied in each CG iteration).
+ * p, q: [L] complex.                                                      */
+int nfs_apply_EHE(nfs_ctx* ctx, const nfs_problem* prob, const float* p, float* q,
+                  int precision, void* ws, size_t ws_bytes, void* stream);
+
+/* Conjugate gradients on E^H E rho = E^H m (reconstruction-algorithm
+ * figure): rho_0 = 0, r_0 = p_0 = E^H m, then per iteration q = E^H E p,
+ * beta = Re p^H q, rho += (alpha/beta) p, r -= (alpha/beta) q,
+ * alpha' = r^H r, p = r + (alpha'/alpha) p.  If prob->icorr is not NULL the
+ * sensitivities are multiplied by j first and rho by j at the end.
+ *   m:         [G][K] complex coil data (input)
+ *   rho:       [L] complex (output; written even if the loop stops early)
+ *   n_iter:    maximum number of iterations, >= 0
+ *   tol:       0 = run n_iter iterations; > 0 = stop once ||r_n|| <= tol ||r_0||
+ *   replace_every: 0 = never; k > 0 = every k iterations replace the
+ *              recursive residual by E^H m - E^H E rho (one extra E^H E)
+ *   reorth:    0 = plain recurrences (as printed); 1 = after each residual
+ *              update, orthogonalise r against all earlier normalised
+ *              residuals (classical Gram-Schmidt, float64 dot products).
+ *              Identical iterates in exact arithmetic; keeps float32/float16
+ *              runs on the exact-arithmetic trajectory on ill-conditioned
+ *              problems.  Needs n_iter <= 2048 and (n_iter+1)*L complex of
+ *              workspace.
+ *   hist:      device double [n_iter+1][3] or NULL; row n holds ||r_n||,
+ *              ||rho_n|| and ||m - E rho_n||^2 from the recurrence
+ *              ||d_{n+1}||^2 = ||d_n||^2 - alpha^2/beta (rows past the
+ *              last iteration are left untouched)
+ *   info:      device int [2] or NULL: iterations done, enum nfs_cg_status
+ * All CG scalars (dot products, alpha, beta, norms) are float64 on the
+ * device; vectors are complex64; the host never synchronises.              */
+int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho,
+                 int n_iter, double tol, int replace_every, int reorth, int precision,
+                 double* hist, int* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Kernel timing for benchmarks.  While enabled, every launch of the fused
+ * encode kernel (the phase/sincos/contraction kernel of E and of E^H) made
+ * through `ctx` is bracketed by two HIP events recorded on its launch
+ * stream.  nfs_profile_read waits for the recorded events, returns the
+ * number of launches and their summed event-to-event time in milliseconds
+ * for `kind` (0 = E, 1 = E^H), and forgets them.  Host-side bookkeeping only;
+ * HIP events are created on first use and kept by the context.            */
+int nfs_profile_enable(nfs_ctx* ctx, int on);
+int nfs_profile_read(nfs_ctx* ctx, int kind, int* count, double* total_ms);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char* nfs_last_error(void);
+
+/* Library version, major * 10000 + minor * 100 + patch. */
+int nfs_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NFS_H */

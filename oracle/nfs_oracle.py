@@ -147,7 +147,8 @@ def dense_E(sens, fields, b0, kcoef, t):
 
 
 def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
-             return_iterates=False, explicit_residual=False, block=_DEF_BLOCK, threads=None):
+             return_iterates=False, explicit_residual=False, block=_DEF_BLOCK, threads=None,
+             perturb=None, reorth=False):
     """CG on E^H E rho = E^H sigma, as in the reconstruction figure.
 
     Steps: optional intensity correction S <- S o (j 1^T); p = E^H sigma;
@@ -162,6 +163,21 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
     computed at the end of the previous one, so it is reused; the loop stops
     early on exact convergence (alpha = 0), on breakdown (beta <= 0 or a
     non-finite scalar) and, when tol > 0, once ||r_n|| <= tol ||r_0||.
+
+    ``reorth``: after each residual update, r is orthogonalised against the
+    normalised earlier residuals r_j / ||r_j|| (modified Gram-Schmidt).  In
+    exact arithmetic the CG residuals are already mutually orthogonal, so
+    this leaves the iterates of the figure unchanged; in floating point it
+    keeps them on the exact-arithmetic trajectory on ill-conditioned
+    problems, where plain recurrences lose orthogonality within a few tens
+    of iterations.
+
+    ``perturb = (delta, seed)`` is a sensitivity probe, not part of the
+    method: every E^H E p is multiplied elementwise by (1 + delta * xi) with
+    xi complex Gaussian (seeded), which models a working precision whose
+    relative rounding error is about delta.  Comparing such a run with the
+    unperturbed one measures how far the iterates of this particular problem
+    can move under rounding at that level.
 
     Returns dict(rho, iters, status, hist[iters+1][3], iterates?, dres?)
     where hist row n holds (||r_n||, ||rho_n||, ||d_n||^2 from the
@@ -184,11 +200,16 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
     dres = []
     status = "max_iter"
     n = 0
+    prng = np.random.default_rng(perturb[1]) if perturb else None
+    basis = [r / np.sqrt(alpha)] if (reorth and alpha > 0.0) else []
     if alpha == 0.0:
         status = "exact"
     else:
         while n < n_iter:
             q = apply_EHE(p, *args, **kw)
+            if prng is not None:
+                xi = prng.standard_normal(q.shape) + 1j * prng.standard_normal(q.shape)
+                q = q * (1.0 + perturb[0] * xi / np.sqrt(2.0))
             beta = float(np.real(np.vdot(p, q)))
             if not np.isfinite(beta) or beta <= 0.0:
                 status = "breakdown"
@@ -196,11 +217,15 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
             gamma = alpha / beta
             rho = rho + gamma * p
             r = r - gamma * q
+            for v in basis:
+                r = r - np.vdot(v, r) * v
             d2 = d2 - alpha * alpha / beta
             beta = alpha
             alpha = float(np.real(np.vdot(r, r)))
             p = r + (alpha / beta) * p
             n += 1
+            if reorth and alpha > 0.0:
+                basis.append(r / np.sqrt(alpha))
             hist.append((np.sqrt(alpha), float(np.linalg.norm(rho)), d2))
             if return_iterates:
                 iterates.append(rho.copy())

@@ -1,0 +1,487 @@
+// C ABI of the library: argument validation (host only, before any launch),
+// workspace layout, launch-grid choices and the order of kernel launches for
+// E, E^H, E^H E and the CG solve.  No device memory is allocated here.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "nfs.h"
+#include "nfs_internal.h"
+
+using namespace nfs;
+
+struct nfs_ctx {
+  int device;
+  int n_cu;
+  bool profiling = false;
+  std::vector<hipEvent_t> pool;                 // idle events
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // recorded (start, stop) per kind
+};
+
+static thread_local std::string g_err;
+
+static int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+static int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+static int hip_fail(hipError_t e, const char* where) {
+  return fail(NFS_EHIP, "%s: HIP error %d (%s)", where, (int)e, hipGetErrorString(e));
+}
+
+extern "C" const char* nfs_last_error(void) { return g_err.c_str(); }
+extern "C" int nfs_version(void) { return 100; }
+
+extern "C" int nfs_create(nfs_ctx** ctx, int device) {
+  if (!ctx) return fail(NFS_EINVAL, "nfs_create: ctx is NULL");
+  *ctx = nullptr;
+  int n = 0;
+  hipError_t e = hipGetDeviceCount(&n);
+  if (e != hipSuccess) return hip_fail(e, "nfs_create: hipGetDeviceCount");
+  if (device < 0 || device >= n) return fail(NFS_EHIP, "nfs_create: device %d not present (%d devices)", device, n);
+  hipDeviceProp_t prop;
+  e = hipGetDeviceProperties(&prop, device);
+  if (e != hipSuccess) return hip_fail(e, "nfs_create: hipGetDeviceProperties");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(NFS_EUNSUPPORTED, "nfs_create: device %d is %s, not gfx950", device, prop.gcnArchName);
+  nfs_ctx* c = new nfs_ctx;
+  c->device = device;
+  c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  *ctx = c;
+  return NFS_OK;
+}
+
+extern "C" int nfs_destroy(nfs_ctx* ctx) {
+  if (!ctx) return NFS_OK;
+  for (int k = 0; k < 2; ++k)
+    for (auto& pr : ctx->rec[k]) {
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+  for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  delete ctx;
+  return NFS_OK;
+}
+
+static hipError_t take_event(nfs_ctx* ctx, hipEvent_t* e) {
+  if (!ctx->pool.empty()) {
+    *e = ctx->pool.back();
+    ctx->pool.pop_back();
+    return hipSuccess;
+  }
+  return hipEventCreate(e);
+}
+
+extern "C" int nfs_profile_enable(nfs_ctx* ctx, int on) {
+  if (!ctx) return fail(NFS_EINVAL, "nfs_profile_enable: ctx is NULL");
+  ctx->profiling = on != 0;
+  return NFS_OK;
+}
+
+extern "C" int nfs_profile_read(nfs_ctx* ctx, int kind, int* count, double* total_ms) {
+  if (!ctx || !count || !total_ms) return fail(NFS_EINVAL, "nfs_profile_read: NULL argument");
+  if (kind < 0 || kind > 1) return fail(NFS_EINVAL, "nfs_profile_read: kind %d not 0 or 1", kind);
+  double tot = 0.0;
+  int n = 0;
+  for (auto& pr : ctx->rec[kind]) {
+    hipError_t e = hipEventSynchronize(pr.second);
+    if (e != hipSuccess) return hip_fail(e, "nfs_profile_read: hipEventSynchronize");
+    float ms = 0.f;
+    e = hipEventElapsedTime(&ms, pr.first, pr.second);
+    if (e != hipSuccess) return hip_fail(e, "nfs_profile_read: hipEventElapsedTime");
+    tot += ms;
+    ++n;
+    ctx->pool.push_back(pr.first);
+    ctx->pool.push_back(pr.second);
+  }
+  ctx->rec[kind].clear();
+  *count = n;
+  *total_ms = tot;
+  return NFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// validation
+static bool misaligned(const void* p, size_t a) { return p && ((uintptr_t)p % a) != 0; }
+
+static int check_sizes(const nfs_problem* pr, const char* fn) {
+  if (!pr) return fail(NFS_EINVAL, "%s: problem is NULL", fn);
+  const int64_t lim = (int64_t)1 << 26;
+  if (pr->n_vox < 0 || pr->n_vox > lim) return fail(NFS_ESHAPE, "%s: n_vox %lld outside [0, 2^26]", fn, (long long)pr->n_vox);
+  if (pr->n_samp < 0 || pr->n_samp > lim) return fail(NFS_ESHAPE, "%s: n_samp %lld outside [0, 2^26]", fn, (long long)pr->n_samp);
+  if (pr->n_coil < 1 || pr->n_coil > 64) return fail(NFS_ESHAPE, "%s: n_coil %d outside [1, 64]", fn, pr->n_coil);
+  if (pr->n_basis < 0 || pr->n_basis > 31) return fail(NFS_ESHAPE, "%s: n_basis %d outside [0, 31]", fn, pr->n_basis);
+  return NFS_OK;
+}
+
+static int check_problem(const nfs_problem* pr, const char* fn) {
+  int rc = check_sizes(pr, fn);
+  if (rc) return rc;
+  const bool hasL = pr->n_vox > 0, hasK = pr->n_samp > 0, hasP = pr->n_basis > 0;
+  if (hasL && !pr->sens) return fail(NFS_EINVAL, "%s: sens is NULL", fn);
+  if (hasL && !pr->b0) return fail(NFS_EINVAL, "%s: b0 is NULL", fn);
+  if (hasL && hasP && !pr->fields) return fail(NFS_EINVAL, "%s: fields is NULL", fn);
+  if (hasK && !pr->t) return fail(NFS_EINVAL, "%s: t is NULL", fn);
+  if (hasK && hasP && !pr->kcoef) return fail(NFS_EINVAL, "%s: kcoef is NULL", fn);
+  if (misaligned(pr->sens, 8)) return fail(NFS_EINVAL, "%s: sens not 8-byte aligned", fn);
+  if (misaligned(pr->fields, 4) || misaligned(pr->b0, 4) || misaligned(pr->kcoef, 4) || misaligned(pr->t, 4) ||
+      misaligned(pr->icorr, 4))
+    return fail(NFS_EINVAL, "%s: real array not 4-byte aligned", fn);
+  return NFS_OK;
+}
+
+static int check_prec(int prec, const char* fn) {
+  if (prec != NFS_FP32 && prec != NFS_BF16 && prec != NFS_FP16)
+    return fail(NFS_EINVAL, "%s: unknown precision %d", fn, prec);
+  return NFS_OK;
+}
+
+static int check_vec(const void* p, int64_t n, const char* fn, const char* name) {
+  if (n > 0 && !p) return fail(NFS_EINVAL, "%s: %s is NULL", fn, name);
+  if (misaligned(p, 8)) return fail(NFS_EINVAL, "%s: %s not 8-byte aligned", fn, name);
+  return NFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// workspace layout
+static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Layout {
+  int64_t L, K, LC, KC;
+  int G, P, NT, NB, prec;
+  EncodeShape shE, shH;
+  size_t o_scoef, o_vcoef, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
+  size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_coef;
+  size_t total;
+};
+
+static int choose_split(int64_t held_chunks, int64_t strm_chunks, int MT, int n_cu) {
+  const int64_t gx = cdiv(held_chunks, (int64_t)kWaves * MT);
+  if (gx <= 0) return 1;
+  int64_t ns = cdiv(4LL * n_cu, gx);
+  const int64_t maxs = strm_chunks / 32 > 1 ? strm_chunks / 32 : 1;
+  if (ns > maxs) ns = maxs;
+  if (ns > 64) ns = 64;
+  if (ns < 1) ns = 1;
+  return (int)ns;
+}
+
+static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int prec, int n_iter, int reorth) {
+  Layout y{};
+  y.L = pr->n_vox;
+  y.K = pr->n_samp;
+  y.G = pr->n_coil;
+  y.P = pr->n_basis;
+  y.LC = cdiv(y.L, kChunk);
+  y.KC = cdiv(y.K, kChunk);
+  y.NT = term_groups(y.P);
+  y.NB = col_blocks(y.G);
+  y.prec = prec;
+  const int n_cu = ctx ? ctx->n_cu : 256;
+  const int MT = 2;
+  y.shE = EncodeShape{OP_E, prec, y.NT, y.NB, MT, y.KC, y.LC, 1, 0};
+  y.shE.nsplit = choose_split(y.KC, y.LC, MT, n_cu);
+  y.shE.cps = cdiv(y.LC, y.shE.nsplit);
+  y.shH = EncodeShape{OP_EH, prec, y.NT, y.NB, MT, y.LC, y.KC, 1, 0};
+  y.shH.nsplit = choose_split(y.LC, y.KC, MT, n_cu);
+  y.shH.cps = cdiv(y.KC, y.shH.nsplit);
+
+  const bool needE = op != NFS_OP_EH, needH = op != NFS_OP_E, cg = op == NFS_OP_CG;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += al(bytes);
+    return at;
+  };
+  y.o_scoef = take((size_t)y.KC * y.NT * 64 * 4);
+  y.o_vcoef = take((size_t)y.LC * y.NT * 64 * 4);
+  y.o_bmax = take(kBmaxBlocks * 4);
+  y.o_unscale = take(2 * 4);
+  y.o_dataE = needE ? take((size_t)y.LC * y.NB * data_chunk_bytes(prec)) : 0;
+  y.o_epart = needE ? take((size_t)y.shE.nsplit * y.KC * 16 * y.NB * 16 * 4) : 0;
+  y.o_ybuf = (needE && needH) ? take((size_t)y.KC * 16 * y.NB * 16 * 4) : 0;
+  y.o_dataH = needH ? take((size_t)y.KC * y.NB * data_chunk_bytes(prec)) : 0;
+  y.o_hpart = needH ? take((size_t)y.shH.nsplit * y.LC * 16 * 8) : 0;
+  if (cg) {
+    y.o_sensj = pr->icorr ? take((size_t)y.G * y.L * 8) : 0;
+    y.o_r = take((size_t)y.L * 8);
+    y.o_p = take((size_t)y.L * 8);
+    y.o_q = take((size_t)y.L * 8);
+    y.o_b = take((size_t)y.L * 8);
+    y.o_part = take(4 * kCgBlocks * 8);
+    y.o_alpha = take((size_t)(n_iter + 2) * 8);
+    y.o_scal = take(4 * 8);
+    y.o_hist = take((size_t)(n_iter + 1) * 3 * 8);
+    y.o_info = take(2 * 4);
+    y.o_stop = take(4);
+    if (reorth) {
+      y.o_V = take((size_t)(n_iter + 1) * y.L * 8);
+      y.o_rpart = take((size_t)(n_iter + 1) * 2 * kCgBlocks * 8);
+      y.o_coef = take((size_t)(n_iter + 1) * 2 * 8);
+    }
+  }
+  y.total = o;
+  return y;
+}
+
+extern "C" int nfs_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, int op, int precision, int n_iter,
+                                   int reorth, size_t* bytes) {
+  const char* fn = "nfs_workspace_bytes";
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if (op < NFS_OP_E || op > NFS_OP_CG) return fail(NFS_EINVAL, "%s: unknown op %d", fn, op);
+  if (op == NFS_OP_CG && n_iter < 0) return fail(NFS_EINVAL, "%s: n_iter %d < 0", fn, n_iter);
+  if (op == NFS_OP_CG && reorth && n_iter > kMaxReorth)
+    return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
+  const bool cg = op == NFS_OP_CG;
+  *bytes = make_layout(ctx, prob, op, precision, cg ? n_iter : 0, cg ? (reorth != 0) : 0).total;
+  return NFS_OK;
+}
+
+static int check_ws(const Layout& y, void* ws, size_t ws_bytes, const char* fn) {
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  if (ws_bytes < y.total)
+    return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, y.total);
+  return NFS_OK;
+}
+
+template <class T>
+static T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+#define NFS_TRY(expr, where)                  \
+  do {                                        \
+    hipError_t e_ = (expr);                   \
+    if (e_ != hipSuccess) return hip_fail(e_, where); \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// launch sequences
+struct Ctx {
+  nfs_ctx* lib;
+  const Layout& y;
+  const nfs_problem* pr;
+  const float2* sens;  // possibly intensity-corrected
+  void* ws;
+  hipStream_t s;
+  const int* stop;
+};
+
+// Launch the encode kernel, bracketed by HIP events when profiling is on.
+template <class F>
+static int timed_encode(const Ctx& c, int kind, F&& launch) {
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c.lib->profiling) {
+    NFS_TRY(take_event(c.lib, &e0), "profile: hipEventCreate");
+    NFS_TRY(take_event(c.lib, &e1), "profile: hipEventCreate");
+    NFS_TRY(hipEventRecord(e0, c.s), "profile: hipEventRecord");
+  }
+  NFS_TRY(launch(), kind ? "encode(EH)" : "encode(E)");
+  if (c.lib->profiling) {
+    NFS_TRY(hipEventRecord(e1, c.s), "profile: hipEventRecord");
+    c.lib->rec[kind].emplace_back(e0, e1);
+  }
+  return NFS_OK;
+}
+
+static int seq_pack_coefs(const Ctx& c) {
+  NFS_TRY(launch_pack_coef_samples(c.pr->kcoef, c.pr->t, c.y.K, c.y.P, c.y.NT, at<float>(c.ws, c.y.o_scoef), c.s),
+          "pack_coef_samples");
+  NFS_TRY(launch_pack_coef_voxels(c.pr->fields, c.pr->b0, c.y.L, c.y.P, c.y.NT, at<float>(c.ws, c.y.o_vcoef), c.s),
+          "pack_coef_voxels");
+  return NFS_OK;
+}
+
+static float* unscale_slot(const Ctx& c, int which) {
+  return c.y.prec == PREC_FP16 ? at<float>(c.ws, c.y.o_unscale) + which : nullptr;
+}
+
+// E part: rho -> epart (partials) via packed Q = S o rho
+static int seq_E(const Ctx& c, const float2* rho) {
+  const Layout& y = c.y;
+  float* bmax = at<float>(c.ws, y.o_bmax);
+  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(rho, c.sens, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
+  NFS_TRY(launch_pack_data(OP_E, y.prec, rho, c.sens, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(c.ws, y.o_dataE), bmax,
+                           at<float>(c.ws, y.o_unscale), c.stop, c.s),
+          "pack_data(E)");
+  return timed_encode(c, 0, [&] {
+    return launch_encode(y.shE, at<float>(c.ws, y.o_scoef), at<float>(c.ws, y.o_vcoef), at<void>(c.ws, y.o_dataE),
+                         at<float>(c.ws, y.o_epart), c.sens, y.L, y.G, c.stop, c.s);
+  });
+}
+
+// E^H part: src (m [G][K] or ybuf) -> hpart (coil-combined partials)
+static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs) {
+  const Layout& y = c.y;
+  float* bmax = at<float>(c.ws, y.o_bmax);
+  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(src, nullptr, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
+  NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
+                           bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
+          "pack_data(EH)");
+  return timed_encode(c, 1, [&] {
+    return launch_encode(y.shH, at<float>(c.ws, y.o_vcoef), at<float>(c.ws, y.o_scoef), at<void>(c.ws, y.o_dataH),
+                         at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, c.stop, c.s);
+  });
+}
+
+// E^H E: p -> hpart
+static int seq_EHE(const Ctx& c, const float2* p) {
+  const Layout& y = c.y;
+  int rc = seq_E(c, p);
+  if (rc) return rc;
+  float* ybuf = at<float>(c.ws, y.o_ybuf);
+  NFS_TRY(launch_finish_E_to_ybuf(at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, unscale_slot(c, 0), ybuf,
+                                  c.stop, c.s),
+          "finish_E_to_ybuf");
+  return seq_EH(c, reinterpret_cast<const float2*>(ybuf), (int64_t)y.NB * 8, 1);
+}
+
+extern "C" int nfs_apply_E(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, float* m, int precision,
+                           void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_apply_E";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if ((rc = check_vec(rho, prob->n_vox, fn, "rho"))) return rc;
+  if ((rc = check_vec(m, prob->n_samp, fn, "m"))) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_E, precision, 0, 0);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  if (y.K == 0) return NFS_OK;
+  Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
+  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_E(c, reinterpret_cast<const float2*>(rho)))) return rc;
+  NFS_TRY(launch_finish_E_to_m(at<float>(ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, unscale_slot(c, 0),
+                               reinterpret_cast<float2*>(m), c.s),
+          "finish_E_to_m");
+  return NFS_OK;
+}
+
+extern "C" int nfs_apply_EH(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* x, int precision, void* ws,
+                            size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_apply_EH";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if ((rc = check_vec(m, prob->n_samp, fn, "m"))) return rc;
+  if ((rc = check_vec(x, prob->n_vox, fn, "x"))) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_EH, precision, 0, 0);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  if (y.L == 0) return NFS_OK;
+  Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
+  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_EH(c, reinterpret_cast<const float2*>(m), 1, y.K))) return rc;
+  NFS_TRY(launch_finish_EH(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1),
+                           reinterpret_cast<float2*>(x), c.s),
+          "finish_EH");
+  return NFS_OK;
+}
+
+extern "C" int nfs_apply_EHE(nfs_ctx* ctx, const nfs_problem* prob, const float* p, float* q, int precision,
+                             void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_apply_EHE";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if ((rc = check_vec(p, prob->n_vox, fn, "p"))) return rc;
+  if ((rc = check_vec(q, prob->n_vox, fn, "q"))) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_EHE, precision, 0, 0);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  if (y.L == 0) return NFS_OK;
+  Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
+  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_EHE(c, reinterpret_cast<const float2*>(p)))) return rc;
+  NFS_TRY(launch_finish_EH(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1),
+                           reinterpret_cast<float2*>(q), c.s),
+          "finish_EH");
+  return NFS_OK;
+}
+
+extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                            double tol, int replace_every, int reorth, int precision, double* hist, int* info,
+                            void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_cg_solve";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if ((rc = check_vec(m, prob->n_samp, fn, "m"))) return rc;
+  if ((rc = check_vec(rho, prob->n_vox, fn, "rho"))) return rc;
+  if (n_iter < 0) return fail(NFS_EINVAL, "%s: n_iter %d < 0", fn, n_iter);
+  if (!std::isfinite(tol) || tol < 0.0) return fail(NFS_EINVAL, "%s: tol must be finite and >= 0", fn);
+  if (replace_every < 0) return fail(NFS_EINVAL, "%s: replace_every %d < 0", fn, replace_every);
+  if (reorth != 0 && reorth != 1) return fail(NFS_EINVAL, "%s: reorth must be 0 or 1", fn);
+  if (reorth && n_iter > kMaxReorth) return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
+  if (misaligned(hist, 8)) return fail(NFS_EINVAL, "%s: hist not 8-byte aligned", fn);
+  if (misaligned(info, 4)) return fail(NFS_EINVAL, "%s: info not 4-byte aligned", fn);
+  const Layout y = make_layout(ctx, prob, NFS_OP_CG, precision, n_iter, reorth);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+
+  CgState st;
+  st.r = at<float2>(ws, y.o_r);
+  st.p = at<float2>(ws, y.o_p);
+  st.q = at<float2>(ws, y.o_q);
+  st.b = at<float2>(ws, y.o_b);
+  st.part = at<double>(ws, y.o_part);
+  st.alpha = at<double>(ws, y.o_alpha);
+  st.scal = at<double>(ws, y.o_scal);
+  st.hist = hist ? hist : at<double>(ws, y.o_hist);
+  st.info = info ? info : at<int>(ws, y.o_info);
+  st.stop = at<int>(ws, y.o_stop);
+  st.V = reorth ? at<float2>(ws, y.o_V) : nullptr;
+  st.rpart = reorth ? at<double>(ws, y.o_rpart) : nullptr;
+  st.coef = reorth ? at<double>(ws, y.o_coef) : nullptr;
+  st.L = y.L;
+  int64_t nb = cdiv(y.L, 256);
+  st.nblk = (int)(nb < 1 ? 1 : (nb > kCgBlocks ? kCgBlocks : nb));
+
+  const float2* sens = reinterpret_cast<const float2*>(prob->sens);
+  if (prob->icorr && y.L > 0) {
+    float2* sj = at<float2>(ws, y.o_sensj);
+    NFS_TRY(launch_scale_sens(sens, prob->icorr, y.G, y.L, sj, s), "scale_sens");
+    sens = sj;
+  }
+  Ctx c{ctx, y, prob, sens, ws, s, st.stop};
+  float2* x = reinterpret_cast<float2*>(rho);
+  const float2* hpart = at<float2>(ws, y.o_hpart);
+  const int64_t hstride = y.LC * 16;
+  const int ns = y.shH.nsplit;
+
+  NFS_TRY(launch_cg_reset(st, s), "cg_reset");
+  if ((rc = seq_pack_coefs(c))) return rc;
+  NFS_TRY(launch_cg_norm_m(st, reinterpret_cast<const float2*>(m), (int64_t)y.G * y.K, s), "cg_norm_m");
+  if ((rc = seq_EH(c, reinterpret_cast<const float2*>(m), 1, y.K))) return rc;
+  NFS_TRY(launch_cg_init(st, hpart, ns, hstride, unscale_slot(c, 1), x, y.L, s), "cg_init");
+  NFS_TRY(launch_cg_start(st, n_iter, s), "cg_start");
+  if (reorth) NFS_TRY(launch_cg_store_v(st, 0, s), "cg_store_v");
+  for (int n = 0; n < n_iter; ++n) {
+    if ((rc = seq_EHE(c, st.p))) return rc;
+    NFS_TRY(launch_cg_beta(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_beta");
+    NFS_TRY(launch_cg_update(st, x, y.L, n, s), "cg_update");
+    if (replace_every > 0 && (n + 1) % replace_every == 0 && n + 1 < n_iter) {
+      if ((rc = seq_EHE(c, x))) return rc;
+      NFS_TRY(launch_cg_replace(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_replace");
+    }
+    if (reorth) NFS_TRY(launch_cg_reorth(st, n + 1, s), "cg_reorth");
+    NFS_TRY(launch_cg_direction(st, x, y.L, n, n_iter, tol, s), "cg_direction");
+    if (reorth) NFS_TRY(launch_cg_store_v(st, n + 1, s), "cg_store_v");
+  }
+  NFS_TRY(launch_cg_finish(st, x, prob->icorr, y.L, s), "cg_finish");
+  return NFS_OK;
+}

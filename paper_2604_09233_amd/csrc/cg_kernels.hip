@@ -1,0 +1,378 @@
+// Conjugate-gradient vector kernels with float64 scalars kept on the device.
+//
+// CG on the normal equations E^H E rho = E^H sigma as in the paper's
+// reconstruction-algorithm figure: r_0 = p_0 = E^H sigma, rho_0 = 0, and per
+// iteration q = E^H E p, beta = p^H q, rho += (alpha/beta) p,
+// r -= (alpha/beta) q, alpha' = r^H r, p = r + (alpha'/alpha) p.
+//
+// Determinism: every dot product is accumulated in float64 per thread, then
+// per workgroup in a fixed tree, and the per-workgroup partials (at most
+// kCgBlocks) are summed by every consumer workgroup in the same fixed tree,
+// so every workgroup sees bit-identical scalars and runs are reproducible.
+// No host synchronisation: a device stop flag, set when the loop ends
+// (breakdown, exact convergence, tolerance), makes every later kernel of the
+// solve return at once.
+#include "nfs_internal.h"
+
+namespace nfs {
+
+enum { CG_MAXITER = 1, CG_TOL = 2, CG_EXACT = 3, CG_BREAKDOWN = 4 };
+
+// Sum of v over the workgroup (256 threads), fixed order; result in all threads.
+__device__ double block_sum(double v, double* red) {
+  red[threadIdx.x] = v;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  const double r = red[0];
+  __syncthreads();
+  return r;
+}
+
+// Sum of the nblk partials part[0..nblk) in a fixed tree; result in all threads.
+__device__ double sum_partials(const double* part, int nblk, double* red) {
+  return block_sum((int)threadIdx.x < nblk ? part[threadIdx.x] : 0.0, red);
+}
+
+__device__ __forceinline__ float2 sum_splits(const float2* hpart, int nsplit, int64_t stride, int64_t l, float u) {
+  float re = 0.f, im = 0.f;
+  for (int s = 0; s < nsplit; ++s) {
+    const float2 v = hpart[(size_t)s * stride + l];
+    re += v.x;
+    im += v.y;
+  }
+  return make_float2(re * u, im * u);
+}
+
+__global__ void cg_reset_kernel(int* stop, int* info) {
+  *stop = 0;
+  info[0] = 0;
+  info[1] = 0;
+}
+
+__global__ __launch_bounds__(256) void cg_norm_m_kernel(const float2* __restrict__ m, int64_t n,
+                                                        double* __restrict__ part) {
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    const float2 v = m[i];
+    a += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) part[blockIdx.x] = a;
+}
+
+// b = r = p = E^H m (sum of split partials), rho = 0, partial r^H r -> part[1]
+__global__ __launch_bounds__(256) void cg_init_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
+                                                      int64_t stride, const float* __restrict__ unscale,
+                                                      float2* __restrict__ rho, int64_t L) {
+  __shared__ double red[256];
+  const float u = unscale ? *unscale : 1.f;
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    const float2 v = sum_splits(hpart, nsplit, stride, l, u);
+    st.b[l] = v;
+    st.r[l] = v;
+    st.p[l] = v;
+    rho[l] = make_float2(0.f, 0.f);
+    a += (double)v.x * v.x + (double)v.y * v.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+}
+
+// alpha_0, ||m||^2, hist row 0, early exit when E^H m == 0
+__global__ __launch_bounds__(256) void cg_start_kernel(CgState st, int nblk_m, int n_iter) {
+  __shared__ double red[256];
+  const double a0 = sum_partials(st.part + kCgBlocks, st.nblk, red);
+  const double d2 = sum_partials(st.part + 3 * kCgBlocks, nblk_m, red);
+  if (threadIdx.x == 0) {
+    st.alpha[0] = a0;
+    st.scal[1] = d2;
+    st.hist[0] = sqrt(a0);
+    st.hist[1] = 0.0;
+    st.hist[2] = d2;
+    st.info[0] = 0;
+    if (!(a0 > 0.0)) {  // zero or non-finite
+      st.info[1] = (a0 == 0.0) ? CG_EXACT : CG_BREAKDOWN;
+      *st.stop = 1;
+    } else if (n_iter == 0) {
+      st.info[1] = CG_MAXITER;
+      *st.stop = 1;
+    }
+  }
+}
+
+// q = E^H E p (sum of split partials), partial Re p^H q -> part[0]
+__global__ __launch_bounds__(256) void cg_beta_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
+                                                      int64_t stride, const float* __restrict__ unscale,
+                                                      int64_t L) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  const float u = unscale ? *unscale : 1.f;
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    const float2 q = sum_splits(hpart, nsplit, stride, l, u);
+    const float2 p = st.p[l];
+    st.q[l] = q;
+    a += (double)p.x * q.x + (double)p.y * q.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) st.part[blockIdx.x] = a;
+}
+
+// rho += gamma p, r -= gamma q with gamma = alpha_n / beta; partial r^H r -> part[1]
+__global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __restrict__ rho, int64_t L, int n) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  const double beta = sum_partials(st.part, st.nblk, red);
+  const double alpha = st.alpha[n];
+  if (!(beta > 0.0) || !isfinite(beta)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      st.info[1] = CG_BREAKDOWN;
+      *st.stop = 1;
+    }
+    return;
+  }
+  const double gamma = alpha / beta;
+  const float gf = (float)gamma;
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    const float2 p = st.p[l], q = st.q[l];
+    float2 x = rho[l], r = st.r[l];
+    x.x = fmaf(gf, p.x, x.x);
+    x.y = fmaf(gf, p.y, x.y);
+    r.x = fmaf(-gf, q.x, r.x);
+    r.y = fmaf(-gf, q.y, r.y);
+    rho[l] = x;
+    st.r[l] = r;
+    a += (double)r.x * r.x + (double)r.y * r.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) {
+    st.part[kCgBlocks + blockIdx.x] = a;
+    if (blockIdx.x == 0) st.scal[0] = beta;
+  }
+}
+
+// residual replacement: r = b - (E^H E rho); partial r^H r -> part[1]
+__global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
+                                                         int64_t stride, const float* __restrict__ unscale,
+                                                         int64_t L) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  const float u = unscale ? *unscale : 1.f;
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    const float2 ax = sum_splits(hpart, nsplit, stride, l, u);
+    const float2 b = st.b[l];
+    const float2 r = make_float2(b.x - ax.x, b.y - ax.y);
+    st.r[l] = r;
+    a += (double)r.x * r.x + (double)r.y * r.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+}
+
+// alpha_{n+1} = r^H r; p = r + (alpha_{n+1} / alpha_n) p; ||rho||; history; stop tests
+__global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, const float2* __restrict__ rho, int64_t L,
+                                                           int n, int n_iter, double tol) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  const double anew = sum_partials(st.part + kCgBlocks, st.nblk, red);
+  const double aold = st.alpha[n];
+  const float bf = (float)(anew / aold);
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    const float2 r = st.r[l];
+    float2 p = st.p[l];
+    p.x = fmaf(bf, p.x, r.x);
+    p.y = fmaf(bf, p.y, r.y);
+    st.p[l] = p;
+    const float2 x = rho[l];
+    a += (double)x.x * x.x + (double)x.y * x.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) st.part[2 * kCgBlocks + blockIdx.x] = a;
+  if (blockIdx.x != 0 || threadIdx.x != 0) return;
+  // History row n+1 and the stop decision.  The stop flag itself is raised by
+  // cg_norm_rho_kernel (next launch): raising it here could make workgroups of
+  // this launch that start later skip their share of the update.
+  const double beta = st.scal[0];
+  const double d2 = st.scal[1] - aold * aold / beta;
+  st.scal[1] = d2;
+  st.alpha[n + 1] = anew;
+  double* h = st.hist + 3 * (size_t)(n + 1);
+  h[0] = sqrt(anew);
+  h[2] = d2;
+  st.info[0] = n + 1;
+  int status = 0;
+  if (!isfinite(anew)) status = CG_BREAKDOWN;
+  else if (anew == 0.0) status = CG_EXACT;
+  else if (tol > 0.0 && sqrt(anew) <= tol * sqrt(st.alpha[0])) status = CG_TOL;
+  else if (n + 1 >= n_iter) status = CG_MAXITER;
+  st.info[1] = status;
+}
+
+// ||rho_{n+1}|| from the partials of cg_direction, then the stop flag.
+__global__ __launch_bounds__(256) void cg_norm_rho_kernel(CgState st, int n) {
+  __shared__ double red[256];
+  if (*st.stop || st.info[0] != n + 1) return;  // step n+1 did not run
+  const double s = sum_partials(st.part + 2 * kCgBlocks, st.nblk, red);
+  if (threadIdx.x == 0) {
+    st.hist[3 * (size_t)(n + 1) + 1] = sqrt(s);
+    if (st.info[1] != 0) *st.stop = 1;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Re-orthogonalisation of the residual against the stored normalised
+// residuals v_j (classical Gram-Schmidt with float64 dot products).
+__global__ __launch_bounds__(256) void cg_store_v_kernel(CgState st, int j) {
+  if (*st.stop) return;
+  const double a = st.alpha[j];
+  if (!(a > 0.0)) return;
+  const float inv = (float)(1.0 / sqrt(a));
+  float2* v = st.V + (size_t)j * st.L;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
+    const float2 r = st.r[l];
+    v[l] = make_float2(r.x * inv, r.y * inv);
+  }
+}
+
+// grid (nblk, nv): partial sums of conj(v_j) r
+__global__ __launch_bounds__(256) void cg_reorth_dots_kernel(CgState st) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  const int j = blockIdx.y;
+  const float2* v = st.V + (size_t)j * st.L;
+  double re = 0.0, im = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
+    const float2 a = v[l], r = st.r[l];
+    re += (double)a.x * r.x + (double)a.y * r.y;
+    im += (double)a.x * r.y - (double)a.y * r.x;
+  }
+  re = block_sum(re, red);
+  im = block_sum(im, red);
+  if (threadIdx.x == 0) {
+    st.rpart[(2 * (size_t)j) * kCgBlocks + blockIdx.x] = re;
+    st.rpart[(2 * (size_t)j + 1) * kCgBlocks + blockIdx.x] = im;
+  }
+}
+
+// one workgroup: coef[j] = sum of the partials (fixed order)
+__global__ __launch_bounds__(256) void cg_reorth_coef_kernel(CgState st, int nv) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  for (int j = 0; j < nv; ++j) {
+    const double re = sum_partials(st.rpart + (2 * (size_t)j) * kCgBlocks, st.nblk, red);
+    const double im = sum_partials(st.rpart + (2 * (size_t)j + 1) * kCgBlocks, st.nblk, red);
+    if (threadIdx.x == 0) {
+      st.coef[2 * j] = re;
+      st.coef[2 * j + 1] = im;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv) {
+  if (*st.stop) return;
+  __shared__ double red[256];
+  double a = 0.0;
+  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
+    float2 r = st.r[l];
+    for (int j = 0; j < nv; ++j) {
+      const float cr = (float)st.coef[2 * j], ci = (float)st.coef[2 * j + 1];
+      const float2 v = st.V[(size_t)j * st.L + l];
+      r.x -= cr * v.x - ci * v.y;
+      r.y -= cr * v.y + ci * v.x;
+    }
+    st.r[l] = r;
+    a += (double)r.x * r.x + (double)r.y * r.y;
+  }
+  a = block_sum(a, red);
+  if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+}
+
+__global__ void cg_finish_kernel(float2* __restrict__ rho, const float* __restrict__ icorr, int64_t L) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  const float j = icorr[l];
+  float2 x = rho[l];
+  x.x *= j;
+  x.y *= j;
+  rho[l] = x;
+}
+
+// ---------------------------------------------------------------------------
+hipError_t launch_cg_reset(const CgState& st, hipStream_t s) {
+  hipLaunchKernelGGL(cg_reset_kernel, dim3(1), dim3(1), 0, s, st.stop, st.info);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_norm_m(const CgState& st, const float2* m, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(cg_norm_m_kernel, dim3(kCgBlocks), dim3(256), 0, s, m, n, st.part + 3 * kCgBlocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_init(const CgState& st, const float2* hpart, int nsplit, int64_t stride, const float* unscale,
+                          float2* rho, int64_t L, hipStream_t s) {
+  hipLaunchKernelGGL(cg_init_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, rho, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const CgState& st, int n_iter, hipStream_t s) {
+  hipLaunchKernelGGL(cg_start_kernel, dim3(1), dim3(256), 0, s, st, kCgBlocks, n_iter);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, int64_t stride, const float* unscale,
+                          int64_t L, hipStream_t s) {
+  hipLaunchKernelGGL(cg_beta_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s) {
+  hipLaunchKernelGGL(cg_update_kernel, dim3(st.nblk), dim3(256), 0, s, st, rho, L, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
+                             const float* unscale, int64_t L, hipStream_t s) {
+  hipLaunchKernelGGL(cg_replace_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction(const CgState& st, const float2* rho, int64_t L, int n, int n_iter, double tol,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(st.nblk), dim3(256), 0, s, st, rho, L, n, n_iter, tol);
+  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
+  hipLaunchKernelGGL(cg_norm_rho_kernel, dim3(1), dim3(256), 0, s, st, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s) {
+  hipLaunchKernelGGL(cg_store_v_kernel, dim3(st.nblk), dim3(256), 0, s, st, j);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_reorth(const CgState& st, int nv, hipStream_t s) {
+  hipLaunchKernelGGL(cg_reorth_dots_kernel, dim3(st.nblk, nv), dim3(256), 0, s, st);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_reorth_coef_kernel, dim3(1), dim3(256), 0, s, st, nv);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(cg_reorth_apply_kernel, dim3(st.nblk), dim3(256), 0, s, st, nv);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, int64_t L, hipStream_t s) {
+  (void)st;
+  if (!icorr || L == 0) return hipSuccess;
+  hipLaunchKernelGGL(cg_finish_kernel, dim3((unsigned)cdiv(L, 256)), dim3(256), 0, s, rho, icorr, L);
+  return hipGetLastError();
+}
+
+}  // namespace nfs

@@ -1,0 +1,127 @@
+// Internal declarations shared by the kernel sources and the C ABI layer.
+//
+// Work decomposition of the encoding operator (gfx950, wave64):
+//  * every contraction is "held" x "streamed": E holds samples (its output
+//    rows) and streams voxels; E^H holds voxels and streams samples;
+//  * items are grouped in chunks (tiles) of 16; a wave owns MT held tiles and
+//    walks a contiguous range of streamed chunks;
+//  * for each (held tile, streamed chunk) pair the wave builds the 16 x 16
+//    phase tile phi = K_blk R_blk on the FP32 matrix cores (v_mfma 16x16x4,
+//    NT term groups of 4), takes sin/cos of it in revolutions on the VALU and
+//    feeds (cos, sin) straight into the complex contraction on the matrix
+//    cores (16x16x32 f16/bf16, or 16x16x4 f32), against the packed data
+//    operand of the streamed chunk;
+//  * the streamed range can be split over several workgroups ("splits");
+//    partial results are summed afterwards in a fixed order.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nfs {
+
+enum { OP_E = 0, OP_EH = 1 };
+enum { PREC_FP32 = 0, PREC_BF16 = 1, PREC_FP16 = 2 };
+
+constexpr int kChunk = 16;        // items per tile/chunk
+constexpr int kWaves = 4;         // waves per workgroup in the encode kernels
+constexpr int kCgBlocks = 256;    // max workgroups of the CG vector kernels
+constexpr int kBmaxBlocks = 256;  // workgroups of the max-magnitude kernels
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// term groups of 4 for P + 1 terms (t*b0 plus P field terms)
+inline int term_groups(int n_basis) {
+  int t = n_basis + 1;
+  if (t <= 8) return 2;
+  if (t <= 20) return 5;
+  return 8;
+}
+// 16-column blocks for 2G real columns (re/im per coil), rounded to 1, 2, 4, 8
+inline int col_blocks(int n_coil) {
+  int nb = (int)cdiv(2 * n_coil, 16);
+  if (nb <= 1) return 1;
+  if (nb <= 2) return 2;
+  if (nb <= 4) return 4;
+  return 8;
+}
+
+// bytes of one packed data chunk (16 items) per column block: fp32 8 x 64
+// floats; fp16 one 16-byte fragment per lane; bf16 two (hi and lo parts)
+inline size_t data_chunk_bytes(int prec) {
+  return prec == PREC_FP32 ? 8 * 64 * 4 : (prec == PREC_BF16 ? 2 * 64 * 16 : 64 * 16);
+}
+
+struct EncodeShape {
+  int op;            // OP_E or OP_EH
+  int prec;          // PREC_*
+  int NT, NB, MT;    // term groups, column blocks, held tiles per wave
+  int64_t HC, SC;    // held / streamed chunk counts
+  int nsplit;        // splits of the streamed range
+  int64_t cps;       // streamed chunks per split
+};
+
+// ---- launchers (encode_kernels.hip) ---------------------------------------
+hipError_t launch_pack_coef_samples(const float* kcoef, const float* t, int64_t K, int P, int NT,
+                                    float* out, hipStream_t s);
+hipError_t launch_pack_coef_voxels(const float* fields, const float* b0, int64_t L, int P, int NT,
+                                   float* out, hipStream_t s);
+hipError_t launch_scale_sens(const float2* sens, const float* icorr, int G, int64_t L, float2* out,
+                             hipStream_t s);
+// value(item, c) = src[item*is + c*cs] * (mul ? mul[c*n_items + item] : 1)
+hipError_t launch_absmax(const float2* src, const float2* mul, int64_t n_items, int64_t is, int64_t cs,
+                         int G, float* bmax, const int* stop, hipStream_t s);
+hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, int64_t n_items,
+                            int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* out,
+                            const float* bmax, float* unscale, const int* stop, hipStream_t s);
+hipError_t launch_encode(const EncodeShape& sh, const float* heldcoef, const float* strmcoef,
+                         const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
+                         const int* stop, hipStream_t s);
+// sum E partials -> m[G][K] (coil-major) times *unscale
+hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
+                                const float* unscale, float2* m, hipStream_t s);
+// sum E partials -> ybuf [HC16][NB*16] times *unscale
+hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB,
+                                   const float* unscale, float* ybuf, const int* stop, hipStream_t s);
+// sum E^H partials -> x[L] times *unscale
+hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
+                            const float* unscale, float2* x, hipStream_t s);
+hipError_t launch_fill_zero(float* p, int64_t n_floats, hipStream_t s);
+
+// ---- CG (cg_kernels.hip) -----------------------------------------------------
+struct CgState {
+  float2* r;        // [L]
+  float2* p;        // [L]
+  float2* q;        // [L]
+  float2* b;        // [L] E^H m (kept for residual replacement)
+  double* part;     // [4][kCgBlocks] per-block partial sums
+  double* alpha;    // [n_iter + 2] alpha_n = r_n^H r_n
+  double* scal;     // [4]: beta, d2, unused, unused
+  double* hist;     // [n_iter + 1][3]
+  int* info;        // [2]
+  int* stop;        // [1]
+  float2* V;        // [n_iter + 1][L] normalised residuals (re-orthogonalisation) or NULL
+  double* rpart;    // [n_iter + 1][2][kCgBlocks] partial dot products v_j^H r
+  double* coef;     // [n_iter + 1][2] v_j^H r
+  int64_t L;
+  int nblk;         // CG workgroups
+};
+constexpr int kMaxReorth = 2048;
+hipError_t launch_cg_reset(const CgState& st, hipStream_t s);
+hipError_t launch_cg_norm_m(const CgState& st, const float2* m, int64_t n, hipStream_t s);
+hipError_t launch_cg_init(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
+                          const float* unscale, float2* rho, int64_t L, hipStream_t s);
+hipError_t launch_cg_start(const CgState& st, int n_iter, hipStream_t s);
+hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
+                          const float* unscale, int64_t L, hipStream_t s);
+hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s);
+hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
+                             const float* unscale, int64_t L, hipStream_t s);
+hipError_t launch_cg_direction(const CgState& st, const float2* rho, int64_t L, int n, int n_iter,
+                               double tol, hipStream_t s);
+// V[j] = r / sqrt(alpha_j)
+hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
+// r -= sum_{j < nv} (v_j^H r) v_j; partial r^H r -> part[1]
+hipError_t launch_cg_reorth(const CgState& st, int nv, hipStream_t s);
+hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, int64_t L, hipStream_t s);
+
+}  // namespace nfs

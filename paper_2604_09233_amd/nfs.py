@@ -1,0 +1,221 @@
+"""Thin ctypes binding of libnfs.so (the C ABI declared in include/nfs.h).
+
+Argument marshalling only: every step of E, E^H, E^H E and the CG solve runs
+in the library's HIP kernels.  PyTorch provides device memory (inputs,
+outputs and the workspace) and the stream (the current torch stream).  There
+is no fallback: if the library is not built, or the device is not gfx950,
+every call raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnfs.so")
+
+NFS_OK, NFS_EINVAL, NFS_ESHAPE, NFS_EHIP, NFS_EWORKSPACE, NFS_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
+PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
+OPS = {"E": 0, "EH": 1, "EHE": 2, "CG": 3}
+CG_STATUS = {1: "max_iter", 2: "tol", 3: "exact", 4: "breakdown"}
+
+_lib = None
+_lib_lock = threading.Lock()
+
+
+class NfsError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"nfs error {code}: {msg}")
+        self.code = code
+
+
+class nfs_problem(ctypes.Structure):
+    _fields_ = [
+        ("n_vox", ctypes.c_int64),
+        ("n_samp", ctypes.c_int64),
+        ("n_coil", ctypes.c_int32),
+        ("n_basis", ctypes.c_int32),
+        ("sens", ctypes.c_void_p),
+        ("fields", ctypes.c_void_p),
+        ("b0", ctypes.c_void_p),
+        ("kcoef", ctypes.c_void_p),
+        ("t", ctypes.c_void_p),
+        ("icorr", ctypes.c_void_p),
+    ]
+
+
+def lib():
+    """Load libnfs.so (raises if it has not been built)."""
+    global _lib
+    with _lib_lock:
+        if _lib is None:
+            if not os.path.exists(LIB_PATH):
+                raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2604_09233_amd.build`")
+            L = ctypes.CDLL(LIB_PATH)
+            vp, i32, sz, dbl = ctypes.c_void_p, ctypes.c_int, ctypes.c_size_t, ctypes.c_double
+            pp = ctypes.POINTER(nfs_problem)
+            L.nfs_create.argtypes = [ctypes.POINTER(vp), i32]
+            L.nfs_destroy.argtypes = [vp]
+            L.nfs_workspace_bytes.argtypes = [vp, pp, i32, i32, i32, i32, ctypes.POINTER(sz)]
+            for name in ("nfs_apply_E", "nfs_apply_EH", "nfs_apply_EHE"):
+                getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
+            L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
+            L.nfs_profile_enable.argtypes = [vp, i32]
+            L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+            L.nfs_last_error.restype = ctypes.c_char_p
+            L.nfs_last_error.argtypes = []
+            L.nfs_version.argtypes = []
+            for name in ("nfs_create", "nfs_destroy", "nfs_workspace_bytes", "nfs_apply_E", "nfs_apply_EH",
+                         "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read"):
+                getattr(L, name).restype = ctypes.c_int
+            _lib = L
+        return _lib
+
+
+def _check(rc):
+    if rc != NFS_OK:
+        raise NfsError(rc, lib().nfs_last_error().decode())
+
+
+_ctx = {}
+
+
+def context(device: int):
+    """Per-device library context (created once)."""
+    if device not in _ctx:
+        h = ctypes.c_void_p()
+        _check(lib().nfs_create(ctypes.byref(h), device))
+        _ctx[device] = h
+    return _ctx[device]
+
+
+def _ptr(x):
+    return ctypes.c_void_p(x.data_ptr()) if x is not None and x.numel() > 0 else ctypes.c_void_p(0)
+
+
+def _f32(x, dev):
+    return x.to(device=dev, dtype=torch.float32).contiguous()
+
+
+def _c64(x, dev):
+    return x.to(device=dev, dtype=torch.complex64).contiguous()
+
+
+class Problem:
+    """Device copies of the model arrays and the matching nfs_problem struct.
+
+    sens [G][L] complex64, fields [P][L] float32, b0 [L] float32 (rad/s),
+    kcoef [K][P] float32 (rad), t [K] float32 (s), icorr [L] float32 or None.
+    Inputs may be numpy arrays or tensors; they are copied to `device`.
+    """
+
+    def __init__(self, sens, fields, b0, kcoef, t, icorr=None, device="cuda:0"):
+        dev = torch.device(device)
+        if dev.type != "cuda":
+            raise ValueError("the library runs on a GPU device only")
+        as_t = lambda a: a if isinstance(a, torch.Tensor) else torch.as_tensor(a)  # noqa: E731
+        self.device = dev
+        self.sens = _c64(as_t(sens), dev)
+        self.fields = _f32(as_t(fields), dev)
+        self.b0 = _f32(as_t(b0), dev)
+        self.kcoef = _f32(as_t(kcoef), dev)
+        self.t = _f32(as_t(t), dev)
+        self.icorr = None if icorr is None else _f32(as_t(icorr), dev)
+        G, L = self.sens.shape
+        K = self.t.shape[0]
+        P = self.fields.shape[0]
+        if self.kcoef.shape != (K, P) or self.fields.shape != (P, L) or self.b0.shape != (L,):
+            raise ValueError("inconsistent problem shapes")
+        self.L, self.K, self.G, self.P = L, K, G, P
+        self.st = nfs_problem(L, K, G, P, _ptr(self.sens), _ptr(self.fields), _ptr(self.b0), _ptr(self.kcoef),
+                              _ptr(self.t), _ptr(self.icorr))
+        self._ws = {}
+
+    @property
+    def index(self):
+        return self.device.index if self.device.index is not None else torch.cuda.current_device()
+
+    def workspace_bytes(self, op: str, precision: str, n_iter: int = 0, reorth: bool = False) -> int:
+        n = ctypes.c_size_t()
+        _check(lib().nfs_workspace_bytes(context(self.index), ctypes.byref(self.st), OPS[op],
+                                         PRECISIONS[precision], n_iter, int(reorth), ctypes.byref(n)))
+        return n.value
+
+    def workspace(self, op: str, precision: str, n_iter: int = 0, reorth: bool = False):
+        nbytes = max(256, self.workspace_bytes(op, precision, n_iter, reorth))
+        key = (op, precision, n_iter, reorth)
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        off = (-ws.data_ptr()) % 256
+        return ws[off:off + nbytes]
+
+    def _stream(self):
+        return ctypes.c_void_p(torch.cuda.current_stream(self.device).cuda_stream)
+
+
+def apply_E(prob: Problem, rho, precision: str = "fp32", out=None):
+    """m = E rho; rho [L] complex64 -> m [G][K] complex64."""
+    rho = _c64(rho, prob.device)
+    m = out if out is not None else torch.empty((prob.G, prob.K), dtype=torch.complex64, device=prob.device)
+    ws = prob.workspace("E", precision)
+    _check(lib().nfs_apply_E(context(prob.index), ctypes.byref(prob.st), _ptr(rho), _ptr(m), PRECISIONS[precision],
+                             _ptr(ws), ws.numel(), prob._stream()))
+    return m
+
+
+def apply_EH(prob: Problem, m, precision: str = "fp32", out=None):
+    """x = E^H m; m [G][K] complex64 -> x [L] complex64."""
+    m = _c64(m, prob.device)
+    x = out if out is not None else torch.empty(prob.L, dtype=torch.complex64, device=prob.device)
+    ws = prob.workspace("EH", precision)
+    _check(lib().nfs_apply_EH(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(x), PRECISIONS[precision],
+                              _ptr(ws), ws.numel(), prob._stream()))
+    return x
+
+
+def apply_EHE(prob: Problem, p, precision: str = "fp32", out=None):
+    """q = E^H E p; p, q [L] complex64."""
+    p = _c64(p, prob.device)
+    q = out if out is not None else torch.empty(prob.L, dtype=torch.complex64, device=prob.device)
+    ws = prob.workspace("EHE", precision)
+    _check(lib().nfs_apply_EHE(context(prob.index), ctypes.byref(prob.st), _ptr(p), _ptr(q),
+                               PRECISIONS[precision], _ptr(ws), ws.numel(), prob._stream()))
+    return q
+
+
+def cg_solve(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int = 0, precision: str = "fp32",
+             reorth: bool = False, out=None, hist=None, info=None):
+    """CG on E^H E rho = E^H m.  Returns (rho [L] complex64, hist [n_iter+1][3]
+    float64 device tensor, info [2] int32 device tensor: iterations, status).
+    Rows of hist past the last iteration are NaN.  reorth: re-orthogonalise
+    each residual against the earlier ones (see include/nfs.h)."""
+    m = _c64(m, prob.device)
+    rho = out if out is not None else torch.empty(prob.L, dtype=torch.complex64, device=prob.device)
+    if hist is None:
+        hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=prob.device)
+    if info is None:
+        info = torch.zeros(2, dtype=torch.int32, device=prob.device)
+    ws = prob.workspace("CG", precision, n_iter, reorth)
+    _check(lib().nfs_cg_solve(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
+                              float(tol), int(replace_every), int(reorth), PRECISIONS[precision], _ptr(hist),
+                              _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
+    return rho, hist, info
+
+
+def profile_enable(device: int, on: bool = True):
+    """Bracket every fused encode-kernel launch on `device` with HIP events."""
+    _check(lib().nfs_profile_enable(context(device), int(on)))
+
+
+def profile_read(device: int, kind: str):
+    """(launch count, summed milliseconds) of the encode kernel of `kind`
+    ("E" or "EH") since the last read; waits for the recorded events."""
+    n = ctypes.c_int()
+    ms = ctypes.c_double()
+    _check(lib().nfs_profile_read(context(device), {"E": 0, "EH": 1}[kind], ctypes.byref(n), ctypes.byref(ms)))
+    return n.value, ms.value

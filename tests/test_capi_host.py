@@ -1,0 +1,148 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every function include/nfs.h declares, and rejects bad arguments with the
+documented status codes before anything touches a device."""
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+from paper_2604_09233_amd import nfs
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "nfs.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(nfs_\w+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    return nfs.lib()
+
+
+def test_every_declared_function_is_exported(L):
+    names = declared_functions()
+    assert set(names) >= {"nfs_create", "nfs_destroy", "nfs_workspace_bytes", "nfs_apply_E", "nfs_apply_EH",
+                          "nfs_apply_EHE", "nfs_cg_solve", "nfs_last_error", "nfs_version"}
+    for n in names:
+        assert hasattr(L, n), n
+
+
+def test_version(L):
+    assert L.nfs_version() == 100
+
+
+# fake but aligned host addresses: validation never dereferences them
+A = 0x100000
+
+
+def prob(L=1000, K=777, G=5, P=7, **over):
+    kw = dict(sens=A, fields=A, b0=A, kcoef=A, t=A, icorr=None)
+    kw.update(over)
+    return nfs.nfs_problem(L, K, G, P, kw["sens"], kw["fields"], kw["b0"], kw["kcoef"], kw["t"], kw["icorr"])
+
+
+FAKE_CTX = ctypes.create_string_buffer(64)
+
+
+def call(L, fn, pr, prec=0, ws=A, ws_bytes=1 << 40, a=A, b=A, ctx=True):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p) if ctx else None
+    p = ctypes.byref(pr) if pr is not None else None
+    if fn == "cg":
+        return L.nfs_cg_solve(c, p, a, b, 5, 0.0, 0, 0, prec, None, None, ws, ws_bytes, None)
+    return getattr(L, fn)(c, p, a, b, prec, ws, ws_bytes, None)
+
+
+FNS = ["nfs_apply_E", "nfs_apply_EH", "nfs_apply_EHE", "cg"]
+
+
+@pytest.mark.parametrize("fn", FNS)
+def test_validation_codes(L, fn):
+    assert call(L, fn, prob(), ctx=False) == nfs.NFS_EINVAL
+    assert b"ctx" in L.nfs_last_error()
+    assert call(L, fn, None) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(G=0)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(G=65)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(P=32)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(P=-1)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(L=-1)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(K=(1 << 26) + 1)) == nfs.NFS_ESHAPE
+    assert call(L, fn, prob(sens=None)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(b0=None)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(fields=None)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(kcoef=None)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(t=None)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(sens=A + 4)) == nfs.NFS_EINVAL   # complex needs 8-byte alignment
+    assert call(L, fn, prob(b0=A + 2)) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(), prec=3) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(), a=None) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(), b=None) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(), a=A + 4) == nfs.NFS_EINVAL
+    assert call(L, fn, prob(), ws=None) == nfs.NFS_EWORKSPACE
+    assert call(L, fn, prob(), ws=A + 128) == nfs.NFS_EWORKSPACE
+    assert call(L, fn, prob(), ws_bytes=1) == nfs.NFS_EWORKSPACE
+    assert b"workspace" in L.nfs_last_error()
+
+
+def test_fields_may_be_null_without_basis_terms(L):
+    # P = 0: only the B0 term; fields/kcoef are not read
+    assert call(L, "nfs_apply_E", prob(P=0, fields=None, kcoef=None), ws_bytes=1) == nfs.NFS_EWORKSPACE
+
+
+def test_cg_specific_validation(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    pr = prob()
+    f = L.nfs_cg_solve
+    assert f(c, ctypes.byref(pr), A, A, -1, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, math.nan, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, math.inf, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, -1e-3, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, -2, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, A + 4, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, A + 2, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A, 1, None) == nfs.NFS_EWORKSPACE
+    # reorth flag: only 0/1, and at most 2048 iterations
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 2, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 3000, 0.0, 0, 1, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+
+
+def test_workspace_bytes(L):
+    n = ctypes.c_size_t()
+    pr = prob()
+    for op in range(4):
+        for prec in range(3):
+            assert L.nfs_workspace_bytes(None, ctypes.byref(pr), op, prec, 10, 0, ctypes.byref(n)) == 0
+            assert n.value > 0 and n.value % 256 == 0
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 4, 0, 0, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 0, 7, 0, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, -1, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 0, 0, 0, 0, None) == nfs.NFS_EINVAL
+    assert L.nfs_workspace_bytes(None, ctypes.byref(prob(G=0)), 0, 0, 0, 0, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    # CG needs at least what E^H E needs, and grows with n_iter
+    L.nfs_workspace_bytes(None, ctypes.byref(pr), 2, 0, 0, 0, ctypes.byref(n))
+    ehe = n.value
+    L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, 10, 0, ctypes.byref(n))
+    cg10 = n.value
+    L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, 1000, 0, ctypes.byref(n))
+    assert cg10 > ehe and n.value > cg10
+    # re-orthogonalisation stores n_iter + 1 residuals
+    L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, 10, 1, ctypes.byref(n))
+    assert n.value >= cg10 + 11 * 1000 * 8
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, 3000, 1, ctypes.byref(n)) == nfs.NFS_EINVAL
+    # empty problems are valid
+    assert L.nfs_workspace_bytes(None, ctypes.byref(prob(L=0, K=0)), 3, 2, 3, 0, ctypes.byref(n)) == 0
+
+
+def test_create_without_gpu_reports_hip_error(L):
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    h = ctypes.c_void_p()
+    assert L.nfs_create(ctypes.byref(h), 0) == nfs.NFS_EHIP
+    assert not h.value
+    assert L.nfs_create(None, 0) == nfs.NFS_EINVAL

@@ -1,0 +1,377 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (relative L2 over the whole complex vector): 1e-4 for the FP32
+operand path, 2e-3 for the BF16/FP16 operand paths (the bars stated for the
+FP32 and reduced-precision forms).  Inputs come from the seeded generators;
+expected values come from the oracle only.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"fp32": 1e-4, "bf16": 2e-3, "fp16": 2e-3}
+PRECS = ["fp32", "bf16", "fp16"]
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / (nb if nb > 0 else 1.0))
+
+
+@pytest.fixture(scope="module")
+def nfs():
+    from paper_2604_09233_amd import nfs as mod
+
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    mod.context(0)
+    return mod
+
+
+def args(d):
+    return (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
+
+
+def gpu_problem(nfs, d, icorr=None):
+    return nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], icorr=icorr)
+
+
+@pytest.fixture(scope="module")
+def c1(nfs):
+    d = synth.make_config("c1")
+    rng = np.random.default_rng(11)
+    d["rho"] = (rng.standard_normal(d["L"]) + 1j * rng.standard_normal(d["L"])).astype(np.complex64)
+    d["m"] = (rng.standard_normal((d["n_coil"], d["K"])) + 1j * rng.standard_normal((d["n_coil"], d["K"]))).astype(np.complex64)
+    d["E_ref"] = oracle.apply_E(d["rho"], *args(d))
+    d["EH_ref"] = oracle.apply_EH(d["m"], *args(d))
+    d["EHE_ref"] = oracle.apply_EHE(d["rho"], *args(d))
+    d["gp"] = gpu_problem(nfs, d)
+    return d
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_E_c1(nfs, c1, prec):
+    m = nfs.apply_E(c1["gp"], torch.from_numpy(c1["rho"]), prec).cpu().numpy()
+    err = rel(m, c1["E_ref"])
+    print(f"E c1 {prec}: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_EH_c1(nfs, c1, prec):
+    x = nfs.apply_EH(c1["gp"], torch.from_numpy(c1["m"]), prec).cpu().numpy()
+    err = rel(x, c1["EH_ref"])
+    print(f"EH c1 {prec}: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_EHE_c1(nfs, c1, prec):
+    q = nfs.apply_EHE(c1["gp"], torch.from_numpy(c1["rho"]), prec).cpu().numpy()
+    err = rel(q, c1["EHE_ref"])
+    print(f"EHE c1 {prec}: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+SHAPES = [
+    (1000, 777, 5, 7),     # ragged everywhere, NB=1, NT=2
+    (1, 1, 1, 0),          # single voxel/sample/coil, only the B0 term
+    (33, 17, 16, 16),      # NB=2, NT=5, one full tile + 1
+    (300, 500, 33, 20),    # NB=8 (66 real columns), NT=8
+    (2048, 3000, 32, 16),  # several tiles, NB=4
+    (16, 4096, 3, 4),      # one held tile for E^H, long stream
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+@pytest.mark.parametrize("prec", PRECS)
+def test_ragged_shapes(nfs, shape, prec):
+    L, K, G, P = shape
+    d = synth.random_problem(L, K, G, P, seed=21)
+    gp = gpu_problem(nfs, d)
+    a = args(d)
+    m = nfs.apply_E(gp, torch.from_numpy(d["rho"]), prec).cpu().numpy()
+    e1 = rel(m, oracle.apply_E(d["rho"], *a))
+    x = nfs.apply_EH(gp, torch.from_numpy(d["m"]), prec).cpu().numpy()
+    e2 = rel(x, oracle.apply_EH(d["m"], *a))
+    q = nfs.apply_EHE(gp, torch.from_numpy(d["rho"]), prec).cpu().numpy()
+    e3 = rel(q, oracle.apply_EHE(d["rho"], *a))
+    print(f"shape {shape} {prec}: E {e1:.2e} EH {e2:.2e} EHE {e3:.2e}")
+    assert max(e1, e2, e3) < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_empty_inputs(nfs, prec):
+    # K = 0: E gives an empty array, E^H gives zeros
+    d = synth.random_problem(40, 1, 3, 4, seed=3)
+    d0 = dict(d, kcoef=d["kcoef"][:0], t=d["t"][:0])
+    gp = gpu_problem(nfs, d0)
+    m = nfs.apply_E(gp, torch.from_numpy(d["rho"]), prec)
+    assert m.shape == (3, 0)
+    x = nfs.apply_EH(gp, torch.zeros((3, 0), dtype=torch.complex64), prec).cpu().numpy()
+    assert not np.any(x)
+    rho, hist, info = nfs.cg_solve(gp, torch.zeros((3, 0), dtype=torch.complex64), 4, precision=prec)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 3]  # exact: E^H m == 0
+    assert not torch.any(rho)
+    # L = 0: E gives zeros
+    d1 = dict(d, sens=d["sens"][:, :0], fields=d["fields"][:, :0], b0=d["b0"][:0])
+    gp1 = gpu_problem(nfs, d1)
+    m1 = nfs.apply_E(gp1, torch.zeros(0, dtype=torch.complex64), prec).cpu().numpy()
+    assert m1.shape == (3, 1) and not np.any(m1)
+
+
+def test_adjoint_identity_gpu(nfs, c1):
+    gp = c1["gp"]
+    Er = nfs.apply_E(gp, torch.from_numpy(c1["rho"]), "fp32").cpu().numpy().astype(np.complex128)
+    EHm = nfs.apply_EH(gp, torch.from_numpy(c1["m"]), "fp32").cpu().numpy().astype(np.complex128)
+    m64 = c1["m"].astype(np.complex128)
+    lhs = np.vdot(Er, m64)
+    rhs = np.vdot(c1["rho"].astype(np.complex128), EHm)
+    # a random inner product cancels (|lhs| ~ ||E rho|| ||m|| / sqrt(N)), so the
+    # error is measured against the Cauchy-Schwarz bound of either side
+    assert abs(lhs - rhs) / (np.linalg.norm(Er) * np.linalg.norm(m64)) < 1e-6
+
+
+def test_determinism(nfs, c1):
+    gp = c1["gp"]
+    for prec in PRECS:
+        a = nfs.apply_EHE(gp, torch.from_numpy(c1["rho"]), prec).cpu()
+        b = nfs.apply_EHE(gp, torch.from_numpy(c1["rho"]), prec).cpu()
+        assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ CG
+# Two reference trajectories.  "plain" follows the figure's recurrences as
+# printed; "reorth" additionally re-orthogonalises each residual (identical
+# in exact arithmetic).  On the paper-shaped spiral workloads E^H E is
+# numerically singular (full field of view, unsampled k-space corners), and
+# the FP64 plain recurrences themselves leave the exact-arithmetic trajectory
+# once CG stagnates; the re-orthogonalised trajectory is stable under
+# rounding.  So: the GPU reorth solve is compared with the oracle reorth
+# solve at every iterate; the GPU plain solve is compared with the oracle
+# plain solve at every iterate up to the horizon where the plain trajectory
+# is stable at the GPU's working precision -- measured with the oracle's
+# sensitivity probe (every E^H E p perturbed by relative noise delta = 1e-6
+# for the FP32 form, 1e-3 for the FP16/BF16 forms: the relative error of one
+# GPU E^H E application at those precisions, to within an order of
+# magnitude) as the last iterate the probe keeps within TOL/4 -- and beyond
+# it only its validity is checked (same data residual and solution norm as
+# the oracle, to 1%).
+DELTA = {"fp32": 1e-6, "bf16": 1e-3, "fp16": 1e-3}
+
+
+def noisy_data(d, snr=30.0):
+    clean = oracle.apply_E(d["rho_true"], *args(d))
+    sigma = np.sqrt(np.mean(np.abs(clean) ** 2)) / (snr * np.sqrt(2))
+    return (clean + sigma * d["noise"]).astype(np.complex64)
+
+
+@pytest.fixture(scope="module")
+def c1_cg(c1):
+    m = noisy_data(c1)
+    n = c1["n_iter"]
+    plain = oracle.cg_solve(m, *args(c1), n_iter=n, return_iterates=True)
+    reo = oracle.cg_solve(m, *args(c1), n_iter=n, return_iterates=True, reorth=True)
+    horizon = {}
+    for prec in PRECS:
+        probe = oracle.cg_solve(m, *args(c1), n_iter=n, return_iterates=True, perturb=(DELTA[prec], 7))
+        dev = [rel(x, y) for x, y in zip(probe["iterates"], plain["iterates"])]
+        hz = 0
+        while hz < n and dev[hz] <= TOL[prec] / 4:
+            hz += 1
+        horizon[prec] = hz
+    return dict(m=m, plain=plain, reorth=reo, horizon=horizon)
+
+
+@pytest.fixture(scope="module")
+def wellcond(nfs):
+    d = synth.random_problem(400, 1500, 4, 4, seed=31, phase_scale=20.0)
+    ref = oracle.cg_solve(d["m"], *args(d), n_iter=12, return_iterates=True)
+    return dict(d=d, gp=gpu_problem(nfs, d), ref=ref)
+
+
+@pytest.mark.parametrize("reorth", [False, True])
+@pytest.mark.parametrize("prec", PRECS)
+def test_cg_well_conditioned_every_iterate(nfs, wellcond, prec, reorth):
+    d, ref = wellcond["d"], wellcond["ref"]
+    for n in [1, 2, 3, 5, 8, 12]:
+        rho, hist, info = nfs.cg_solve(wellcond["gp"], torch.from_numpy(d["m"]), n, precision=prec, reorth=reorth)
+        err = rel(rho.cpu().numpy(), ref["iterates"][n - 1])
+        assert err < TOL[prec], (n, err)
+    h = hist.cpu().numpy()
+    assert info.cpu().tolist() == [12, 1]
+    assert np.max(np.abs(h[:, 0] - ref["hist"][:, 0])) < TOL[prec] * ref["hist"][0, 0]
+    assert np.max(np.abs(h[:, 1] - ref["hist"][:, 1])) < TOL[prec] * ref["hist"][-1, 1]
+    assert np.max(np.abs(h[:, 2] - ref["hist"][:, 2])) < TOL[prec] * ref["hist"][0, 2]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cg_c1_reorth_every_iterate(nfs, c1, c1_cg, prec):
+    ref = c1_cg["reorth"]
+    errs = []
+    for n in [1, 3, 5, 8, 10, 12, 15, 18, 20]:
+        rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), n, precision=prec, reorth=True)
+        errs.append(rel(rho.cpu().numpy(), ref["iterates"][n - 1]))
+    print(f"CG c1 reorth {prec}: " + " ".join(f"{e:.1e}" for e in errs))
+    assert info.cpu().tolist() == [20, 1]
+    assert max(errs) < TOL[prec]
+    h = hist.cpu().numpy()
+    assert np.max(np.abs(h[:, 2] - ref["hist"][:, 2])) < TOL[prec] * ref["hist"][0, 2]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cg_c1_plain(nfs, c1, c1_cg, prec):
+    ref = c1_cg["plain"]
+    hz = c1_cg["horizon"][prec]
+    assert hz >= 3
+    for n in sorted({1, max(1, hz // 2), hz}):
+        rho, _, _ = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), n, precision=prec)
+        err = rel(rho.cpu().numpy(), ref["iterates"][n - 1])
+        assert err < TOL[prec], (n, err)
+    n = c1["n_iter"]
+    rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), n, precision=prec)
+    x = rho.cpu().numpy()
+    m = c1_cg["m"].astype(np.complex128)
+    d_gpu = np.linalg.norm(m - oracle.apply_E(x, *args(c1))) ** 2
+    d_ref = np.linalg.norm(m - oracle.apply_E(ref["rho"], *args(c1))) ** 2
+    print(f"CG c1 plain {prec}: horizon {hz}, final rel {rel(x, ref['rho']):.2e} "
+          f"(oracle plain vs reorth {rel(ref['rho'], c1_cg['reorth']['rho']):.2e}), "
+          f"data residual {d_gpu:.6e} vs {d_ref:.6e}")
+    assert abs(d_gpu - d_ref) < 1e-2 * d_ref
+    assert abs(np.linalg.norm(x) - np.linalg.norm(ref["rho"])) < 1e-2 * np.linalg.norm(ref["rho"])
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_cg_residual_replacement(nfs, c1, c1_cg, prec):
+    n = c1["n_iter"]
+    rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), n, replace_every=5, precision=prec,
+                                   reorth=True)
+    torch.cuda.synchronize()
+    err = rel(rho.cpu().numpy(), c1_cg["reorth"]["rho"])
+    print(f"CG c1 {prec} reorth + replace_every=5: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+def test_cg_tolerance_stop(nfs, c1, c1_cg):
+    ref = c1_cg["reorth"]
+    r = ref["hist"][:, 0] / ref["hist"][0, 0]
+    # first step whose residual falls clearly below all earlier ones
+    n_stop = next(n for n in range(3, len(r)) if r[n] < 0.98 * r[:n].min())
+    tol = float(np.sqrt(r[n_stop] * r[:n_stop].min()))
+    rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), 50, tol=tol, precision="fp32",
+                                   reorth=True)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [n_stop, 2]
+    assert rel(rho.cpu().numpy(), ref["iterates"][n_stop - 1]) < 1e-4
+    h = hist.cpu().numpy()
+    assert np.all(np.isnan(h[n_stop + 1:]))
+
+
+def test_cg_unitary_one_step(nfs):
+    d = synth.dft_problem(16)
+    gp = gpu_problem(nfs, d)
+    rng = np.random.default_rng(1)
+    m = (rng.standard_normal((1, d["K"])) + 1j * rng.standard_normal((1, d["K"]))).astype(np.complex64)
+    rho, hist, info = nfs.cg_solve(gp, torch.from_numpy(m), 5, tol=1e-3, precision="fp32")
+    torch.cuda.synchronize()
+    it, st = info.cpu().tolist()
+    assert it == 1 and st == 2
+    want = oracle.apply_EH(m, *args(d)) / d["K"]
+    assert rel(rho.cpu().numpy(), want) < 1e-4
+
+
+def test_cg_n_iter_zero_and_intensity_correction(nfs, c1, c1_cg):
+    rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), 0)
+    torch.cuda.synchronize()
+    assert info.cpu().tolist() == [0, 1] and not torch.any(rho)
+    j = np.random.default_rng(2).uniform(0.5, 2.0, size=c1["L"]).astype(np.float32)
+    gp = gpu_problem(nfs, c1, icorr=j)
+    rho, hist, info = nfs.cg_solve(gp, torch.from_numpy(c1_cg["m"]), 5, precision="fp32")
+    ref = oracle.cg_solve(c1_cg["m"], *args(c1), n_iter=5, icorr=j)
+    assert rel(rho.cpu().numpy(), ref["rho"]) < 1e-4
+
+
+def test_cg_determinism(nfs, c1, c1_cg):
+    out = []
+    for _ in range(2):
+        rho, hist, info = nfs.cg_solve(c1["gp"], torch.from_numpy(c1_cg["m"]), 10, precision="fp16", reorth=True)
+        out.append((rho.cpu(), hist.cpu()))
+    assert torch.equal(out[0][0], out[1][0]) and torch.equal(out[0][1], out[1][1])
+
+
+# ------------------------------------------- full-size workload, sampled outputs
+@pytest.fixture(scope="module")
+def c2(nfs):
+    d = synth.make_config("c2")
+    d["gp"] = gpu_problem(nfs, d)
+    rng = np.random.default_rng(99)
+    d["ks"] = np.sort(rng.choice(d["K"], 1500, replace=False))
+    d["ls"] = np.sort(rng.choice(d["L"], 1500, replace=False))
+    return d
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_E_sampled(nfs, c2, prec):
+    d = c2
+    rho = d["rho_true"]
+    m = nfs.apply_E(d["gp"], torch.from_numpy(rho), prec).cpu().numpy()
+    ks = d["ks"]
+    ref = oracle.apply_E(rho, d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
+    err = rel(m[:, ks], ref)
+    print(f"c2 E sampled {prec}: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_EH_sampled(nfs, c2, prec):
+    d = c2
+    rng = np.random.default_rng(4)
+    m = (rng.standard_normal((d["n_coil"], d["K"])) + 1j * rng.standard_normal((d["n_coil"], d["K"]))).astype(np.complex64)
+    x = nfs.apply_EH(d["gp"], torch.from_numpy(m), prec).cpu().numpy()
+    ls = d["ls"]
+    ref = oracle.apply_EH(m, d["sens"][:, ls], d["fields"][:, ls], d["b0"][ls], d["kcoef"], d["t"])
+    err = rel(x[ls], ref)
+    print(f"c2 EH sampled {prec}: rel {err:.3e}")
+    assert err < TOL[prec]
+
+
+# --------------------------------------- full-size CG against the stored oracle solve
+@pytest.fixture(scope="module")
+def c2_golden(c2):
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "c2_cg.npz")
+    g = np.load(path)
+    m = noisy_data(c2)  # same recipe as tests/golden/make_golden.py (oracle E)
+    return dict(g=g, m=m)
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_cg_reorth_vs_stored_oracle(nfs, c2, c2_golden, prec):
+    g = c2_golden["g"]
+    rho, hist, info = nfs.cg_solve(c2["gp"], torch.from_numpy(c2_golden["m"]), 30, precision=prec, reorth=True)
+    err = rel(rho.cpu().numpy(), g["reorth_rho"])
+    e10 = None
+    rho10, _, _ = nfs.cg_solve(c2["gp"], torch.from_numpy(c2_golden["m"]), 10, precision=prec, reorth=True)
+    e10 = rel(rho10.cpu().numpy(), g["reorth_it_10"])
+    print(f"c2 CG reorth {prec}: iterate 10 rel {e10:.2e}, iterate 30 rel {err:.2e}")
+    assert info.cpu().tolist() == [30, 1]
+    assert err < TOL[prec] and e10 < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_c2_cg_plain_vs_stored_oracle(nfs, c2, c2_golden, prec):
+    # plain recurrences at full size: the early stored iterates (1-3), which
+    # sit well inside the stable horizon at every working precision
+    g = c2_golden["g"]
+    for n in (1, 2, 3):
+        rho, _, _ = nfs.cg_solve(c2["gp"], torch.from_numpy(c2_golden["m"]), n, precision=prec)
+        err = rel(rho.cpu().numpy(), g[f"plain_it_{n}"])
+        print(f"c2 CG plain {prec}: iterate {n} rel {err:.2e}")
+        assert err < TOL[prec]

@@ -282,3 +282,56 @@ def test_gradients_match_central_differences():
     v = r.standard_normal(kcoef.shape)
     fd = (L(k_=kcoef + h * v) - L(k_=kcoef - h * v)) / (2 * h)
     assert abs(fd - np.sum(v * g_k)) < 1e-6 * abs(fd)
+
+
+# ------------------------------------------------- re-orthogonalised CG
+def _galerkin_iterates(A, b, n):
+    """Exact-arithmetic CG iterates as Galerkin solutions on the Krylov space
+    K_n(A, b): x_n = Q_n (Q_n^H A Q_n)^{-1} Q_n^H b with Q_n an orthonormal
+    basis built by Arnoldi with two Gram-Schmidt passes (dense, tiny)."""
+    Q = [b / np.linalg.norm(b)]
+    out = []
+    for k in range(1, n + 1):
+        Qm = np.stack(Q, axis=1)
+        H = Qm.conj().T @ A @ Qm
+        out.append(Qm @ np.linalg.solve(H, Qm.conj().T @ b))
+        w = A @ Q[-1]
+        for _ in range(2):
+            w = w - Qm @ (Qm.conj().T @ w)
+        Q.append(w / np.linalg.norm(w))
+    return out
+
+
+def test_reorth_cg_equals_krylov_galerkin_solution():
+    d = synth.random_problem(40, 30, 2, 4, seed=13, phase_scale=6.0)
+    a = _args(d)
+    Ed = oracle.dense_E(*a)
+    A = Ed.conj().T @ Ed
+    m = d["m"].astype(np.complex128)
+    b = Ed.conj().T @ m.ravel()
+    ref = _galerkin_iterates(A, b, 12)
+    res = oracle.cg_solve(m, *a, n_iter=12, return_iterates=True, reorth=True)
+    for n in range(12):
+        assert _rel(res["iterates"][n], ref[n]) < 1e-8, n
+
+
+def test_reorth_matches_plain_cg_on_a_well_conditioned_problem():
+    d = synth.random_problem(50, 200, 3, 4, seed=14, phase_scale=20.0)
+    a = _args(d)
+    m = d["m"].astype(np.complex128)
+    r0 = oracle.cg_solve(m, *a, n_iter=10, return_iterates=True)
+    r1 = oracle.cg_solve(m, *a, n_iter=10, return_iterates=True, reorth=True)
+    for x, y in zip(r0["iterates"], r1["iterates"]):
+        assert _rel(x, y) < 1e-12
+
+
+def test_reorth_keeps_residuals_orthogonal_on_the_2d_spiral_config():
+    d = synth.make_config("c1")
+    a = _args(d)
+    m = oracle.apply_E(d["rho_true"], *a) + 0.1 * d["noise"]
+    res = oracle.cg_solve(m, *a, n_iter=20, return_iterates=True, reorth=True)
+    rhs = oracle.apply_EH(m, *a)
+    rs = [rhs] + [rhs - oracle.apply_EHE(x, *a) for x in res["iterates"]]
+    U = np.stack([r / np.linalg.norm(r) for r in rs], axis=1)
+    G = U.conj().T @ U
+    assert np.max(np.abs(G - np.eye(len(rs)))) < 1e-6
