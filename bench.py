@@ -2,8 +2,9 @@
 """Benchmark of the non-Fourier SENSE hot path on one MI355X.
 
 One step = one full CG solve (setup, E^H m, n_iter iterations of E^H E with
-the FP64 scalar updates) on the 2D 128x128 / 16-coil / 4 x 15000-sample /
-16-field-term workload (30 iterations), inputs resident in HBM.
+the FP64 scalar updates and residual re-orthogonalisation) on the 2D
+128x128 / 16-coil / 4 x 15000-sample / 16-field-term workload (30
+iterations), inputs resident in HBM.
 
 Reported value: E^H E voxel*sample*coil per second over the solve, i.e.
 (n_iter + 1/2) * L * K * G / (solve time), the initial E^H m counting as half
@@ -43,6 +44,7 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--trans-rate", type=float, default=0.25,
                     help="v_sin/v_cos issue rate as a fraction of the FP32 FMA rate (for the ALU peak)")
     return ap.parse_args()
@@ -98,15 +100,15 @@ def main():
     m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
     torch.cuda.synchronize()
 
-    def solve(prec, out, hist, info):
-        return nfs.cg_solve(prob, m, n_iter, precision=prec, out=out, hist=hist, info=info)
+    def solve(prec, out, hist, info, reorth):
+        return nfs.cg_solve(prob, m, n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
 
-    def time_solves(prec, steps, warmup, profile=False):
+    def time_solves(prec, steps, warmup, profile=False, reorth=not args.plain):
         out = torch.empty(L, dtype=torch.complex64, device=dev)
         hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
         info = torch.zeros(2, dtype=torch.int32, device=dev)
         for _ in range(warmup):
-            solve(prec, out, hist, info)
+            solve(prec, out, hist, info, reorth)
         torch.cuda.synchronize()
         if profile:
             nfs.profile_enable(0, True)
@@ -116,7 +118,7 @@ def main():
         t0 = time.perf_counter()
         ev0.record()
         for _ in range(steps):
-            solve(prec, out, hist, info)
+            solve(prec, out, hist, info, reorth)
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -133,10 +135,11 @@ def main():
 
     # accuracy against the stored FP64 oracle solve of this workload
     err = None
+    kind = "plain" if args.plain else "reorth"
     gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}_cg.npz")
     if os.path.exists(gpath):
         g = np.load(gpath)
-        err = rel(rho.cpu().numpy(), g["rho"])
+        err = rel(rho.cpu().numpy(), g[f"{kind}_rho"])
 
     # one E^H E application alone (median of 20 after 3 warm-ups)
     p = torch.from_numpy(d["rho_true"]).to(dev)
@@ -159,19 +162,26 @@ def main():
     if not args.no_fp32_form and args.precision != "fp32":
         rho32, _, _, ms32, _, _ = time_solves("fp32", max(1, args.steps // 2), 1)
         fp32 = dict(ms_per_step=ms32, value=(n_iter + 0.5) * vsc / (ms32 * 1e-3),
-                    rel_err_vs_oracle=rel(rho32.cpu().numpy(), g["rho"]) if err is not None else None)
+                    rel_err_vs_oracle=rel(rho32.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
+    # plain recurrences, same precision, for reference
+    plain = None
+    if not args.plain:
+        rhop, _, _, msp, _, _ = time_solves(args.precision, max(1, args.steps // 2), 1, reorth=False)
+        plain = dict(ms_per_step=msp,
+                     rel_err_vs_oracle_plain=rel(rhop.cpu().numpy(), g["plain_rho"]) if err is not None else None,
+                     oracle_plain_vs_reorth=float(g["plain_vs_reorth"][-1]) if err is not None else None)
 
     # roofline of the dominant kernel (the fused encode kernel, E or E^H)
     n_e, ms_e = kt["E"]
     n_h, ms_h = kt["EH"]
-    kind, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
+    kname, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
     avg_ms = ms_k / max(n_k, 1)
     pairs = L * K  # voxel-sample pairs per launch
     # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
     trans_peak = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 * args.trans_rate  # ops/s
     achieved = 2 * pairs / (avg_ms * 1e-3)
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=trans_peak / 1e12, unit="Tsincos-ops/s",
-                    frac=achieved / trans_peak, traffic=None, kernel=f"encode_kernel ({kind})",
+                    frac=achieved / trans_peak, traffic=None, kernel=f"encode_kernel ({kname})",
                     avg_launch_ms=avg_ms, launches=n_k,
                     mfma_frac=(8 * G * pairs / (avg_ms * 1e-3)) / (MFMA_PEAK_TFLOPS[args.precision] * 1e12))
 
@@ -191,11 +201,13 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: 2D 128x128, 16 coils, 4x15000-sample R=4 spiral, 16 field terms, "
                                f"B0 +-100 Hz, {n_iter} CG iterations (one step = one CG solve)",
-                   "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision},
+                   "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision,
+                   "cg": "plain" if args.plain else "re-orthogonalised"},
         "rel_err_vs_oracle": err,
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
         "fp32_form": fp32,
+        "plain_recurrences": plain,
         "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
         "roofline": roofline,
         "wall_s_timed": wall,

@@ -262,17 +262,16 @@ __global__ __launch_bounds__(256) void cg_reorth_dots_kernel(CgState st) {
   }
 }
 
-// one workgroup: coef[j] = sum of the partials (fixed order)
-__global__ __launch_bounds__(256) void cg_reorth_coef_kernel(CgState st, int nv) {
+// workgroup j: coef[j] = sum of the partials of v_j^H r (fixed order)
+__global__ __launch_bounds__(256) void cg_reorth_coef_kernel(CgState st) {
   if (*st.stop) return;
   __shared__ double red[256];
-  for (int j = 0; j < nv; ++j) {
-    const double re = sum_partials(st.rpart + (2 * (size_t)j) * kCgBlocks, st.nblk, red);
-    const double im = sum_partials(st.rpart + (2 * (size_t)j + 1) * kCgBlocks, st.nblk, red);
-    if (threadIdx.x == 0) {
-      st.coef[2 * j] = re;
-      st.coef[2 * j + 1] = im;
-    }
+  const int j = blockIdx.x;
+  const double re = sum_partials(st.rpart + (2 * (size_t)j) * kCgBlocks, st.nblk, red);
+  const double im = sum_partials(st.rpart + (2 * (size_t)j + 1) * kCgBlocks, st.nblk, red);
+  if (threadIdx.x == 0) {
+    st.coef[2 * j] = re;
+    st.coef[2 * j + 1] = im;
   }
 }
 
@@ -361,7 +360,7 @@ hipError_t launch_cg_reorth(const CgState& st, int nv, hipStream_t s) {
   hipLaunchKernelGGL(cg_reorth_dots_kernel, dim3(st.nblk, nv), dim3(256), 0, s, st);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cg_reorth_coef_kernel, dim3(1), dim3(256), 0, s, st, nv);
+  hipLaunchKernelGGL(cg_reorth_coef_kernel, dim3(nv), dim3(256), 0, s, st);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(cg_reorth_apply_kernel, dim3(st.nblk), dim3(256), 0, s, st, nv);

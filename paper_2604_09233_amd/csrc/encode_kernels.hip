@@ -100,13 +100,13 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
   if (stop && *stop) return;
   __shared__ float red[256];
   float mx = 0.f;
-  const int64_t total = n_items * G;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (int64_t)gridDim.x * 256) {
-    const int64_t item = i % n_items;
-    const int64_t c = i / n_items;
-    float2 v = src[item * is + c * cs];
-    if (mul) v = cmul(mul[c * n_items + item], v);
-    mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+  for (int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x; item < n_items;
+       item += (int64_t)gridDim.x * 256) {
+    for (int c = 0; c < G; ++c) {
+      float2 v = src[item * is + (int64_t)c * cs];
+      if (mul) v = cmul(mul[(int64_t)c * n_items + item], v);
+      mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+    }
   }
   red[threadIdx.x] = mx;
   __syncthreads();
@@ -259,11 +259,19 @@ __global__ __launch_bounds__(256) void encode_kernel(
 #pragma unroll
     for (int t = 0; t < NT; ++t) hc[mt][t] = tile < HC ? heldcoef[(tile * NT + t) * 64 + lane] : 0.f;
   }
-  f4 acc[MT][NB];
+  // Two-level accumulation: the matrix cores add into `inner`, which is
+  // flushed into `acc` on the VALU every IC chunks, so the long running sum
+  // is rounded once per IC chunks instead of once per MFMA.
+  constexpr int IC = PREC == PREC_FP32 ? 1 : 8;
+  f4 acc[MT][NB], inner[MT][NB];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int nb = 0; nb < NB; ++nb) {
+      acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+      inner[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+    }
+  int since_flush = 0;
 
   const int64_t c0 = split * cps;
   const int64_t c1 = (c0 + cps < SC) ? c0 + cps : SC;
@@ -308,7 +316,7 @@ __global__ __launch_bounds__(256) void encode_kernel(
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb)
-          acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, bh[nb][0]), acc[mt][nb], 0, 0, 0);
+          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, bh[nb][0]), inner[mt][nb], 0, 0, 0);
       } else if (PREC == PREC_BF16) {
         b8 a;
 #pragma unroll
@@ -318,8 +326,8 @@ __global__ __launch_bounds__(256) void encode_kernel(
         }
 #pragma unroll
         for (int nb = 0; nb < NB; ++nb) {
-          acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][0]), acc[mt][nb], 0, 0, 0);
-          acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][NFRAG - 1]), acc[mt][nb], 0, 0, 0);
+          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][0]), inner[mt][nb], 0, 0, 0);
+          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][NFRAG - 1]), inner[mt][nb], 0, 0, 0);
         }
       } else {
 #pragma unroll
@@ -327,11 +335,25 @@ __global__ __launch_bounds__(256) void encode_kernel(
           const float a = (u & 1) ? sn[u >> 1] : cs[u >> 1];
 #pragma unroll
           for (int nb = 0; nb < NB; ++nb)
-            acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[nb][u], acc[mt][nb], 0, 0, 0);
+            inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[nb][u], inner[mt][nb], 0, 0, 0);
         }
       }
     }
+    if (++since_flush == IC) {
+      since_flush = 0;
+#pragma unroll
+      for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          acc[mt][nb] += inner[mt][nb];
+          inner[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+    }
   }
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] += inner[mt][nb];
 
   const int g = lane >> 4, n = lane & 15;
   if (OP == OP_E) {
