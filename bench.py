@@ -29,10 +29,12 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published / derived peaks
+# MI355X published / derived peaks.  VALU: 256 CUs x 4 SIMDs x 32 FP32 lanes
+# per clock at 2.4 GHz = 157.3 TFLOP/s (FMA); transcendental ops (v_sin_f32,
+# v_cos_f32) issue at a quarter of that lane rate.
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
-N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 16, 2.4
+N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 32, 2.4
 
 
 def parse():
@@ -46,7 +48,7 @@ def parse():
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--trans-rate", type=float, default=0.25,
-                    help="v_sin/v_cos issue rate as a fraction of the FP32 FMA rate (for the ALU peak)")
+                    help="v_sin/v_cos issue rate as a fraction of the FP32 lane rate (for the ALU peak)")
     return ap.parse_args()
 
 
@@ -180,10 +182,16 @@ def main():
     # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
     trans_peak = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 * args.trans_rate  # ops/s
     achieved = 2 * pairs / (avg_ms * 1e-3)
+    # matrix-pipe time of the algorithmic contractions: the (P+1)-term phase
+    # product on the FP32 matrix cores and the 8G-flop complex contraction at
+    # the operand precision, as a fraction of the measured launch time
+    P = d["n_basis"]
+    t_mfma = pairs * (2 * (P + 1) / (MFMA_PEAK_TFLOPS["fp32"] * 1e12)
+                      + 8 * G / (MFMA_PEAK_TFLOPS[args.precision] * 1e12))
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=trans_peak / 1e12, unit="Tsincos-ops/s",
                     frac=achieved / trans_peak, traffic=None, kernel=f"encode_kernel ({kname})",
                     avg_launch_ms=avg_ms, launches=n_k,
-                    mfma_frac=(8 * G * pairs / (avg_ms * 1e-3)) / (MFMA_PEAK_TFLOPS[args.precision] * 1e12))
+                    mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
 
     st = info.cpu().tolist()
     out = {

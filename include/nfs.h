@@ -150,6 +150,22 @@ int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* r
                  int n_iter, double tol, int replace_every, int reorth, int precision,
                  double* hist, int* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Backward of m = E rho for a real loss L, for field-map and trajectory
+ * refinement.  grad_m is dL/dm in PyTorch's convention for complex tensors
+ * (for L = ||E rho - sigma||^2 it is 2 (E rho - sigma)).  Differentiating the
+ * signal model's phase phi = K R (Methods, signal-model equations) gives
+ *   grad_rho[l]      = (E^H grad_m)[l]
+ *   grad_b0[l]       = Im(conj(rho[l]) (E^H (t o grad_m))[l])
+ *   grad_kcoef[k][b] = Im(sum_c grad_m[c][k] conj((E (fields[b] o rho))[c][k]))
+ * (the paper has no gradients; this is their derivation).  rho: [L]
+ * complex; grad_m: [G][K] complex; grad_rho: [L] complex, grad_b0: [L]
+ * real, grad_kcoef: [K][P] real -- each output may be NULL to skip it.
+ * Cost: one E^H for grad_rho, one for grad_b0, one E per field term for
+ * grad_kcoef.  Workspace: nfs_workspace_bytes(NFS_OP_EHE).                 */
+int nfs_encode_backward(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, const float* grad_m,
+                        float* grad_rho, float* grad_b0, float* grad_kcoef, int precision,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* Kernel timing for benchmarks.  While enabled, every launch of the fused
  * encode kernel (the phase/sincos/contraction kernel of E and of E^H) made
  * through `ctx` is bracketed by two HIP events recorded on its launch

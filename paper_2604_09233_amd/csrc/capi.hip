@@ -157,9 +157,9 @@ static size_t al(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct Layout {
   int64_t L, K, LC, KC;
-  int G, P, NT, NB, prec;
+  int G, P, NQ, NB, prec;
   EncodeShape shE, shH;
-  size_t o_scoef, o_vcoef, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
+  size_t o_sA, o_sB, o_vA, o_vB, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
   size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_coef;
   size_t total;
 };
@@ -183,27 +183,31 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.P = pr->n_basis;
   y.LC = cdiv(y.L, kChunk);
   y.KC = cdiv(y.K, kChunk);
-  y.NT = term_groups(y.P);
+  y.NQ = phase_instrs(y.P);
   y.NB = col_blocks(y.G);
   y.prec = prec;
   const int n_cu = ctx ? ctx->n_cu : 256;
   const int MT = 2;
-  y.shE = EncodeShape{OP_E, prec, y.NT, y.NB, MT, y.KC, y.LC, 1, 0};
+  y.shE = EncodeShape{OP_E, prec, y.NQ, y.NB, MT, y.KC, y.LC, 1, 0};
   y.shE.nsplit = choose_split(y.KC, y.LC, MT, n_cu);
   y.shE.cps = cdiv(y.LC, y.shE.nsplit);
-  y.shH = EncodeShape{OP_EH, prec, y.NT, y.NB, MT, y.LC, y.KC, 1, 0};
+  y.shH = EncodeShape{OP_EH, prec, y.NQ, y.NB, MT, y.LC, y.KC, 1, 0};
   y.shH.nsplit = choose_split(y.LC, y.KC, MT, n_cu);
   y.shH.cps = cdiv(y.KC, y.shH.nsplit);
-
   const bool needE = op != NFS_OP_EH, needH = op != NFS_OP_E, cg = op == NFS_OP_CG;
+
   size_t o = 0;
   auto take = [&](size_t bytes) {
     const size_t at = o;
     o += al(bytes);
     return at;
   };
-  y.o_scoef = take((size_t)y.KC * y.NT * 64 * 4);
-  y.o_vcoef = take((size_t)y.LC * y.NT * 64 * 4);
+  // phase parts: E streams voxels (role A) against held samples (role B);
+  // E^H streams samples (role A) against held voxels (role B)
+  y.o_vA = needE ? take((size_t)y.LC * phase_chunk_bytes(y.NQ)) : 0;
+  y.o_sB = needE ? take((size_t)y.KC * phase_chunk_bytes(y.NQ)) : 0;
+  y.o_sA = needH ? take((size_t)y.KC * phase_chunk_bytes(y.NQ)) : 0;
+  y.o_vB = needH ? take((size_t)y.LC * phase_chunk_bytes(y.NQ)) : 0;
   y.o_bmax = take(kBmaxBlocks * 4);
   y.o_unscale = take(2 * 4);
   y.o_dataE = needE ? take((size_t)y.LC * y.NB * data_chunk_bytes(prec)) : 0;
@@ -297,11 +301,17 @@ static int timed_encode(const Ctx& c, int kind, F&& launch) {
   return NFS_OK;
 }
 
-static int seq_pack_coefs(const Ctx& c) {
-  NFS_TRY(launch_pack_coef_samples(c.pr->kcoef, c.pr->t, c.y.K, c.y.P, c.y.NT, at<float>(c.ws, c.y.o_scoef), c.s),
-          "pack_coef_samples");
-  NFS_TRY(launch_pack_coef_voxels(c.pr->fields, c.pr->b0, c.y.L, c.y.P, c.y.NT, at<float>(c.ws, c.y.o_vcoef), c.s),
-          "pack_coef_voxels");
+static int seq_pack_coefs(const Ctx& c, bool forE, bool forH) {
+  const Layout& y = c.y;
+  const nfs_problem* p = c.pr;
+  if (forE) {
+    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 0, y.NQ, at<void>(c.ws, y.o_vA), c.s), "pack_phase");
+    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 1, y.NQ, at<void>(c.ws, y.o_sB), c.s), "pack_phase");
+  }
+  if (forH) {
+    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 0, y.NQ, at<void>(c.ws, y.o_sA), c.s), "pack_phase");
+    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 1, y.NQ, at<void>(c.ws, y.o_vB), c.s), "pack_phase");
+  }
   return NFS_OK;
 }
 
@@ -309,30 +319,31 @@ static float* unscale_slot(const Ctx& c, int which) {
   return c.y.prec == PREC_FP16 ? at<float>(c.ws, c.y.o_unscale) + which : nullptr;
 }
 
-// E part: rho -> epart (partials) via packed Q = S o rho
-static int seq_E(const Ctx& c, const float2* rho) {
+// E part: rho -> epart (partials) via packed Q = S o rho (o wgt)
+static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
-  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(rho, c.sens, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
-  NFS_TRY(launch_pack_data(OP_E, y.prec, rho, c.sens, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(c.ws, y.o_dataE), bmax,
-                           at<float>(c.ws, y.o_unscale), c.stop, c.s),
+  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(rho, c.sens, wgt, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
+  NFS_TRY(launch_pack_data(OP_E, y.prec, rho, c.sens, wgt, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(c.ws, y.o_dataE),
+                           bmax, at<float>(c.ws, y.o_unscale), c.stop, c.s),
           "pack_data(E)");
   return timed_encode(c, 0, [&] {
-    return launch_encode(y.shE, at<float>(c.ws, y.o_scoef), at<float>(c.ws, y.o_vcoef), at<void>(c.ws, y.o_dataE),
+    return launch_encode(y.shE, at<void>(c.ws, y.o_sB), at<void>(c.ws, y.o_vA), at<void>(c.ws, y.o_dataE),
                          at<float>(c.ws, y.o_epart), c.sens, y.L, y.G, c.stop, c.s);
   });
 }
 
-// E^H part: src (m [G][K] or ybuf) -> hpart (coil-combined partials)
-static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs) {
+// E^H part: src (m [G][K] or ybuf) (o wgt) -> hpart (coil-combined partials)
+static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
-  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(src, nullptr, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
-  NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
+  if (y.prec == PREC_FP16)
+    NFS_TRY(launch_absmax(src, nullptr, wgt, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
+  NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, wgt, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
                            bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
           "pack_data(EH)");
   return timed_encode(c, 1, [&] {
-    return launch_encode(y.shH, at<float>(c.ws, y.o_vcoef), at<float>(c.ws, y.o_scoef), at<void>(c.ws, y.o_dataH),
+    return launch_encode(y.shH, at<void>(c.ws, y.o_vB), at<void>(c.ws, y.o_sA), at<void>(c.ws, y.o_dataH),
                          at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, c.stop, c.s);
   });
 }
@@ -362,7 +373,7 @@ extern "C" int nfs_apply_E(nfs_ctx* ctx, const nfs_problem* prob, const float* r
   if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
   if (y.K == 0) return NFS_OK;
   Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
-  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_pack_coefs(c, true, false))) return rc;
   if ((rc = seq_E(c, reinterpret_cast<const float2*>(rho)))) return rc;
   NFS_TRY(launch_finish_E_to_m(at<float>(ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, unscale_slot(c, 0),
                                reinterpret_cast<float2*>(m), c.s),
@@ -383,7 +394,7 @@ extern "C" int nfs_apply_EH(nfs_ctx* ctx, const nfs_problem* prob, const float* 
   if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
   if (y.L == 0) return NFS_OK;
   Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
-  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_pack_coefs(c, false, true))) return rc;
   if ((rc = seq_EH(c, reinterpret_cast<const float2*>(m), 1, y.K))) return rc;
   NFS_TRY(launch_finish_EH(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1),
                            reinterpret_cast<float2*>(x), c.s),
@@ -404,7 +415,7 @@ extern "C" int nfs_apply_EHE(nfs_ctx* ctx, const nfs_problem* prob, const float*
   if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
   if (y.L == 0) return NFS_OK;
   Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
-  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_pack_coefs(c, true, true))) return rc;
   if ((rc = seq_EHE(c, reinterpret_cast<const float2*>(p)))) return rc;
   NFS_TRY(launch_finish_EH(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1),
                            reinterpret_cast<float2*>(q), c.s),
@@ -464,7 +475,7 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
   const int ns = y.shH.nsplit;
 
   NFS_TRY(launch_cg_reset(st, s), "cg_reset");
-  if ((rc = seq_pack_coefs(c))) return rc;
+  if ((rc = seq_pack_coefs(c, true, true))) return rc;
   NFS_TRY(launch_cg_norm_m(st, reinterpret_cast<const float2*>(m), (int64_t)y.G * y.K, s), "cg_norm_m");
   if ((rc = seq_EH(c, reinterpret_cast<const float2*>(m), 1, y.K))) return rc;
   NFS_TRY(launch_cg_init(st, hpart, ns, hstride, unscale_slot(c, 1), x, y.L, s), "cg_init");
@@ -483,5 +494,47 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
     if (reorth) NFS_TRY(launch_cg_store_v(st, n + 1, s), "cg_store_v");
   }
   NFS_TRY(launch_cg_finish(st, x, prob->icorr, y.L, s), "cg_finish");
+  return NFS_OK;
+}
+
+extern "C" int nfs_encode_backward(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, const float* grad_m,
+                                   float* grad_rho, float* grad_b0, float* grad_kcoef, int precision, void* ws,
+                                   size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_encode_backward";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if ((rc = check_vec(grad_m, prob->n_samp, fn, "grad_m"))) return rc;
+  if ((grad_b0 || grad_kcoef) && (rc = check_vec(rho, prob->n_vox, fn, "rho"))) return rc;
+  if ((rc = check_vec(grad_rho, 0, fn, "grad_rho"))) return rc;
+  if (misaligned(grad_b0, 4) || misaligned(grad_kcoef, 4))
+    return fail(NFS_EINVAL, "%s: gradient array not 4-byte aligned", fn);
+  const Layout y = make_layout(ctx, prob, NFS_OP_EHE, precision, 0, 0);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  Ctx c{ctx, y, prob, reinterpret_cast<const float2*>(prob->sens), ws, (hipStream_t)stream, nullptr};
+  const float2* G = reinterpret_cast<const float2*>(grad_m);
+  const float2* r = reinterpret_cast<const float2*>(rho);
+  if ((rc = seq_pack_coefs(c, grad_kcoef != nullptr && y.P > 0, grad_rho != nullptr || grad_b0 != nullptr))) return rc;
+  if (grad_rho && y.L > 0) {
+    if ((rc = seq_EH(c, G, 1, y.K))) return rc;
+    NFS_TRY(launch_finish_EH(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1),
+                             reinterpret_cast<float2*>(grad_rho), c.s),
+            "finish_EH");
+  }
+  if (grad_b0 && y.L > 0) {
+    if ((rc = seq_EH(c, G, 1, y.K, prob->t))) return rc;
+    NFS_TRY(launch_grad_b0(at<float2>(ws, y.o_hpart), y.shH.nsplit, y.LC * 16, y.L, unscale_slot(c, 1), r, grad_b0,
+                           c.s),
+            "grad_b0");
+  }
+  if (grad_kcoef && y.K > 0 && y.P > 0) {
+    for (int b = 0; b < y.P; ++b) {
+      if ((rc = seq_E(c, r, prob->fields + (int64_t)b * y.L))) return rc;
+      NFS_TRY(launch_grad_kcoef(at<float>(ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, unscale_slot(c, 0), G, y.K,
+                                y.G, y.P, b, grad_kcoef, c.s),
+              "grad_kcoef");
+    }
+  }
   return NFS_OK;
 }

@@ -22,6 +22,7 @@ namespace nfs {
 
 typedef _Float16 h8 __attribute__((ext_vector_type(8)));
 typedef __bf16 b8 __attribute__((ext_vector_type(8)));
+typedef b8 b8_t;
 typedef float f4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 
@@ -32,51 +33,79 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase coefficients in MFMA fragment order.
-// out[(chunk * NT + tg) * 64 + lane] = coef[item = 16 chunk + lane % 16][term = 4 tg + lane / 16]
-// This is the per-lane operand of v_mfma_f32_16x16x4_f32 for both the A side
-// (row = lane % 16, k = lane / 16) and the B side (k = lane / 16,
-// column = lane % 16), so one packed array serves either role.
-// Sample side: term 0 = t, term b+1 = kcoef[.][b], both scaled to revolutions.
-// Voxel side:  term 0 = b0, term b+1 = fields[b][.].
-__global__ void pack_coef_samples_kernel(const float* __restrict__ kcoef, const float* __restrict__ t,
-                                         int64_t K, int P, int NT, float* __restrict__ out,
-                                         int64_t total) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const int lane = (int)(i & 63);
-  const int64_t q = i >> 6;
-  const int tg = (int)(q % NT);
-  const int64_t chunk = q / NT;
-  const int64_t k = chunk * kChunk + (lane & 15);
-  const int term = tg * 4 + (lane >> 4);
-  float v = 0.f;
-  if (k < K) {
-    if (term == 0)
-      v = (float)((double)t[k] * kInv2Pi);
-    else if (term <= P)
-      v = (float)((double)kcoef[k * P + (term - 1)] * kInv2Pi);
+// Phase coefficients, split into bf16 parts, in MFMA fragment order.
+//
+// phi(k, l) = sum_b a_b(k) h_b(l) with a the sample-side coefficients
+// (a_0 = t / 2 pi, a_{b+1} = kcoef[.][b] / 2 pi: phase in revolutions) and h
+// the voxel-side ones (h_0 = b0, h_{b+1} = fields[b][.]).  Every coefficient
+// x (taken in double, so the 1/2pi scaling adds no rounding) is split into
+// bf16 parts x = x1 + x2 + x3 + O(2^-27 x); the phase is the sum over terms of
+// the six products x_i y_j with i + j <= 4, which reproduces a_b h_b to about
+// 2^-26 relative, computed on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16)
+// with float32 accumulation.
+//
+// K-slot layout of one (16-item chunk): NQ instructions of 32 slots.  The
+// first NQ-1 instructions hold the five small products, in the order
+// (3,1) (1,3) (2,2) (2,1) (1,2), term-major within each (slot = pair * T + b,
+// zero past 5T); the last instruction holds the (1,1) products (slot = b,
+// zero past T).  The large products are thus added last, once, to a running
+// sum that is still small.  Slot k multiplies slot k of the other operand,
+// so the two operands carry complementary parts: role A (the streamed side,
+// MFMA operand A) takes part i, role B (the held side, operand B) part j.
+// Per lane (g = lane / 16, n = lane % 16): item 16 chunk + n, slots
+// 32 q + 8 g + e, e = 0..7, stored as one 16-byte vector
+// out[(chunk * NQ + q) * 64 + lane].
+__device__ __forceinline__ float bf16_part(double x, int part) {
+  double r = x;
+  float p = 0.f;
+  for (int i = 1; i <= part; ++i) {
+    p = (float)(__bf16)(float)r;
+    r -= (double)p;
   }
-  out[i] = v;
+  return p;
 }
 
-__global__ void pack_coef_voxels_kernel(const float* __restrict__ fields, const float* __restrict__ b0,
-                                        int64_t L, int P, int NT, float* __restrict__ out,
-                                        int64_t total) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__device__ __forceinline__ int phase_slot(int k, int T, int NQ, int role, int* b) {
+  // returns the part index for slot k (0 = zero slot) and the term in *b
+  const int small = 32 * (NQ - 1);
+  if (k < small) {
+    const int ps = k / T;
+    *b = k - ps * T;
+    if (ps >= 5) return 0;
+    const int pa[5] = {3, 1, 2, 2, 1}, pb[5] = {1, 3, 2, 1, 2};
+    return role == 0 ? pa[ps] : pb[ps];
+  }
+  *b = k - small;
+  return *b < T ? 1 : 0;
+}
+
+// side 0: samples (t, kcoef, K items); side 1: voxels (b0, fields, L items)
+__global__ void pack_phase_kernel(const float* __restrict__ c0, const float* __restrict__ cb, int64_t n_items,
+                                  int P, int side, int role, int NQ, b8_t* __restrict__ out, int64_t total) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int lane = (int)(i & 63);
-  const int64_t q = i >> 6;
-  const int tg = (int)(q % NT);
-  const int64_t chunk = q / NT;
-  const int64_t l = chunk * kChunk + (lane & 15);
-  const int term = tg * 4 + (lane >> 4);
-  float v = 0.f;
-  if (l < L) {
-    if (term == 0)
-      v = b0[l];
-    else if (term <= P)
-      v = fields[(int64_t)(term - 1) * L + l];
+  const int64_t qq = i >> 6;
+  const int q = (int)(qq % NQ);
+  const int64_t chunk = qq / NQ;
+  const int64_t item = chunk * kChunk + (lane & 15);
+  const int g = lane >> 4;
+  const int T = P + 1;
+  b8_t v;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) {
+    int b = 0;
+    const int part = phase_slot(32 * q + 8 * g + e, T, NQ, role, &b);
+    float x = 0.f;
+    if (part && item < n_items) {
+      double c;
+      if (side == 0)
+        c = (b == 0 ? (double)c0[item] : (double)cb[item * P + (b - 1)]) * kInv2Pi;
+      else
+        c = b == 0 ? (double)c0[item] : (double)cb[(int64_t)(b - 1) * n_items + item];
+      x = bf16_part(c, part);
+    }
+    v[e] = (__bf16)x;
   }
   out[i] = v;
 }
@@ -91,21 +120,22 @@ __global__ void scale_sens_kernel(const float2* __restrict__ sens, const float* 
 }
 
 // ---------------------------------------------------------------------------
-// Largest |re| or |im| of value(item, c) = src[item*is + c*cs] * mul[c][item]
+// Largest |re| or |im| of value(item, c) = src[item*is + c*cs] * mul[c][item] * wgt[item]
 // per workgroup (kBmaxBlocks workgroups, every entry of bmax written).
 __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ src,
-                                                     const float2* __restrict__ mul, int64_t n_items,
-                                                     int64_t is, int64_t cs, int G,
+                                                     const float2* __restrict__ mul, const float* __restrict__ wgt,
+                                                     int64_t n_items, int64_t is, int64_t cs, int G,
                                                      float* __restrict__ bmax, const int* stop) {
   if (stop && *stop) return;
   __shared__ float red[256];
   float mx = 0.f;
   for (int64_t item = (int64_t)blockIdx.x * 256 + threadIdx.x; item < n_items;
        item += (int64_t)gridDim.x * 256) {
+    const float w = wgt ? fabsf(wgt[item]) : 1.f;
     for (int c = 0; c < G; ++c) {
       float2 v = src[item * is + (int64_t)c * cs];
       if (mul) v = cmul(mul[(int64_t)c * n_items + item], v);
-      mx = fmaxf(mx, fmaxf(fabsf(v.x), fabsf(v.y)));
+      mx = fmaxf(mx, w * fmaxf(fabsf(v.x), fabsf(v.y)));
     }
   }
   red[threadIdx.x] = mx;
@@ -128,13 +158,16 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
 //         [((ch*NB + nb)*2 + part)*64 + lane]; the kernel runs one MFMA per
 //         part into the same accumulator, so the data operand carries ~16
 //         significant bits and only the (cos, sin) operand is 8-bit
-//   fp32: [((ch*NB + nb)*8 + u)*64 + lane]
+//   fp32: slots 0-3 and 4-7 as two 16-byte vectors:
+//         [((ch*NB + nb)*2 + u/4)*64 + lane][u % 4]
 // FP16: the values are scaled by a power of two so that the largest
 // magnitude lands just below 2^14; 1/scale is stored in *unscale.
+// An optional real per-item weight wgt multiplies every value (used by the
+// backward pass: t o G for the B0 gradient, h_b o rho for the field terms).
 template <int PREC, int OP>
 __global__ __launch_bounds__(256) void pack_data_kernel(
-    const float2* __restrict__ src, const float2* __restrict__ mul, int64_t n_items, int64_t is,
-    int64_t cs, int G, int NB, int64_t nchunks, void* __restrict__ out, const float* __restrict__ bmax,
+    const float2* __restrict__ src, const float2* __restrict__ mul, const float* __restrict__ wgt, int64_t n_items,
+    int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* __restrict__ out, const float* __restrict__ bmax,
     float* __restrict__ unscale, const int* stop) {
   if (stop && *stop) return;
   float scale = 1.f;
@@ -173,8 +206,9 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
     if (item < n_items && c < G) {
       v = src[item * is + (int64_t)c * cs];
       if (mul) v = cmul(mul[(int64_t)c * n_items + item], v);
-      v.x *= scale;
-      v.y *= scale;
+      const float w = wgt ? wgt[item] * scale : scale;
+      v.x *= w;
+      v.y *= w;
     }
     float cosrow, sinrow;
     if (OP == OP_E) {
@@ -188,9 +222,9 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
     vals[2 * j + 1] = sinrow;
   }
   if (PREC == PREC_FP32) {
-    float* o = (float*)out;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) o[((ch * NB + nb) * 8 + u) * 64 + lane] = vals[u];
+    float4* o = (float4*)out;
+    o[((ch * NB + nb) * 2 + 0) * 64 + lane] = make_float4(vals[0], vals[1], vals[2], vals[3]);
+    o[((ch * NB + nb) * 2 + 1) * 64 + lane] = make_float4(vals[4], vals[5], vals[6], vals[7]);
   } else if (PREC == PREC_FP16) {
     h8 h;
 #pragma unroll
@@ -216,30 +250,132 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
 // places on one XCD (ids congruent mod 8) take a contiguous range of
 // (split, held tile) pairs and so share their streamed chunks in that XCD's
 // L2.  Wave w of workgroup x owns held tiles (x * 4 + w) * MT + [0, MT) and
-// walks streamed chunks [split * cps, min(SC, (split + 1) * cps)).
+// walks streamed chunks [split * cps, min(SC, (split + 1) * cps)); the 4
+// waves share every streamed chunk through a double-buffered LDS stage
+// filled by direct global-to-LDS loads one chunk ahead of its use.
 //
 // Per (held tile, streamed chunk):
-//   1. phase tile on the FP32 matrix cores: NT x v_mfma_f32_16x16x4_f32 with
-//      A = streamed coefficients, B = held coefficients.  Lane (g, j) ends up
-//      with phi for streamed items 4g + r (r = 0..3) and held item j, in
-//      revolutions;
+//   1. phase tile on the bf16 matrix cores: NQ x v_mfma_f32_16x16x32_bf16
+//      with A = streamed phase parts, B = held phase parts (see the packing
+//      above).  Lane (g, j) ends up with phi for streamed items 4g + r
+//      (r = 0..3) and held item j, in revolutions;
 //   2. v_fract + v_sin/v_cos (hardware, argument in revolutions);
 //   3. these (cos, sin) pairs are exactly the A fragment of the complex
 //      contraction (row = held item j, k-slots = streamed items 4g..4g+3 x
 //      {cos, sin}), so they go to the matrix cores without any data movement:
-//      one v_mfma_f32_16x16x32_{f16,bf16} per column block, or 8
-//      v_mfma_f32_16x16x4_f32 per column block for FP32.
+//      one v_mfma_f32_16x16x32_{f16,bf16} per column block (two for bf16: hi
+//      and lo data parts), or 8 v_mfma_f32_16x16x4_f32 per column block for
+//      FP32.
 // Accumulators: lane (g, n) holds rows (held items) 4g + r, column 16 nb + n.
 //
 // Epilogue.  E: the partial y rows go to out_part[split][HC*16][NB*16].
 // E^H: each lane forms conj(S) times its column's re or im part, the 16 lanes
 // of a row group are summed with xor-shuffles (fixed order), and the
 // coil-combined partial x goes to out_part (as float2) [split][HC*16].
-template <int OP, int PREC, int NT, int NB, int MT>
+// Operands of one streamed chunk as seen by one lane, read from LDS.
+// The staged chunk is a sequence of 1 KB blocks, each [64 lanes][16 B]:
+// NQ phase blocks, then the data blocks (NB blocks for fp16, 2 NB for bf16
+// (hi, lo) and for fp32 (slots 0-3, 4-7)); lane l reads its 16 bytes of
+// every block (conflict-free).
+template <int PREC>
+constexpr int data_blocks_per_nb() {
+  return PREC == PREC_FP16 ? 1 : 2;
+}
+
+template <int PREC, int NB, int NQ>
+struct Stream {
+  static constexpr int NDB = NB * data_blocks_per_nb<PREC>();
+  static constexpr int NBLK = NQ + NDB;
+  u4 ph[NQ];
+  u4 d[NDB];
+  __device__ __forceinline__ void read(const u4* lds, int lane) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) ph[q] = lds[q * 64 + lane];
+#pragma unroll
+    for (int i = 0; i < NDB; ++i) d[i] = lds[(NQ + i) * 64 + lane];
+  }
+};
+
+typedef __attribute__((address_space(3))) void lds_void;
+
+// Wave `wave` copies blocks wave, wave + 4, ... of chunk ch into `dst`
+// (global -> LDS directly, 16 bytes per lane, no registers involved).
+template <int PREC, int NB, int NQ>
+__device__ __forceinline__ void stage_chunk(const u4* __restrict__ strmcoef, const u4* __restrict__ sdata, int64_t ch,
+                                            u4* dst, int wave, int lane) {
+  constexpr int NDB = Stream<PREC, NB, NQ>::NDB;
+  constexpr int NBLK = NQ + NDB;
+#pragma unroll
+  for (int blk = wave; blk < NBLK; blk += kWaves) {
+    const u4* src = blk < NQ ? strmcoef + (ch * NQ + blk) * 64 + lane : sdata + (ch * NDB + (blk - NQ)) * 64 + lane;
+    __builtin_amdgcn_global_load_lds((const void*)src, (lds_void*)(dst + blk * 64), 16, 0, 0);
+  }
+}
+
+// One (streamed chunk) x (MT held tiles) step: phase tile, sin/cos, complex
+// contraction into acc (see the kernel comment).
+template <int PREC, int NB, int NQ, int MT>
+__device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, const u4 (&hc)[MT][NQ],
+                                           f4 (&acc)[MT][NB]) {
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) {
+    f4 ph = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      ph = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, cur.ph[q]), __builtin_bit_cast(b8, hc[mt][q]),
+                                                   ph, 0, 0, 0);
+    float cs[4], sn[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const float x = __builtin_amdgcn_fractf(ph[r]);
+      sn[r] = __builtin_amdgcn_sinf(x);
+      cs[r] = __builtin_amdgcn_cosf(x);
+    }
+    if (PREC == PREC_FP16) {
+      h8 a;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[2 * r] = (_Float16)cs[r];
+        a[2 * r + 1] = (_Float16)sn[r];
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, cur.d[nb]), acc[mt][nb], 0, 0, 0);
+    } else if (PREC == PREC_BF16) {
+      b8 a;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        a[2 * r] = (__bf16)cs[r];
+        a[2 * r + 1] = (__bf16)sn[r];
+      }
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, cur.d[2 * nb]), acc[mt][nb], 0,
+                                                              0, 0);
+        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, cur.d[2 * nb + 1]), acc[mt][nb],
+                                                              0, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb) {
+        const f4 lo = __builtin_bit_cast(f4, cur.d[2 * nb]), hi = __builtin_bit_cast(f4, cur.d[2 * nb + 1]);
+        f4 t = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const float bv = u < 4 ? lo[u] : hi[u - 4];
+          t = __builtin_amdgcn_mfma_f32_16x16x4f32((u & 1) ? sn[u >> 1] : cs[u >> 1], bv, t, 0, 0, 0);
+        }
+        acc[mt][nb] += t;
+      }
+    }
+  }
+}
+
+template <int OP, int PREC, int NQ, int NB, int MT>
 __global__ __launch_bounds__(256) void encode_kernel(
-    const float* __restrict__ heldcoef, const float* __restrict__ strmcoef,
-    const void* __restrict__ sdata, int64_t HC, int64_t SC, int64_t cps, float* __restrict__ out_part,
-    const float2* __restrict__ sens, int64_t L, int G, const int* stop) {
+    const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef, const void* __restrict__ sdata, int64_t HC,
+    int64_t SC, int64_t cps, float* __restrict__ out_part, const float2* __restrict__ sens, int64_t L, int G,
+    const int* stop) {
   if (stop && *stop) return;
   const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
   int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
@@ -252,108 +388,41 @@ __global__ __launch_bounds__(256) void encode_kernel(
   const int wave = threadIdx.x >> 6;
   const int64_t tile0 = (bx * kWaves + wave) * MT;
 
-  float hc[MT][NT];
+  u4 hc[MT][NQ];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
     const int64_t tile = tile0 + mt;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) hc[mt][t] = tile < HC ? heldcoef[(tile * NT + t) * 64 + lane] : 0.f;
+    for (int q = 0; q < NQ; ++q) hc[mt][q] = tile < HC ? heldcoef[(tile * NQ + q) * 64 + lane] : u4{0, 0, 0, 0};
   }
-  // Two-level accumulation: the matrix cores add into `inner`, which is
-  // flushed into `acc` on the VALU every IC chunks, so the long running sum
-  // is rounded once per IC chunks instead of once per MFMA.
-  constexpr int IC = PREC == PREC_FP32 ? 1 : 8;
-  f4 acc[MT][NB], inner[MT][NB];
+  // Accumulation: the matrix cores add straight into acc for the half
+  // precisions (their operand rounding dominates); for FP32 the 8 MFMAs of a
+  // chunk start from zero and their sum is added on the VALU, so the long
+  // running sum is rounded once per chunk instead of once per MFMA.
+  f4 acc[MT][NB];
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt)
 #pragma unroll
-    for (int nb = 0; nb < NB; ++nb) {
-      acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
-      inner[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
-    }
-  int since_flush = 0;
+    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
+  // Streamed chunks are staged through LDS, double-buffered and shared by
+  // the 4 waves: the loads for chunk ch + 1 are issued right after the
+  // barrier that publishes chunk ch, and overlap the compute of chunk ch.
+  __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
   const int64_t c0 = split * cps;
   const int64_t c1 = (c0 + cps < SC) ? c0 + cps : SC;
+  const u4* sd = (const u4*)sdata;
+  if (c0 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, c0, stage[0], wave, lane);
+  int buf = 0;
   for (int64_t ch = c0; ch < c1; ++ch) {
-    float sc[NT];
-#pragma unroll
-    for (int t = 0; t < NT; ++t) sc[t] = strmcoef[(ch * NT + t) * 64 + lane];
-    constexpr int NFRAG = PREC == PREC_BF16 ? 2 : 1;
-    u4 bh[PREC == PREC_FP32 ? 1 : NB][NFRAG];
-    float bf[PREC == PREC_FP32 ? NB : 1][8];
-    if (PREC == PREC_FP32) {
-      const float* d = (const float*)sdata;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int u = 0; u < 8; ++u) bf[nb][u] = d[((ch * NB + nb) * 8 + u) * 64 + lane];
-    } else {
-      const u4* d = (const u4*)sdata;
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-#pragma unroll
-        for (int f = 0; f < NFRAG; ++f) bh[nb][f] = d[((ch * NB + nb) * NFRAG + f) * 64 + lane];
-    }
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      f4 ph = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-      for (int t = 0; t < NT; ++t) ph = __builtin_amdgcn_mfma_f32_16x16x4f32(sc[t], hc[mt][t], ph, 0, 0, 0);
-      float cs[4], sn[4];
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float x = __builtin_amdgcn_fractf(ph[r]);
-        sn[r] = __builtin_amdgcn_sinf(x);
-        cs[r] = __builtin_amdgcn_cosf(x);
-      }
-      if (PREC == PREC_FP16) {
-        h8 a;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          a[2 * r] = (_Float16)cs[r];
-          a[2 * r + 1] = (_Float16)sn[r];
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb)
-          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, bh[nb][0]), inner[mt][nb], 0, 0, 0);
-      } else if (PREC == PREC_BF16) {
-        b8 a;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-          a[2 * r] = (__bf16)cs[r];
-          a[2 * r + 1] = (__bf16)sn[r];
-        }
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][0]), inner[mt][nb], 0, 0, 0);
-          inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, bh[nb][NFRAG - 1]), inner[mt][nb], 0, 0, 0);
-        }
-      } else {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const float a = (u & 1) ? sn[u >> 1] : cs[u >> 1];
-#pragma unroll
-          for (int nb = 0; nb < NB; ++nb)
-            inner[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, bf[nb][u], inner[mt][nb], 0, 0, 0);
-        }
-      }
-    }
-    if (++since_flush == IC) {
-      since_flush = 0;
-#pragma unroll
-      for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          acc[mt][nb] += inner[mt][nb];
-          inner[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
-        }
-    }
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk ch have landed
+    __syncthreads();                 // ... and every wave's; buffer buf ^ 1 is free
+    if (ch + 1 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, ch + 1, stage[buf ^ 1], wave, lane);
+    Stream<PREC, NB, NQ> cur;
+    cur.read(stage[buf], lane);
+    chunk_step<PREC, NB, NQ, MT>(cur, hc, acc);
+    buf ^= 1;
   }
-#pragma unroll
-  for (int mt = 0; mt < MT; ++mt)
-#pragma unroll
-    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] += inner[mt][nb];
 
   const int g = lane >> 4, n = lane & 15;
   if (OP == OP_E) {
@@ -450,6 +519,44 @@ __global__ void finish_EH_kernel(const float2* __restrict__ hpart, int nsplit, i
   x[l] = make_float2(re * u, im * u);
 }
 
+// grad_b0[l] = Im(conj(rho[l]) x[l]), x = E^H (t o G) as split partials
+__global__ void grad_b0_kernel(const float2* __restrict__ hpart, int nsplit, int64_t HC16, int64_t L,
+                               const float* __restrict__ unscale, const float2* __restrict__ rho,
+                               float* __restrict__ out) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  float re = 0.f, im = 0.f;
+  for (int s = 0; s < nsplit; ++s) {
+    const float2 v = hpart[(size_t)s * HC16 + l];
+    re += v.x;
+    im += v.y;
+  }
+  const float u = unscale ? *unscale : 1.f;
+  const float2 r = rho[l];
+  out[l] = (r.x * im - r.y * re) * u;
+}
+
+// grad_kcoef[k][b] = Im(sum_c G[c][k] conj(Z[k][c])), Z = E (h_b o rho) as E partials
+__global__ void grad_kcoef_kernel(const float* __restrict__ epart, int nsplit, int64_t HC16, int NB,
+                                  const float* __restrict__ unscale, const float2* __restrict__ grad_m, int64_t K,
+                                  int G, int P, int b, float* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  const int ncol = NB * 16;
+  float acc = 0.f;
+  for (int c = 0; c < G; ++c) {
+    float zr = 0.f, zi = 0.f;
+    for (int s = 0; s < nsplit; ++s) {
+      const float* row = epart + ((size_t)s * HC16 + k) * ncol;
+      zr += row[2 * c];
+      zi += row[2 * c + 1];
+    }
+    const float2 g = grad_m[(int64_t)c * K + k];
+    acc += g.y * zr - g.x * zi;
+  }
+  out[k * P + b] = acc * (unscale ? *unscale : 1.f);
+}
+
 __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0.f;
@@ -459,19 +566,12 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
 // launchers
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(n, bs)); }
 
-hipError_t launch_pack_coef_samples(const float* kcoef, const float* t, int64_t K, int P, int NT, float* out,
-                                    hipStream_t s) {
-  const int64_t total = cdiv(K, kChunk) * NT * 64;
+hipError_t launch_pack_phase(const float* c0, const float* cb, int64_t n_items, int P, int side, int role, int NQ,
+                             void* out, hipStream_t s) {
+  const int64_t total = cdiv(n_items, kChunk) * NQ * 64;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_coef_samples_kernel, grid1(total), dim3(256), 0, s, kcoef, t, K, P, NT, out, total);
-  return hipGetLastError();
-}
-
-hipError_t launch_pack_coef_voxels(const float* fields, const float* b0, int64_t L, int P, int NT, float* out,
-                                   hipStream_t s) {
-  const int64_t total = cdiv(L, kChunk) * NT * 64;
-  if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_coef_voxels_kernel, grid1(total), dim3(256), 0, s, fields, b0, L, P, NT, out, total);
+  hipLaunchKernelGGL(pack_phase_kernel, grid1(total), dim3(256), 0, s, c0, cb, n_items, P, side, role, NQ,
+                     (b8_t*)out, total);
   return hipGetLastError();
 }
 
@@ -482,20 +582,21 @@ hipError_t launch_scale_sens(const float2* sens, const float* icorr, int G, int6
   return hipGetLastError();
 }
 
-hipError_t launch_absmax(const float2* src, const float2* mul, int64_t n_items, int64_t is, int64_t cs, int G,
-                         float* bmax, const int* stop, hipStream_t s) {
-  hipLaunchKernelGGL(absmax_kernel, dim3(kBmaxBlocks), dim3(256), 0, s, src, mul, n_items, is, cs, G, bmax, stop);
+hipError_t launch_absmax(const float2* src, const float2* mul, const float* wgt, int64_t n_items, int64_t is,
+                         int64_t cs, int G, float* bmax, const int* stop, hipStream_t s) {
+  hipLaunchKernelGGL(absmax_kernel, dim3(kBmaxBlocks), dim3(256), 0, s, src, mul, wgt, n_items, is, cs, G, bmax,
+                     stop);
   return hipGetLastError();
 }
 
-hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, int64_t n_items, int64_t is,
-                            int64_t cs, int G, int NB, int64_t nchunks, void* out, const float* bmax,
+hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, const float* wgt, int64_t n_items,
+                            int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* out, const float* bmax,
                             float* unscale, const int* stop, hipStream_t s) {
   const int64_t total = nchunks * NB * 64;
   if (total == 0) return hipSuccess;
   const dim3 gr = grid1(total), bl(256);
 #define NFS_PACK(P_, O_)                                                                                   \
-  hipLaunchKernelGGL((pack_data_kernel<P_, O_>), gr, bl, 0, s, src, mul, n_items, is, cs, G, NB, nchunks, \
+  hipLaunchKernelGGL((pack_data_kernel<P_, O_>), gr, bl, 0, s, src, mul, wgt, n_items, is, cs, G, NB, nchunks, \
                      out, bmax, unscale, stop)
   if (op == OP_E) {
     if (prec == PREC_FP32) NFS_PACK(PREC_FP32, OP_E);
@@ -510,53 +611,52 @@ hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* m
   return hipGetLastError();
 }
 
-template <int OP, int PREC, int NT, int NB, int MT>
-static hipError_t launch_encode_t(const EncodeShape& sh, const float* heldcoef, const float* strmcoef,
+template <int OP, int PREC, int NQ, int NB, int MT>
+static hipError_t launch_encode_t(const EncodeShape& sh, const void* heldcoef, const void* strmcoef,
                                   const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
                                   const int* stop, hipStream_t s) {
   const dim3 gr((unsigned)cdiv(sh.HC, (int64_t)kWaves * MT), (unsigned)sh.nsplit);
-  hipLaunchKernelGGL((encode_kernel<OP, PREC, NT, NB, MT>), gr, dim3(64 * kWaves), 0, s, heldcoef, strmcoef,
-                     sdata, sh.HC, sh.SC, sh.cps, out_part, sens, L, G, stop);
+  hipLaunchKernelGGL((encode_kernel<OP, PREC, NQ, NB, MT>), gr, dim3(64 * kWaves), 0, s, (const u4*)heldcoef,
+                     (const u4*)strmcoef, sdata, sh.HC, sh.SC, sh.cps, out_part, sens, L, G, stop);
   return hipGetLastError();
 }
 
-template <int OP, int PREC, int NT>
-static hipError_t launch_encode_nb(const EncodeShape& sh, const float* hc, const float* scf, const void* sd,
-                                   float* op, const float2* sens, int64_t L, int G, const int* stop,
-                                   hipStream_t s) {
+template <int OP, int PREC, int NQ>
+static hipError_t launch_encode_nb(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
+                                   const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
   switch (sh.NB) {
-    case 1: return launch_encode_t<OP, PREC, NT, 1, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 2: return launch_encode_t<OP, PREC, NT, 2, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 4: return launch_encode_t<OP, PREC, NT, 4, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 8: return launch_encode_t<OP, PREC, NT, 8, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 1: return launch_encode_t<OP, PREC, NQ, 1, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 2: return launch_encode_t<OP, PREC, NQ, 2, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 4: return launch_encode_t<OP, PREC, NQ, 4, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 8: return launch_encode_t<OP, PREC, NQ, 8, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
   }
   return hipErrorInvalidValue;
 }
 
 template <int OP, int PREC>
-static hipError_t launch_encode_nt(const EncodeShape& sh, const float* hc, const float* scf, const void* sd,
-                                   float* op, const float2* sens, int64_t L, int G, const int* stop,
-                                   hipStream_t s) {
-  switch (sh.NT) {
+static hipError_t launch_encode_nq(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
+                                   const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+  switch (sh.NQ) {
     case 2: return launch_encode_nb<OP, PREC, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 5: return launch_encode_nb<OP, PREC, 5>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 8: return launch_encode_nb<OP, PREC, 8>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 3: return launch_encode_nb<OP, PREC, 3>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 4: return launch_encode_nb<OP, PREC, 4>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 6: return launch_encode_nb<OP, PREC, 6>(sh, hc, scf, sd, op, sens, L, G, stop, s);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_encode(const EncodeShape& sh, const float* heldcoef, const float* strmcoef, const void* sdata,
+hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void* strmcoef, const void* sdata,
                          float* out_part, const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
   if (sh.HC == 0) return hipSuccess;
   if (sh.MT != 2) return hipErrorInvalidValue;
   if (sh.op == OP_E) {
-    if (sh.prec == PREC_FP32) return launch_encode_nt<OP_E, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-    if (sh.prec == PREC_BF16) return launch_encode_nt<OP_E, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-    return launch_encode_nt<OP_E, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+    if (sh.prec == PREC_FP32) return launch_encode_nq<OP_E, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+    if (sh.prec == PREC_BF16) return launch_encode_nq<OP_E, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+    return launch_encode_nq<OP_E, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
   }
-  if (sh.prec == PREC_FP32) return launch_encode_nt<OP_EH, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-  if (sh.prec == PREC_BF16) return launch_encode_nt<OP_EH, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-  return launch_encode_nt<OP_EH, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+  if (sh.prec == PREC_FP32) return launch_encode_nq<OP_EH, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+  if (sh.prec == PREC_BF16) return launch_encode_nq<OP_EH, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+  return launch_encode_nq<OP_EH, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
 }
 
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
@@ -578,6 +678,21 @@ hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64
                             float2* x, hipStream_t s) {
   if (L == 0) return hipSuccess;
   hipLaunchKernelGGL(finish_EH_kernel, grid1(L), dim3(256), 0, s, hpart, nsplit, HC16, L, unscale, x);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_b0(const float2* hpart, int nsplit, int64_t HC16, int64_t L, const float* unscale,
+                          const float2* rho, float* out, hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(grad_b0_kernel, grid1(L), dim3(256), 0, s, hpart, nsplit, HC16, L, unscale, rho, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_grad_kcoef(const float* epart, int nsplit, int64_t HC16, int NB, const float* unscale,
+                             const float2* grad_m, int64_t K, int G, int P, int b, float* out, hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(grad_kcoef_kernel, grid1(K), dim3(256), 0, s, epart, nsplit, HC16, NB, unscale, grad_m, K, G, P,
+                     b, out);
   return hipGetLastError();
 }
 

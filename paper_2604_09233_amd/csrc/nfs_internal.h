@@ -6,11 +6,11 @@
 //  * items are grouped in chunks (tiles) of 16; a wave owns MT held tiles and
 //    walks a contiguous range of streamed chunks;
 //  * for each (held tile, streamed chunk) pair the wave builds the 16 x 16
-//    phase tile phi = K_blk R_blk on the FP32 matrix cores (v_mfma 16x16x4,
-//    NT term groups of 4), takes sin/cos of it in revolutions on the VALU and
-//    feeds (cos, sin) straight into the complex contraction on the matrix
-//    cores (16x16x32 f16/bf16, or 16x16x4 f32), against the packed data
-//    operand of the streamed chunk;
+//    phase tile phi = K_blk R_blk on the bf16 matrix cores (coefficients
+//    split into three bf16 parts, NQ v_mfma 16x16x32 instructions), takes
+//    sin/cos of it in revolutions on the VALU and feeds (cos, sin) straight
+//    into the complex contraction on the matrix cores (16x16x32 f16/bf16, or
+//    16x16x4 f32), against the packed data operand of the streamed chunk;
 //  * the streamed range can be split over several workgroups ("splits");
 //    partial results are summed afterwards in a fixed order.
 #pragma once
@@ -29,13 +29,16 @@ constexpr int kBmaxBlocks = 256;  // workgroups of the max-magnitude kernels
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// term groups of 4 for P + 1 terms (t*b0 plus P field terms)
-inline int term_groups(int n_basis) {
-  int t = n_basis + 1;
-  if (t <= 8) return 2;
-  if (t <= 20) return 5;
-  return 8;
+// phase MFMA instructions for P + 1 terms (t*b0 plus P field terms): the
+// five small split products need ceil(5 (P+1) / 32) instructions, the (1,1)
+// products one more; rounded up to 2, 3, 4 or 6
+inline int phase_instrs(int n_basis) {
+  const int T = n_basis + 1;
+  const int nq = (int)cdiv(5 * T, 32) + 1;
+  return nq <= 2 ? 2 : (nq <= 4 ? nq : 6);
 }
+// bytes of one packed phase chunk (16 items): NQ instructions x 64 lanes x 16 B
+inline size_t phase_chunk_bytes(int nq) { return (size_t)nq * 64 * 16; }
 // 16-column blocks for 2G real columns (re/im per coil), rounded to 1, 2, 4, 8
 inline int col_blocks(int n_coil) {
   int nb = (int)cdiv(2 * n_coil, 16);
@@ -54,26 +57,26 @@ inline size_t data_chunk_bytes(int prec) {
 struct EncodeShape {
   int op;            // OP_E or OP_EH
   int prec;          // PREC_*
-  int NT, NB, MT;    // term groups, column blocks, held tiles per wave
+  int NQ, NB, MT;    // phase instructions, column blocks, held tiles per wave
   int64_t HC, SC;    // held / streamed chunk counts
   int nsplit;        // splits of the streamed range
   int64_t cps;       // streamed chunks per split
 };
 
 // ---- launchers (encode_kernels.hip) ---------------------------------------
-hipError_t launch_pack_coef_samples(const float* kcoef, const float* t, int64_t K, int P, int NT,
-                                    float* out, hipStream_t s);
-hipError_t launch_pack_coef_voxels(const float* fields, const float* b0, int64_t L, int P, int NT,
-                                   float* out, hipStream_t s);
+// side 0: samples (c0 = t, cb = kcoef [K][P]); side 1: voxels (c0 = b0, cb = fields [P][L]);
+// role 0: streamed side (MFMA operand A), role 1: held side (operand B)
+hipError_t launch_pack_phase(const float* c0, const float* cb, int64_t n_items, int P, int side, int role, int NQ,
+                             void* out, hipStream_t s);
 hipError_t launch_scale_sens(const float2* sens, const float* icorr, int G, int64_t L, float2* out,
                              hipStream_t s);
-// value(item, c) = src[item*is + c*cs] * (mul ? mul[c*n_items + item] : 1)
-hipError_t launch_absmax(const float2* src, const float2* mul, int64_t n_items, int64_t is, int64_t cs,
-                         int G, float* bmax, const int* stop, hipStream_t s);
-hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, int64_t n_items,
-                            int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* out,
+// value(item, c) = src[item*is + c*cs] * (mul ? mul[c*n_items + item] : 1) * (wgt ? wgt[item] : 1)
+hipError_t launch_absmax(const float2* src, const float2* mul, const float* wgt, int64_t n_items, int64_t is,
+                         int64_t cs, int G, float* bmax, const int* stop, hipStream_t s);
+hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, const float* wgt,
+                            int64_t n_items, int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* out,
                             const float* bmax, float* unscale, const int* stop, hipStream_t s);
-hipError_t launch_encode(const EncodeShape& sh, const float* heldcoef, const float* strmcoef,
+hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void* strmcoef,
                          const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
                          const int* stop, hipStream_t s);
 // sum E partials -> m[G][K] (coil-major) times *unscale
@@ -86,6 +89,11 @@ hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16,
 hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
                             const float* unscale, float2* x, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n_floats, hipStream_t s);
+// backward: grad_b0 from E^H(t o G) partials; grad_kcoef[:, b] from E(h_b o rho) partials
+hipError_t launch_grad_b0(const float2* hpart, int nsplit, int64_t HC16, int64_t L, const float* unscale,
+                          const float2* rho, float* out, hipStream_t s);
+hipError_t launch_grad_kcoef(const float* epart, int nsplit, int64_t HC16, int NB, const float* unscale,
+                             const float2* grad_m, int64_t K, int G, int P, int b, float* out, hipStream_t s);
 
 // ---- CG (cg_kernels.hip) -----------------------------------------------------
 struct CgState {

@@ -63,13 +63,15 @@ def lib():
             for name in ("nfs_apply_E", "nfs_apply_EH", "nfs_apply_EHE"):
                 getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
             L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
+            L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
             L.nfs_profile_enable.argtypes = [vp, i32]
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
             L.nfs_last_error.restype = ctypes.c_char_p
             L.nfs_last_error.argtypes = []
             L.nfs_version.argtypes = []
             for name in ("nfs_create", "nfs_destroy", "nfs_workspace_bytes", "nfs_apply_E", "nfs_apply_EH",
-                         "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read"):
+                         "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read",
+                         "nfs_encode_backward"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -205,6 +207,24 @@ def cg_solve(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int
                               float(tol), int(replace_every), int(reorth), PRECISIONS[precision], _ptr(hist),
                               _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
     return rho, hist, info
+
+
+def encode_backward(prob: Problem, rho, grad_m, precision: str = "fp32", need_rho: bool = True,
+                    need_b0: bool = True, need_kcoef: bool = True):
+    """Gradients through m = E rho (see include/nfs.h): returns (grad_rho [L]
+    complex64 or None, grad_b0 [L] float32 or None, grad_kcoef [K][P] float32
+    or None)."""
+    rho = _c64(rho, prob.device)
+    grad_m = _c64(grad_m, prob.device)
+    dev = prob.device
+    g_rho = torch.empty(prob.L, dtype=torch.complex64, device=dev) if need_rho else None
+    g_b0 = torch.empty(prob.L, dtype=torch.float32, device=dev) if need_b0 else None
+    g_k = torch.empty((prob.K, prob.P), dtype=torch.float32, device=dev) if need_kcoef else None
+    ws = prob.workspace("EHE", precision)
+    p = lambda x: _ptr(x) if x is not None else ctypes.c_void_p(0)  # noqa: E731
+    _check(lib().nfs_encode_backward(context(prob.index), ctypes.byref(prob.st), _ptr(rho), _ptr(grad_m), p(g_rho),
+                                     p(g_b0), p(g_k), PRECISIONS[precision], _ptr(ws), ws.numel(), prob._stream()))
+    return g_rho, g_b0, g_k
 
 
 def profile_enable(device: int, on: bool = True):
