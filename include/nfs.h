@@ -150,6 +150,32 @@ int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* r
                  int n_iter, double tol, int replace_every, int reorth, int precision,
                  double* hist, int* info, void* ws, size_t ws_bytes, void* stream);
 
+/* Many independent reconstructions (slices with uneven L, K and G) solved
+ * together: each slice runs exactly the nfs_cg_solve sequence (same kernels,
+ * so each slice's result is bit-identical to its single solve), forked from
+ * `stream` onto up to 8 library-owned streams (default priority; slices
+ * assigned longest-first by L*K*G) and joined back, so the slices overlap
+ * on the GPU.  n_iter, tol, replace_every, reorth and precision apply to all
+ * slices.  m, rho: host arrays of n_slices device pointers (as for
+ * nfs_cg_solve); hist, info: host arrays of device pointers, or NULL (and
+ * individual entries may be NULL).  The workspace (256-byte aligned, at
+ * least nfs_workspace_bytes_batched bytes) is split into one CG workspace
+ * per slice.                                                               */
+int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
+                                int n_iter, int reorth, size_t* bytes);
+int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, const float* const* m,
+                         float* const* rho, int n_iter, double tol, int replace_every, int reorth,
+                         int precision, double* const* hist, int* const* info, void* ws, size_t ws_bytes,
+                         void* stream);
+
+/* Graph replay for repeated solves.  When on, nfs_cg_solve and
+ * nfs_cg_solve_batched capture their whole launch sequence into a hipGraph
+ * the first time they see a given set of pointers and parameters and
+ * replay it (one hipGraphLaunch) on later identical calls.  Ignored while
+ * the caller's stream is itself being captured and while kernel profiling
+ * is on.  Graphs live until nfs_destroy.  Default off.                    */
+int nfs_set_graphs(nfs_ctx* ctx, int on);
+
 /* Backward of m = E rho for a real loss L, for field-map and trajectory
  * refinement.  grad_m is dL/dm in PyTorch's convention for complex tensors
  * (for L = ||E rho - sigma||^2 it is 2 (E rho - sigma)).  Differentiating the

@@ -5,7 +5,9 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "nfs.h"
@@ -17,6 +19,11 @@ struct nfs_ctx {
   int device;
   int n_cu;
   bool profiling = false;
+  bool graphs = false;
+  std::unordered_map<std::string, hipGraphExec_t> graph_cache;
+  std::vector<hipStream_t> bstreams;  // batched solves: forked streams (default priority)
+  std::vector<hipEvent_t> bevents;    // ... and their join events
+  hipEvent_t fork_event = nullptr;
   std::vector<hipEvent_t> pool;                 // idle events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // recorded (start, stop) per kind
 };
@@ -68,6 +75,10 @@ extern "C" int nfs_destroy(nfs_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
+  for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  for (auto st : ctx->bstreams) (void)hipStreamDestroy(st);
+  for (auto e : ctx->bevents) (void)hipEventDestroy(e);
+  if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
   delete ctx;
   return NFS_OK;
 }
@@ -423,10 +434,9 @@ extern "C" int nfs_apply_EHE(nfs_ctx* ctx, const nfs_problem* prob, const float*
   return NFS_OK;
 }
 
-extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
-                            double tol, int replace_every, int reorth, int precision, double* hist, int* info,
-                            void* ws, size_t ws_bytes, void* stream) {
-  const char* fn = "nfs_cg_solve";
+static int check_cg_args(const nfs_ctx* ctx, const nfs_problem* prob, const float* m, const float* rho, int n_iter,
+                         double tol, int replace_every, int reorth, int precision, const double* hist, const int* info,
+                         const char* fn) {
   if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
   int rc = check_problem(prob, fn);
   if (rc) return rc;
@@ -440,10 +450,13 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
   if (reorth && n_iter > kMaxReorth) return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
   if (misaligned(hist, 8)) return fail(NFS_EINVAL, "%s: hist not 8-byte aligned", fn);
   if (misaligned(info, 4)) return fail(NFS_EINVAL, "%s: info not 4-byte aligned", fn);
-  const Layout y = make_layout(ctx, prob, NFS_OP_CG, precision, n_iter, reorth);
-  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
-  hipStream_t s = (hipStream_t)stream;
+  return NFS_OK;
+}
 
+// The launch sequence of one CG solve (arguments already checked).
+static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const float* m, float* rho, int n_iter,
+                  double tol, int replace_every, int reorth, double* hist, int* info, void* ws, hipStream_t s) {
+  int rc;
   CgState st;
   st.r = at<float2>(ws, y.o_r);
   st.p = at<float2>(ws, y.o_p);
@@ -495,6 +508,192 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
   }
   NFS_TRY(launch_cg_finish(st, x, prob->icorr, y.L, s), "cg_finish");
   return NFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Optional hipGraph capture of whole solves (nfs_set_graphs).  A graph is
+// keyed by every pointer and parameter the launch sequence bakes in; the
+// first call captures and instantiates it, later identical calls replay it
+// with one hipGraphLaunch.  Not used while the caller's stream is itself
+// being captured (the launches then simply go into the caller's graph) or
+// while kernel profiling is on.
+static std::string graph_key(const char* kind, const nfs_problem* probs, int n, const void* const* ptrs, int np,
+                             int n_iter, double tol, int replace_every, int reorth, int precision, const void* ws,
+                             size_t ws_bytes, const void* stream) {
+  std::string k(kind);
+  auto add = [&](const void* p, size_t len) { k.append(static_cast<const char*>(p), len); };
+  for (int i = 0; i < n; ++i) add(&probs[i], sizeof(nfs_problem));
+  for (int i = 0; i < np; ++i) add(&ptrs[i], sizeof(void*));
+  add(&n_iter, sizeof n_iter);
+  add(&tol, sizeof tol);
+  add(&replace_every, sizeof replace_every);
+  add(&reorth, sizeof reorth);
+  add(&precision, sizeof precision);
+  add(&ws, sizeof ws);
+  add(&ws_bytes, sizeof ws_bytes);
+  add(&stream, sizeof stream);
+  return k;
+}
+
+template <class F>
+static int run_maybe_graph(nfs_ctx* ctx, const std::string& key, hipStream_t s, F&& enqueue) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  NFS_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (!ctx->graphs || ctx->profiling || cs != hipStreamCaptureStatusNone) return enqueue(s);
+  auto it = ctx->graph_cache.find(key);
+  if (it == ctx->graph_cache.end()) {
+    NFS_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const int rc = enqueue(s);
+    hipGraph_t g = nullptr;
+    const hipError_t e = hipStreamEndCapture(s, &g);
+    if (rc) {
+      if (g) (void)hipGraphDestroy(g);
+      return rc;
+    }
+    if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
+    it = ctx->graph_cache.emplace(key, ex).first;
+  }
+  NFS_TRY(hipGraphLaunch(it->second, s), "hipGraphLaunch");
+  return NFS_OK;
+}
+
+extern "C" int nfs_set_graphs(nfs_ctx* ctx, int on) {
+  if (!ctx) return fail(NFS_EINVAL, "nfs_set_graphs: ctx is NULL");
+  ctx->graphs = on != 0;
+  return NFS_OK;
+}
+
+extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                            double tol, int replace_every, int reorth, int precision, double* hist, int* info,
+                            void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_cg_solve";
+  int rc = check_cg_args(ctx, prob, m, rho, n_iter, tol, replace_every, reorth, precision, hist, info, fn);
+  if (rc) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_CG, precision, n_iter, reorth);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const void* ptrs[4] = {m, rho, hist, info};
+  const std::string key =
+      graph_key("cg", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
+  return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
+    return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Batched solves: independent slices, forked from the caller's stream onto
+// the context's streams (longest-processing-time assignment by L*K*G) and
+// joined back.
+constexpr int kBatchStreams = 8;
+
+static int ensure_batch_streams(nfs_ctx* ctx) {
+  if ((int)ctx->bstreams.size() == kBatchStreams) return NFS_OK;
+  int cur = 0;
+  NFS_TRY(hipGetDevice(&cur), "hipGetDevice");
+  NFS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+  while ((int)ctx->bstreams.size() < kBatchStreams) {
+    hipStream_t st = nullptr;
+    hipEvent_t ev = nullptr;
+    NFS_TRY(hipStreamCreateWithFlags(&st, hipStreamNonBlocking), "hipStreamCreateWithFlags");
+    NFS_TRY(hipEventCreateWithFlags(&ev, hipEventDisableTiming), "hipEventCreateWithFlags");
+    ctx->bstreams.push_back(st);
+    ctx->bevents.push_back(ev);
+  }
+  if (!ctx->fork_event) NFS_TRY(hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming), "hipEventCreate");
+  NFS_TRY(hipSetDevice(cur), "hipSetDevice");
+  return NFS_OK;
+}
+
+static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs, int precision, int n_iter, int reorth,
+                            std::vector<Layout>* ys, std::vector<size_t>* offs) {
+  size_t tot = 0;
+  for (int i = 0; i < n; ++i) {
+    Layout y = make_layout(ctx, &probs[i], NFS_OP_CG, precision, n_iter, reorth);
+    if (offs) offs->push_back(tot);
+    tot += al(y.total);
+    if (ys) ys->push_back(y);
+  }
+  return tot;
+}
+
+extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
+                                           int n_iter, int reorth, size_t* bytes) {
+  const char* fn = "nfs_workspace_bytes_batched";
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  if (n_slices < 0 || (n_slices > 0 && !probs)) return fail(NFS_EINVAL, "%s: bad slice list", fn);
+  int rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if (n_iter < 0) return fail(NFS_EINVAL, "%s: n_iter %d < 0", fn, n_iter);
+  if (reorth && n_iter > kMaxReorth) return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
+  for (int i = 0; i < n_slices; ++i)
+    if ((rc = check_sizes(&probs[i], fn))) return rc;
+  *bytes = batch_layouts(ctx, n_slices, probs, precision, n_iter, reorth != 0, nullptr, nullptr);
+  return NFS_OK;
+}
+
+extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, const float* const* m,
+                                    float* const* rho, int n_iter, double tol, int replace_every, int reorth,
+                                    int precision, double* const* hist, int* const* info, void* ws, size_t ws_bytes,
+                                    void* stream) {
+  const char* fn = "nfs_cg_solve_batched";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (n_slices < 0 || (n_slices > 0 && (!probs || !m || !rho))) return fail(NFS_EINVAL, "%s: bad slice list", fn);
+  int rc;
+  for (int i = 0; i < n_slices; ++i) {
+    rc = check_cg_args(ctx, &probs[i], m[i], rho[i], n_iter, tol, replace_every, reorth, precision,
+                       hist ? hist[i] : nullptr, info ? info[i] : nullptr, fn);
+    if (rc) return rc;
+  }
+  std::vector<Layout> ys;
+  std::vector<size_t> offs;
+  const size_t need = batch_layouts(ctx, n_slices, probs, precision, n_iter, reorth, &ys, &offs);
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  if (ws_bytes < need) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, need);
+  if (n_slices == 0) return NFS_OK;
+  if ((rc = ensure_batch_streams(ctx))) return rc;
+  // longest-processing-time assignment of slices to streams
+  std::vector<int> order(n_slices);
+  for (int i = 0; i < n_slices; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)probs[i].n_vox * probs[i].n_samp * probs[i].n_coil; };
+  std::sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  const int ns = n_slices < kBatchStreams ? n_slices : kBatchStreams;
+  std::vector<std::vector<int>> lanes(ns);
+  std::vector<double> load(ns, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[k].push_back(i);
+    load[k] += work(i);
+  }
+  std::vector<const void*> ptrs;
+  for (int i = 0; i < n_slices; ++i) {
+    ptrs.push_back(m[i]);
+    ptrs.push_back(rho[i]);
+    ptrs.push_back(hist ? hist[i] : nullptr);
+    ptrs.push_back(info ? info[i] : nullptr);
+  }
+  const std::string key = graph_key("cgb", probs, n_slices, ptrs.data(), (int)ptrs.size(), n_iter, tol,
+                                    replace_every, reorth, precision, ws, ws_bytes, stream);
+  return run_maybe_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> int {
+    NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
+    for (int k = 0; k < ns; ++k) {
+      hipStream_t sk = ctx->bstreams[k];
+      NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
+      for (int i : lanes[k]) {
+        const int r2 = run_cg(ctx, &probs[i], ys[i], m[i], rho[i], n_iter, tol, replace_every, reorth,
+                              hist ? hist[i] : nullptr, info ? info[i] : nullptr,
+                              static_cast<char*>(ws) + offs[i], sk);
+        if (r2) return r2;
+      }
+      NFS_TRY(hipEventRecord(ctx->bevents[k], sk), "hipEventRecord");
+      NFS_TRY(hipStreamWaitEvent(s, ctx->bevents[k], 0), "hipStreamWaitEvent");
+    }
+    return NFS_OK;
+  });
 }
 
 extern "C" int nfs_encode_backward(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, const float* grad_m,

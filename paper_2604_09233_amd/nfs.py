@@ -64,6 +64,10 @@ def lib():
                 getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
             L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
             L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+            L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
+            L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
+                                               i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]
+            L.nfs_set_graphs.argtypes = [vp, i32]
             L.nfs_profile_enable.argtypes = [vp, i32]
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
             L.nfs_last_error.restype = ctypes.c_char_p
@@ -71,7 +75,8 @@ def lib():
             L.nfs_version.argtypes = []
             for name in ("nfs_create", "nfs_destroy", "nfs_workspace_bytes", "nfs_apply_E", "nfs_apply_EH",
                          "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read",
-                         "nfs_encode_backward"):
+                         "nfs_encode_backward", "nfs_workspace_bytes_batched", "nfs_cg_solve_batched",
+                         "nfs_set_graphs"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -225,6 +230,48 @@ def encode_backward(prob: Problem, rho, grad_m, precision: str = "fp32", need_rh
     _check(lib().nfs_encode_backward(context(prob.index), ctypes.byref(prob.st), _ptr(rho), _ptr(grad_m), p(g_rho),
                                      p(g_b0), p(g_k), PRECISIONS[precision], _ptr(ws), ws.numel(), prob._stream()))
     return g_rho, g_b0, g_k
+
+
+def set_graphs(device: int, on: bool = True):
+    """Capture repeated solves into hipGraphs and replay them (see include/nfs.h)."""
+    _check(lib().nfs_set_graphs(context(device), int(on)))
+
+
+_batch_ws = {}
+
+
+def cg_solve_batched(probs, ms, n_iter: int, tol: float = 0.0, replace_every: int = 0, precision: str = "fp32",
+                     reorth: bool = False, outs=None, hists=None, infos=None):
+    """Solve every slice (Problem, data) pair in one batched call.  Returns
+    lists (rho, hist, info) per slice, as cg_solve does."""
+    n = len(probs)
+    if n == 0:
+        return [], [], []
+    dev = probs[0].device
+    if any(p.device != dev for p in probs):
+        raise ValueError("all slices must live on one device")
+    ms = [_c64(m, dev) for m in ms]
+    outs = outs or [torch.empty(p.L, dtype=torch.complex64, device=dev) for p in probs]
+    hists = hists or [torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev) for _ in probs]
+    infos = infos or [torch.zeros(2, dtype=torch.int32, device=dev) for _ in probs]
+    arr = (nfs_problem * n)(*[p.st for p in probs])
+    vp = ctypes.c_void_p
+    nbytes = ctypes.c_size_t()
+    idx = probs[0].index
+    _check(lib().nfs_workspace_bytes_batched(context(idx), n, arr, PRECISIONS[precision], n_iter, int(reorth),
+                                             ctypes.byref(nbytes)))
+    key = (id(probs[0]), n, precision, n_iter, reorth)
+    ws = _batch_ws.get(key)
+    if ws is None or ws.numel() < nbytes.value + 256:
+        ws = torch.empty(max(256, nbytes.value) + 256, dtype=torch.uint8, device=dev)
+        _batch_ws[key] = ws
+    off = (-ws.data_ptr()) % 256
+    w = ws[off:off + max(256, nbytes.value)]
+    P = lambda xs: (vp * n)(*[vp(x.data_ptr()) if x is not None and x.numel() else vp(0) for x in xs])  # noqa: E731
+    _check(lib().nfs_cg_solve_batched(context(idx), n, arr, P(ms), P(outs), int(n_iter), float(tol),
+                                      int(replace_every), int(reorth), PRECISIONS[precision], P(hists), P(infos),
+                                      _ptr(w), w.numel(), probs[0]._stream()))
+    return outs, hists, infos
 
 
 def profile_enable(device: int, on: bool = True):

@@ -317,17 +317,18 @@ def dft_problem(n: int, n_coil: int = 1, full: bool = True, exact: bool = False)
     )
 
 
-def batched_slices(n_slices: int = 24, seed: int = 0):
-    """Batched workload: uneven 2D slices (96..160 square, 8..32 coils,
-    8000..30000 samples, 16 basis terms, per-slice B0).  Returns a list of
-    dicts shaped like ``make_config`` output."""
+def batched_slices(n_slices: int = 24, seed: int = 0, n_range=(96, 160), g_range=(8, 32),
+                   k_range=(8000, 30000)):
+    """Batched workload: uneven 2D slices (by default 96..160 square, 8..32
+    coils, 8000..30000 samples, 16 basis terms, per-slice B0).  Returns a list
+    of dicts shaped like ``make_config`` output."""
     ss = np.random.SeedSequence([_SEED_BASE + 4, seed])
     rng_sizes = np.random.default_rng(ss.spawn(1)[0])
     out = []
     for s in range(n_slices):
-        n = int(rng_sizes.integers(96, 161)) // 2 * 2
-        G = int(rng_sizes.integers(8, 33))
-        Ks = int(rng_sizes.integers(8000, 30001))
+        n = int(rng_sizes.integers(n_range[0], n_range[1] + 1)) // 2 * 2
+        G = int(rng_sizes.integers(g_range[0], g_range[1] + 1))
+        Ks = int(rng_sizes.integers(k_range[0], k_range[1] + 1))
         cfg = dict(index=100 + s, dims=(n, n), n_coil=G, n_basis=16, shots=1,
                    interleaves=4, k_shot=Ks, b0_hz=100.0, b0_kind="smooth_noise", n_iter=30)
         rs = _streams(cfg["index"] + 1000 * seed)

@@ -146,3 +146,25 @@ def test_create_without_gpu_reports_hip_error(L):
     assert L.nfs_create(ctypes.byref(h), 0) == nfs.NFS_EHIP
     assert not h.value
     assert L.nfs_create(None, 0) == nfs.NFS_EINVAL
+
+
+def test_batched_validation(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    arr = (nfs.nfs_problem * 2)(prob(), prob(G=65))
+    ptrs = (ctypes.c_void_p * 2)(A, A)
+    f = L.nfs_cg_solve_batched
+    assert f(None, 2, arr, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, -1, arr, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, 2, None, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, 2, arr, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_ESHAPE  # slice 1
+    ok = (nfs.nfs_problem * 2)(prob(), prob(L=64, K=99, G=3, P=16))
+    assert f(c, 2, ok, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1, None) == nfs.NFS_EWORKSPACE
+    assert f(c, 0, ok, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1, None) == nfs.NFS_OK  # nothing to do
+    n = ctypes.c_size_t()
+    assert L.nfs_workspace_bytes_batched(None, 2, ok, 2, 30, 1, ctypes.byref(n)) == 0
+    one = ctypes.c_size_t()
+    L.nfs_workspace_bytes(None, ctypes.byref(ok[0]), 3, 2, 30, 1, ctypes.byref(one))
+    two = ctypes.c_size_t()
+    L.nfs_workspace_bytes(None, ctypes.byref(ok[1]), 3, 2, 30, 1, ctypes.byref(two))
+    assert n.value == one.value + two.value
+    assert L.nfs_set_graphs(None, 1) == nfs.NFS_EINVAL

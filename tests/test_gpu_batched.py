@@ -1,0 +1,119 @@
+"""Batched multi-slice solves and graph replay, through the C ABI."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.fixture(scope="module")
+def nfs():
+    from paper_2604_09233_amd import nfs as mod
+
+    assert torch.cuda.is_available()
+    return mod
+
+
+def args(d):
+    return (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
+
+
+@pytest.fixture(scope="module")
+def small_batch(nfs):
+    sl = synth.batched_slices(6, seed=3, n_range=(20, 40), g_range=(2, 12), k_range=(800, 3000))
+    probs, ms = [], []
+    for d in sl:
+        probs.append(nfs.Problem(*args(d)))
+        clean = oracle.apply_E(d["rho_true"], *args(d))
+        sig = np.sqrt(np.mean(np.abs(clean) ** 2)) / (30 * np.sqrt(2))
+        ms.append((clean + sig * d["noise"]).astype(np.complex64))
+    return sl, probs, ms
+
+
+@pytest.mark.parametrize("prec,reorth", [("fp16", True), ("fp32", True), ("bf16", False)])
+def test_batched_equals_single_solves(nfs, small_batch, prec, reorth):
+    sl, probs, ms = small_batch
+    rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 12, precision=prec, reorth=reorth)
+    torch.cuda.synchronize()
+    for i, (p, m) in enumerate(zip(probs, ms)):
+        r1, h1, i1 = nfs.cg_solve(p, torch.from_numpy(m), 12, precision=prec, reorth=reorth)
+        torch.cuda.synchronize()
+        assert torch.equal(rb[i].cpu(), r1.cpu()), i
+        assert torch.equal(ib[i].cpu(), i1.cpu()), i
+        assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
+
+
+def test_batched_slice_matches_oracle(nfs, small_batch):
+    sl, probs, ms = small_batch
+    rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 10, precision="fp32", reorth=True)
+    torch.cuda.synchronize()
+    for i in (0, 3):
+        ref = oracle.cg_solve(ms[i], *args(sl[i]), n_iter=10, reorth=True)
+        err = rel(rb[i].cpu().numpy(), ref["rho"])
+        print(f"batched slice {i} (L={sl[i]['L']}, K={sl[i]['K']}, G={sl[i]['n_coil']}): rel {err:.2e}")
+        assert err < 1e-4
+
+
+def test_batched_tolerance_freezes_slices_independently(nfs, small_batch):
+    sl, probs, ms = small_batch
+    rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 40, tol=1e-2, precision="fp32",
+                                      reorth=True)
+    torch.cuda.synchronize()
+    for i in range(len(probs)):
+        it, st = ib[i].cpu().tolist()
+        h = hb[i].cpu().numpy()
+        assert st == 2 and 1 <= it < 40
+        assert h[it, 0] <= 1e-2 * h[0, 0] and h[it - 1, 0] > 1e-2 * h[0, 0]
+
+
+def test_graph_replay_matches_eager(nfs, small_batch):
+    sl, probs, ms = small_batch
+    p, m = probs[1], torch.from_numpy(ms[1]).cuda()
+    out = torch.empty(p.L, dtype=torch.complex64, device="cuda")
+    hist = torch.full((16, 3), float("nan"), dtype=torch.float64, device="cuda")
+    info = torch.zeros(2, dtype=torch.int32, device="cuda")
+    nfs.set_graphs(0, False)
+    eager, _, _ = nfs.cg_solve(p, m, 15, precision="fp16", reorth=True)
+    eager = eager.cpu()
+    nfs.set_graphs(0, True)
+    try:
+        for rep in range(4):
+            out.zero_()
+            hist.fill_(float("nan"))
+            nfs.cg_solve(p, m, 15, precision="fp16", reorth=True, out=out, hist=hist, info=info)
+            torch.cuda.synchronize()
+            assert torch.equal(out.cpu(), eager), rep
+            assert info.cpu().tolist() == [15, 1]
+            # eager work in between replays
+            nfs.apply_EHE(p, out, "fp32")
+            torch.cuda.synchronize()
+        # batched graph replay: device-resident data and fixed output buffers,
+        # so that every call after the first replays the captured graph
+        dms = [torch.from_numpy(x).cuda() for x in ms]
+        outs = [torch.empty(q.L, dtype=torch.complex64, device="cuda") for q in probs]
+        hists = [torch.empty((9, 3), dtype=torch.float64, device="cuda") for _ in probs]
+        infos = [torch.zeros(2, dtype=torch.int32, device="cuda") for _ in probs]
+        nfs.set_graphs(0, False)
+        ref, _, _ = nfs.cg_solve_batched(probs, dms, 8, precision="fp16", reorth=True)
+        ref = [r.clone() for r in ref]
+        nfs.set_graphs(0, True)
+        for rep in range(3):
+            for o in outs:
+                o.zero_()
+            nfs.cg_solve_batched(probs, dms, 8, precision="fp16", reorth=True, outs=outs, hists=hists, infos=infos)
+            torch.cuda.synchronize()
+            for a, b in zip(outs, ref):
+                assert torch.equal(a, b), rep
+            nfs.apply_E(probs[0], outs[0], "fp16")
+            torch.cuda.synchronize()
+    finally:
+        nfs.set_graphs(0, False)
