@@ -24,6 +24,7 @@ struct nfs_ctx {
   std::vector<hipStream_t> bstreams;  // batched solves: forked streams (default priority)
   std::vector<hipEvent_t> bevents;    // ... and their join events
   hipEvent_t fork_event = nullptr;
+  hipStream_t capture_stream = nullptr;  // graph capture only
   std::vector<hipEvent_t> pool;                 // idle events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // recorded (start, stop) per kind
 };
@@ -79,6 +80,7 @@ extern "C" int nfs_destroy(nfs_ctx* ctx) {
   for (auto st : ctx->bstreams) (void)hipStreamDestroy(st);
   for (auto e : ctx->bevents) (void)hipEventDestroy(e);
   if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
+  if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
   delete ctx;
   return NFS_OK;
 }
@@ -344,11 +346,13 @@ static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr) {
   });
 }
 
-// E^H part: src (m [G][K] or ybuf) (o wgt) -> hpart (coil-combined partials)
-static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr) {
+// E^H part: src (m [G][K] or ybuf) (o wgt) -> hpart (coil-combined partials);
+// max_ready: the FP16 block maxima of src are already in bmax
+static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr,
+                  bool max_ready = false) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
-  if (y.prec == PREC_FP16)
+  if (y.prec == PREC_FP16 && !max_ready)
     NFS_TRY(launch_absmax(src, nullptr, wgt, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
   NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, wgt, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
                            bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
@@ -365,10 +369,11 @@ static int seq_EHE(const Ctx& c, const float2* p) {
   int rc = seq_E(c, p);
   if (rc) return rc;
   float* ybuf = at<float>(c.ws, y.o_ybuf);
-  NFS_TRY(launch_finish_E_to_ybuf(at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, unscale_slot(c, 0), ybuf,
-                                  c.stop, c.s),
+  const bool fp16 = y.prec == PREC_FP16;
+  NFS_TRY(launch_finish_E_to_ybuf(at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G,
+                                  unscale_slot(c, 0), ybuf, fp16 ? at<float>(c.ws, y.o_bmax) : nullptr, c.stop, c.s),
           "finish_E_to_ybuf");
-  return seq_EH(c, reinterpret_cast<const float2*>(ybuf), (int64_t)y.NB * 8, 1);
+  return seq_EH(c, reinterpret_cast<const float2*>(ybuf), (int64_t)y.NB * 8, 1, nullptr, fp16);
 }
 
 extern "C" int nfs_apply_E(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, float* m, int precision,
@@ -503,8 +508,7 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
       NFS_TRY(launch_cg_replace(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_replace");
     }
     if (reorth) NFS_TRY(launch_cg_reorth(st, n + 1, s), "cg_reorth");
-    NFS_TRY(launch_cg_direction(st, x, y.L, n, n_iter, tol, s), "cg_direction");
-    if (reorth) NFS_TRY(launch_cg_store_v(st, n + 1, s), "cg_store_v");
+    NFS_TRY(launch_cg_direction(st, y.L, n, n_iter, tol, s), "cg_direction");
   }
   NFS_TRY(launch_cg_finish(st, x, prob->icorr, y.L, s), "cg_finish");
   return NFS_OK;
@@ -535,17 +539,29 @@ static std::string graph_key(const char* kind, const nfs_problem* probs, int n, 
   return k;
 }
 
+// Capture happens on a library-owned stream (the caller's stream may be the
+// legacy null stream, which cannot be captured); the instantiated graph is
+// then launched on the caller's stream, after the work already queued there.
 template <class F>
 static int run_maybe_graph(nfs_ctx* ctx, const std::string& key, hipStream_t s, F&& enqueue) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-  NFS_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (s) NFS_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
   if (!ctx->graphs || ctx->profiling || cs != hipStreamCaptureStatusNone) return enqueue(s);
   auto it = ctx->graph_cache.find(key);
   if (it == ctx->graph_cache.end()) {
-    NFS_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
-    const int rc = enqueue(s);
+    if (!ctx->capture_stream) {
+      int cur = 0;
+      NFS_TRY(hipGetDevice(&cur), "hipGetDevice");
+      NFS_TRY(hipSetDevice(ctx->device), "hipSetDevice");
+      const hipError_t ec = hipStreamCreateWithFlags(&ctx->capture_stream, hipStreamNonBlocking);
+      NFS_TRY(hipSetDevice(cur), "hipSetDevice");
+      NFS_TRY(ec, "hipStreamCreateWithFlags");
+    }
+    hipStream_t cap = ctx->capture_stream;
+    NFS_TRY(hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal), "hipStreamBeginCapture");
+    const int rc = enqueue(cap);
     hipGraph_t g = nullptr;
-    const hipError_t e = hipStreamEndCapture(s, &g);
+    const hipError_t e = hipStreamEndCapture(cap, &g);
     if (rc) {
       if (g) (void)hipGraphDestroy(g);
       return rc;

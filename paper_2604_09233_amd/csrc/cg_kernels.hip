@@ -138,7 +138,7 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
   }
   const double gamma = alpha / beta;
   const float gf = (float)gamma;
-  double a = 0.0;
+  double a = 0.0, xx = 0.0;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
     const float2 p = st.p[l], q = st.q[l];
     float2 x = rho[l], r = st.r[l];
@@ -149,10 +149,13 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
     rho[l] = x;
     st.r[l] = r;
     a += (double)r.x * r.x + (double)r.y * r.y;
+    xx += (double)x.x * x.x + (double)x.y * x.y;
   }
   a = block_sum(a, red);
+  xx = block_sum(xx, red);
   if (threadIdx.x == 0) {
     st.part[kCgBlocks + blockIdx.x] = a;
+    st.part[2 * kCgBlocks + blockIdx.x] = xx;
     if (blockIdx.x == 0) st.scal[0] = beta;
   }
 }
@@ -176,36 +179,39 @@ __global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float
   if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
 }
 
-// alpha_{n+1} = r^H r; p = r + (alpha_{n+1} / alpha_n) p; ||rho||; history; stop tests
-__global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, const float2* __restrict__ rho, int64_t L,
-                                                           int n, int n_iter, double tol) {
+// alpha_{n+1} = r^H r; p = r + (alpha_{n+1} / alpha_n) p; with
+// re-orthogonalisation also V[n+1] = r / sqrt(alpha_{n+1}).  Workgroup 0
+// writes history row n+1 (||rho_{n+1}|| from the partials of cg_update) and
+// takes the stop decision.  It raises the stop flag itself: a workgroup of
+// this launch that starts after that skips its share of the p and V
+// updates, which is harmless because neither is read once the loop stops.
+__global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L, int n, int n_iter, double tol) {
   if (*st.stop) return;
   __shared__ double red[256];
   const double anew = sum_partials(st.part + kCgBlocks, st.nblk, red);
   const double aold = st.alpha[n];
   const float bf = (float)(anew / aold);
-  double a = 0.0;
+  const bool store = st.V && anew > 0.0 && isfinite(anew);
+  const float inv = store ? (float)(1.0 / sqrt(anew)) : 0.f;
+  float2* v = store ? st.V + (size_t)(n + 1) * L : nullptr;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
     const float2 r = st.r[l];
     float2 p = st.p[l];
     p.x = fmaf(bf, p.x, r.x);
     p.y = fmaf(bf, p.y, r.y);
     st.p[l] = p;
-    const float2 x = rho[l];
-    a += (double)x.x * x.x + (double)x.y * x.y;
+    if (store) v[l] = make_float2(r.x * inv, r.y * inv);
   }
-  a = block_sum(a, red);
-  if (threadIdx.x == 0) st.part[2 * kCgBlocks + blockIdx.x] = a;
-  if (blockIdx.x != 0 || threadIdx.x != 0) return;
-  // History row n+1 and the stop decision.  The stop flag itself is raised by
-  // cg_norm_rho_kernel (next launch): raising it here could make workgroups of
-  // this launch that start later skip their share of the update.
+  if (blockIdx.x != 0) return;
+  const double xx = sum_partials(st.part + 2 * kCgBlocks, st.nblk, red);
+  if (threadIdx.x != 0) return;
   const double beta = st.scal[0];
   const double d2 = st.scal[1] - aold * aold / beta;
   st.scal[1] = d2;
   st.alpha[n + 1] = anew;
   double* h = st.hist + 3 * (size_t)(n + 1);
   h[0] = sqrt(anew);
+  h[1] = sqrt(xx);
   h[2] = d2;
   st.info[0] = n + 1;
   int status = 0;
@@ -213,17 +219,9 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, const flo
   else if (anew == 0.0) status = CG_EXACT;
   else if (tol > 0.0 && sqrt(anew) <= tol * sqrt(st.alpha[0])) status = CG_TOL;
   else if (n + 1 >= n_iter) status = CG_MAXITER;
-  st.info[1] = status;
-}
-
-// ||rho_{n+1}|| from the partials of cg_direction, then the stop flag.
-__global__ __launch_bounds__(256) void cg_norm_rho_kernel(CgState st, int n) {
-  __shared__ double red[256];
-  if (*st.stop || st.info[0] != n + 1) return;  // step n+1 did not run
-  const double s = sum_partials(st.part + 2 * kCgBlocks, st.nblk, red);
-  if (threadIdx.x == 0) {
-    st.hist[3 * (size_t)(n + 1) + 1] = sqrt(s);
-    if (st.info[1] != 0) *st.stop = 1;
+  if (status) {
+    st.info[1] = status;
+    *st.stop = 1;
   }
 }
 
@@ -343,11 +341,8 @@ hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit,
   return hipGetLastError();
 }
 
-hipError_t launch_cg_direction(const CgState& st, const float2* rho, int64_t L, int n, int n_iter, double tol,
-                               hipStream_t s) {
-  hipLaunchKernelGGL(cg_direction_kernel, dim3(st.nblk), dim3(256), 0, s, st, rho, L, n, n_iter, tol);
-  if (hipGetLastError() != hipSuccess) return hipErrorLaunchFailure;
-  hipLaunchKernelGGL(cg_norm_rho_kernel, dim3(1), dim3(256), 0, s, st, n);
+hipError_t launch_cg_direction(const CgState& st, int64_t L, int n, int n_iter, double tol, hipStream_t s) {
+  hipLaunchKernelGGL(cg_direction_kernel, dim3(st.nblk), dim3(256), 0, s, st, L, n, n_iter, tol);
   return hipGetLastError();
 }
 

@@ -494,15 +494,37 @@ __global__ void finish_E_to_m_kernel(const float* __restrict__ epart, int nsplit
   m[i] = make_float2(re * u, im * u);
 }
 
-__global__ void finish_E_to_ybuf_kernel(const float* __restrict__ epart, int nsplit, int64_t n,
-                                        const float* __restrict__ unscale, float* __restrict__ ybuf,
-                                        const int* stop) {
+// ybuf = (sum of split partials) * unscale over all padded rows; with bmax,
+// also the per-workgroup largest |re| / |im| over the valid rows (k < K) and
+// columns (< 2G), as absmax_kernel would give for ybuf (kBmaxBlocks
+// workgroups, every entry written).
+// (1024 threads per workgroup; ncol = 16 NB is a power of two, 2^lncol)
+__global__ __launch_bounds__(1024) void finish_E_to_ybuf_kernel(const float* __restrict__ epart, int nsplit, int64_t n,
+                                                                int lncol, int64_t K, int G,
+                                                                const float* __restrict__ unscale,
+                                                                float* __restrict__ ybuf, float* __restrict__ bmax,
+                                                                const int* stop) {
   if (stop && *stop) return;
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  float v = 0.f;
-  for (int s = 0; s < nsplit; ++s) v += epart[(size_t)s * n + i];
-  ybuf[i] = v * (unscale ? *unscale : 1.f);
+  const float u = unscale ? *unscale : 1.f;
+  const int64_t cmask = ((int64_t)1 << lncol) - 1;
+  float mx = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 1024) {
+    float v = 0.f;
+    for (int s = 0; s < nsplit; ++s) v += epart[(size_t)s * n + i];
+    v *= u;
+    ybuf[i] = v;
+    if ((i >> lncol) < K && (i & cmask) < 2 * G) mx = fmaxf(mx, fabsf(v));
+  }
+  if (bmax) {
+    __shared__ float red[1024];
+    red[threadIdx.x] = mx;
+    __syncthreads();
+    for (int w = 512; w > 0; w >>= 1) {
+      if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
+  }
 }
 
 __global__ void finish_EH_kernel(const float2* __restrict__ hpart, int nsplit, int64_t HC16, int64_t L,
@@ -666,11 +688,13 @@ hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, in
   return hipGetLastError();
 }
 
-hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB, const float* unscale,
-                                   float* ybuf, const int* stop, hipStream_t s) {
+hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
+                                   const float* unscale, float* ybuf, float* bmax, const int* stop, hipStream_t s) {
   const int64_t n = HC16 * NB * 16;
-  if (n == 0) return hipSuccess;
-  hipLaunchKernelGGL(finish_E_to_ybuf_kernel, grid1(n), dim3(256), 0, s, epart, nsplit, n, unscale, ybuf, stop);
+  if (n == 0 && !bmax) return hipSuccess;
+  const int lncol = NB == 1 ? 4 : (NB == 2 ? 5 : (NB == 4 ? 6 : 7));
+  hipLaunchKernelGGL(finish_E_to_ybuf_kernel, dim3(kBmaxBlocks), dim3(1024), 0, s, epart, nsplit, n, lncol, K, G,
+                     unscale, ybuf, bmax, stop);
   return hipGetLastError();
 }
 

@@ -82,9 +82,10 @@ hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void
 // sum E partials -> m[G][K] (coil-major) times *unscale
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s);
-// sum E partials -> ybuf [HC16][NB*16] times *unscale
-hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB,
-                                   const float* unscale, float* ybuf, const int* stop, hipStream_t s);
+// sum E partials -> ybuf [HC16][NB*16] times *unscale; with bmax also the
+// per-workgroup max magnitudes of the valid entries (rows < K, columns < 2G)
+hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
+                                   const float* unscale, float* ybuf, float* bmax, const int* stop, hipStream_t s);
 // sum E^H partials -> x[L] times *unscale
 hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
                             const float* unscale, float2* x, hipStream_t s);
@@ -124,8 +125,7 @@ hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, in
 hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s);
 hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
                              const float* unscale, int64_t L, hipStream_t s);
-hipError_t launch_cg_direction(const CgState& st, const float2* rho, int64_t L, int n, int n_iter,
-                               double tol, hipStream_t s);
+hipError_t launch_cg_direction(const CgState& st, int64_t L, int n, int n_iter, double tol, hipStream_t s);
 // V[j] = r / sqrt(alpha_j)
 hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
 // r -= sum_{j < nv} (v_j^H r) v_j; partial r^H r -> part[1]

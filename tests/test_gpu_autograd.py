@@ -55,8 +55,12 @@ def test_autograd_matches_oracle_gradients(mods, prec):
 
 
 def test_autograd_finite_differences_float32(mods):
-    """Central differences (h = 1e-3) of the float32 GPU loss along the 16
-    per-term gains of the field coefficients and along the B0 map."""
+    """Central differences (h = 1e-3) of the loss of the float32 GPU forward
+    (summed in float64) against the autograd gradients, along random
+    directions over all field coefficients and over the B0 map, and along the
+    per-term gains of the field coefficients whose derivative stands above
+    the difference quotient's noise floor (the forward's float32 rounding,
+    about 1e-7 of the loss, divided by 2h)."""
     nfs, ag = mods
     d = synth.random_problem(200, 400, 3, 16, seed=42, phase_scale=6.0)
     dev = torch.device("cuda:0")
@@ -68,22 +72,34 @@ def test_autograd_finite_differences_float32(mods):
 
     def loss_fn(kcoef, b0v):
         y = ag.encode(rho, b0v, kcoef, T["sens"], T["fields"], T["t"], "fp32")
-        return torch.sum(torch.abs(y - m) ** 2)
+        return torch.sum(torch.abs(y.to(torch.complex128) - m.to(torch.complex128)) ** 2)
 
     L0 = loss_fn(kc, b0)
     L0.backward()
     h = 1e-3
+    floor = 2e-7 * L0.item() / (2 * h)
+    gen = torch.Generator(device=dev).manual_seed(5)
+    checked = 0
     with torch.no_grad():
+        for trial in range(3):
+            v = torch.randn(kc.shape, device=dev, generator=gen) * kc.abs().mean(0, keepdim=True)
+            fd = (loss_fn(kc + h * v, b0) - loss_fn(kc - h * v, b0)).item() / (2 * h)
+            an = torch.sum(kc.grad * v).item()
+            assert abs(fd - an) < 2e-2 * abs(an) + 10 * floor, ("kcoef dir", trial, fd, an)
+            vb = torch.randn(b0.shape, device=dev, generator=gen) * 50.0  # rad/s
+            fd = (loss_fn(kc, b0 + h * vb) - loss_fn(kc, b0 - h * vb)).item() / (2 * h)
+            an = torch.sum(b0.grad * vb).item()
+            assert abs(fd - an) < 2e-2 * abs(an) + 10 * floor, ("b0 dir", trial, fd, an)
         for b in range(16):
             e = torch.zeros_like(kc)
             e[:, b] = kc[:, b]
-            fd = (loss_fn(kc + h * e, b0) - loss_fn(kc - h * e, b0)).item() / (2 * h)
             an = torch.sum(kc.grad * e).item()
-            assert abs(fd - an) < 2e-2 * max(abs(an), 1e-3 * L0.item()), (b, fd, an)
-        v = torch.randn_like(b0) * 50.0  # rad/s
-        fd = (loss_fn(kc, b0 + h * v) - loss_fn(kc, b0 - h * v)).item() / (2 * h)
-        an = torch.sum(b0.grad * v).item()
-        assert abs(fd - an) < 2e-2 * max(abs(an), 1e-4 * L0.item()), (fd, an)
+            if abs(an) < 30 * floor:
+                continue
+            fd = (loss_fn(kc + h * e, b0) - loss_fn(kc - h * e, b0)).item() / (2 * h)
+            assert abs(fd - an) < 2e-2 * abs(an) + 10 * floor, ("gain", b, fd, an)
+            checked += 1
+    assert checked >= 1
 
 
 @pytest.fixture(scope="module")
