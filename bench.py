@@ -47,6 +47,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
+    ap.add_argument("--profile-run", action="store_true",
+                    help="one solve only (no side measurements, no CPU baseline), for counter collection")
     ap.add_argument("--trans-rate", type=float, default=0.25,
                     help="v_sin/v_cos issue rate as a fraction of the FP32 lane rate (for the ALU peak)")
     return ap.parse_args()
@@ -131,6 +133,11 @@ def main():
             nfs.profile_enable(0, False)
         return out, hist, info, ms, wall, kt
 
+    if args.profile_run:
+        time_solves(args.precision, 1, 0, profile=False)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": "done"}))
+        return
     rho, hist, info, ms, wall, kt = time_solves(args.precision, args.steps, args.warmup, profile=True)
     vsc = L * K * G
     value = (n_iter + 0.5) * vsc / (ms * 1e-3)

@@ -19,6 +19,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnfs.so")
 SOURCES = ["encode_kernels.hip", "cg_kernels.hip", "capi.hip"]
+# The encode kernels keep MFMA accumulators in ordinary VGPRs (no AGPR
+# round trips between the phase tile and the sine/cosine that consume it).
+SOURCE_FLAGS = {"encode_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # Packed FP32 VALU ops are disabled for the device code (see the design notes).
@@ -43,7 +46,8 @@ def build(verbose: bool = False) -> str:
     for src in SOURCES:
         obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
         objs.append(obj)
-        cmds.append([HIPCC, *COMMON, *DEVICE_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj])
+        cmds.append([HIPCC, *COMMON, *DEVICE_FLAGS, *SOURCE_FLAGS.get(src, []), "-c", os.path.join(CSRC, src), "-o",
+                     obj])
     with ThreadPoolExecutor(len(cmds)) as ex:
         outs = list(ex.map(_run, cmds))
     if verbose:

@@ -172,7 +172,7 @@ struct Layout {
   int64_t L, K, LC, KC;
   int G, P, NQ, NB, prec;
   EncodeShape shE, shH;
-  size_t o_sA, o_sB, o_vA, o_vB, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
+  size_t o_sA, o_sB, o_vA, o_vB, o_tmax, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
   size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_coef;
   size_t total;
 };
@@ -200,7 +200,7 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.NB = col_blocks(y.G);
   y.prec = prec;
   const int n_cu = ctx ? ctx->n_cu : 256;
-  const int MT = 2;
+  const int MT = held_tiles(y.NB);
   y.shE = EncodeShape{OP_E, prec, y.NQ, y.NB, MT, y.KC, y.LC, 1, 0};
   y.shE.nsplit = choose_split(y.KC, y.LC, MT, n_cu);
   y.shE.cps = cdiv(y.LC, y.shE.nsplit);
@@ -221,6 +221,7 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.o_sB = needE ? take((size_t)y.KC * phase_chunk_bytes(y.NQ)) : 0;
   y.o_sA = needH ? take((size_t)y.KC * phase_chunk_bytes(y.NQ)) : 0;
   y.o_vB = needH ? take((size_t)y.LC * phase_chunk_bytes(y.NQ)) : 0;
+  y.o_tmax = take(2 * kMaxTerms * 4);
   y.o_bmax = take(kBmaxBlocks * 4);
   y.o_unscale = take(2 * 4);
   y.o_dataE = needE ? take((size_t)y.LC * y.NB * data_chunk_bytes(prec)) : 0;
@@ -317,13 +318,19 @@ static int timed_encode(const Ctx& c, int kind, F&& launch) {
 static int seq_pack_coefs(const Ctx& c, bool forE, bool forH) {
   const Layout& y = c.y;
   const nfs_problem* p = c.pr;
+  unsigned* tmax = at<unsigned>(c.ws, y.o_tmax);
+  NFS_TRY(launch_term_absmax(p->t, p->kcoef, y.K, p->b0, p->fields, y.L, y.P, tmax, c.s), "term_absmax");
   if (forE) {
-    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 0, y.NQ, at<void>(c.ws, y.o_vA), c.s), "pack_phase");
-    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 1, y.NQ, at<void>(c.ws, y.o_sB), c.s), "pack_phase");
+    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 0, y.NQ, tmax, at<void>(c.ws, y.o_vA), c.s),
+            "pack_phase");
+    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 1, y.NQ, tmax, at<void>(c.ws, y.o_sB), c.s),
+            "pack_phase");
   }
   if (forH) {
-    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 0, y.NQ, at<void>(c.ws, y.o_sA), c.s), "pack_phase");
-    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 1, y.NQ, at<void>(c.ws, y.o_vB), c.s), "pack_phase");
+    NFS_TRY(launch_pack_phase(p->t, p->kcoef, y.K, y.P, 0, 0, y.NQ, tmax, at<void>(c.ws, y.o_sA), c.s),
+            "pack_phase");
+    NFS_TRY(launch_pack_phase(p->b0, p->fields, y.L, y.P, 1, 1, y.NQ, tmax, at<void>(c.ws, y.o_vB), c.s),
+            "pack_phase");
   }
   return NFS_OK;
 }
@@ -342,7 +349,8 @@ static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr) {
           "pack_data(E)");
   return timed_encode(c, 0, [&] {
     return launch_encode(y.shE, at<void>(c.ws, y.o_sB), at<void>(c.ws, y.o_vA), at<void>(c.ws, y.o_dataE),
-                         at<float>(c.ws, y.o_epart), c.sens, y.L, y.G, c.stop, c.s);
+                         at<float>(c.ws, y.o_epart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
+                         c.s);
   });
 }
 
@@ -359,7 +367,8 @@ static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const
           "pack_data(EH)");
   return timed_encode(c, 1, [&] {
     return launch_encode(y.shH, at<void>(c.ws, y.o_vB), at<void>(c.ws, y.o_sA), at<void>(c.ws, y.o_dataH),
-                         at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, c.stop, c.s);
+                         at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
+                         c.s);
   });
 }
 

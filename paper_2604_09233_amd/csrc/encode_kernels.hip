@@ -33,55 +33,85 @@ __device__ __forceinline__ float2 cmul(float2 a, float2 b) {
 }
 
 // ---------------------------------------------------------------------------
-// Phase coefficients, split into bf16 parts, in MFMA fragment order.
+// Phase coefficients, split into f16 parts, in MFMA fragment order.
 //
 // phi(k, l) = sum_b a_b(k) h_b(l) with a the sample-side coefficients
 // (a_0 = t / 2 pi, a_{b+1} = kcoef[.][b] / 2 pi: phase in revolutions) and h
-// the voxel-side ones (h_0 = b0, h_{b+1} = fields[b][.]).  Every coefficient
-// x (taken in double, so the 1/2pi scaling adds no rounding) is split into
-// bf16 parts x = x1 + x2 + x3 + O(2^-27 x); the phase is the sum over terms of
-// the six products x_i y_j with i + j <= 4, which reproduces a_b h_b to about
-// 2^-26 relative, computed on the bf16 matrix cores (v_mfma_f32_16x16x32_bf16)
-// with float32 accumulation.
+// the voxel-side ones (h_0 = b0, h_{b+1} = fields[b][.]).
 //
-// K-slot layout of one (16-item chunk): NQ instructions of 32 slots.  The
-// first NQ-1 instructions hold the five small products, in the order
-// (3,1) (1,3) (2,2) (2,1) (1,2), term-major within each (slot = pair * T + b,
-// zero past 5T); the last instruction holds the (1,1) products (slot = b,
-// zero past T).  The large products are thus added last, once, to a running
-// sum that is still small.  Slot k multiplies slot k of the other operand,
-// so the two operands carry complementary parts: role A (the streamed side,
-// MFMA operand A) takes part i, role B (the held side, operand B) part j.
+// Per term, a power of two 2^e_b moves magnitude from one side to the other
+// (a_b 2^-e_b and h_b 2^e_b), chosen from the two largest magnitudes so that
+// both sides peak near sqrt(max|a_b| max|h_b|), inside float16's range.  Each
+// balanced coefficient x (in double, so neither scaling rounds) is split as
+// x1 = f16(x), x2 = f16(x - x1), x = x1 + x2 + O(2^-22 x), and the term is
+// a1 h1 + a1 h2 + a2 h1: products of f16 values are exact in the float32
+// accumulator of v_mfma_f32_16x16x32_f16, and the dropped a2 h2 and the
+// split remainders are O(2^-21) of max|a_b| max|h_b|.
+//
+// K-slot layout of one 16-item chunk: 3T slots over NQ = ceil(3T / 32)
+// instructions; slot b holds the (1,2) product of term b, slot T + b the
+// (2,1) product and slot 2T + b the (1,1) product; slots past 3T are zero.
+// The small products thus enter the running sum before the large ones.
+// Slot k multiplies slot k of the other operand, so the two operands carry
+// complementary parts: role A (the streamed side, MFMA operand A) takes
+// part i of product (i, j), role B (the held side, operand B) part j.
 // Per lane (g = lane / 16, n = lane % 16): item 16 chunk + n, slots
 // 32 q + 8 g + e, e = 0..7, stored as one 16-byte vector
 // out[(chunk * NQ + q) * 64 + lane].
-__device__ __forceinline__ float bf16_part(double x, int part) {
-  double r = x;
-  float p = 0.f;
-  for (int i = 1; i <= part; ++i) {
-    p = (float)(__bf16)(float)r;
-    r -= (double)p;
-  }
-  return p;
+
+// e_b of the balancing power for term b, from the term maxima (identical on
+// both sides and in every kernel that reads it)
+__device__ __forceinline__ int term_shift(const unsigned* __restrict__ tmax, int b) {
+  const float ma = __uint_as_float(tmax[b]) * (float)kInv2Pi;
+  const float mh = __uint_as_float(tmax[kMaxTerms + b]);
+  if (!(ma > 0.f) || !(mh > 0.f) || !isfinite(ma) || !isfinite(mh)) return 0;
+  int ea, eh;
+  frexpf(ma, &ea);
+  frexpf(mh, &eh);
+  return (ea - eh) / 2;
 }
 
-__device__ __forceinline__ int phase_slot(int k, int T, int NQ, int role, int* b) {
-  // returns the part index for slot k (0 = zero slot) and the term in *b
-  const int small = 32 * (NQ - 1);
-  if (k < small) {
-    const int ps = k / T;
-    *b = k - ps * T;
-    if (ps >= 5) return 0;
-    const int pa[5] = {3, 1, 2, 2, 1}, pb[5] = {1, 3, 2, 1, 2};
-    return role == 0 ? pa[ps] : pb[ps];
+// largest |a_b| (side 0, before the 1/2pi scaling) and |h_b| (side 1) per
+// term; grid (kTmaxBlocks, 2), one atomic max per term per workgroup
+__global__ __launch_bounds__(256) void term_absmax_kernel(const float* __restrict__ t, const float* __restrict__ kcoef,
+                                                          int64_t K, const float* __restrict__ b0,
+                                                          const float* __restrict__ fields, int64_t L, int P,
+                                                          unsigned* __restrict__ tmax) {
+  const int side = blockIdx.y;
+  const int64_t n = side == 0 ? K : L;
+  const float* c0 = side == 0 ? t : b0;
+  float mx[kMaxTerms];
+#pragma unroll
+  for (int b = 0; b < kMaxTerms; ++b) mx[b] = 0.f;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+    mx[0] = fmaxf(mx[0], fabsf(c0[i]));
+#pragma unroll
+    for (int b = 1; b < kMaxTerms; ++b)
+      if (b <= P) {
+        const float v = side == 0 ? kcoef[i * P + (b - 1)] : fields[(int64_t)(b - 1) * L + i];
+        mx[b] = fmaxf(mx[b], fabsf(v));
+      }
   }
-  *b = k - small;
-  return *b < T ? 1 : 0;
+  __shared__ float red[kWaves][kMaxTerms];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int b = 0; b < kMaxTerms; ++b) {
+    float v = mx[b];
+    for (int off = 32; off > 0; off >>= 1) v = fmaxf(v, __shfl_xor(v, off));
+    if (lane == 0) red[wave][b] = v;
+  }
+  __syncthreads();
+  if ((int)threadIdx.x <= P) {
+    float v = red[0][threadIdx.x];
+    for (int w = 1; w < kWaves; ++w) v = fmaxf(v, red[w][threadIdx.x]);
+    if (v > 0.f) atomicMax(&tmax[side * kMaxTerms + threadIdx.x], __float_as_uint(v));
+  }
 }
 
 // side 0: samples (t, kcoef, K items); side 1: voxels (b0, fields, L items)
 __global__ void pack_phase_kernel(const float* __restrict__ c0, const float* __restrict__ cb, int64_t n_items,
-                                  int P, int side, int role, int NQ, b8_t* __restrict__ out, int64_t total) {
+                                  int P, int side, int role, int NQ, const unsigned* __restrict__ tmax,
+                                  h8* __restrict__ out, int64_t total) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
   const int lane = (int)(i & 63);
@@ -91,21 +121,25 @@ __global__ void pack_phase_kernel(const float* __restrict__ c0, const float* __r
   const int64_t item = chunk * kChunk + (lane & 15);
   const int g = lane >> 4;
   const int T = P + 1;
-  b8_t v;
+  h8 v;
 #pragma unroll
   for (int e = 0; e < 8; ++e) {
-    int b = 0;
-    const int part = phase_slot(32 * q + 8 * g + e, T, NQ, role, &b);
+    const int k = 32 * q + 8 * g + e;
+    const int pair = k / T, b = k - pair * T;
     float x = 0.f;
-    if (part && item < n_items) {
+    if (pair < 3 && item < n_items) {
+      // part of this side in product `pair`: (1,2), (2,1), (1,1)
+      const int part = pair == 2 ? 1 : ((pair == 0) == (role == 0) ? 1 : 2);
+      const int sh = term_shift(tmax, b);
       double c;
       if (side == 0)
-        c = (b == 0 ? (double)c0[item] : (double)cb[item * P + (b - 1)]) * kInv2Pi;
+        c = ldexp((b == 0 ? (double)c0[item] : (double)cb[item * P + (b - 1)]) * kInv2Pi, -sh);
       else
-        c = b == 0 ? (double)c0[item] : (double)cb[(int64_t)(b - 1) * n_items + item];
-      x = bf16_part(c, part);
+        c = ldexp(b == 0 ? (double)c0[item] : (double)cb[(int64_t)(b - 1) * n_items + item], sh);
+      const float x1 = (float)(_Float16)(float)c;
+      x = part == 1 ? x1 : (float)(_Float16)(float)(c - (double)x1);
     }
-    v[e] = (__bf16)x;
+    v[e] = (_Float16)x;
   }
   out[i] = v;
 }
@@ -255,11 +289,15 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
 // filled by direct global-to-LDS loads one chunk ahead of its use.
 //
 // Per (held tile, streamed chunk):
-//   1. phase tile on the bf16 matrix cores: NQ x v_mfma_f32_16x16x32_bf16
+//   1. phase tile on the f16 matrix cores: NQ x v_mfma_f32_16x16x32_f16
 //      with A = streamed phase parts, B = held phase parts (see the packing
 //      above).  Lane (g, j) ends up with phi for streamed items 4g + r
 //      (r = 0..3) and held item j, in revolutions;
-//   2. v_fract + v_sin/v_cos (hardware, argument in revolutions);
+//   2. v_sin/v_cos (hardware, argument in revolutions), taken on the phase
+//      directly while the bound sum_b max|a_b| max|h_b| (from the term
+//      maxima, evaluated once per wave) stays below kRawPhaseBound, else
+//      after v_fract; the hardware reduces an in-range argument itself, at
+//      least as accurately as v_fract does;
 //   3. these (cos, sin) pairs are exactly the A fragment of the complex
 //      contraction (row = held item j, k-slots = streamed items 4g..4g+3 x
 //      {cos, sin}), so they go to the matrix cores without any data movement:
@@ -314,7 +352,9 @@ __device__ __forceinline__ void stage_chunk(const u4* __restrict__ strmcoef, con
 
 // One (streamed chunk) x (MT held tiles) step: phase tile, sin/cos, complex
 // contraction into acc (see the kernel comment).
-template <int PREC, int NB, int NQ, int MT>
+// FRACT: reduce the phase with v_fract before the hardware sine/cosine
+// (needed only when the phase may leave the +-256 revolution input range).
+template <int PREC, int NB, int NQ, int MT, bool FRACT>
 __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, const u4 (&hc)[MT][NQ],
                                            f4 (&acc)[MT][NB]) {
 #pragma unroll
@@ -322,12 +362,12 @@ __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, cons
     f4 ph = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
     for (int q = 0; q < NQ; ++q)
-      ph = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, cur.ph[q]), __builtin_bit_cast(b8, hc[mt][q]),
-                                                   ph, 0, 0, 0);
+      ph = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, cur.ph[q]), __builtin_bit_cast(h8, hc[mt][q]),
+                                                  ph, 0, 0, 0);
     float cs[4], sn[4];
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-      const float x = __builtin_amdgcn_fractf(ph[r]);
+      const float x = FRACT ? __builtin_amdgcn_fractf(ph[r]) : ph[r];
       sn[r] = __builtin_amdgcn_sinf(x);
       cs[r] = __builtin_amdgcn_cosf(x);
     }
@@ -371,11 +411,31 @@ __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, cons
   }
 }
 
+// Walk streamed chunks [c0, c1) through the double-buffered LDS stage: the
+// loads for chunk ch + 1 are issued right after the barrier that publishes
+// chunk ch and overlap its compute.
+template <int PREC, int NQ, int NB, int MT, bool FRACT>
+__device__ __forceinline__ void stream_range(const u4* __restrict__ strmcoef, const u4* __restrict__ sd, int64_t c0,
+                                             int64_t c1, const u4 (&hc)[MT][NQ], f4 (&acc)[MT][NB], u4* stage0,
+                                             u4* stage1, int wave, int lane) {
+  if (c0 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, c0, stage0, wave, lane);
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk ch have landed
+    __syncthreads();                 // ... and every wave's; the other buffer is free
+    if (ch + 1 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, ch + 1, buf ? stage0 : stage1, wave, lane);
+    Stream<PREC, NB, NQ> cur;
+    cur.read(buf ? stage1 : stage0, lane);
+    chunk_step<PREC, NB, NQ, MT, FRACT>(cur, hc, acc);
+    buf ^= 1;
+  }
+}
+
 template <int OP, int PREC, int NQ, int NB, int MT>
 __global__ __launch_bounds__(256) void encode_kernel(
     const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef, const void* __restrict__ sdata, int64_t HC,
     int64_t SC, int64_t cps, float* __restrict__ out_part, const float2* __restrict__ sens, int64_t L, int G,
-    const int* stop) {
+    const unsigned* __restrict__ tmax, int T, const int* stop) {
   if (stop && *stop) return;
   const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
   int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
@@ -387,6 +447,12 @@ __global__ __launch_bounds__(256) void encode_kernel(
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t tile0 = (bx * kWaves + wave) * MT;
+
+  // bound on |phi| in revolutions: sum over terms of max|a_b| max|h_b|
+  float bound = 0.f;
+  if (lane < T) bound = __uint_as_float(tmax[lane]) * (float)kInv2Pi * __uint_as_float(tmax[kMaxTerms + lane]);
+  for (int off = 32; off > 0; off >>= 1) bound += __shfl_xor(bound, off);
+  const bool raw = bound < kRawPhaseBound;  // also false for NaN
 
   u4 hc[MT][NQ];
 #pragma unroll
@@ -406,23 +472,15 @@ __global__ __launch_bounds__(256) void encode_kernel(
     for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
 
   // Streamed chunks are staged through LDS, double-buffered and shared by
-  // the 4 waves: the loads for chunk ch + 1 are issued right after the
-  // barrier that publishes chunk ch, and overlap the compute of chunk ch.
+  // the 4 waves.
   __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
   const int64_t c0 = split * cps;
   const int64_t c1 = (c0 + cps < SC) ? c0 + cps : SC;
   const u4* sd = (const u4*)sdata;
-  if (c0 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, c0, stage[0], wave, lane);
-  int buf = 0;
-  for (int64_t ch = c0; ch < c1; ++ch) {
-    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk ch have landed
-    __syncthreads();                 // ... and every wave's; buffer buf ^ 1 is free
-    if (ch + 1 < c1) stage_chunk<PREC, NB, NQ>(strmcoef, sd, ch + 1, stage[buf ^ 1], wave, lane);
-    Stream<PREC, NB, NQ> cur;
-    cur.read(stage[buf], lane);
-    chunk_step<PREC, NB, NQ, MT>(cur, hc, acc);
-    buf ^= 1;
-  }
+  if (raw)
+    stream_range<PREC, NQ, NB, MT, false>(strmcoef, sd, c0, c1, hc, acc, stage[0], stage[1], wave, lane);
+  else
+    stream_range<PREC, NQ, NB, MT, true>(strmcoef, sd, c0, c1, hc, acc, stage[0], stage[1], wave, lane);
 
   const int g = lane >> 4, n = lane & 15;
   if (OP == OP_E) {
@@ -588,12 +646,20 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
 // launchers
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(n, bs)); }
 
+hipError_t launch_term_absmax(const float* t, const float* kcoef, int64_t K, const float* b0, const float* fields,
+                              int64_t L, int P, unsigned* tmax, hipStream_t s) {
+  hipError_t e = launch_fill_zero((float*)tmax, 2 * kMaxTerms, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(term_absmax_kernel, dim3(kTmaxBlocks, 2), dim3(256), 0, s, t, kcoef, K, b0, fields, L, P, tmax);
+  return hipGetLastError();
+}
+
 hipError_t launch_pack_phase(const float* c0, const float* cb, int64_t n_items, int P, int side, int role, int NQ,
-                             void* out, hipStream_t s) {
+                             const unsigned* tmax, void* out, hipStream_t s) {
   const int64_t total = cdiv(n_items, kChunk) * NQ * 64;
   if (total == 0) return hipSuccess;
-  hipLaunchKernelGGL(pack_phase_kernel, grid1(total), dim3(256), 0, s, c0, cb, n_items, P, side, role, NQ,
-                     (b8_t*)out, total);
+  hipLaunchKernelGGL(pack_phase_kernel, grid1(total), dim3(256), 0, s, c0, cb, n_items, P, side, role, NQ, tmax,
+                     (h8*)out, total);
   return hipGetLastError();
 }
 
@@ -636,50 +702,54 @@ hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* m
 template <int OP, int PREC, int NQ, int NB, int MT>
 static hipError_t launch_encode_t(const EncodeShape& sh, const void* heldcoef, const void* strmcoef,
                                   const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
-                                  const int* stop, hipStream_t s) {
+                                  const unsigned* tmax, int T, const int* stop, hipStream_t s) {
   const dim3 gr((unsigned)cdiv(sh.HC, (int64_t)kWaves * MT), (unsigned)sh.nsplit);
   hipLaunchKernelGGL((encode_kernel<OP, PREC, NQ, NB, MT>), gr, dim3(64 * kWaves), 0, s, (const u4*)heldcoef,
-                     (const u4*)strmcoef, sdata, sh.HC, sh.SC, sh.cps, out_part, sens, L, G, stop);
+                     (const u4*)strmcoef, sdata, sh.HC, sh.SC, sh.cps, out_part, sens, L, G, tmax, T, stop);
   return hipGetLastError();
 }
 
+#define NFS_ENC_ARGS sh, hc, scf, sd, op, sens, L, G, tmax, T, stop, s
 template <int OP, int PREC, int NQ>
 static hipError_t launch_encode_nb(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
-                                   const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+                                   const float2* sens, int64_t L, int G, const unsigned* tmax, int T, const int* stop,
+                                   hipStream_t s) {
   switch (sh.NB) {
-    case 1: return launch_encode_t<OP, PREC, NQ, 1, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 2: return launch_encode_t<OP, PREC, NQ, 2, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 4: return launch_encode_t<OP, PREC, NQ, 4, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 8: return launch_encode_t<OP, PREC, NQ, 8, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 1: return launch_encode_t<OP, PREC, NQ, 1, 4>(NFS_ENC_ARGS);
+    case 2: return launch_encode_t<OP, PREC, NQ, 2, 4>(NFS_ENC_ARGS);
+    case 4: return launch_encode_t<OP, PREC, NQ, 4, 2>(NFS_ENC_ARGS);
+    case 8: return launch_encode_t<OP, PREC, NQ, 8, 2>(NFS_ENC_ARGS);
   }
   return hipErrorInvalidValue;
 }
 
 template <int OP, int PREC>
 static hipError_t launch_encode_nq(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
-                                   const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+                                   const float2* sens, int64_t L, int G, const unsigned* tmax, int T, const int* stop,
+                                   hipStream_t s) {
   switch (sh.NQ) {
-    case 2: return launch_encode_nb<OP, PREC, 2>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 3: return launch_encode_nb<OP, PREC, 3>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 4: return launch_encode_nb<OP, PREC, 4>(sh, hc, scf, sd, op, sens, L, G, stop, s);
-    case 6: return launch_encode_nb<OP, PREC, 6>(sh, hc, scf, sd, op, sens, L, G, stop, s);
+    case 1: return launch_encode_nb<OP, PREC, 1>(NFS_ENC_ARGS);
+    case 2: return launch_encode_nb<OP, PREC, 2>(NFS_ENC_ARGS);
+    case 3: return launch_encode_nb<OP, PREC, 3>(NFS_ENC_ARGS);
   }
   return hipErrorInvalidValue;
 }
 
-hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void* strmcoef, const void* sdata,
-                         float* out_part, const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+hipError_t launch_encode(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
+                         const float2* sens, int64_t L, int G, const unsigned* tmax, int T, const int* stop,
+                         hipStream_t s) {
   if (sh.HC == 0) return hipSuccess;
-  if (sh.MT != 2) return hipErrorInvalidValue;
+  if (sh.MT != held_tiles(sh.NB) || T < 1 || T > kMaxTerms) return hipErrorInvalidValue;
   if (sh.op == OP_E) {
-    if (sh.prec == PREC_FP32) return launch_encode_nq<OP_E, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-    if (sh.prec == PREC_BF16) return launch_encode_nq<OP_E, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-    return launch_encode_nq<OP_E, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+    if (sh.prec == PREC_FP32) return launch_encode_nq<OP_E, PREC_FP32>(NFS_ENC_ARGS);
+    if (sh.prec == PREC_BF16) return launch_encode_nq<OP_E, PREC_BF16>(NFS_ENC_ARGS);
+    return launch_encode_nq<OP_E, PREC_FP16>(NFS_ENC_ARGS);
   }
-  if (sh.prec == PREC_FP32) return launch_encode_nq<OP_EH, PREC_FP32>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-  if (sh.prec == PREC_BF16) return launch_encode_nq<OP_EH, PREC_BF16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
-  return launch_encode_nq<OP_EH, PREC_FP16>(sh, heldcoef, strmcoef, sdata, out_part, sens, L, G, stop, s);
+  if (sh.prec == PREC_FP32) return launch_encode_nq<OP_EH, PREC_FP32>(NFS_ENC_ARGS);
+  if (sh.prec == PREC_BF16) return launch_encode_nq<OP_EH, PREC_BF16>(NFS_ENC_ARGS);
+  return launch_encode_nq<OP_EH, PREC_FP16>(NFS_ENC_ARGS);
 }
+#undef NFS_ENC_ARGS
 
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s) {

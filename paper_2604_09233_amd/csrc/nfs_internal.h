@@ -6,11 +6,12 @@
 //  * items are grouped in chunks (tiles) of 16; a wave owns MT held tiles and
 //    walks a contiguous range of streamed chunks;
 //  * for each (held tile, streamed chunk) pair the wave builds the 16 x 16
-//    phase tile phi = K_blk R_blk on the bf16 matrix cores (coefficients
-//    split into three bf16 parts, NQ v_mfma 16x16x32 instructions), takes
-//    sin/cos of it in revolutions on the VALU and feeds (cos, sin) straight
-//    into the complex contraction on the matrix cores (16x16x32 f16/bf16, or
-//    16x16x4 f32), against the packed data operand of the streamed chunk;
+//    phase tile phi = K_blk R_blk on the f16 matrix cores (coefficients
+//    balanced per term and split into two f16 parts, NQ v_mfma 16x16x32
+//    instructions), takes sin/cos of it in revolutions on the VALU and feeds
+//    (cos, sin) straight into the complex contraction on the matrix cores
+//    (16x16x32 f16/bf16, or 16x16x4 f32), against the packed data operand of
+//    the streamed chunk;
 //  * the streamed range can be split over several workgroups ("splits");
 //    partial results are summed afterwards in a fixed order.
 #pragma once
@@ -26,17 +27,22 @@ constexpr int kChunk = 16;        // items per tile/chunk
 constexpr int kWaves = 4;         // waves per workgroup in the encode kernels
 constexpr int kCgBlocks = 256;    // max workgroups of the CG vector kernels
 constexpr int kBmaxBlocks = 256;  // workgroups of the max-magnitude kernels
+constexpr int kMaxTerms = 32;     // phase terms (t*b0 plus up to 31 field terms)
+constexpr int kTmaxBlocks = 64;   // workgroups per side of the term-maxima kernel
+// Largest phase bound (revolutions) for which the hardware sine and cosine
+// take the phase directly; above it the argument is first reduced with
+// v_fract.  The hardware range is +-256 revolutions; the margin covers the
+// rounding of the bound itself.
+constexpr float kRawPhaseBound = 128.f;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// phase MFMA instructions for P + 1 terms (t*b0 plus P field terms): the
-// five small split products need ceil(5 (P+1) / 32) instructions, the (1,1)
-// products one more; rounded up to 2, 3, 4 or 6
-inline int phase_instrs(int n_basis) {
-  const int T = n_basis + 1;
-  const int nq = (int)cdiv(5 * T, 32) + 1;
-  return nq <= 2 ? 2 : (nq <= 4 ? nq : 6);
-}
+// phase MFMA instructions for P + 1 terms (t*b0 plus P field terms): three
+// split products per term, 32 k-slots per instruction (1, 2 or 3)
+inline int phase_instrs(int n_basis) { return (int)cdiv(3 * (n_basis + 1), 32); }
+// held tiles per wave: 4 while the accumulators stay small (up to 16 coils),
+// else 2
+inline int held_tiles(int nb) { return nb <= 2 ? 4 : 2; }
 // bytes of one packed phase chunk (16 items): NQ instructions x 64 lanes x 16 B
 inline size_t phase_chunk_bytes(int nq) { return (size_t)nq * 64 * 16; }
 // 16-column blocks for 2G real columns (re/im per coil), rounded to 1, 2, 4, 8
@@ -64,10 +70,16 @@ struct EncodeShape {
 };
 
 // ---- launchers (encode_kernels.hip) ---------------------------------------
+// per-term largest magnitudes of the phase coefficients, as float bits:
+// tmax[b] = max_k |a_b(k)| (a_0 = t, a_{b+1} = kcoef[.][b], before the 1/2pi
+// scaling), tmax[kMaxTerms + b] = max_l |h_b(l)| (h_0 = b0, h_{b+1} =
+// fields[b]); clears tmax first
+hipError_t launch_term_absmax(const float* t, const float* kcoef, int64_t K, const float* b0, const float* fields,
+                              int64_t L, int P, unsigned* tmax, hipStream_t s);
 // side 0: samples (c0 = t, cb = kcoef [K][P]); side 1: voxels (c0 = b0, cb = fields [P][L]);
 // role 0: streamed side (MFMA operand A), role 1: held side (operand B)
 hipError_t launch_pack_phase(const float* c0, const float* cb, int64_t n_items, int P, int side, int role, int NQ,
-                             void* out, hipStream_t s);
+                             const unsigned* tmax, void* out, hipStream_t s);
 hipError_t launch_scale_sens(const float2* sens, const float* icorr, int G, int64_t L, float2* out,
                              hipStream_t s);
 // value(item, c) = src[item*is + c*cs] * (mul ? mul[c*n_items + item] : 1) * (wgt ? wgt[item] : 1)
@@ -76,9 +88,10 @@ hipError_t launch_absmax(const float2* src, const float2* mul, const float* wgt,
 hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* mul, const float* wgt,
                             int64_t n_items, int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* out,
                             const float* bmax, float* unscale, const int* stop, hipStream_t s);
+// tmax/T: the term maxima above and the term count P + 1 (phase range check)
 hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void* strmcoef,
                          const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
-                         const int* stop, hipStream_t s);
+                         const unsigned* tmax, int T, const int* stop, hipStream_t s);
 // sum E partials -> m[G][K] (coil-major) times *unscale
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s);
