@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
+    ap.add_argument("--graphs", action="store_true",
+                    help="replay each solve from a captured hipGraph (the encode-kernel timing pass runs eagerly)")
     ap.add_argument("--trans-rate", type=float, default=0.25,
                     help="v_sin/v_cos issue rate as a fraction of the FP32 lane rate (for the ALU peak)")
     return ap.parse_args()
@@ -138,7 +140,14 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"profile_run": "done"}))
         return
-    rho, hist, info, ms, wall, kt = time_solves(args.precision, args.steps, args.warmup, profile=True)
+    if args.graphs:
+        nfs.set_graphs(0, True)
+        rho, hist, info, ms, wall, _ = time_solves(args.precision, args.steps, args.warmup)
+        nfs.set_graphs(0, False)
+        # kernel timing (HIP events around every encode launch) on eager solves
+        _, _, _, _, _, kt = time_solves(args.precision, max(1, args.steps // 2), 0, profile=True)
+    else:
+        rho, hist, info, ms, wall, kt = time_solves(args.precision, args.steps, args.warmup, profile=True)
     vsc = L * K * G
     value = (n_iter + 0.5) * vsc / (ms * 1e-3)
 
@@ -189,14 +198,28 @@ def main():
     # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
     trans_peak = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 * args.trans_rate  # ops/s
     achieved = 2 * pairs / (avg_ms * 1e-3)
-    # matrix-pipe time of the algorithmic contractions: the (P+1)-term phase
-    # product on the FP32 matrix cores and the 8G-flop complex contraction at
-    # the operand precision, as a fraction of the measured launch time
+    # matrix-pipe time of the MFMA instructions the kernel issues, at the
+    # published dense peaks, as a fraction of the measured launch time: per
+    # 16 x 16 tile (256 pairs) ceil(3 (P+1) / 32) f16 16x16x32 phase
+    # instructions, and per 16-column block of the 2G real columns one f16
+    # 16x16x32 (fp16), two bf16 16x16x32 (bf16: hi and lo data parts) or
+    # eight f32 16x16x4 (fp32) contraction instructions
     P = d["n_basis"]
-    t_mfma = pairs * (2 * (P + 1) / (MFMA_PEAK_TFLOPS["fp32"] * 1e12)
-                      + 8 * G / (MFMA_PEAK_TFLOPS[args.precision] * 1e12))
+    nq = -(-3 * (P + 1) // 32)
+    nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
+    tiles = pairs / 256.0
+    flops_phase = tiles * nq * 16384
+    flops_con = tiles * nb * {"fp16": 16384, "bf16": 2 * 16384, "fp32": 8 * 2048}[args.precision]
+    t_mfma = flops_phase / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) + flops_con / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
+    # HBM bytes per launch from the committed counter summary (FETCH_SIZE +
+    # WRITE_SIZE, copy-calibrated), only while the kernel sources match the
+    # ones the counters were taken on
+    from paper_2604_09233_amd.profile_summary import read_traffic
+    tr = read_traffic(os.path.join(ROOT, "profiles", f"encode_kernel_{args.config}_{args.precision}_counters.md"))
+    traffic = tr.get(kname) if tr else None
     roofline = dict(bound="alu", achieved=achieved / 1e12, peak=trans_peak / 1e12, unit="Tsincos-ops/s",
-                    frac=achieved / trans_peak, traffic=None, kernel=f"encode_kernel ({kname})",
+                    frac=achieved / trans_peak, traffic=traffic, traffic_unit="bytes per launch",
+                    kernel=f"encode_kernel ({kname})",
                     avg_launch_ms=avg_ms, launches=n_k,
                     mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
 
@@ -217,7 +240,7 @@ def main():
         "config": {"workload": f"{args.config}: 2D 128x128, 16 coils, 4x15000-sample R=4 spiral, 16 field terms, "
                                f"B0 +-100 Hz, {n_iter} CG iterations (one step = one CG solve)",
                    "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision,
-                   "cg": "plain" if args.plain else "re-orthogonalised"},
+                   "cg": "plain" if args.plain else "re-orthogonalised", "hip_graphs": bool(args.graphs)},
         "rel_err_vs_oracle": err,
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},

@@ -172,7 +172,7 @@ struct Layout {
   int64_t L, K, LC, KC;
   int G, P, NQ, NB, prec;
   EncodeShape shE, shH;
-  size_t o_sA, o_sB, o_vA, o_vB, o_tmax, o_dataE, o_dataH, o_epart, o_ybuf, o_hpart, o_bmax, o_unscale, o_sensj;
+  size_t o_sA, o_sB, o_vA, o_vB, o_tmax, o_dataE, o_dataH, o_epart, o_hpart, o_bmax, o_unscale, o_sensj, o_smax;
   size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_coef;
   size_t total;
 };
@@ -226,11 +226,11 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.o_unscale = take(2 * 4);
   y.o_dataE = needE ? take((size_t)y.LC * y.NB * data_chunk_bytes(prec)) : 0;
   y.o_epart = needE ? take((size_t)y.shE.nsplit * y.KC * 16 * y.NB * 16 * 4) : 0;
-  y.o_ybuf = (needE && needH) ? take((size_t)y.KC * 16 * y.NB * 16 * 4) : 0;
   y.o_dataH = needH ? take((size_t)y.KC * y.NB * data_chunk_bytes(prec)) : 0;
   y.o_hpart = needH ? take((size_t)y.shH.nsplit * y.LC * 16 * 8) : 0;
   if (cg) {
     y.o_sensj = pr->icorr ? take((size_t)y.G * y.L * 8) : 0;
+    y.o_smax = scaled_prec(prec) ? take((size_t)y.L * 4) : 0;
     y.o_r = take((size_t)y.L * 8);
     y.o_p = take((size_t)y.L * 8);
     y.o_q = take((size_t)y.L * 8);
@@ -336,14 +336,15 @@ static int seq_pack_coefs(const Ctx& c, bool forE, bool forH) {
 }
 
 static float* unscale_slot(const Ctx& c, int which) {
-  return c.y.prec == PREC_FP16 ? at<float>(c.ws, c.y.o_unscale) + which : nullptr;
+  return scaled_prec(c.y.prec) ? at<float>(c.ws, c.y.o_unscale) + which : nullptr;
 }
 
-// E part: rho -> epart (partials) via packed Q = S o rho (o wgt)
-static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr) {
+// E part: rho -> epart (partials) via packed Q = S o rho (o wgt);
+// bmax_ready: the FP16 scale bound of Q is already in bmax
+static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr, bool bmax_ready = false) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
-  if (y.prec == PREC_FP16) NFS_TRY(launch_absmax(rho, c.sens, wgt, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
+  if (scaled_prec(y.prec) && !bmax_ready) NFS_TRY(launch_absmax(rho, c.sens, wgt, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
   NFS_TRY(launch_pack_data(OP_E, y.prec, rho, c.sens, wgt, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(c.ws, y.o_dataE),
                            bmax, at<float>(c.ws, y.o_unscale), c.stop, c.s),
           "pack_data(E)");
@@ -354,13 +355,11 @@ static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr) {
   });
 }
 
-// E^H part: src (m [G][K] or ybuf) (o wgt) -> hpart (coil-combined partials);
-// max_ready: the FP16 block maxima of src are already in bmax
-static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr,
-                  bool max_ready = false) {
+// E^H part: src (m [G][K]) (o wgt) -> hpart (coil-combined partials)
+static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
-  if (y.prec == PREC_FP16 && !max_ready)
+  if (scaled_prec(y.prec))
     NFS_TRY(launch_absmax(src, nullptr, wgt, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
   NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, wgt, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
                            bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
@@ -372,17 +371,20 @@ static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const
   });
 }
 
-// E^H E: p -> hpart
-static int seq_EHE(const Ctx& c, const float2* p) {
+// E^H E: p -> hpart; the E^H operand is packed straight from the E partials
+static int seq_EHE(const Ctx& c, const float2* p, bool bmax_ready = false) {
   const Layout& y = c.y;
-  int rc = seq_E(c, p);
+  int rc = seq_E(c, p, nullptr, bmax_ready);
   if (rc) return rc;
-  float* ybuf = at<float>(c.ws, y.o_ybuf);
-  const bool fp16 = y.prec == PREC_FP16;
-  NFS_TRY(launch_finish_E_to_ybuf(at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G,
-                                  unscale_slot(c, 0), ybuf, fp16 ? at<float>(c.ws, y.o_bmax) : nullptr, c.stop, c.s),
-          "finish_E_to_ybuf");
-  return seq_EH(c, reinterpret_cast<const float2*>(ybuf), (int64_t)y.NB * 8, 1, nullptr, fp16);
+  float* us = at<float>(c.ws, y.o_unscale);
+  NFS_TRY(launch_pack_EH_from_epart(y.prec, at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L,
+                                    us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
+          "pack_EH_from_epart");
+  return timed_encode(c, 1, [&] {
+    return launch_encode(y.shH, at<void>(c.ws, y.o_vB), at<void>(c.ws, y.o_sA), at<void>(c.ws, y.o_dataH),
+                         at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
+                         c.s);
+  });
 }
 
 extern "C" int nfs_apply_E(nfs_ctx* ctx, const nfs_problem* prob, const float* rho, float* m, int precision,
@@ -485,6 +487,9 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
   st.V = reorth ? at<float2>(ws, y.o_V) : nullptr;
   st.rpart = reorth ? at<double>(ws, y.o_rpart) : nullptr;
   st.coef = reorth ? at<double>(ws, y.o_coef) : nullptr;
+  const bool f16ops = scaled_prec(y.prec);  // f16 operand fragments, power-of-two scaled
+  st.smax = f16ops ? at<float>(ws, y.o_smax) : nullptr;
+  st.bmax = f16ops ? at<float>(ws, y.o_bmax) : nullptr;
   st.L = y.L;
   int64_t nb = cdiv(y.L, 256);
   st.nblk = (int)(nb < 1 ? 1 : (nb > kCgBlocks ? kCgBlocks : nb));
@@ -495,6 +500,7 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
     NFS_TRY(launch_scale_sens(sens, prob->icorr, y.G, y.L, sj, s), "scale_sens");
     sens = sj;
   }
+  if (f16ops) NFS_TRY(launch_sens_absmax(sens, y.G, y.L, at<float>(ws, y.o_smax), s), "sens_absmax");
   Ctx c{ctx, y, prob, sens, ws, s, st.stop};
   float2* x = reinterpret_cast<float2*>(rho);
   const float2* hpart = at<float2>(ws, y.o_hpart);
@@ -509,7 +515,7 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
   NFS_TRY(launch_cg_start(st, n_iter, s), "cg_start");
   if (reorth) NFS_TRY(launch_cg_store_v(st, 0, s), "cg_store_v");
   for (int n = 0; n < n_iter; ++n) {
-    if ((rc = seq_EHE(c, st.p))) return rc;
+    if ((rc = seq_EHE(c, st.p, f16ops))) return rc;
     NFS_TRY(launch_cg_beta(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_beta");
     NFS_TRY(launch_cg_update(st, x, y.L, n, s), "cg_update");
     if (replace_every > 0 && (n + 1) % replace_every == 0 && n + 1 < n_iter) {

@@ -36,6 +36,24 @@ __device__ double sum_partials(const double* part, int nblk, double* red) {
   return block_sum((int)threadIdx.x < nblk ? part[threadIdx.x] : 0.0, red);
 }
 
+// Bound on the FP16 E operand entries S[c][l] p[l] of the new direction:
+// workgroup maximum of smax[l] |p[l]| (smax[l] = max_c |S[c][l]|) into
+// bmax[blockIdx.x], the entries past the CG grid cleared by workgroup 0, so
+// that the E operand packing (which reads all kBmaxBlocks entries) needs no
+// pass of its own.  The bound is at most sqrt(2) above the largest |re| or
+// |im|, which only moves the power-of-two scale.
+__device__ void direction_bound(const CgState& st, float mx, float* redf) {
+  redf[threadIdx.x] = mx;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) redf[threadIdx.x] = fmaxf(redf[threadIdx.x], redf[threadIdx.x + w]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) st.bmax[blockIdx.x] = redf[0];
+  if (blockIdx.x == 0)
+    for (int i = st.nblk + threadIdx.x; i < kBmaxBlocks; i += 256) st.bmax[i] = 0.f;
+}
+
 __device__ __forceinline__ float2 sum_splits(const float2* hpart, int nsplit, int64_t stride, int64_t l, float u) {
   float re = 0.f, im = 0.f;
   for (int s = 0; s < nsplit; ++s) {
@@ -44,6 +62,18 @@ __device__ __forceinline__ float2 sum_splits(const float2* hpart, int nsplit, in
     im += v.y;
   }
   return make_float2(re * u, im * u);
+}
+
+// smax[l] = max_c |S[c][l]|
+__global__ void sens_absmax_kernel(const float2* __restrict__ sens, int G, int64_t L, float* __restrict__ smax) {
+  const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (l >= L) return;
+  float m = 0.f;
+  for (int c = 0; c < G; ++c) {
+    const float2 v = sens[(int64_t)c * L + l];
+    m = fmaxf(m, sqrtf(v.x * v.x + v.y * v.y));
+  }
+  smax[l] = m;
 }
 
 __global__ void cg_reset_kernel(int* stop, int* info) {
@@ -69,8 +99,10 @@ __global__ __launch_bounds__(256) void cg_init_kernel(CgState st, const float2* 
                                                       int64_t stride, const float* __restrict__ unscale,
                                                       float2* __restrict__ rho, int64_t L) {
   __shared__ double red[256];
+  __shared__ float redf[256];
   const float u = unscale ? *unscale : 1.f;
   double a = 0.0;
+  float mx = 0.f;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
     const float2 v = sum_splits(hpart, nsplit, stride, l, u);
     st.b[l] = v;
@@ -78,9 +110,11 @@ __global__ __launch_bounds__(256) void cg_init_kernel(CgState st, const float2* 
     st.p[l] = v;
     rho[l] = make_float2(0.f, 0.f);
     a += (double)v.x * v.x + (double)v.y * v.y;
+    if (st.smax) mx = fmaxf(mx, st.smax[l] * sqrtf(v.x * v.x + v.y * v.y));
   }
   a = block_sum(a, red);
   if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+  if (st.smax) direction_bound(st, mx, redf);
 }
 
 // alpha_0, ||m||^2, hist row 0, early exit when E^H m == 0
@@ -194,6 +228,7 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L
   const bool store = st.V && anew > 0.0 && isfinite(anew);
   const float inv = store ? (float)(1.0 / sqrt(anew)) : 0.f;
   float2* v = store ? st.V + (size_t)(n + 1) * L : nullptr;
+  float mx = 0.f;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
     const float2 r = st.r[l];
     float2 p = st.p[l];
@@ -201,6 +236,11 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L
     p.y = fmaf(bf, p.y, r.y);
     st.p[l] = p;
     if (store) v[l] = make_float2(r.x * inv, r.y * inv);
+    if (st.smax) mx = fmaxf(mx, st.smax[l] * sqrtf(p.x * p.x + p.y * p.y));
+  }
+  if (st.smax) {
+    __shared__ float redf[256];
+    direction_bound(st, mx, redf);
   }
   if (blockIdx.x != 0) return;
   const double xx = sum_partials(st.part + 2 * kCgBlocks, st.nblk, red);
@@ -316,6 +356,12 @@ hipError_t launch_cg_norm_m(const CgState& st, const float2* m, int64_t n, hipSt
 hipError_t launch_cg_init(const CgState& st, const float2* hpart, int nsplit, int64_t stride, const float* unscale,
                           float2* rho, int64_t L, hipStream_t s) {
   hipLaunchKernelGGL(cg_init_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, rho, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_sens_absmax(const float2* sens, int G, int64_t L, float* smax, hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(sens_absmax_kernel, dim3((unsigned)cdiv(L, 256)), dim3(256), 0, s, sens, G, L, smax);
   return hipGetLastError();
 }
 

@@ -181,6 +181,37 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
   if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
 }
 
+// One lane's 8 fragment values of (chunk ch, column block nb) in the layout
+// of precision PREC (see below).
+template <int PREC>
+__device__ __forceinline__ void store_fragment(const float (&vals)[8], void* __restrict__ out, int64_t ch, int nb,
+                                               int NB, int lane) {
+  if (PREC == PREC_FP32) {
+    h8 hi, lo;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hi[u] = (_Float16)vals[u];
+      lo[u] = (_Float16)(vals[u] - (float)hi[u]);
+    }
+    ((h8*)out)[((ch * NB + nb) * 2 + 0) * 64 + lane] = hi;
+    ((h8*)out)[((ch * NB + nb) * 2 + 1) * 64 + lane] = lo;
+  } else if (PREC == PREC_FP16) {
+    h8 h;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) h[u] = (_Float16)vals[u];
+    ((h8*)out)[(ch * NB + nb) * 64 + lane] = h;
+  } else {
+    b8 hi, lo;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      hi[u] = (__bf16)vals[u];
+      lo[u] = (__bf16)(vals[u] - (float)hi[u]);
+    }
+    ((b8*)out)[((ch * NB + nb) * 2 + 0) * 64 + lane] = hi;
+    ((b8*)out)[((ch * NB + nb) * 2 + 1) * 64 + lane] = lo;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Data operand in MFMA fragment order (B side of the complex contraction).
 // For chunk ch, column block nb and lane (g = lane / 16, n = lane % 16) the
@@ -192,9 +223,9 @@ __global__ __launch_bounds__(256) void absmax_kernel(const float2* __restrict__ 
 //         [((ch*NB + nb)*2 + part)*64 + lane]; the kernel runs one MFMA per
 //         part into the same accumulator, so the data operand carries ~16
 //         significant bits and only the (cos, sin) operand is 8-bit
-//   fp32: slots 0-3 and 4-7 as two 16-byte vectors:
-//         [((ch*NB + nb)*2 + u/4)*64 + lane][u % 4]
-// FP16: the values are scaled by a power of two so that the largest
+//   fp32: two f16 fragments, v_hi = f16(v) and v_lo = f16(v - v_hi):
+//         [((ch*NB + nb)*2 + part)*64 + lane]; v = v_hi + v_lo + O(2^-22 v)
+// FP16 and FP32: the values are scaled by a power of two so that the largest
 // magnitude lands just below 2^14; 1/scale is stored in *unscale.
 // An optional real per-item weight wgt multiplies every value (used by the
 // backward pass: t o G for the B0 gradient, h_b o rho for the field terms).
@@ -205,7 +236,7 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
     float* __restrict__ unscale, const int* stop) {
   if (stop && *stop) return;
   float scale = 1.f;
-  if (PREC == PREC_FP16) {
+  if (PREC != PREC_BF16) {
     __shared__ float red[kBmaxBlocks];
     red[threadIdx.x] = bmax[threadIdx.x];
     __syncthreads();
@@ -255,25 +286,55 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
     vals[2 * j] = cosrow;
     vals[2 * j + 1] = sinrow;
   }
-  if (PREC == PREC_FP32) {
-    float4* o = (float4*)out;
-    o[((ch * NB + nb) * 2 + 0) * 64 + lane] = make_float4(vals[0], vals[1], vals[2], vals[3]);
-    o[((ch * NB + nb) * 2 + 1) * 64 + lane] = make_float4(vals[4], vals[5], vals[6], vals[7]);
-  } else if (PREC == PREC_FP16) {
-    h8 h;
+  store_fragment<PREC>(vals, out, ch, nb, NB, lane);
+}
+
+// E^H data operand straight from the E partials (the E^H E chain): the
+// streamed items are the samples, with value(k, c) = sum over splits, in
+// split order, of epart[s][k][2c] + i epart[s][k][2c + 1], times `scale`.
+// FP16 and FP32: the E operand entries are below 2^14 in magnitude, so every real
+// column of the E output is below 2^15 L; the caller passes scale =
+// 2^-(ceil(log2 L) + 1), which keeps the packed values below 2^14 without a
+// pass over the E output, and *unscale_out = *unscale_in / scale.  (Values
+// far below the bound only leave float16's normal range 29 binades under
+// it.)
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __restrict__ epart, int nsplit,
+                                                                 int64_t HC16, int NB, int64_t K, int G, float scale,
+                                                                 const float* __restrict__ unscale_in,
+                                                                 float* __restrict__ unscale_out, int64_t nchunks,
+                                                                 void* __restrict__ out, const int* stop) {
+  if (stop && *stop) return;
+  if (PREC != PREC_BF16 && blockIdx.x == 0 && threadIdx.x == 0) *unscale_out = *unscale_in / scale;
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= nchunks * NB * 64) return;
+  const int lane = (int)(i & 63);
+  const int64_t q = i >> 6;
+  const int nb = (int)(q % NB);
+  const int64_t ch = q / NB;
+  const int g = lane >> 4, n = lane & 15;
+  const int N = nb * 16 + n;
+  const int c = N >> 1, reim = N & 1;
+  const int64_t ncol = (int64_t)NB * 16, pstride = HC16 * ncol;
+  float vals[8];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) h[u] = (_Float16)vals[u];
-    ((h8*)out)[(ch * NB + nb) * 64 + lane] = h;
-  } else {
-    b8 hi, lo;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      hi[u] = (__bf16)vals[u];
-      lo[u] = (__bf16)(vals[u] - (float)hi[u]);
+  for (int j = 0; j < 4; ++j) {
+    const int64_t item = ch * kChunk + g * 4 + j;
+    float2 v = make_float2(0.f, 0.f);
+    if (item < K && c < G) {
+      const float2* src = (const float2*)(epart + item * ncol + 2 * c);
+      for (int sp = 0; sp < nsplit; ++sp) {
+        const float2 w = src[sp * (pstride / 2)];
+        v.x += w.x;
+        v.y += w.y;
+      }
+      v.x *= scale;
+      v.y *= scale;
     }
-    ((b8*)out)[((ch * NB + nb) * 2 + 0) * 64 + lane] = hi;
-    ((b8*)out)[((ch * NB + nb) * 2 + 1) * 64 + lane] = lo;
+    vals[2 * j] = reim ? v.y : v.x;
+    vals[2 * j + 1] = reim ? -v.x : v.y;
   }
+  store_fragment<PREC>(vals, out, ch, nb, NB, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -302,8 +363,10 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
 //      contraction (row = held item j, k-slots = streamed items 4g..4g+3 x
 //      {cos, sin}), so they go to the matrix cores without any data movement:
 //      one v_mfma_f32_16x16x32_{f16,bf16} per column block (two for bf16: hi
-//      and lo data parts), or 8 v_mfma_f32_16x16x4_f32 per column block for
-//      FP32.
+//      and lo data parts); FP32 splits the (cos, sin) operand as well and
+//      takes the three products hi.lo, lo.hi, hi.hi of two-part f16
+//      operands (three v_mfma_f32_16x16x32_f16 per column block, about
+//      2^-21 relative per product, below the float32 phase's own error).
 // Accumulators: lane (g, n) holds rows (held items) 4g + r, column 16 nb + n.
 //
 // Epilogue.  E: the partial y rows go to out_part[split][HC*16][NB*16].
@@ -396,15 +459,26 @@ __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, cons
                                                               0, 0, 0);
       }
     } else {
+      // (cos, sin) split: hi keeps the leading 11 significant bits (exact in
+      // f16 for normal values), lo = x - hi is exact in float32 and rounded
+      // once to f16
+      h8 ahi, alo;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float ch = __uint_as_float(__float_as_uint(cs[r]) & 0xFFFFE000u);
+        const float sh = __uint_as_float(__float_as_uint(sn[r]) & 0xFFFFE000u);
+        ahi[2 * r] = (_Float16)ch;
+        ahi[2 * r + 1] = (_Float16)sh;
+        alo[2 * r] = (_Float16)(cs[r] - ch);
+        alo[2 * r + 1] = (_Float16)(sn[r] - sh);
+      }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
-        const f4 lo = __builtin_bit_cast(f4, cur.d[2 * nb]), hi = __builtin_bit_cast(f4, cur.d[2 * nb + 1]);
+        const h8 dhi = __builtin_bit_cast(h8, cur.d[2 * nb]), dlo = __builtin_bit_cast(h8, cur.d[2 * nb + 1]);
         f4 t = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int u = 0; u < 8; ++u) {
-          const float bv = u < 4 ? lo[u] : hi[u - 4];
-          t = __builtin_amdgcn_mfma_f32_16x16x4f32((u & 1) ? sn[u >> 1] : cs[u >> 1], bv, t, 0, 0, 0);
-        }
+        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo, dhi, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi, dlo, t, 0, 0, 0);
+        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi, dhi, t, 0, 0, 0);
         acc[mt][nb] += t;
       }
     }
@@ -462,7 +536,7 @@ __global__ __launch_bounds__(256) void encode_kernel(
     for (int q = 0; q < NQ; ++q) hc[mt][q] = tile < HC ? heldcoef[(tile * NQ + q) * 64 + lane] : u4{0, 0, 0, 0};
   }
   // Accumulation: the matrix cores add straight into acc for the half
-  // precisions (their operand rounding dominates); for FP32 the 8 MFMAs of a
+  // precisions (their operand rounding dominates); for FP32 the 3 MFMAs of a
   // chunk start from zero and their sum is added on the VALU, so the long
   // running sum is rounded once per chunk instead of once per MFMA.
   f4 acc[MT][NB];
@@ -550,39 +624,6 @@ __global__ void finish_E_to_m_kernel(const float* __restrict__ epart, int nsplit
   }
   const float u = unscale ? *unscale : 1.f;
   m[i] = make_float2(re * u, im * u);
-}
-
-// ybuf = (sum of split partials) * unscale over all padded rows; with bmax,
-// also the per-workgroup largest |re| / |im| over the valid rows (k < K) and
-// columns (< 2G), as absmax_kernel would give for ybuf (kBmaxBlocks
-// workgroups, every entry written).
-// (1024 threads per workgroup; ncol = 16 NB is a power of two, 2^lncol)
-__global__ __launch_bounds__(1024) void finish_E_to_ybuf_kernel(const float* __restrict__ epart, int nsplit, int64_t n,
-                                                                int lncol, int64_t K, int G,
-                                                                const float* __restrict__ unscale,
-                                                                float* __restrict__ ybuf, float* __restrict__ bmax,
-                                                                const int* stop) {
-  if (stop && *stop) return;
-  const float u = unscale ? *unscale : 1.f;
-  const int64_t cmask = ((int64_t)1 << lncol) - 1;
-  float mx = 0.f;
-  for (int64_t i = (int64_t)blockIdx.x * 1024 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 1024) {
-    float v = 0.f;
-    for (int s = 0; s < nsplit; ++s) v += epart[(size_t)s * n + i];
-    v *= u;
-    ybuf[i] = v;
-    if ((i >> lncol) < K && (i & cmask) < 2 * G) mx = fmaxf(mx, fabsf(v));
-  }
-  if (bmax) {
-    __shared__ float red[1024];
-    red[threadIdx.x] = mx;
-    __syncthreads();
-    for (int w = 512; w > 0; w >>= 1) {
-      if ((int)threadIdx.x < w) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + w]);
-      __syncthreads();
-    }
-    if (threadIdx.x == 0) bmax[blockIdx.x] = red[0];
-  }
 }
 
 __global__ void finish_EH_kernel(const float2* __restrict__ hpart, int nsplit, int64_t HC16, int64_t L,
@@ -758,13 +799,22 @@ hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, in
   return hipGetLastError();
 }
 
-hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
-                                   const float* unscale, float* ybuf, float* bmax, const int* stop, hipStream_t s) {
-  const int64_t n = HC16 * NB * 16;
-  if (n == 0 && !bmax) return hipSuccess;
-  const int lncol = NB == 1 ? 4 : (NB == 2 ? 5 : (NB == 4 ? 6 : 7));
-  hipLaunchKernelGGL(finish_E_to_ybuf_kernel, dim3(kBmaxBlocks), dim3(1024), 0, s, epart, nsplit, n, lncol, K, G,
-                     unscale, ybuf, bmax, stop);
+hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
+                                     int64_t L, const float* unscale_in, float* unscale_out, int64_t nchunks, void* out,
+                                     const int* stop, hipStream_t s) {
+  const int64_t total = nchunks * NB * 64;
+  if (total == 0) return hipSuccess;
+  int lg = 0;
+  while (((int64_t)1 << lg) < L) ++lg;
+  const float scale = prec != PREC_BF16 ? ldexpf(1.f, -(lg + 1)) : 1.f;
+  const dim3 gr = grid1(total), bl(256);
+#define NFS_PACKH(P_)                                                                                           \
+  hipLaunchKernelGGL(pack_EH_from_epart_kernel<P_>, gr, bl, 0, s, epart, nsplit, HC16, NB, K, G, scale, unscale_in, \
+                     unscale_out, nchunks, out, stop)
+  if (prec == PREC_FP32) NFS_PACKH(PREC_FP32);
+  else if (prec == PREC_BF16) NFS_PACKH(PREC_BF16);
+  else NFS_PACKH(PREC_FP16);
+#undef NFS_PACKH
   return hipGetLastError();
 }
 

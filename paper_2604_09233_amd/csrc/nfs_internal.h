@@ -54,11 +54,11 @@ inline int col_blocks(int n_coil) {
   return 8;
 }
 
-// bytes of one packed data chunk (16 items) per column block: fp32 8 x 64
-// floats; fp16 one 16-byte fragment per lane; bf16 two (hi and lo parts)
-inline size_t data_chunk_bytes(int prec) {
-  return prec == PREC_FP32 ? 8 * 64 * 4 : (prec == PREC_BF16 ? 2 * 64 * 16 : 64 * 16);
-}
+// bytes of one packed data chunk (16 items) per column block: fp16 one
+// 16-byte fragment per lane; bf16 and fp32 two (hi and lo parts)
+inline size_t data_chunk_bytes(int prec) { return prec == PREC_FP16 ? 64 * 16 : 2 * 64 * 16; }
+// FP16 and FP32 operands (f16 fragments) are scaled by powers of two
+inline bool scaled_prec(int prec) { return prec != PREC_BF16; }
 
 struct EncodeShape {
   int op;            // OP_E or OP_EH
@@ -95,10 +95,12 @@ hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void
 // sum E partials -> m[G][K] (coil-major) times *unscale
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s);
-// sum E partials -> ybuf [HC16][NB*16] times *unscale; with bmax also the
-// per-workgroup max magnitudes of the valid entries (rows < K, columns < 2G)
-hipError_t launch_finish_E_to_ybuf(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
-                                   const float* unscale, float* ybuf, float* bmax, const int* stop, hipStream_t s);
+// E^H data operand of the samples straight from the E partials (E^H E):
+// value(k, c) = sum_s epart[s][k][2c] + i epart[s][k][2c+1]; for FP16 scaled
+// by 2^-(ceil(log2 L) + 1) with *unscale_out = *unscale_in times the inverse
+hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
+                                     int64_t L, const float* unscale_in, float* unscale_out, int64_t nchunks, void* out,
+                                     const int* stop, hipStream_t s);
 // sum E^H partials -> x[L] times *unscale
 hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
                             const float* unscale, float2* x, hipStream_t s);
@@ -124,11 +126,15 @@ struct CgState {
   float2* V;        // [n_iter + 1][L] normalised residuals (re-orthogonalisation) or NULL
   double* rpart;    // [n_iter + 1][2][kCgBlocks] partial dot products v_j^H r
   double* coef;     // [n_iter + 1][2] v_j^H r
+  const float* smax;  // [L] max_c |S[c][l]| (FP16 operands) or NULL
+  float* bmax;        // [kBmaxBlocks] bound on the next E operand (with smax)
   int64_t L;
   int nblk;         // CG workgroups
 };
 constexpr int kMaxReorth = 2048;
 hipError_t launch_cg_reset(const CgState& st, hipStream_t s);
+// smax[l] = max_c |S[c][l]|
+hipError_t launch_sens_absmax(const float2* sens, int G, int64_t L, float* smax, hipStream_t s);
 hipError_t launch_cg_norm_m(const CgState& st, const float2* m, int64_t n, hipStream_t s);
 hipError_t launch_cg_init(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
                           const float* unscale, float2* rho, int64_t L, hipStream_t s);
@@ -138,6 +144,7 @@ hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, in
 hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s);
 hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
                              const float* unscale, int64_t L, hipStream_t s);
+// p = r + (alpha'/alpha) p (and, with st.smax, the E operand bound into st.bmax)
 hipError_t launch_cg_direction(const CgState& st, int64_t L, int n, int n_iter, double tol, hipStream_t s);
 // V[j] = r / sqrt(alpha_j)
 hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
