@@ -46,6 +46,7 @@ def parse():
     ap.add_argument("--config", default="c2")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched-solve measurement")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
@@ -82,6 +83,37 @@ def cpu_baseline(d):
                 sample=f"FP64 E^H E on every 8th sample ({len(ks)} of {d['K']}) x {d['L']} voxels x "
                        f"{d['n_coil']} coils, repeated {work / (d['L'] * len(ks) * d['n_coil']):.0f}x "
                        f"in {el:.1f} s, numpy with {os.cpu_count()} threads")
+
+
+def batched_run(nfs, synth, torch, dev, args, steps=2):
+    """The 24-slice batched workload (uneven 2D slices, 8..32 coils, 8000..30000
+    samples, 16 terms, per-slice B0): every slice's 30-iteration solve in one
+    batched call, BF16 operands, re-orthogonalised CG, replayed from a
+    captured hipGraph.  Reports whole-batch voxel*sample*coil/s."""
+    sl = synth.batched_slices(24)
+    probs = [nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev) for d in sl]
+    ms = []
+    for d, pr in zip(sl, probs):
+        clean = nfs.apply_E(pr, torch.from_numpy(d["rho_true"]), "fp32")
+        sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
+        ms.append(clean + sig * torch.from_numpy(d["noise"]).to(dev))
+    n_iter = 30
+    work = sum((n_iter + 0.5) * d["L"] * d["K"] * d["n_coil"] for d in sl)
+    nfs.set_graphs(0, True)
+    outs, hists, infos = nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(steps):
+        nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True, outs=outs, hists=hists, infos=infos)
+    ev1.record()
+    torch.cuda.synchronize()
+    nfs.set_graphs(0, False)
+    t = ev0.elapsed_time(ev1) / steps
+    return dict(workload="24 slices, 2D 96..160 square, 8..32 coils, 8000..30000 samples, 16 terms, per-slice B0, "
+                         "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch",
+                ms_per_batch=t, value=work / (t * 1e-3), unit="voxel*sample*coil/s",
+                pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps)
 
 
 def main():
@@ -175,12 +207,14 @@ def main():
         times.append(e0.elapsed_time(e1))
     ehe_ms = float(np.median(times))
 
-    # FP32 operand form for comparison
-    fp32 = None
-    if not args.no_fp32_form and args.precision != "fp32":
-        rho32, _, _, ms32, _, _ = time_solves("fp32", max(1, args.steps // 2), 1)
-        fp32 = dict(ms_per_step=ms32, value=(n_iter + 0.5) * vsc / (ms32 * 1e-3),
-                    rel_err_vs_oracle=rel(rho32.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
+    # FP32 and BF16 operand forms for comparison (same workload, same solve)
+    def form(prec):
+        rho_f, _, _, ms_f, _, _ = time_solves(prec, max(1, args.steps // 2), 1)
+        return dict(ms_per_step=ms_f, value=(n_iter + 0.5) * vsc / (ms_f * 1e-3),
+                    rel_err_vs_oracle=rel(rho_f.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
+
+    fp32 = form("fp32") if not args.no_fp32_form and args.precision != "fp32" else None
+    bf16 = form("bf16") if not args.no_fp32_form and args.precision != "bf16" else None
     # plain recurrences, same precision, for reference
     plain = None
     if not args.plain:
@@ -223,6 +257,8 @@ def main():
                     avg_launch_ms=avg_ms, launches=n_k,
                     mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
 
+    batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
+
     st = info.cpu().tolist()
     out = {
         "metric": "E^H·E voxel·sample·coil/s (over the CG solve); CG solve time at rel.err <=2e-3 vs FP64 oracle",
@@ -245,9 +281,11 @@ def main():
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
         "fp32_form": fp32,
+        "bf16_form": bf16,
         "plain_recurrences": plain,
         "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
         "roofline": roofline,
+        "batched": batched,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:

@@ -3,14 +3,15 @@ profiles/.
 
   python -m paper_2604_09233_amd.profile_summary stats <kernel_stats.csv> <title> <command> [note]
       per-kernel durations from `--kernel-trace --stats`
-  python -m paper_2604_09233_amd.profile_summary counters <out.md> <command-prefix> <copy-bytes> \
+  python -m paper_2604_09233_amd.profile_summary counters <out.md> <precision> <command-prefix> <copy-bytes> \
       <sq_dir> [<sq_dir> ...] <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
       per-dispatch counter averages of the encode kernels from `--pmc` runs
       (each *_dir holds run_counter_collection.csv and run_kernel_trace.csv),
       the HBM traffic per launch from FETCH_SIZE / WRITE_SIZE scaled by what
       the same counters read for a plain copy of <copy-bytes> bytes, and the
       SHA-256 of the encode-kernel sources the counters were taken on (the
-      benchmark reports the traffic only while the sources still match).
+      benchmark reports the traffic only while the sources still match);
+      the traffic line covers the kernels of <precision> (fp32, bf16, fp16).
 """
 import csv
 import hashlib
@@ -89,7 +90,10 @@ def _per_dispatch(d, match=None):
             {k: sum(v) / len(v) for k, v in dur.items()})
 
 
-def counters(out_md, command, copy_bytes, *dirs):
+PREC_ARG = {"fp32": "0", "bf16": "1", "fp16": "2"}
+
+
+def counters(out_md, precision, command, copy_bytes, *dirs):
     sq_dirs, (fetch_dir, write_dir, cfetch_dir, cwrite_dir) = dirs[:-4], dirs[-4:]
     copy_bytes = float(copy_bytes)
     merged, durs = defaultdict(dict), defaultdict(list)
@@ -107,9 +111,17 @@ def counters(out_md, command, copy_bytes, *dirs):
     cwk = max(cw, key=lambda k: cw[k].get("WRITE_SIZE", 0.0))
     f_fac = copy_bytes / (cf[cfk]["FETCH_SIZE"] * 1024.0)
     w_fac = copy_bytes / (cw[cwk]["WRITE_SIZE"] * 1024.0)
-    lines = ["# Encode-kernel counters: CG solve, 2D 128x128 / 16 coils / 60000 samples / 16 terms, FP16 operands", "",
+    lines = ["# Encode-kernel counters: CG solve, 2D 128x128 / 16 coils / 60000 samples / 16 terms, "
+             f"{precision.upper()} operands", "",
+             "encode_kernel<OP, PREC, NQ, NB, MT>: OP 0 = E, 1 = E^H; PREC 0 = fp32, 1 = bf16, 2 = fp16. The run "
+             "also holds the single FP32 E that generates the data.", "",
              "Commands (from the repository root, one MI355X), one rocprofv3 run per counter set:", "",
              f"    {command} --pmc <counters> -- python3 bench.py --profile-run", "",
+             "with these counter sets (one run each):", ""]
+    for i, d in enumerate(list(sq_dirs) + [fetch_dir, write_dir]):
+        names = sorted({r["Counter_Name"] for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))})
+        lines.append(f"{i + 1}. `{' '.join(names)}`")
+    lines += ["",
              "Copy calibration: the same FETCH_SIZE / WRITE_SIZE runs over `torch` copying "
              f"{copy_bytes / 2**20:.0f} MiB (`{cfk}`): FETCH_SIZE reads {cf[cfk]['FETCH_SIZE']:.0f} KiB "
              f"(factor {f_fac:.3f}), WRITE_SIZE {cw[cwk]['WRITE_SIZE']:.0f} KiB (factor {w_fac:.3f}).", ""]
@@ -139,7 +151,8 @@ def counters(out_md, command, copy_bytes, *dirs):
         if "SQ_VALU_MFMA_BUSY_CYCLES" in c:
             derived.append(f"MFMA busy: {c['SQ_VALU_MFMA_BUSY_CYCLES'] / (1024 * dur * 2.4e9):.1%} of SIMD-cycles "
                            "at 2.4 GHz")
-        if k in fetch and k in write:
+        prec_ok = k.split("<")[1].split(",")[1].strip() == PREC_ARG[precision]
+        if prec_ok and k in fetch and k in write:
             fb = fetch[k]["FETCH_SIZE"] * 1024.0 * f_fac
             wb = write[k]["WRITE_SIZE"] * 1024.0 * w_fac
             traffic[op] = fb + wb
