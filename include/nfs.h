@@ -55,13 +55,21 @@ enum nfs_status {
   NFS_EUNSUPPORTED = -6  /* device is not gfx950 */
 };
 
-/* Operand precision of the two complex contractions (the phase and its
- * sin/cos are always float32; accumulation is always float32).
- *  NFS_FP32: float32 operands on the FP32 matrix cores.
- *  NFS_BF16: bfloat16 operands (round to nearest even).
- *  NFS_FP16: float16 operands; the data operand is scaled by a power of two
- *            chosen on the device from its maximum magnitude, and unscaled
- *            after the contraction (exact).                                  */
+/* Operand precision of the two complex contractions (the phase is always
+ * float32-grade and its sin/cos float32; accumulation is always float32).
+ *  NFS_FP32: float32-grade: both operands split into two float16 parts and
+ *            the three leading products taken on the f16 matrix cores (about
+ *            2^-21 relative per product).
+ *  NFS_BF16: bfloat16 (cos, sin) operand against a two-part bfloat16 data
+ *            operand (round to nearest even).
+ *  NFS_FP16: float16 operands.
+ *  For NFS_FP32 and NFS_FP16 the data operand is scaled by a power of two
+ *  chosen on the device (from its maximum magnitude or a bound on it) and
+ *  unscaled after the contraction (exact).
+ * The phase is computed in revolutions; inputs whose phase bound
+ * sum_b max|kcoef_b|/2pi * max|fields_b| (with t and b0 as term 0) exceeds
+ * 2^20 revolutions carry no fractional phase in float32 and are outside the
+ * supported range (results are not meaningful there).                       */
 enum nfs_precision { NFS_FP32 = 0, NFS_BF16 = 1, NFS_FP16 = 2 };
 
 /* Operation selector for nfs_workspace_bytes. */
