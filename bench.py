@@ -29,12 +29,13 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
-# MI355X published / derived peaks.  VALU: 256 CUs x 4 SIMDs x 32 FP32 lanes
-# per clock at 2.4 GHz = 157.3 TFLOP/s (FMA); transcendental ops (v_sin_f32,
-# v_cos_f32) issue at a quarter of that lane rate.
+# MI355X published / derived peaks.  Transcendental ops (v_sin_f32,
+# v_cos_f32): a wave64 instruction occupies a SIMD for 8 clocks, i.e.
+# 256 CUs x 4 SIMDs x 8 lanes per clock x 2.4 GHz = 1.966e13 ops/s.
 HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
-N_CU, SIMD_PER_CU, LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 32, 2.4
+N_CU, SIMD_PER_CU, TRANS_LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 8, 2.4
+TRANS_PEAK = N_CU * SIMD_PER_CU * TRANS_LANES_PER_SIMD * CLOCK_GHZ * 1e9
 
 
 def parse():
@@ -47,13 +48,12 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched-solve measurement")
+    ap.add_argument("--no-3d", action="store_true", help="skip the 3D 96x96x48 / 32-coil solve measurement")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
     ap.add_argument("--graphs", action="store_true",
                     help="replay each solve from a captured hipGraph (the encode-kernel timing pass runs eagerly)")
-    ap.add_argument("--trans-rate", type=float, default=0.25,
-                    help="v_sin/v_cos issue rate as a fraction of the FP32 lane rate (for the ALU peak)")
     return ap.parse_args()
 
 
@@ -83,6 +83,57 @@ def cpu_baseline(d):
                 sample=f"FP64 E^H E on every 8th sample ({len(ks)} of {d['K']}) x {d['L']} voxels x "
                        f"{d['n_coil']} coils, repeated {work / (d['L'] * len(ks) * d['n_coil']):.0f}x "
                        f"in {el:.1f} s, numpy with {os.cpu_count()} threads")
+
+
+def threed_run(nfs, synth, torch, dev, args):
+    """The 3D workload (96x96x48, 32 coils, 16 x 35750 samples, 16 terms,
+    B0 +-150 Hz, 15 CG iterations): one warm-up and one timed solve at the
+    benchmark's precision, re-orthogonalised; E checked against the FP64
+    oracle on 48 sampled k-space rows (all voxels, all coils)."""
+    import oracle
+
+    d = synth.make_config("c3")
+    L, K, G, n_iter = d["L"], d["K"], d["n_coil"], d["n_iter"]
+    prob = nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev)
+    rho_t = torch.from_numpy(d["rho_true"]).to(dev)
+    clean = nfs.apply_E(prob, rho_t, "fp32")
+    sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
+    m = clean + sig * torch.from_numpy(d["noise"]).to(dev)
+    del clean
+    ks = np.sort(np.random.default_rng(3).choice(K, 48, replace=False))
+    e_gpu = nfs.apply_E(prob, rho_t, args.precision).cpu().numpy()[:, ks]
+    e_ref = oracle.apply_E(d["rho_true"], d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
+    out = torch.empty(L, dtype=torch.complex64, device=dev)
+    hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    nfs.cg_solve(prob, m, n_iter, precision=args.precision, reorth=True, out=out, hist=hist, info=info)
+    torch.cuda.synchronize()
+    nfs.profile_enable(0, True)
+    nfs.profile_read(0, "E")
+    nfs.profile_read(0, "EH")
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    nfs.cg_solve(prob, m, n_iter, precision=args.precision, reorth=True, out=out, hist=hist, info=info)
+    ev1.record()
+    torch.cuda.synchronize()
+    kt = {k: nfs.profile_read(0, k) for k in ("E", "EH")}
+    nfs.profile_enable(0, False)
+    ms = ev0.elapsed_time(ev1)
+    pairs = L * K
+    enc = {k: v[1] / max(v[0], 1) for k, v in kt.items()}
+    # MFMA instructions issued per 16 x 16 tile: the phase (f16) and the
+    # contraction (one f16, two bf16 or three f16 per 16-column block)
+    nq = -(-3 * (d["n_basis"] + 1) // 32)
+    nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
+    flops = pairs / 256.0 * 16384 * (nq + nb * {"fp16": 1, "bf16": 2, "fp32": 3}[args.precision])
+    return dict(workload="3D 96x96x48, 32 coils, 16 x 35750-sample spiral shots, 16 field terms, B0 +-150 Hz, "
+                         "15 CG iterations, re-orthogonalised",
+                precision=args.precision, ms_per_solve=ms, value=(n_iter + 0.5) * pairs * G / (ms * 1e-3),
+                unit="voxel*sample*coil/s", encode_kernel_ms=enc,
+                sincos_frac_of_peak={k: 2 * pairs / (v * 1e-3) / TRANS_PEAK for k, v in enc.items()},
+                mfma_frac_of_peak={k: flops / (v * 1e-3) / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) for k, v in enc.items()},
+                rel_err_E_sampled=rel(e_gpu, e_ref), sampled_rows=len(ks),
+                cg_info=info.cpu().tolist())
 
 
 def batched_run(nfs, synth, torch, dev, args, steps=2):
@@ -230,21 +281,21 @@ def main():
     avg_ms = ms_k / max(n_k, 1)
     pairs = L * K  # voxel-sample pairs per launch
     # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
-    trans_peak = N_CU * SIMD_PER_CU * LANES_PER_SIMD * CLOCK_GHZ * 1e9 * args.trans_rate  # ops/s
+    trans_peak = TRANS_PEAK  # ops/s
     achieved = 2 * pairs / (avg_ms * 1e-3)
     # matrix-pipe time of the MFMA instructions the kernel issues, at the
     # published dense peaks, as a fraction of the measured launch time: per
     # 16 x 16 tile (256 pairs) ceil(3 (P+1) / 32) f16 16x16x32 phase
     # instructions, and per 16-column block of the 2G real columns one f16
     # 16x16x32 (fp16), two bf16 16x16x32 (bf16: hi and lo data parts) or
-    # eight f32 16x16x4 (fp32) contraction instructions
+    # three f16 16x16x32 (fp32: split operands) contraction instructions
     P = d["n_basis"]
     nq = -(-3 * (P + 1) // 32)
     nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
     tiles = pairs / 256.0
     flops_phase = tiles * nq * 16384
-    flops_con = tiles * nb * {"fp16": 16384, "bf16": 2 * 16384, "fp32": 8 * 2048}[args.precision]
-    t_mfma = flops_phase / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) + flops_con / (MFMA_PEAK_TFLOPS[args.precision] * 1e12)
+    flops_con = tiles * nb * {"fp16": 16384, "bf16": 2 * 16384, "fp32": 3 * 16384}[args.precision]
+    t_mfma = (flops_phase + flops_con) / (MFMA_PEAK_TFLOPS["fp16"] * 1e12)
     # HBM bytes per launch from the committed counter summary (FETCH_SIZE +
     # WRITE_SIZE, copy-calibrated), only while the kernel sources match the
     # ones the counters were taken on
@@ -258,6 +309,7 @@ def main():
                     mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
 
     batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
+    threed = None if args.no_3d else threed_run(nfs, synth, torch, dev, args)
 
     st = info.cpu().tolist()
     out = {
@@ -286,6 +338,7 @@ def main():
         "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
         "roofline": roofline,
         "batched": batched,
+        "3d": threed,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
