@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--no-fp32-form", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched-solve measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 96x96x48 / 32-coil solve measurement")
+    ap.add_argument("--no-tune", action="store_true", help="use the default encode shapes instead of autotuned ones")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
@@ -100,6 +101,8 @@ def threed_run(nfs, synth, torch, dev, args):
     sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
     m = clean + sig * torch.from_numpy(d["noise"]).to(dev)
     del clean
+    if not args.no_tune:
+        nfs.autotune(prob, args.precision)
     ks = np.sort(np.random.default_rng(3).choice(K, 48, replace=False))
     e_gpu = nfs.apply_E(prob, rho_t, args.precision).cpu().numpy()[:, ks]
     e_ref = oracle.apply_E(d["rho_true"], d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
@@ -133,6 +136,7 @@ def threed_run(nfs, synth, torch, dev, args):
                 sincos_frac_of_peak={k: 2 * pairs / (v * 1e-3) / TRANS_PEAK for k, v in enc.items()},
                 mfma_frac_of_peak={k: flops / (v * 1e-3) / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) for k, v in enc.items()},
                 rel_err_E_sampled=rel(e_gpu, e_ref), sampled_rows=len(ks),
+                held_tiles_nsplit=nfs.tuned_shape(prob, args.precision),
                 cg_info=info.cpu().tolist())
 
 
@@ -149,6 +153,8 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
         sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
         ms.append(clean + sig * torch.from_numpy(d["noise"]).to(dev))
     n_iter = 30
+    if not args.no_tune:
+        nfs.autotune_batched(probs, "bf16")
     work = sum((n_iter + 0.5) * d["L"] * d["K"] * d["n_coil"] for d in sl)
     nfs.set_graphs(0, True)
     outs, hists, infos = nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True)
@@ -164,7 +170,7 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
     return dict(workload="24 slices, 2D 96..160 square, 8..32 coils, 8000..30000 samples, 16 terms, per-slice B0, "
                          "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch",
                 ms_per_batch=t, value=work / (t * 1e-3), unit="voxel*sample*coil/s",
-                pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps)
+                pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps, tuned=not args.no_tune)
 
 
 def main():
@@ -188,6 +194,11 @@ def main():
     sigma = rms / (30 * np.sqrt(2))
     m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
     torch.cuda.synchronize()
+
+    tuned = {}
+    if not args.no_tune:
+        for prec in {args.precision, "fp32", "bf16"}:
+            tuned[prec] = nfs.autotune(prob, prec)
 
     def solve(prec, out, hist, info, reorth):
         return nfs.cg_solve(prob, m, n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
@@ -330,6 +341,8 @@ def main():
                    "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision,
                    "cg": "plain" if args.plain else "re-orthogonalised", "hip_graphs": bool(args.graphs)},
         "rel_err_vs_oracle": err,
+        "encode_shapes": {"tuned": not args.no_tune,
+                          "held_tiles_nsplit": nfs.tuned_shape(prob, args.precision)},
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
         "fp32_form": fp32,

@@ -184,6 +184,40 @@ int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, c
  * is on.  Graphs live until nfs_destroy.  Default off.                    */
 int nfs_set_graphs(nfs_ctx* ctx, int on);
 
+/* Tile-shape autotuning of the fused encode kernel (the kernel that builds
+ * the phase tiles of the signal model, takes their sine/cosine and applies
+ * them, for E and for E^H).  For this problem's shape class (L, K, G, P and
+ * `precision`) it times every candidate shape on the caller's stream, with
+ * the problem's own phase coefficients and realistic operands (E of
+ * rho = 1 + i, then E^H of that output): held tiles per wave (2 or 4) and the
+ * split count of the streamed range (targets of 2..16 workgroups per CU).
+ * The fastest shape per direction is kept in `ctx` and used by every later
+ * call on a problem of the same shape class; nfs_workspace_bytes then
+ * reflects it, so query workspace sizes after tuning.  Results of a tuned
+ * call differ from an untuned one only in the order of the split sums.
+ * Synchronises the stream (host waits on events); fails with NFS_EINVAL
+ * while the stream is being captured.  Workspace: nfs_tune_workspace_bytes
+ * (256-byte aligned, contents undefined afterwards).                       */
+int nfs_tune_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, int precision, size_t* bytes);
+int nfs_autotune(nfs_ctx* ctx, const nfs_problem* prob, int precision, void* ws, size_t ws_bytes, void* stream);
+/* Batch tuning.  The slices of nfs_cg_solve_batched run concurrently, so
+ * the best shape of a slice inside the batch is not its best shape alone.
+ * This times batch-wide candidates (held tiles 2 or 4 where a slice allows
+ * it, and a target of 1/4 .. 4 workgroups per CU per slice from which each
+ * slice derives its split counts) as concurrent E^H E passes over all
+ * slices, forked and joined as the batched solve does, and keeps the
+ * resulting per-slice shapes in `ctx` (replacing earlier entries of the same
+ * shape classes).  Same synchronisation, capture and workspace rules as
+ * nfs_autotune; workspace: nfs_tune_workspace_bytes_batched.              */
+int nfs_tune_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
+                                     size_t* bytes);
+int nfs_autotune_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision, void* ws,
+                         size_t ws_bytes, void* stream);
+/* The encode shape later calls will use for `op` (NFS_OP_E or NFS_OP_EH):
+ * held tiles per wave and split count (tuned, else the default choice).    */
+int nfs_tuned_shape(const nfs_ctx* ctx, const nfs_problem* prob, int precision, int op, int* held_tiles,
+                    int* nsplit);
+
 /* Backward of m = E rho for a real loss L, for field-map and trajectory
  * refinement.  grad_m is dL/dm in PyTorch's convention for complex tensors
  * (for L = ||E rho - sigma||^2 it is 2 (E rho - sigma)).  Differentiating the

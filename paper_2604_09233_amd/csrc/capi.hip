@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <map>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -27,7 +28,17 @@ struct nfs_ctx {
   hipStream_t capture_stream = nullptr;  // graph capture only
   std::vector<hipEvent_t> pool;                 // idle events
   std::vector<std::pair<hipEvent_t, hipEvent_t>> rec[2];  // recorded (start, stop) per kind
+  // autotuned encode shapes: key (op, precision, L, K, G, P) -> (MT, nsplit)
+  std::map<std::string, std::pair<int, int>> tune;
+  unsigned tune_generation = 0;  // bumped by every autotune (part of graph keys)
 };
+
+static std::string tune_key(int op, int prec, const nfs_problem* pr) {
+  char b[128];
+  snprintf(b, sizeof b, "%d/%d/%lld/%lld/%d/%d", op, prec, (long long)pr->n_vox, (long long)pr->n_samp, pr->n_coil,
+           pr->n_basis);
+  return b;
+}
 
 static thread_local std::string g_err;
 
@@ -177,6 +188,9 @@ struct Layout {
   size_t total;
 };
 
+static size_t epart_bytes(const EncodeShape& sh, int NB) { return (size_t)sh.nsplit * sh.HC * 16 * NB * 16 * 4; }
+static size_t hpart_bytes(const EncodeShape& sh) { return (size_t)sh.nsplit * sh.HC * 16 * 8; }
+
 static int choose_split(int64_t held_chunks, int64_t strm_chunks, int MT, int n_cu) {
   const int64_t gx = cdiv(held_chunks, (int64_t)kWaves * MT);
   if (gx <= 0) return 1;
@@ -188,7 +202,32 @@ static int choose_split(int64_t held_chunks, int64_t strm_chunks, int MT, int n_
   return (int)ns;
 }
 
-static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int prec, int n_iter, int reorth) {
+// Encode shape of one direction: held-tile count MT and split count, from
+// (in order) an explicit override, the context's autotuned entry, or the
+// default heuristic.
+static EncodeShape encode_shape(const nfs_ctx* ctx, const nfs_problem* pr, int op, int prec, int NQ, int NB,
+                                int64_t HC, int64_t SC, const int* ov) {
+  const int n_cu = ctx ? ctx->n_cu : 256;
+  int MT = held_tiles(NB), ns = 0;
+  if (ov) {
+    MT = ov[0];
+    ns = ov[1];
+  } else if (ctx) {
+    auto it = ctx->tune.find(tune_key(op, prec, pr));
+    if (it != ctx->tune.end()) {
+      MT = it->second.first;
+      ns = it->second.second;
+    }
+  }
+  if (ns < 1) ns = choose_split(HC, SC, MT, n_cu);
+  EncodeShape sh{op, prec, NQ, NB, MT, HC, SC, ns, 0};
+  sh.cps = cdiv(SC, ns > 0 ? ns : 1);
+  return sh;
+}
+
+// ovE / ovH: optional {MT, nsplit} overrides of the E / E^H shapes (tuning)
+static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int prec, int n_iter, int reorth,
+                          const int* ovE = nullptr, const int* ovH = nullptr) {
   Layout y{};
   y.L = pr->n_vox;
   y.K = pr->n_samp;
@@ -199,14 +238,8 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.NQ = phase_instrs(y.P);
   y.NB = col_blocks(y.G);
   y.prec = prec;
-  const int n_cu = ctx ? ctx->n_cu : 256;
-  const int MT = held_tiles(y.NB);
-  y.shE = EncodeShape{OP_E, prec, y.NQ, y.NB, MT, y.KC, y.LC, 1, 0};
-  y.shE.nsplit = choose_split(y.KC, y.LC, MT, n_cu);
-  y.shE.cps = cdiv(y.LC, y.shE.nsplit);
-  y.shH = EncodeShape{OP_EH, prec, y.NQ, y.NB, MT, y.LC, y.KC, 1, 0};
-  y.shH.nsplit = choose_split(y.LC, y.KC, MT, n_cu);
-  y.shH.cps = cdiv(y.KC, y.shH.nsplit);
+  y.shE = encode_shape(ctx, pr, OP_E, prec, y.NQ, y.NB, y.KC, y.LC, ovE);
+  y.shH = encode_shape(ctx, pr, OP_EH, prec, y.NQ, y.NB, y.LC, y.KC, ovH);
   const bool needE = op != NFS_OP_EH, needH = op != NFS_OP_E, cg = op == NFS_OP_CG;
 
   size_t o = 0;
@@ -225,9 +258,7 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.o_bmax = take(kBmaxBlocks * 4);
   y.o_unscale = take(2 * 4);
   y.o_dataE = needE ? take((size_t)y.LC * y.NB * data_chunk_bytes(prec)) : 0;
-  y.o_epart = needE ? take((size_t)y.shE.nsplit * y.KC * 16 * y.NB * 16 * 4) : 0;
   y.o_dataH = needH ? take((size_t)y.KC * y.NB * data_chunk_bytes(prec)) : 0;
-  y.o_hpart = needH ? take((size_t)y.shH.nsplit * y.LC * 16 * 8) : 0;
   if (cg) {
     y.o_sensj = pr->icorr ? take((size_t)y.G * y.L * 8) : 0;
     y.o_smax = scaled_prec(prec) ? take((size_t)y.L * 4) : 0;
@@ -247,6 +278,9 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
       y.o_coef = take((size_t)(n_iter + 1) * 2 * 8);
     }
   }
+  // split partials last: their sizes depend on the encode shapes
+  y.o_epart = needE ? take(epart_bytes(y.shE, y.NB)) : 0;
+  y.o_hpart = needH ? take(hpart_bytes(y.shH)) : 0;
   y.total = o;
   return y;
 }
@@ -536,10 +570,11 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
 // with one hipGraphLaunch.  Not used while the caller's stream is itself
 // being captured (the launches then simply go into the caller's graph) or
 // while kernel profiling is on.
-static std::string graph_key(const char* kind, const nfs_problem* probs, int n, const void* const* ptrs, int np,
-                             int n_iter, double tol, int replace_every, int reorth, int precision, const void* ws,
-                             size_t ws_bytes, const void* stream) {
+static std::string graph_key(const nfs_ctx* ctx, const char* kind, const nfs_problem* probs, int n,
+                             const void* const* ptrs, int np, int n_iter, double tol, int replace_every, int reorth,
+                             int precision, const void* ws, size_t ws_bytes, const void* stream) {
   std::string k(kind);
+  k.append(reinterpret_cast<const char*>(&ctx->tune_generation), sizeof ctx->tune_generation);
   auto add = [&](const void* p, size_t len) { k.append(static_cast<const char*>(p), len); };
   for (int i = 0; i < n; ++i) add(&probs[i], sizeof(nfs_problem));
   for (int i = 0; i < np; ++i) add(&ptrs[i], sizeof(void*));
@@ -609,7 +644,7 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
   hipStream_t s = (hipStream_t)stream;
   const void* ptrs[4] = {m, rho, hist, info};
   const std::string key =
-      graph_key("cg", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
+      graph_key(ctx, "cg", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
   return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
     return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st);
   });
@@ -637,6 +672,24 @@ static int ensure_batch_streams(nfs_ctx* ctx) {
   if (!ctx->fork_event) NFS_TRY(hipEventCreateWithFlags(&ctx->fork_event, hipEventDisableTiming), "hipEventCreate");
   NFS_TRY(hipSetDevice(cur), "hipSetDevice");
   return NFS_OK;
+}
+
+// longest-processing-time assignment of slices (by L*K*G) to at most
+// kBatchStreams lanes
+static std::vector<std::vector<int>> assign_lanes(int n_slices, const nfs_problem* probs) {
+  std::vector<int> order(n_slices);
+  for (int i = 0; i < n_slices; ++i) order[i] = i;
+  auto work = [&](int i) { return (double)probs[i].n_vox * probs[i].n_samp * probs[i].n_coil; };
+  std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+  const int ns = n_slices < kBatchStreams ? n_slices : kBatchStreams;
+  std::vector<std::vector<int>> lanes(ns);
+  std::vector<double> load(ns, 0.0);
+  for (int i : order) {
+    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+    lanes[k].push_back(i);
+    load[k] += work(i);
+  }
+  return lanes;
 }
 
 static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs, int precision, int n_iter, int reorth,
@@ -687,19 +740,8 @@ extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_proble
   if (ws_bytes < need) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, need);
   if (n_slices == 0) return NFS_OK;
   if ((rc = ensure_batch_streams(ctx))) return rc;
-  // longest-processing-time assignment of slices to streams
-  std::vector<int> order(n_slices);
-  for (int i = 0; i < n_slices; ++i) order[i] = i;
-  auto work = [&](int i) { return (double)probs[i].n_vox * probs[i].n_samp * probs[i].n_coil; };
-  std::sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
-  const int ns = n_slices < kBatchStreams ? n_slices : kBatchStreams;
-  std::vector<std::vector<int>> lanes(ns);
-  std::vector<double> load(ns, 0.0);
-  for (int i : order) {
-    const int k = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-    lanes[k].push_back(i);
-    load[k] += work(i);
-  }
+  const std::vector<std::vector<int>> lanes = assign_lanes(n_slices, probs);
+  const int ns = (int)lanes.size();
   std::vector<const void*> ptrs;
   for (int i = 0; i < n_slices; ++i) {
     ptrs.push_back(m[i]);
@@ -707,7 +749,7 @@ extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_proble
     ptrs.push_back(hist ? hist[i] : nullptr);
     ptrs.push_back(info ? info[i] : nullptr);
   }
-  const std::string key = graph_key("cgb", probs, n_slices, ptrs.data(), (int)ptrs.size(), n_iter, tol,
+  const std::string key = graph_key(ctx, "cgb", probs, n_slices, ptrs.data(), (int)ptrs.size(), n_iter, tol,
                                     replace_every, reorth, precision, ws, ws_bytes, stream);
   return run_maybe_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> int {
     NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
@@ -766,5 +808,353 @@ extern "C" int nfs_encode_backward(nfs_ctx* ctx, const nfs_problem* prob, const 
               "grad_kcoef");
     }
   }
+  return NFS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Autotuning of the encode shapes: held tiles per wave (MT) and the split
+// count of the streamed range, per direction, measured on the problem's own
+// phase coefficients with realistic operands (E of rho = 1 + i, then E^H of
+// that E output).  The objective of a shape includes the kernel that
+// consumes its split partials (the E^H operand pack after E, the E^H finish
+// after E^H), since more splits mean more partials to sum.  The fastest
+// shape is kept in the context under the shape class (direction, precision,
+// L, K, G, P) and used by every later call.
+struct TuneCand {
+  int MT, ns;
+};
+
+static std::vector<TuneCand> tune_candidates(const nfs_ctx* ctx, int NB, int64_t HC, int64_t SC) {
+  std::vector<TuneCand> v;
+  const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(64, SC / 8));
+  for (int MT : {2, 4}) {
+    if (!valid_held_tiles(NB, MT)) continue;
+    const int64_t gx = std::max<int64_t>(1, cdiv(HC, (int64_t)kWaves * MT));
+    std::vector<int> seen;
+    for (int per_cu : {1, 2, 3, 4, 5, 6, 8, 12, 16}) {  // target workgroups per CU
+      const int ns = (int)std::min(std::max<int64_t>(cdiv((int64_t)per_cu * ctx->n_cu, gx), 1), maxs);
+      if (std::find(seen.begin(), seen.end(), ns) == seen.end()) {
+        seen.push_back(ns);
+        v.push_back({MT, ns});
+      }
+    }
+  }
+  return v;
+}
+
+// split count for a target of quarter_wg_per_cu / 4 workgroups per CU (batches)
+static int split_for_target(const nfs_ctx* ctx, int MT, int64_t HC, int64_t SC, int quarter_wg_per_cu) {
+  const int64_t maxs = std::max<int64_t>(1, std::min<int64_t>(64, SC / 8));
+  const int64_t gx = std::max<int64_t>(1, cdiv(HC, (int64_t)kWaves * MT));
+  return (int)std::min(std::max<int64_t>(cdiv((int64_t)quarter_wg_per_cu * ctx->n_cu, 4 * gx), 1), maxs);
+}
+
+struct TuneLayout {
+  Layout y;  // E^H E layout with the default shapes (phase parts, operands)
+  std::vector<TuneCand> cE, cH;
+  size_t o_epart, o_hpart, o_ones, total;
+};
+
+static TuneLayout tune_layout(const nfs_ctx* ctx, const nfs_problem* prob, int prec) {
+  TuneLayout t;
+  t.y = make_layout(ctx, prob, NFS_OP_EHE, prec, 0, 0);
+  const Layout& y = t.y;
+  t.cE = tune_candidates(ctx, y.NB, y.KC, y.LC);
+  t.cH = tune_candidates(ctx, y.NB, y.LC, y.KC);
+  size_t maxE = 0, maxH = 0;
+  for (const TuneCand& c : t.cE) {
+    const int ov[2] = {c.MT, c.ns};
+    maxE = std::max(maxE, epart_bytes(encode_shape(ctx, prob, OP_E, prec, y.NQ, y.NB, y.KC, y.LC, ov), y.NB));
+  }
+  for (const TuneCand& c : t.cH) {
+    const int ov[2] = {c.MT, c.ns};
+    maxH = std::max(maxH, hpart_bytes(encode_shape(ctx, prob, OP_EH, prec, y.NQ, y.NB, y.LC, y.KC, ov)));
+  }
+  t.o_epart = y.o_epart;  // the split partials come last in the layout
+  t.o_hpart = al(t.o_epart + maxE);
+  t.o_ones = al(t.o_hpart + maxH);
+  t.total = al(t.o_ones + (size_t)y.L * 8);
+  return t;
+}
+
+// One problem under tuning: its layout, workspace and launch context.
+struct TuneSlice {
+  const nfs_problem* pr;
+  TuneLayout tl;
+  void* ws;
+};
+
+// phase coefficients and the E operand of rho = 1 + i
+static int tune_prepare(nfs_ctx* ctx, const TuneSlice& t, hipStream_t s) {
+  const Layout& y = t.tl.y;
+  Ctx c{ctx, y, t.pr, reinterpret_cast<const float2*>(t.pr->sens), t.ws, s, nullptr};
+  int rc = seq_pack_coefs(c, true, true);
+  if (rc) return rc;
+  float2* ones = at<float2>(t.ws, t.tl.o_ones);
+  NFS_TRY(launch_fill(reinterpret_cast<float*>(ones), 2 * y.L, 1.f, s), "fill");
+  float* bmax = at<float>(t.ws, y.o_bmax);
+  if (scaled_prec(y.prec))
+    NFS_TRY(launch_absmax(ones, c.sens, nullptr, y.L, 1, 0, y.G, bmax, nullptr, s), "absmax");
+  NFS_TRY(launch_pack_data(OP_E, y.prec, ones, c.sens, nullptr, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(t.ws, y.o_dataE),
+                           bmax, at<float>(t.ws, y.o_unscale), nullptr, s),
+          "pack_data(E)");
+  return NFS_OK;
+}
+
+// E with shape ovE then the E^H operand pack (ovE non-null), and/or E^H with
+// shape ovH then the E^H finish (ovH non-null)
+static int tune_pass(const nfs_ctx* ctx, const TuneSlice& t, const int* ovE, const int* ovH, hipStream_t s) {
+  const Layout& y = t.tl.y;
+  void* ws = t.ws;
+  const float2* sens = reinterpret_cast<const float2*>(t.pr->sens);
+  const unsigned* tmax = at<unsigned>(ws, y.o_tmax);
+  float* us = at<float>(ws, y.o_unscale);
+  if (ovE) {
+    const EncodeShape sh = encode_shape(ctx, t.pr, OP_E, y.prec, y.NQ, y.NB, y.KC, y.LC, ovE);
+    float* epart = at<float>(ws, t.tl.o_epart);
+    NFS_TRY(launch_encode(sh, at<void>(ws, y.o_sB), at<void>(ws, y.o_vA), at<void>(ws, y.o_dataE), epart, sens, y.L,
+                          y.G, tmax, y.P + 1, nullptr, s),
+            "encode E (tuning)");
+    NFS_TRY(launch_pack_EH_from_epart(y.prec, epart, sh.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L, us, us + 1, y.KC,
+                                      at<void>(ws, y.o_dataH), nullptr, s),
+            "pack_EH_from_epart (tuning)");
+  }
+  if (ovH) {
+    const EncodeShape sh = encode_shape(ctx, t.pr, OP_EH, y.prec, y.NQ, y.NB, y.LC, y.KC, ovH);
+    float2* hpart = at<float2>(ws, t.tl.o_hpart);
+    NFS_TRY(launch_encode(sh, at<void>(ws, y.o_vB), at<void>(ws, y.o_sA), at<void>(ws, y.o_dataH), (float*)hpart,
+                          sens, y.L, y.G, tmax, y.P + 1, nullptr, s),
+            "encode EH (tuning)");
+    // the E operand has been packed already, so the ones vector is free
+    NFS_TRY(launch_finish_EH(hpart, sh.nsplit, y.LC * 16, y.L, scaled_prec(y.prec) ? us + 1 : nullptr,
+                             at<float2>(ws, t.tl.o_ones), s),
+            "finish_EH (tuning)");
+  }
+  return NFS_OK;
+}
+
+// Mean duration of `enqueue` on stream s: one untimed run, then 1 timed run,
+// or 3 when that one took under 5 ms.
+struct TuneTimer {
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  ~TuneTimer() {
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  int init() {
+    for (hipEvent_t& e : ev) NFS_TRY(hipEventCreate(&e), "hipEventCreate");
+    return NFS_OK;
+  }
+  template <class F>
+  int time(hipStream_t s, F&& enqueue, float* ms) {
+    int rc = enqueue();
+    if (rc) return rc;
+    NFS_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
+    if ((rc = enqueue())) return rc;
+    NFS_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
+    NFS_TRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+    float first = 0.f;
+    NFS_TRY(hipEventElapsedTime(&first, ev[0], ev[1]), "hipEventElapsedTime");
+    if (first > 5.f) {
+      *ms = first;
+      return NFS_OK;
+    }
+    NFS_TRY(hipEventRecord(ev[0], s), "hipEventRecord");
+    for (int r = 0; r < 3; ++r)
+      if ((rc = enqueue())) return rc;
+    NFS_TRY(hipEventRecord(ev[1], s), "hipEventRecord");
+    NFS_TRY(hipEventSynchronize(ev[1]), "hipEventSynchronize");
+    float tot = 0.f;
+    NFS_TRY(hipEventElapsedTime(&tot, ev[0], ev[1]), "hipEventElapsedTime");
+    *ms = tot / 3;
+    return NFS_OK;
+  }
+};
+
+static int check_tune_stream(hipStream_t s, const char* fn) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  if (s) NFS_TRY(hipStreamIsCapturing(s, &cs), "hipStreamIsCapturing");
+  if (cs != hipStreamCaptureStatusNone) return fail(NFS_EINVAL, "%s: the stream is being captured", fn);
+  return NFS_OK;
+}
+
+extern "C" int nfs_tune_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, int precision, size_t* bytes) {
+  const char* fn = "nfs_tune_workspace_bytes";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  *bytes = tune_layout(ctx, prob, precision).total;
+  return NFS_OK;
+}
+
+extern "C" int nfs_autotune(nfs_ctx* ctx, const nfs_problem* prob, int precision, void* ws, size_t ws_bytes,
+                            void* stream) {
+  const char* fn = "nfs_autotune";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_problem(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  TuneSlice t{prob, tune_layout(ctx, prob, precision), ws};
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  if (ws_bytes < t.tl.total)
+    return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, t.tl.total);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_tune_stream(s, fn))) return rc;
+  if (t.tl.y.L == 0 || t.tl.y.K == 0) return NFS_OK;
+  if ((rc = tune_prepare(ctx, t, s))) return rc;
+  TuneTimer tm;
+  if ((rc = tm.init())) return rc;
+  TuneCand bE{}, bH{};
+  float best = 0.f;
+  for (size_t i = 0; i < t.tl.cE.size(); ++i) {
+    const int ov[2] = {t.tl.cE[i].MT, t.tl.cE[i].ns};
+    float ms = 0.f;
+    if ((rc = tm.time(s, [&] { return tune_pass(ctx, t, ov, nullptr, s); }, &ms))) return rc;
+    if (i == 0 || ms < best) {
+      best = ms;
+      bE = t.tl.cE[i];
+    }
+  }
+  const int ovE[2] = {bE.MT, bE.ns};
+  if ((rc = tune_pass(ctx, t, ovE, nullptr, s))) return rc;  // E^H operand of the chosen E shape
+  for (size_t i = 0; i < t.tl.cH.size(); ++i) {
+    const int ov[2] = {t.tl.cH[i].MT, t.tl.cH[i].ns};
+    float ms = 0.f;
+    if ((rc = tm.time(s, [&] { return tune_pass(ctx, t, nullptr, ov, s); }, &ms))) return rc;
+    if (i == 0 || ms < best) {
+      best = ms;
+      bH = t.tl.cH[i];
+    }
+  }
+  ctx->tune[tune_key(OP_E, precision, prob)] = {bE.MT, bE.ns};
+  ctx->tune[tune_key(OP_EH, precision, prob)] = {bH.MT, bH.ns};
+  ++ctx->tune_generation;
+  return NFS_OK;
+}
+
+// Batched tuning: the slices of a batch run concurrently on the context's
+// streams, so the shape that is fastest for a slice alone (one that fills
+// the GPU by itself) is not the fastest inside the batch.  Candidates here
+// are batch-wide: a held-tile count (2 or 4, where the slice allows it) and
+// a target of 1/4, 1/2, 1, 2 or 4 workgroups per CU per slice, from which
+// every slice derives its split counts; each candidate is timed as one
+// concurrent E^H E pass over all slices (with the kernels that consume the
+// split partials), forked and joined exactly as the batched solve does.
+extern "C" int nfs_tune_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs,
+                                                int precision, size_t* bytes) {
+  const char* fn = "nfs_tune_workspace_bytes_batched";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  if (n_slices < 0 || (n_slices > 0 && !probs)) return fail(NFS_EINVAL, "%s: bad slice list", fn);
+  int rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  size_t tot = 0;
+  for (int i = 0; i < n_slices; ++i) {
+    if ((rc = check_sizes(&probs[i], fn))) return rc;
+    tot += al(tune_layout(ctx, &probs[i], precision).total);
+  }
+  *bytes = tot;
+  return NFS_OK;
+}
+
+extern "C" int nfs_autotune_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision, void* ws,
+                                    size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_autotune_batched";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (n_slices < 0 || (n_slices > 0 && !probs)) return fail(NFS_EINVAL, "%s: bad slice list", fn);
+  int rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  std::vector<TuneSlice> ts;
+  size_t off = 0;
+  for (int i = 0; i < n_slices; ++i) {
+    if ((rc = check_problem(&probs[i], fn))) return rc;
+    ts.push_back(TuneSlice{&probs[i], tune_layout(ctx, &probs[i], precision), nullptr});
+    off += al(ts.back().tl.total);
+  }
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  if (ws_bytes < off) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, off);
+  hipStream_t s = (hipStream_t)stream;
+  if ((rc = check_tune_stream(s, fn))) return rc;
+  off = 0;
+  std::vector<int> live;  // slices with work
+  for (int i = 0; i < n_slices; ++i) {
+    ts[i].ws = static_cast<char*>(ws) + off;
+    off += al(ts[i].tl.total);
+    if (ts[i].tl.y.L > 0 && ts[i].tl.y.K > 0) live.push_back(i);
+  }
+  if (live.empty()) return NFS_OK;
+  if ((rc = ensure_batch_streams(ctx))) return rc;
+  for (int i : live)
+    if ((rc = tune_prepare(ctx, ts[i], s))) return rc;
+  const std::vector<std::vector<int>> lanes = assign_lanes(n_slices, probs);
+  // per-slice shapes of a batch candidate
+  auto shapes = [&](int i, int MT, int q, int* ovE, int* ovH) {
+    const Layout& y = ts[i].tl.y;
+    const int mt = valid_held_tiles(y.NB, MT) ? MT : 2;
+    ovE[0] = ovH[0] = mt;
+    ovE[1] = split_for_target(ctx, mt, y.KC, y.LC, q);
+    ovH[1] = split_for_target(ctx, mt, y.LC, y.KC, q);
+  };
+  TuneTimer tm;
+  if ((rc = tm.init())) return rc;
+  int bestMT = 2, bestQ = 4;
+  float best = 0.f;
+  bool first = true;
+  for (int MT : {2, 4}) {
+    for (int q : {1, 2, 4, 8, 16}) {
+      auto enqueue = [&]() -> int {
+        NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
+        for (size_t k = 0; k < lanes.size(); ++k) {
+          hipStream_t sk = ctx->bstreams[k];
+          NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
+          for (int i : lanes[k]) {
+            if (ts[i].tl.y.L == 0 || ts[i].tl.y.K == 0) continue;
+            int ovE[2], ovH[2];
+            shapes(i, MT, q, ovE, ovH);
+            const int r2 = tune_pass(ctx, ts[i], ovE, ovH, sk);
+            if (r2) return r2;
+          }
+          NFS_TRY(hipEventRecord(ctx->bevents[k], sk), "hipEventRecord");
+          NFS_TRY(hipStreamWaitEvent(s, ctx->bevents[k], 0), "hipStreamWaitEvent");
+        }
+        return NFS_OK;
+      };
+      float ms = 0.f;
+      if ((rc = tm.time(s, enqueue, &ms))) return rc;
+      if (first || ms < best) {
+        best = ms;
+        bestMT = MT;
+        bestQ = q;
+        first = false;
+      }
+    }
+  }
+  for (int i : live) {
+    int ovE[2], ovH[2];
+    shapes(i, bestMT, bestQ, ovE, ovH);
+    ctx->tune[tune_key(OP_E, precision, &probs[i])] = {ovE[0], ovE[1]};
+    ctx->tune[tune_key(OP_EH, precision, &probs[i])] = {ovH[0], ovH[1]};
+  }
+  ++ctx->tune_generation;
+  return NFS_OK;
+}
+
+extern "C" int nfs_tuned_shape(const nfs_ctx* ctx, const nfs_problem* prob, int precision, int op, int* held_tiles_out,
+                               int* nsplit_out) {
+  const char* fn = "nfs_tuned_shape";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (!held_tiles_out || !nsplit_out) return fail(NFS_EINVAL, "%s: output pointer is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if (op != NFS_OP_E && op != NFS_OP_EH) return fail(NFS_EINVAL, "%s: op must be NFS_OP_E or NFS_OP_EH", fn);
+  const Layout y = make_layout(ctx, prob, NFS_OP_EHE, precision, 0, 0);
+  const EncodeShape& sh = op == NFS_OP_E ? y.shE : y.shH;
+  *held_tiles_out = sh.MT;
+  *nsplit_out = sh.nsplit;
   return NFS_OK;
 }

@@ -683,6 +683,11 @@ __global__ void fill_zero_kernel(float* __restrict__ p, int64_t n) {
   if (i < n) p[i] = 0.f;
 }
 
+__global__ void fill_kernel(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
 // ---------------------------------------------------------------------------
 // launchers
 static inline dim3 grid1(int64_t n, int bs = 256) { return dim3((unsigned)cdiv(n, bs)); }
@@ -755,11 +760,15 @@ template <int OP, int PREC, int NQ>
 static hipError_t launch_encode_nb(const EncodeShape& sh, const void* hc, const void* scf, const void* sd, float* op,
                                    const float2* sens, int64_t L, int G, const unsigned* tmax, int T, const int* stop,
                                    hipStream_t s) {
-  switch (sh.NB) {
-    case 1: return launch_encode_t<OP, PREC, NQ, 1, 4>(NFS_ENC_ARGS);
-    case 2: return launch_encode_t<OP, PREC, NQ, 2, 4>(NFS_ENC_ARGS);
-    case 4: return launch_encode_t<OP, PREC, NQ, 4, 2>(NFS_ENC_ARGS);
-    case 8: return launch_encode_t<OP, PREC, NQ, 8, 2>(NFS_ENC_ARGS);
+  const int k = sh.NB * 8 + sh.MT;
+  switch (k) {
+    case 1 * 8 + 2: return launch_encode_t<OP, PREC, NQ, 1, 2>(NFS_ENC_ARGS);
+    case 1 * 8 + 4: return launch_encode_t<OP, PREC, NQ, 1, 4>(NFS_ENC_ARGS);
+    case 2 * 8 + 2: return launch_encode_t<OP, PREC, NQ, 2, 2>(NFS_ENC_ARGS);
+    case 2 * 8 + 4: return launch_encode_t<OP, PREC, NQ, 2, 4>(NFS_ENC_ARGS);
+    case 4 * 8 + 2: return launch_encode_t<OP, PREC, NQ, 4, 2>(NFS_ENC_ARGS);
+    case 4 * 8 + 4: return launch_encode_t<OP, PREC, NQ, 4, 4>(NFS_ENC_ARGS);
+    case 8 * 8 + 2: return launch_encode_t<OP, PREC, NQ, 8, 2>(NFS_ENC_ARGS);
   }
   return hipErrorInvalidValue;
 }
@@ -780,7 +789,7 @@ hipError_t launch_encode(const EncodeShape& sh, const void* hc, const void* scf,
                          const float2* sens, int64_t L, int G, const unsigned* tmax, int T, const int* stop,
                          hipStream_t s) {
   if (sh.HC == 0) return hipSuccess;
-  if (sh.MT != held_tiles(sh.NB) || T < 1 || T > kMaxTerms) return hipErrorInvalidValue;
+  if (!valid_held_tiles(sh.NB, sh.MT) || sh.nsplit < 1 || T < 1 || T > kMaxTerms) return hipErrorInvalidValue;
   if (sh.op == OP_E) {
     if (sh.prec == PREC_FP32) return launch_encode_nq<OP_E, PREC_FP32>(NFS_ENC_ARGS);
     if (sh.prec == PREC_BF16) return launch_encode_nq<OP_E, PREC_BF16>(NFS_ENC_ARGS);
@@ -837,6 +846,12 @@ hipError_t launch_grad_kcoef(const float* epart, int nsplit, int64_t HC16, int N
   if (K == 0) return hipSuccess;
   hipLaunchKernelGGL(grad_kcoef_kernel, grid1(K), dim3(256), 0, s, epart, nsplit, HC16, NB, unscale, grad_m, K, G, P,
                      b, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(float* p, int64_t n, float v, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(fill_kernel, grid1(n), dim3(256), 0, s, p, n, v);
   return hipGetLastError();
 }
 

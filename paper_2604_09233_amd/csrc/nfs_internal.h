@@ -41,8 +41,11 @@ inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 // split products per term, 32 k-slots per instruction (1, 2 or 3)
 inline int phase_instrs(int n_basis) { return (int)cdiv(3 * (n_basis + 1), 32); }
 // held tiles per wave: 4 while the accumulators stay small (up to 16 coils),
-// else 2
+// else 2 (the default; the autotuner may pick any valid count)
 inline int held_tiles(int nb) { return nb <= 2 ? 4 : 2; }
+// held-tile counts the encode kernel is built for: 2, and 4 up to 4 column
+// blocks (8 blocks x 4 tiles would not fit the register file)
+inline bool valid_held_tiles(int nb, int mt) { return mt == 2 || (mt == 4 && nb <= 4); }
 // bytes of one packed phase chunk (16 items): NQ instructions x 64 lanes x 16 B
 inline size_t phase_chunk_bytes(int nq) { return (size_t)nq * 64 * 16; }
 // 16-column blocks for 2G real columns (re/im per coil), rounded to 1, 2, 4, 8
@@ -105,6 +108,7 @@ hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, i
 hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
                             const float* unscale, float2* x, hipStream_t s);
 hipError_t launch_fill_zero(float* p, int64_t n_floats, hipStream_t s);
+hipError_t launch_fill(float* p, int64_t n_floats, float v, hipStream_t s);
 // backward: grad_b0 from E^H(t o G) partials; grad_kcoef[:, b] from E(h_b o rho) partials
 hipError_t launch_grad_b0(const float2* hpart, int nsplit, int64_t HC16, int64_t L, const float* unscale,
                           const float2* rho, float* out, hipStream_t s);

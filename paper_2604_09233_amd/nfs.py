@@ -68,6 +68,11 @@ def lib():
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
                                                i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]
             L.nfs_set_graphs.argtypes = [vp, i32]
+            L.nfs_tune_workspace_bytes.argtypes = [vp, pp, i32, ctypes.POINTER(sz)]
+            L.nfs_autotune.argtypes = [vp, pp, i32, vp, sz, vp]
+            L.nfs_tuned_shape.argtypes = [vp, pp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.nfs_tune_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, ctypes.POINTER(sz)]
+            L.nfs_autotune_batched.argtypes = [vp, i32, pp, i32, vp, sz, vp]
             L.nfs_profile_enable.argtypes = [vp, i32]
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
             L.nfs_last_error.restype = ctypes.c_char_p
@@ -76,7 +81,8 @@ def lib():
             for name in ("nfs_create", "nfs_destroy", "nfs_workspace_bytes", "nfs_apply_E", "nfs_apply_EH",
                          "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read",
                          "nfs_encode_backward", "nfs_workspace_bytes_batched", "nfs_cg_solve_batched",
-                         "nfs_set_graphs"):
+                         "nfs_set_graphs", "nfs_tune_workspace_bytes", "nfs_autotune", "nfs_tuned_shape",
+                         "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -230,6 +236,50 @@ def encode_backward(prob: Problem, rho, grad_m, precision: str = "fp32", need_rh
     _check(lib().nfs_encode_backward(context(prob.index), ctypes.byref(prob.st), _ptr(rho), _ptr(grad_m), p(g_rho),
                                      p(g_b0), p(g_k), PRECISIONS[precision], _ptr(ws), ws.numel(), prob._stream()))
     return g_rho, g_b0, g_k
+
+
+def autotune(prob: Problem, precision: str = "fp16"):
+    """Time the encode-kernel tile shapes for this problem's shape class and
+    keep the fastest in the device context (see include/nfs.h).  Returns the
+    chosen {"E": (held_tiles, nsplit), "EH": (...)}; synchronises the stream."""
+    ctx = context(prob.index)
+    n = ctypes.c_size_t()
+    _check(lib().nfs_tune_workspace_bytes(ctx, ctypes.byref(prob.st), PRECISIONS[precision], ctypes.byref(n)))
+    ws = torch.empty(n.value + 256, dtype=torch.uint8, device=prob.device)
+    off = (-ws.data_ptr()) % 256
+    w = ws[off:off + n.value]
+    _check(lib().nfs_autotune(ctx, ctypes.byref(prob.st), PRECISIONS[precision], _ptr(w), n.value, prob._stream()))
+    return tuned_shape(prob, precision)
+
+
+def autotune_batched(probs, precision: str = "fp16"):
+    """Batch-wide tuning of the encode shapes for solving `probs` together
+    with cg_solve_batched (see include/nfs.h).  Returns the per-slice shapes."""
+    if not probs:
+        return []
+    dev = probs[0].device
+    ctx = context(probs[0].index)
+    n = len(probs)
+    arr = (nfs_problem * n)(*[p.st for p in probs])
+    nbytes = ctypes.c_size_t()
+    _check(lib().nfs_tune_workspace_bytes_batched(ctx, n, arr, PRECISIONS[precision], ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    w = ws[off:off + nbytes.value]
+    _check(lib().nfs_autotune_batched(ctx, n, arr, PRECISIONS[precision], _ptr(w), nbytes.value, probs[0]._stream()))
+    return [tuned_shape(p, precision) for p in probs]
+
+
+def tuned_shape(prob: Problem, precision: str = "fp16"):
+    """{"E": (held_tiles, nsplit), "EH": (held_tiles, nsplit)} that calls on
+    this problem's shape class will use."""
+    out = {}
+    for name, op in (("E", OPS["E"]), ("EH", OPS["EH"])):
+        mt, ns = ctypes.c_int(), ctypes.c_int()
+        _check(lib().nfs_tuned_shape(context(prob.index), ctypes.byref(prob.st), PRECISIONS[precision], op,
+                                     ctypes.byref(mt), ctypes.byref(ns)))
+        out[name] = (mt.value, ns.value)
+    return out
 
 
 def set_graphs(device: int, on: bool = True):

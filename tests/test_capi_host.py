@@ -47,7 +47,10 @@ def prob(L=1000, K=777, G=5, P=7, **over):
     return nfs.nfs_problem(L, K, G, P, kw["sens"], kw["fields"], kw["b0"], kw["kcoef"], kw["t"], kw["icorr"])
 
 
-FAKE_CTX = ctypes.create_string_buffer(64)
+# a zero-filled stand-in context, larger than the library's context struct:
+# validation paths read only its plain fields (CU count 0, empty tuning
+# table) and never a device handle
+FAKE_CTX = ctypes.create_string_buffer(4096)
 
 
 def call(L, fn, pr, prec=0, ws=A, ws_bytes=1 << 40, a=A, b=A, ctx=True):
@@ -168,3 +171,47 @@ def test_batched_validation(L):
     L.nfs_workspace_bytes(None, ctypes.byref(ok[1]), 3, 2, 30, 1, ctypes.byref(two))
     assert n.value == one.value + two.value
     assert L.nfs_set_graphs(None, 1) == nfs.NFS_EINVAL
+
+
+def test_autotune_validation(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    pr = prob(L=3000, K=5000, G=12, P=16)
+    n = ctypes.c_size_t()
+    assert L.nfs_tune_workspace_bytes(None, ctypes.byref(pr), 2, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_tune_workspace_bytes(c, ctypes.byref(pr), 2, None) == nfs.NFS_EINVAL
+    assert L.nfs_tune_workspace_bytes(c, ctypes.byref(pr), 9, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_tune_workspace_bytes(c, ctypes.byref(prob(G=0)), 2, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert L.nfs_tune_workspace_bytes(c, ctypes.byref(pr), 2, ctypes.byref(n)) == 0
+    ehe = ctypes.c_size_t()
+    assert L.nfs_workspace_bytes(c, ctypes.byref(pr), 2, 2, 0, 0, ctypes.byref(ehe)) == 0
+    assert n.value > ehe.value and n.value % 256 == 0
+    f = L.nfs_autotune
+    assert f(None, ctypes.byref(pr), 2, A, n.value, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), 2, None, n.value, None) == nfs.NFS_EWORKSPACE
+    assert f(c, ctypes.byref(pr), 2, A + 128, n.value, None) == nfs.NFS_EWORKSPACE
+    assert f(c, ctypes.byref(pr), 2, A, n.value - 256, None) == nfs.NFS_EWORKSPACE
+    assert f(c, ctypes.byref(prob(sens=None)), 2, A, n.value, None) == nfs.NFS_EINVAL
+    mt, ns = ctypes.c_int(), ctypes.c_int()
+    assert L.nfs_tuned_shape(c, ctypes.byref(pr), 2, 0, ctypes.byref(mt), ctypes.byref(ns)) == 0
+    assert mt.value in (2, 4) and ns.value >= 1
+    assert L.nfs_tuned_shape(c, ctypes.byref(pr), 2, 2, ctypes.byref(mt), ctypes.byref(ns)) == nfs.NFS_EINVAL
+    assert L.nfs_tuned_shape(c, ctypes.byref(pr), 2, 1, None, ctypes.byref(ns)) == nfs.NFS_EINVAL
+
+
+def test_autotune_batched_validation(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    arr = (nfs.nfs_problem * 2)(prob(), prob(L=64, K=99, G=3, P=16))
+    n = ctypes.c_size_t()
+    f = L.nfs_tune_workspace_bytes_batched
+    assert f(None, 2, arr, 2, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert f(c, -1, arr, 2, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert f(c, 2, None, 2, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert f(c, 2, arr, 2, None) == nfs.NFS_EINVAL
+    assert f(c, 2, (nfs.nfs_problem * 2)(prob(), prob(G=65)), 2, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert f(c, 2, arr, 2, ctypes.byref(n)) == 0 and n.value > 0 and n.value % 256 == 0
+    g = L.nfs_autotune_batched
+    assert g(None, 2, arr, 2, A, n.value, None) == nfs.NFS_EINVAL
+    assert g(c, 2, arr, 2, None, n.value, None) == nfs.NFS_EWORKSPACE
+    assert g(c, 2, arr, 2, A, n.value - 256, None) == nfs.NFS_EWORKSPACE
+    assert g(c, 2, (nfs.nfs_problem * 2)(prob(), prob(t=None)), 2, A, n.value, None) == nfs.NFS_EINVAL
+    assert g(c, 0, arr, 2, A, 0, None) == 0  # an empty batch has nothing to tune
