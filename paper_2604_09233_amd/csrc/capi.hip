@@ -184,7 +184,7 @@ struct Layout {
   int G, P, NQ, NB, prec;
   EncodeShape shE, shH;
   size_t o_sA, o_sB, o_vA, o_vB, o_tmax, o_dataE, o_dataH, o_epart, o_hpart, o_bmax, o_unscale, o_sensj, o_smax;
-  size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_coef;
+  size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_rn;
   size_t total;
 };
 
@@ -274,8 +274,8 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
     y.o_stop = take(4);
     if (reorth) {
       y.o_V = take((size_t)(n_iter + 1) * y.L * 8);
+      y.o_rn = take((size_t)y.L * 8);
       y.o_rpart = take((size_t)(n_iter + 1) * 2 * kCgBlocks * 8);
-      y.o_coef = take((size_t)(n_iter + 1) * 2 * 8);
     }
   }
   // split partials last: their sizes depend on the encode shapes
@@ -519,8 +519,8 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
   st.info = info ? info : at<int>(ws, y.o_info);
   st.stop = at<int>(ws, y.o_stop);
   st.V = reorth ? at<float2>(ws, y.o_V) : nullptr;
+  st.rn = reorth ? at<float2>(ws, y.o_rn) : nullptr;
   st.rpart = reorth ? at<double>(ws, y.o_rpart) : nullptr;
-  st.coef = reorth ? at<double>(ws, y.o_coef) : nullptr;
   const bool f16ops = scaled_prec(y.prec);  // f16 operand fragments, power-of-two scaled
   st.smax = f16ops ? at<float>(ws, y.o_smax) : nullptr;
   st.bmax = f16ops ? at<float>(ws, y.o_bmax) : nullptr;
@@ -551,12 +551,16 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
   for (int n = 0; n < n_iter; ++n) {
     if ((rc = seq_EHE(c, st.p, f16ops))) return rc;
     NFS_TRY(launch_cg_beta(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_beta");
-    NFS_TRY(launch_cg_update(st, x, y.L, n, s), "cg_update");
-    if (replace_every > 0 && (n + 1) % replace_every == 0 && n + 1 < n_iter) {
+    // the re-orthogonalisation dot products come with the kernel that
+    // writes the final r of this iteration (update, or the replacement)
+    const bool replace = replace_every > 0 && (n + 1) % replace_every == 0 && n + 1 < n_iter;
+    const int nv = reorth ? n + 1 : 0;
+    NFS_TRY(launch_cg_update(st, x, y.L, n, replace ? 0 : nv, s), "cg_update");
+    if (replace) {
       if ((rc = seq_EHE(c, x))) return rc;
-      NFS_TRY(launch_cg_replace(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, s), "cg_replace");
+      NFS_TRY(launch_cg_replace(st, hpart, ns, hstride, unscale_slot(c, 1), y.L, nv, s), "cg_replace");
     }
-    if (reorth) NFS_TRY(launch_cg_reorth(st, n + 1, s), "cg_reorth");
+    if (reorth) NFS_TRY(launch_cg_reorth_apply(st, nv, !replace, s), "cg_reorth_apply");
     NFS_TRY(launch_cg_direction(st, y.L, n, n_iter, tol, s), "cg_direction");
   }
   NFS_TRY(launch_cg_finish(st, x, prob->icorr, y.L, s), "cg_finish");

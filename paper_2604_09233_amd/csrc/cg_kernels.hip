@@ -157,14 +157,51 @@ __global__ __launch_bounds__(256) void cg_beta_kernel(CgState st, const float2* 
   if (threadIdx.x == 0) st.part[blockIdx.x] = a;
 }
 
-// rho += gamma p, r -= gamma q with gamma = alpha_n / beta; partial r^H r -> part[1]
-__global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __restrict__ rho, int64_t L, int n) {
+// Partial sums, over the elements of workgroup column blockIdx.x, of
+// conj(v_j) r for the stored residuals v_j, j in [j0, j1) (re-orthogonal-
+// isation), into rpart.  r[l] is given by rfun(l).  Wave w takes j = j0 + w,
+// j0 + w + 4, ...: each lane accumulates in float64 over its elements (in
+// element order) and the wave reduces with a fixed xor-shuffle tree.
+template <class RF>
+__device__ void reorth_dots(const CgState& st, int j0, int j1, RF&& rfun) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = j0 + wave; j < j1; j += kWaves) {
+    const float2* v = st.V + (size_t)j * st.L;
+    double re = 0.0, im = 0.0;
+    for (int64_t base = (int64_t)blockIdx.x * 256; base < st.L; base += (int64_t)gridDim.x * 256)
+      for (int k = lane; k < 256; k += 64) {
+        const int64_t l = base + k;
+        if (l >= st.L) break;
+        const float2 a = v[l], r = rfun(l);
+        re += (double)a.x * r.x + (double)a.y * r.y;
+        im += (double)a.x * r.y - (double)a.y * r.x;
+      }
+    for (int off = 32; off > 0; off >>= 1) {
+      re += __shfl_xor(re, off);
+      im += __shfl_xor(im, off);
+    }
+    if (lane == 0) {
+      st.rpart[(2 * (size_t)j) * kCgBlocks + blockIdx.x] = re;
+      st.rpart[(2 * (size_t)j + 1) * kCgBlocks + blockIdx.x] = im;
+    }
+  }
+}
+
+// rho += gamma p, r -= gamma q with gamma = alpha_n / beta.  Grid
+// (nblk, ny).  Row y = 0 does the update: rho, and the new r into st.r
+// (partial r^H r -> part[1]) or, with re-orthogonalisation (nv > 0), into
+// st.rn, left for cg_reorth_apply; partial ||rho||^2 -> part[2].  With
+// nv > 0 every workgroup (x, y) also forms the partial dot products of the
+// new r with v_j, j in [4y, 4y + 4), recomputing the new r of its elements
+// from the unmodified r and q with the same arithmetic.
+__global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __restrict__ rho, int64_t L, int n,
+                                                        int nv) {
   if (*st.stop) return;
   __shared__ double red[256];
   const double beta = sum_partials(st.part, st.nblk, red);
   const double alpha = st.alpha[n];
   if (!(beta > 0.0) || !isfinite(beta)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
       st.info[1] = CG_BREAKDOWN;
       *st.stop = 1;
     }
@@ -172,32 +209,46 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
   }
   const double gamma = alpha / beta;
   const float gf = (float)gamma;
-  double a = 0.0, xx = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
-    const float2 p = st.p[l], q = st.q[l];
-    float2 x = rho[l], r = st.r[l];
-    x.x = fmaf(gf, p.x, x.x);
-    x.y = fmaf(gf, p.y, x.y);
-    r.x = fmaf(-gf, q.x, r.x);
-    r.y = fmaf(-gf, q.y, r.y);
-    rho[l] = x;
-    st.r[l] = r;
-    a += (double)r.x * r.x + (double)r.y * r.y;
-    xx += (double)x.x * x.x + (double)x.y * x.y;
+  if (blockIdx.y == 0) {
+    float2* rout = nv > 0 ? st.rn : st.r;
+    double a = 0.0, xx = 0.0;
+    for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+      const float2 p = st.p[l], q = st.q[l];
+      float2 x = rho[l], r = st.r[l];
+      x.x = fmaf(gf, p.x, x.x);
+      x.y = fmaf(gf, p.y, x.y);
+      r.x = fmaf(-gf, q.x, r.x);
+      r.y = fmaf(-gf, q.y, r.y);
+      rho[l] = x;
+      rout[l] = r;
+      a += (double)r.x * r.x + (double)r.y * r.y;
+      xx += (double)x.x * x.x + (double)x.y * x.y;
+    }
+    a = block_sum(a, red);
+    xx = block_sum(xx, red);
+    if (threadIdx.x == 0) {
+      st.part[kCgBlocks + blockIdx.x] = a;
+      st.part[2 * kCgBlocks + blockIdx.x] = xx;
+      if (blockIdx.x == 0) st.scal[0] = beta;
+    }
   }
-  a = block_sum(a, red);
-  xx = block_sum(xx, red);
-  if (threadIdx.x == 0) {
-    st.part[kCgBlocks + blockIdx.x] = a;
-    st.part[2 * kCgBlocks + blockIdx.x] = xx;
-    if (blockIdx.x == 0) st.scal[0] = beta;
+  if (nv > 0) {
+    const int j0 = 4 * blockIdx.y, j1 = j0 + 4 < nv ? j0 + 4 : nv;
+    reorth_dots(st, j0, j1, [&](int64_t l) {
+      const float2 q = st.q[l];
+      float2 r = st.r[l];
+      r.x = fmaf(-gf, q.x, r.x);
+      r.y = fmaf(-gf, q.y, r.y);
+      return r;
+    });
   }
 }
 
 // residual replacement: r = b - (E^H E rho); partial r^H r -> part[1]
+// (with nv > 0 also the re-orthogonalisation dot products of the new r)
 __global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
                                                          int64_t stride, const float* __restrict__ unscale,
-                                                         int64_t L) {
+                                                         int64_t L, int nv) {
   if (*st.stop) return;
   __shared__ double red[256];
   const float u = unscale ? *unscale : 1.f;
@@ -211,6 +262,10 @@ __global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float
   }
   a = block_sum(a, red);
   if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+  if (nv > 0) {
+    __syncthreads();  // this workgroup's r writes are visible to all its waves
+    reorth_dots(st, 0, nv, [&](int64_t l) { return st.r[l]; });
+  }
 }
 
 // alpha_{n+1} = r^H r; p = r + (alpha_{n+1} / alpha_n) p; with
@@ -280,47 +335,27 @@ __global__ __launch_bounds__(256) void cg_store_v_kernel(CgState st, int j) {
   }
 }
 
-// grid (nblk, nv): partial sums of conj(v_j) r
-__global__ __launch_bounds__(256) void cg_reorth_dots_kernel(CgState st) {
+// r = src - sum_j (v_j^H src) v_j with src = st.rn (after cg_update) or st.r
+// (after a residual replacement).  Every workgroup first sums the nblk
+// partials of each v_j^H src itself (thread i takes sum i, partials in
+// workgroup order), so all workgroups use bit-identical coefficients;
+// partial r^H r -> part[1].
+__global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv, int from_rn) {
   if (*st.stop) return;
   __shared__ double red[256];
-  const int j = blockIdx.y;
-  const float2* v = st.V + (size_t)j * st.L;
-  double re = 0.0, im = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
-    const float2 a = v[l], r = st.r[l];
-    re += (double)a.x * r.x + (double)a.y * r.y;
-    im += (double)a.x * r.y - (double)a.y * r.x;
+  __shared__ double coef[2 * (kMaxReorth + 1)];
+  for (int i = threadIdx.x; i < 2 * nv; i += 256) {
+    const double* pp = st.rpart + (size_t)i * kCgBlocks;
+    double t = 0.0;
+    for (int b = 0; b < st.nblk; ++b) t += pp[b];
+    coef[i] = t;
   }
-  re = block_sum(re, red);
-  im = block_sum(im, red);
-  if (threadIdx.x == 0) {
-    st.rpart[(2 * (size_t)j) * kCgBlocks + blockIdx.x] = re;
-    st.rpart[(2 * (size_t)j + 1) * kCgBlocks + blockIdx.x] = im;
-  }
-}
-
-// workgroup j: coef[j] = sum of the partials of v_j^H r (fixed order)
-__global__ __launch_bounds__(256) void cg_reorth_coef_kernel(CgState st) {
-  if (*st.stop) return;
-  __shared__ double red[256];
-  const int j = blockIdx.x;
-  const double re = sum_partials(st.rpart + (2 * (size_t)j) * kCgBlocks, st.nblk, red);
-  const double im = sum_partials(st.rpart + (2 * (size_t)j + 1) * kCgBlocks, st.nblk, red);
-  if (threadIdx.x == 0) {
-    st.coef[2 * j] = re;
-    st.coef[2 * j + 1] = im;
-  }
-}
-
-__global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv) {
-  if (*st.stop) return;
-  __shared__ double red[256];
+  __syncthreads();
   double a = 0.0;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
-    float2 r = st.r[l];
+    float2 r = from_rn ? st.rn[l] : st.r[l];
     for (int j = 0; j < nv; ++j) {
-      const float cr = (float)st.coef[2 * j], ci = (float)st.coef[2 * j + 1];
+      const float cr = (float)coef[2 * j], ci = (float)coef[2 * j + 1];
       const float2 v = st.V[(size_t)j * st.L + l];
       r.x -= cr * v.x - ci * v.y;
       r.y -= cr * v.y + ci * v.x;
@@ -376,14 +411,15 @@ hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, in
   return hipGetLastError();
 }
 
-hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s) {
-  hipLaunchKernelGGL(cg_update_kernel, dim3(st.nblk), dim3(256), 0, s, st, rho, L, n);
+hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, int nv, hipStream_t s) {
+  const unsigned ny = nv > 0 ? (unsigned)cdiv(nv, 4) : 1u;
+  hipLaunchKernelGGL(cg_update_kernel, dim3(st.nblk, ny), dim3(256), 0, s, st, rho, L, n, nv);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
-                             const float* unscale, int64_t L, hipStream_t s) {
-  hipLaunchKernelGGL(cg_replace_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, L);
+                             const float* unscale, int64_t L, int nv, hipStream_t s) {
+  hipLaunchKernelGGL(cg_replace_kernel, dim3(st.nblk), dim3(256), 0, s, st, hpart, nsplit, stride, unscale, L, nv);
   return hipGetLastError();
 }
 
@@ -397,14 +433,8 @@ hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_cg_reorth(const CgState& st, int nv, hipStream_t s) {
-  hipLaunchKernelGGL(cg_reorth_dots_kernel, dim3(st.nblk, nv), dim3(256), 0, s, st);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cg_reorth_coef_kernel, dim3(nv), dim3(256), 0, s, st);
-  e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(cg_reorth_apply_kernel, dim3(st.nblk), dim3(256), 0, s, st, nv);
+hipError_t launch_cg_reorth_apply(const CgState& st, int nv, bool from_rn, hipStream_t s) {
+  hipLaunchKernelGGL(cg_reorth_apply_kernel, dim3(st.nblk), dim3(256), 0, s, st, nv, (int)from_rn);
   return hipGetLastError();
 }
 

@@ -128,8 +128,8 @@ struct CgState {
   int* info;        // [2]
   int* stop;        // [1]
   float2* V;        // [n_iter + 1][L] normalised residuals (re-orthogonalisation) or NULL
+  float2* rn;       // [L] the updated residual before re-orthogonalisation, or NULL
   double* rpart;    // [n_iter + 1][2][kCgBlocks] partial dot products v_j^H r
-  double* coef;     // [n_iter + 1][2] v_j^H r
   const float* smax;  // [L] max_c |S[c][l]| (FP16 operands) or NULL
   float* bmax;        // [kBmaxBlocks] bound on the next E operand (with smax)
   int64_t L;
@@ -145,15 +145,20 @@ hipError_t launch_cg_init(const CgState& st, const float2* hpart, int nsplit, in
 hipError_t launch_cg_start(const CgState& st, int n_iter, hipStream_t s);
 hipError_t launch_cg_beta(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
                           const float* unscale, int64_t L, hipStream_t s);
-hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, hipStream_t s);
+// nv > 0: the new r goes to st.rn, and the partial dot products of it with
+// V[0..nv) to rpart (grid (nblk, ceil(nv / 4)))
+hipError_t launch_cg_update(const CgState& st, float2* rho, int64_t L, int n, int nv, hipStream_t s);
+// nv > 0: also the partial dot products of the new r with V[0..nv) (rpart)
 hipError_t launch_cg_replace(const CgState& st, const float2* hpart, int nsplit, int64_t stride,
-                             const float* unscale, int64_t L, hipStream_t s);
+                             const float* unscale, int64_t L, int nv, hipStream_t s);
 // p = r + (alpha'/alpha) p (and, with st.smax, the E operand bound into st.bmax)
 hipError_t launch_cg_direction(const CgState& st, int64_t L, int n, int n_iter, double tol, hipStream_t s);
 // V[j] = r / sqrt(alpha_j)
 hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
 // r -= sum_{j < nv} (v_j^H r) v_j; partial r^H r -> part[1]
-hipError_t launch_cg_reorth(const CgState& st, int nv, hipStream_t s);
+// r = src - sum_{j < nv} (v_j^H src) v_j from the partials in rpart, src = st.rn
+// (from_rn) or st.r; partial r^H r -> part[1]
+hipError_t launch_cg_reorth_apply(const CgState& st, int nv, bool from_rn, hipStream_t s);
 hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, int64_t L, hipStream_t s);
 
 }  // namespace nfs
