@@ -55,6 +55,7 @@ def parse():
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched-solve measurement")
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 96x96x48 / 32-coil solve measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default encode shapes instead of autotuned ones")
+    ap.add_argument("--no-resident", action="store_true", help="skip the resident-P (non-split) solve measurement")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
@@ -324,6 +325,32 @@ def main():
                     avg_launch_ms=avg_ms, launches=n_k,
                     mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
 
+    resident = None
+    if not args.no_resident and args.precision == "fp16":
+        # non-split form: P built once per solve (2 K L x 4 bytes), streamed by every E and E^H
+        def t_res(n):
+            o = torch.empty(L, dtype=torch.complex64, device=dev)
+            h = torch.full((n + 1, 3), float("nan"), dtype=torch.float64, device=dev)
+            f = torch.zeros(2, dtype=torch.int32, device=dev)
+            nfs.cg_solve_resident(prob, m, n, reorth=not args.plain, out=o, hist=h, info=f)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nfs.cg_solve_resident(prob, m, n, reorth=not args.plain, out=o, hist=h, info=f)
+            e1.record()
+            torch.cuda.synchronize()
+            return o, e0.elapsed_time(e1)
+        rr, ms_r = t_res(n_iter)
+        _, ms_r1 = t_res(1)
+        resident = dict(ms_per_step=ms_r, ms_per_iteration=(ms_r - ms_r1) / (n_iter - 1),
+                        ms_build_and_first_iteration=ms_r1, P_bytes=2 * L * K * 4,
+                        identical_to_split=bool(torch.equal(rr.cpu(), rho.cpu())),
+                        rel_err_vs_oracle=rel(rr.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
+        del rr
+        prob._ws.pop(("CG_RESIDENT", args.precision, n_iter, not args.plain), None)
+        prob._ws.pop(("CG_RESIDENT", args.precision, 1, not args.plain), None)
+        torch.cuda.empty_cache()
+
     batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
     threed = None if args.no_3d else threed_run(nfs, synth, torch, dev, args)
 
@@ -355,6 +382,7 @@ def main():
         "plain_recurrences": plain,
         "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
         "roofline": roofline,
+        "resident_P": resident,
         "batched": batched,
         "3d": threed,
         "wall_s_timed": wall,

@@ -73,7 +73,7 @@ enum nfs_status {
 enum nfs_precision { NFS_FP32 = 0, NFS_BF16 = 1, NFS_FP16 = 2 };
 
 /* Operation selector for nfs_workspace_bytes. */
-enum nfs_op { NFS_OP_E = 0, NFS_OP_EH = 1, NFS_OP_EHE = 2, NFS_OP_CG = 3 };
+enum nfs_op { NFS_OP_E = 0, NFS_OP_EH = 1, NFS_OP_EHE = 2, NFS_OP_CG = 3, NFS_OP_CG_RESIDENT = 4 };
 
 /* Values of info[1] written by nfs_cg_solve. */
 enum nfs_cg_status {
@@ -108,9 +108,11 @@ int nfs_destroy(nfs_ctx* ctx);
 
 /* Workspace bytes needed by `op` (enum nfs_op) at `precision` for problem
  * sizes `prob` (only the sizes and whether icorr is NULL are read; array
- * pointers may be NULL here).  For NFS_OP_CG the size also depends on
- * n_iter and reorth (both ignored for the other ops).  Host-only; never
- * touches the device.                                                    */
+ * pointers may be NULL here).  For NFS_OP_CG and NFS_OP_CG_RESIDENT the size
+ * also depends on n_iter and reorth (both ignored for the other ops);
+ * NFS_OP_CG_RESIDENT (nfs_cg_solve_resident) adds 2 K L x 4 bytes for the
+ * resident P and takes only NFS_FP16 (NFS_EUNSUPPORTED otherwise).
+ * Host-only; never touches the device.                                    */
 int nfs_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, int op, int precision,
                         int n_iter, int reorth, size_t* bytes);
 
@@ -157,6 +159,19 @@ int nfs_apply_EHE(nfs_ctx* ctx, const nfs_problem* prob, const float* p, float* 
 int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho,
                  int n_iter, double tol, int replace_every, int reorth, int precision,
                  double* hist, int* info, void* ws, size_t ws_bytes, void* stream);
+
+/* The same solve in the non-split form of the reconstruction figure (left
+ * column): the phase factors P = exp(i phi) are built once per solve, as the
+ * float16 (cos, sin) operand of the FP16 contraction (2 K L x 4 bytes of
+ * workspace: one copy per direction), and every E and E^H of the solve
+ * streams them from memory instead of rebuilding them.  Same arguments,
+ * results and rules as nfs_cg_solve; precision must be NFS_FP16
+ * (NFS_EUNSUPPORTED otherwise); workspace: NFS_OP_CG_RESIDENT.  Meant for
+ * problems whose P fits in memory (2D slices); results agree with
+ * nfs_cg_solve up to the order of float32 sums.                            */
+int nfs_cg_solve_resident(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                          double tol, int replace_every, int reorth, int precision, double* hist, int* info,
+                          void* ws, size_t ws_bytes, void* stream);
 
 /* Many independent reconstructions (slices with uneven L, K and G) solved
  * together: each slice runs exactly the nfs_cg_solve sequence (same kernels,

@@ -185,6 +185,7 @@ struct Layout {
   EncodeShape shE, shH;
   size_t o_sA, o_sB, o_vA, o_vB, o_tmax, o_dataE, o_dataH, o_epart, o_hpart, o_bmax, o_unscale, o_sensj, o_smax;
   size_t o_r, o_p, o_q, o_b, o_part, o_alpha, o_scal, o_hist, o_info, o_stop, o_V, o_rpart, o_rn;
+  size_t o_PE, o_PH;  // resident P (NFS_OP_CG_RESIDENT)
   size_t total;
 };
 
@@ -240,7 +241,8 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
   y.prec = prec;
   y.shE = encode_shape(ctx, pr, OP_E, prec, y.NQ, y.NB, y.KC, y.LC, ovE);
   y.shH = encode_shape(ctx, pr, OP_EH, prec, y.NQ, y.NB, y.LC, y.KC, ovH);
-  const bool needE = op != NFS_OP_EH, needH = op != NFS_OP_E, cg = op == NFS_OP_CG;
+  const bool needE = op != NFS_OP_EH, needH = op != NFS_OP_E;
+  const bool cg = op == NFS_OP_CG || op == NFS_OP_CG_RESIDENT;
 
   size_t o = 0;
   auto take = [&](size_t bytes) {
@@ -278,6 +280,10 @@ static Layout make_layout(const nfs_ctx* ctx, const nfs_problem* pr, int op, int
       y.o_rpart = take((size_t)(n_iter + 1) * 2 * kCgBlocks * 8);
     }
   }
+  if (op == NFS_OP_CG_RESIDENT) {
+    y.o_PE = take(resident_P_bytes(y.KC, y.LC));
+    y.o_PH = take(resident_P_bytes(y.LC, y.KC));
+  }
   // split partials last: their sizes depend on the encode shapes
   y.o_epart = needE ? take(epart_bytes(y.shE, y.NB)) : 0;
   y.o_hpart = needH ? take(hpart_bytes(y.shH)) : 0;
@@ -292,11 +298,12 @@ extern "C" int nfs_workspace_bytes(const nfs_ctx* ctx, const nfs_problem* prob, 
   int rc = check_sizes(prob, fn);
   if (rc) return rc;
   if ((rc = check_prec(precision, fn))) return rc;
-  if (op < NFS_OP_E || op > NFS_OP_CG) return fail(NFS_EINVAL, "%s: unknown op %d", fn, op);
-  if (op == NFS_OP_CG && n_iter < 0) return fail(NFS_EINVAL, "%s: n_iter %d < 0", fn, n_iter);
-  if (op == NFS_OP_CG && reorth && n_iter > kMaxReorth)
-    return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
-  const bool cg = op == NFS_OP_CG;
+  if (op < NFS_OP_E || op > NFS_OP_CG_RESIDENT) return fail(NFS_EINVAL, "%s: unknown op %d", fn, op);
+  const bool cg = op == NFS_OP_CG || op == NFS_OP_CG_RESIDENT;
+  if (cg && n_iter < 0) return fail(NFS_EINVAL, "%s: n_iter %d < 0", fn, n_iter);
+  if (cg && reorth && n_iter > kMaxReorth) return fail(NFS_EINVAL, "%s: reorth needs n_iter <= %d", fn, kMaxReorth);
+  if (op == NFS_OP_CG_RESIDENT && precision != NFS_FP16)
+    return fail(NFS_EUNSUPPORTED, "%s: the resident form takes NFS_FP16 operands", fn);
   *bytes = make_layout(ctx, prob, op, precision, cg ? n_iter : 0, cg ? (reorth != 0) : 0).total;
   return NFS_OK;
 }
@@ -330,6 +337,8 @@ struct Ctx {
   void* ws;
   hipStream_t s;
   const int* stop;
+  const void* PE = nullptr;  // resident P of E and of E^H (non-split form), or NULL
+  const void* PH = nullptr;
 };
 
 // Launch the encode kernel, bracketed by HIP events when profiling is on.
@@ -383,6 +392,9 @@ static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr, bo
                            bmax, at<float>(c.ws, y.o_unscale), c.stop, c.s),
           "pack_data(E)");
   return timed_encode(c, 0, [&] {
+    if (c.PE)
+      return launch_resident(y.shE, c.PE, at<void>(c.ws, y.o_dataE), at<float>(c.ws, y.o_epart), c.sens, y.L, y.G,
+                             c.stop, c.s);
     return launch_encode(y.shE, at<void>(c.ws, y.o_sB), at<void>(c.ws, y.o_vA), at<void>(c.ws, y.o_dataE),
                          at<float>(c.ws, y.o_epart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
                          c.s);
@@ -399,6 +411,9 @@ static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const
                            bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
           "pack_data(EH)");
   return timed_encode(c, 1, [&] {
+    if (c.PH)
+      return launch_resident(y.shH, c.PH, at<void>(c.ws, y.o_dataH), at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G,
+                             c.stop, c.s);
     return launch_encode(y.shH, at<void>(c.ws, y.o_vB), at<void>(c.ws, y.o_sA), at<void>(c.ws, y.o_dataH),
                          at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
                          c.s);
@@ -415,6 +430,9 @@ static int seq_EHE(const Ctx& c, const float2* p, bool bmax_ready = false) {
                                     us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
           "pack_EH_from_epart");
   return timed_encode(c, 1, [&] {
+    if (c.PH)
+      return launch_resident(y.shH, c.PH, at<void>(c.ws, y.o_dataH), at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G,
+                             c.stop, c.s);
     return launch_encode(y.shH, at<void>(c.ws, y.o_vB), at<void>(c.ws, y.o_sA), at<void>(c.ws, y.o_dataH),
                          at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G, at<unsigned>(c.ws, y.o_tmax), y.P + 1, c.stop,
                          c.s);
@@ -504,8 +522,11 @@ static int check_cg_args(const nfs_ctx* ctx, const nfs_problem* prob, const floa
 }
 
 // The launch sequence of one CG solve (arguments already checked).
+// resident: build P once (the non-split form) and stream it in every E and
+// E^H instead of rebuilding the phase tiles
 static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const float* m, float* rho, int n_iter,
-                  double tol, int replace_every, int reorth, double* hist, int* info, void* ws, hipStream_t s) {
+                  double tol, int replace_every, int reorth, double* hist, int* info, void* ws, hipStream_t s,
+                  bool resident = false) {
   int rc;
   CgState st;
   st.r = at<float2>(ws, y.o_r);
@@ -543,6 +564,17 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
 
   NFS_TRY(launch_cg_reset(st, s), "cg_reset");
   if ((rc = seq_pack_coefs(c, true, true))) return rc;
+  if (resident) {
+    const unsigned* tmax = at<unsigned>(ws, y.o_tmax);
+    NFS_TRY(launch_build_P(y.NQ, at<void>(ws, y.o_sB), at<void>(ws, y.o_vA), y.KC, y.LC, tmax, y.P + 1,
+                           at<void>(ws, y.o_PE), s),
+            "build_P(E)");
+    NFS_TRY(launch_build_P(y.NQ, at<void>(ws, y.o_vB), at<void>(ws, y.o_sA), y.LC, y.KC, tmax, y.P + 1,
+                           at<void>(ws, y.o_PH), s),
+            "build_P(EH)");
+    c.PE = at<void>(ws, y.o_PE);
+    c.PH = at<void>(ws, y.o_PH);
+  }
   NFS_TRY(launch_cg_norm_m(st, reinterpret_cast<const float2*>(m), (int64_t)y.G * y.K, s), "cg_norm_m");
   if ((rc = seq_EH(c, reinterpret_cast<const float2*>(m), 1, y.K))) return rc;
   NFS_TRY(launch_cg_init(st, hpart, ns, hstride, unscale_slot(c, 1), x, y.L, s), "cg_init");
@@ -651,6 +683,24 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
       graph_key(ctx, "cg", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
   return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
     return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st);
+  });
+}
+
+extern "C" int nfs_cg_solve_resident(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                                     double tol, int replace_every, int reorth, int precision, double* hist,
+                                     int* info, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_cg_solve_resident";
+  int rc = check_cg_args(ctx, prob, m, rho, n_iter, tol, replace_every, reorth, precision, hist, info, fn);
+  if (rc) return rc;
+  if (precision != NFS_FP16) return fail(NFS_EUNSUPPORTED, "%s: the resident form takes NFS_FP16 operands", fn);
+  const Layout y = make_layout(ctx, prob, NFS_OP_CG_RESIDENT, precision, n_iter, reorth);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const void* ptrs[4] = {m, rho, hist, info};
+  const std::string key =
+      graph_key(ctx, "cgr", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
+  return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
+    return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st, true);
   });
 }
 

@@ -16,6 +16,8 @@
 //   E:   [y_re y_im] = [cos sin] . [[Q_re, Q_im], [-Q_im, Q_re]]
 //   E^H: [x_re x_im] = [cos sin] . [[m_re, m_im], [ m_im, -m_re]]
 // (real columns interleaved per coil: column 2c is re, 2c+1 is im).
+#include <algorithm>
+
 #include "nfs_internal.h"
 
 namespace nfs {
@@ -485,6 +487,66 @@ __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, cons
   }
 }
 
+// Epilogue of the contraction kernels.  E: the partial y rows go to
+// out_part[split][HC*16][NB*16].  E^H: each lane forms conj(S) times its
+// column's re or im part, the 16 lanes of a row group are summed with
+// xor-shuffles (fixed order), and the coil-combined partial x goes to
+// out_part (as float2) [split][HC*16].
+template <int OP, int NB, int MT>
+__device__ __forceinline__ void write_partials(const f4 (&acc)[MT][NB], int64_t tile0, int64_t split, int64_t HC,
+                                               float* __restrict__ out_part, const float2* __restrict__ sens,
+                                               int64_t L, int G, int lane) {
+  const int g = lane >> 4, n = lane & 15;
+  if (OP == OP_E) {
+    float* o = out_part + (size_t)split * (size_t)HC * 16 * (NB * 16);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t tile = tile0 + mt;
+      if (tile >= HC) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t row = tile * 16 + g * 4 + r;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) o[row * (NB * 16) + nb * 16 + n] = acc[mt][nb][r];
+      }
+    }
+  } else {
+    float2* o = (float2*)out_part + (size_t)split * (size_t)HC * 16;
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t tile = tile0 + mt;
+      if (tile >= HC) continue;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t l = tile * 16 + g * 4 + r;
+        float xr = 0.f, xi = 0.f;
+#pragma unroll
+        for (int nb = 0; nb < NB; ++nb) {
+          const int N = nb * 16 + n;
+          const int c = N >> 1;
+          if (c < G && l < L) {
+            const float2 s = sens[(int64_t)c * L + l];
+            const float v = acc[mt][nb][r];
+            if ((N & 1) == 0) {
+              xr += s.x * v;
+              xi -= s.y * v;
+            } else {
+              xr += s.y * v;
+              xi += s.x * v;
+            }
+          }
+        }
+#pragma unroll
+        for (int off = 8; off > 0; off >>= 1) {
+          xr += __shfl_xor(xr, off);
+          xi += __shfl_xor(xi, off);
+        }
+        if (n == r) o[l] = make_float2(xr, xi);
+      }
+    }
+  }
+}
+
 // Walk streamed chunks [c0, c1) through the double-buffered LDS stage: the
 // loads for chunk ch + 1 are issued right after the barrier that publishes
 // chunk ch and overlap its compute.
@@ -556,55 +618,115 @@ __global__ __launch_bounds__(256) void encode_kernel(
   else
     stream_range<PREC, NQ, NB, MT, true>(strmcoef, sd, c0, c1, hc, acc, stage[0], stage[1], wave, lane);
 
-  const int g = lane >> 4, n = lane & 15;
-  if (OP == OP_E) {
-    float* o = out_part + (size_t)split * (size_t)HC * 16 * (NB * 16);
+  write_partials<OP, NB, MT>(acc, tile0, split, HC, out_part, sens, L, G, lane);
+}
+
+// ---------------------------------------------------------------------------
+// Resident P (the non-split form of the reconstruction figure): the (cos,
+// sin) fragments of every (held tile, streamed chunk) pair are built once
+// and kept in HBM, and every later E or E^H streams them instead of
+// rebuilding them.  Layout, one array per direction:
+//   P[(held tile * SC + streamed chunk) * 64 + lane] = 8 f16,
+// the A fragment of the FP16 contraction exactly as the encode kernel forms
+// it in registers (row = held item, k-slots = 4 streamed items x {cos, sin}).
+
+// grid-stride over pairs, one wave per pair
+template <int NQ>
+__global__ __launch_bounds__(256) void build_P_kernel(const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef,
+                                                      int64_t HC, int64_t SC, const unsigned* __restrict__ tmax,
+                                                      int T, h8* __restrict__ P) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  float bound = 0.f;
+  if (lane < T) bound = __uint_as_float(tmax[lane]) * (float)kInv2Pi * __uint_as_float(tmax[kMaxTerms + lane]);
+  for (int off = 32; off > 0; off >>= 1) bound += __shfl_xor(bound, off);
+  const bool raw = bound < kRawPhaseBound;
+  const int64_t npair = HC * SC;
+  for (int64_t pair = (int64_t)blockIdx.x * kWaves + wave; pair < npair; pair += (int64_t)gridDim.x * kWaves) {
+    const int64_t ht = pair / SC, ch = pair - ht * SC;
+    f4 ph = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int64_t tile = tile0 + mt;
-      if (tile >= HC) continue;
+    for (int q = 0; q < NQ; ++q)
+      ph = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, strmcoef[(ch * NQ + q) * 64 + lane]),
+                                                  __builtin_bit_cast(h8, heldcoef[(ht * NQ + q) * 64 + lane]), ph, 0,
+                                                  0, 0);
+    h8 a;
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = tile * 16 + g * 4 + r;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) o[row * (NB * 16) + nb * 16 + n] = acc[mt][nb][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const float x = raw ? ph[r] : __builtin_amdgcn_fractf(ph[r]);
+      a[2 * r] = (_Float16)__builtin_amdgcn_cosf(x);
+      a[2 * r + 1] = (_Float16)__builtin_amdgcn_sinf(x);
     }
-  } else {
-    float2* o = (float2*)out_part + (size_t)split * (size_t)HC * 16;
-#pragma unroll
-    for (int mt = 0; mt < MT; ++mt) {
-      const int64_t tile = tile0 + mt;
-      if (tile >= HC) continue;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t l = tile * 16 + g * 4 + r;
-        float xr = 0.f, xi = 0.f;
-#pragma unroll
-        for (int nb = 0; nb < NB; ++nb) {
-          const int N = nb * 16 + n;
-          const int c = N >> 1;
-          if (c < G && l < L) {
-            const float2 s = sens[(int64_t)c * L + l];
-            const float v = acc[mt][nb][r];
-            if ((N & 1) == 0) {
-              xr += s.x * v;
-              xi -= s.y * v;
-            } else {
-              xr += s.y * v;
-              xi += s.x * v;
-            }
-          }
-        }
-#pragma unroll
-        for (int off = 8; off > 0; off >>= 1) {
-          xr += __shfl_xor(xr, off);
-          xi += __shfl_xor(xi, off);
-        }
-        if (n == r) o[l] = make_float2(xr, xi);
-      }
-    }
+    P[pair * 64 + lane] = a;
   }
+}
+
+// The FP16 contraction against a resident P: same grid, split, LDS staging of
+// the streamed data operand and epilogue as the encode kernel; the A
+// fragments of the next chunk are loaded from P one chunk ahead.
+template <int OP, int NB, int MT>
+__global__ __launch_bounds__(256) void resident_kernel(const u4* __restrict__ P, const u4* __restrict__ sdata,
+                                                       int64_t HC, int64_t SC, int64_t cps,
+                                                       float* __restrict__ out_part, const float2* __restrict__ sens,
+                                                       int64_t L, int G, const int* stop) {
+  if (stop && *stop) return;
+  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
+  int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
+  const int64_t per = nblk / 8;
+  if (b < per * 8) b = (b % 8) * per + b / 8;
+  const int64_t bx = b % gridDim.x;
+  const int64_t split = b / gridDim.x;
+  const int lane = threadIdx.x & 63;
+  const int wave = threadIdx.x >> 6;
+  const int64_t tile0 = (bx * kWaves + wave) * MT;
+
+  f4 acc[MT][NB];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) acc[mt][nb] = f4{0.f, 0.f, 0.f, 0.f};
+  __shared__ u4 stage[2][NB * 64];
+  const int64_t c0 = split * cps;
+  const int64_t c1 = (c0 + cps < SC) ? c0 + cps : SC;
+  auto stage_data = [&](int64_t ch, u4* dst) {
+#pragma unroll
+    for (int blk = wave; blk < NB; blk += kWaves)
+      __builtin_amdgcn_global_load_lds((const void*)(sdata + (ch * NB + blk) * 64 + lane), (lds_void*)(dst + blk * 64),
+                                       16, 0, 0);
+  };
+  auto load_p = [&](int64_t ch, u4 (&pa)[MT]) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) {
+      const int64_t tile = tile0 + mt;
+      pa[mt] = tile < HC ? P[(tile * SC + ch) * 64 + lane] : u4{0, 0, 0, 0};
+    }
+  };
+  u4 pc[MT], pn[MT];
+  if (c0 < c1) {
+    stage_data(c0, stage[0]);
+    load_p(c0, pc);
+  }
+  int buf = 0;
+  for (int64_t ch = c0; ch < c1; ++ch) {
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's loads of chunk ch (LDS copies and P) have landed
+    __syncthreads();                 // ... and every wave's; the other buffer is free
+    if (ch + 1 < c1) {
+      stage_data(ch + 1, stage[buf ^ 1]);
+      load_p(ch + 1, pn);
+    }
+    u4 d[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) d[nb] = stage[buf][nb * 64 + lane];
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+#pragma unroll
+      for (int nb = 0; nb < NB; ++nb)
+        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, pc[mt]),
+                                                             __builtin_bit_cast(h8, d[nb]), acc[mt][nb], 0, 0, 0);
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt) pc[mt] = pn[mt];
+    buf ^= 1;
+  }
+  write_partials<OP, NB, MT>(acc, tile0, split, HC, out_part, sens, L, G, lane);
 }
 
 // ---------------------------------------------------------------------------
@@ -800,6 +922,52 @@ hipError_t launch_encode(const EncodeShape& sh, const void* hc, const void* scf,
   return launch_encode_nq<OP_EH, PREC_FP16>(NFS_ENC_ARGS);
 }
 #undef NFS_ENC_ARGS
+
+hipError_t launch_build_P(int NQ, const void* heldcoef, const void* strmcoef, int64_t HC, int64_t SC,
+                          const unsigned* tmax, int T, void* P, hipStream_t s) {
+  const int64_t npair = HC * SC;
+  if (npair == 0) return hipSuccess;
+  const dim3 gr((unsigned)std::min<int64_t>(cdiv(npair, kWaves), 1 << 20)), bl(64 * kWaves);
+  switch (NQ) {
+    case 1: hipLaunchKernelGGL(build_P_kernel<1>, gr, bl, 0, s, (const u4*)heldcoef, (const u4*)strmcoef, HC, SC, tmax, T, (h8*)P); break;
+    case 2: hipLaunchKernelGGL(build_P_kernel<2>, gr, bl, 0, s, (const u4*)heldcoef, (const u4*)strmcoef, HC, SC, tmax, T, (h8*)P); break;
+    case 3: hipLaunchKernelGGL(build_P_kernel<3>, gr, bl, 0, s, (const u4*)heldcoef, (const u4*)strmcoef, HC, SC, tmax, T, (h8*)P); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int OP, int NB, int MT>
+static hipError_t launch_resident_t(const EncodeShape& sh, const void* P, const void* sdata, float* out_part,
+                                    const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+  const dim3 gr((unsigned)cdiv(sh.HC, (int64_t)kWaves * MT), (unsigned)sh.nsplit);
+  hipLaunchKernelGGL((resident_kernel<OP, NB, MT>), gr, dim3(64 * kWaves), 0, s, (const u4*)P, (const u4*)sdata,
+                     sh.HC, sh.SC, sh.cps, out_part, sens, L, G, stop);
+  return hipGetLastError();
+}
+
+template <int OP>
+static hipError_t launch_resident_op(const EncodeShape& sh, const void* P, const void* sd, float* op,
+                                     const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+  switch (sh.NB * 8 + sh.MT) {
+    case 1 * 8 + 2: return launch_resident_t<OP, 1, 2>(sh, P, sd, op, sens, L, G, stop, s);
+    case 1 * 8 + 4: return launch_resident_t<OP, 1, 4>(sh, P, sd, op, sens, L, G, stop, s);
+    case 2 * 8 + 2: return launch_resident_t<OP, 2, 2>(sh, P, sd, op, sens, L, G, stop, s);
+    case 2 * 8 + 4: return launch_resident_t<OP, 2, 4>(sh, P, sd, op, sens, L, G, stop, s);
+    case 4 * 8 + 2: return launch_resident_t<OP, 4, 2>(sh, P, sd, op, sens, L, G, stop, s);
+    case 4 * 8 + 4: return launch_resident_t<OP, 4, 4>(sh, P, sd, op, sens, L, G, stop, s);
+    case 8 * 8 + 2: return launch_resident_t<OP, 8, 2>(sh, P, sd, op, sens, L, G, stop, s);
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_resident(const EncodeShape& sh, const void* P, const void* sdata, float* out_part,
+                           const float2* sens, int64_t L, int G, const int* stop, hipStream_t s) {
+  if (sh.HC == 0) return hipSuccess;
+  if (sh.prec != PREC_FP16 || !valid_held_tiles(sh.NB, sh.MT) || sh.nsplit < 1) return hipErrorInvalidValue;
+  return sh.op == OP_E ? launch_resident_op<OP_E>(sh, P, sdata, out_part, sens, L, G, stop, s)
+                       : launch_resident_op<OP_EH>(sh, P, sdata, out_part, sens, L, G, stop, s);
+}
 
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s) {

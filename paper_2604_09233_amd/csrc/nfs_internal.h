@@ -95,6 +95,13 @@ hipError_t launch_pack_data(int op, int prec, const float2* src, const float2* m
 hipError_t launch_encode(const EncodeShape& sh, const void* heldcoef, const void* strmcoef,
                          const void* sdata, float* out_part, const float2* sens, int64_t L, int G,
                          const unsigned* tmax, int T, const int* stop, hipStream_t s);
+// resident P (FP16 only): build the (cos, sin) fragments of all held-tile x
+// streamed-chunk pairs into P [HC][SC][64][8 f16], and contract against them
+hipError_t launch_build_P(int NQ, const void* heldcoef, const void* strmcoef, int64_t HC, int64_t SC,
+                          const unsigned* tmax, int T, void* P, hipStream_t s);
+hipError_t launch_resident(const EncodeShape& sh, const void* P, const void* sdata, float* out_part,
+                           const float2* sens, int64_t L, int G, const int* stop, hipStream_t s);
+inline size_t resident_P_bytes(int64_t HC, int64_t SC) { return (size_t)HC * (size_t)SC * 64 * 16; }
 // sum E partials -> m[G][K] (coil-major) times *unscale
 hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                 const float* unscale, float2* m, hipStream_t s);

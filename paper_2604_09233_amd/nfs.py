@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libnfs.so")
 
 NFS_OK, NFS_EINVAL, NFS_ESHAPE, NFS_EHIP, NFS_EWORKSPACE, NFS_EUNSUPPORTED = 0, -1, -2, -3, -4, -6
 PRECISIONS = {"fp32": 0, "bf16": 1, "fp16": 2}
-OPS = {"E": 0, "EH": 1, "EHE": 2, "CG": 3}
+OPS = {"E": 0, "EH": 1, "EHE": 2, "CG": 3, "CG_RESIDENT": 4}
 CG_STATUS = {1: "max_iter", 2: "tol", 3: "exact", 4: "breakdown"}
 
 _lib = None
@@ -63,6 +63,7 @@ def lib():
             for name in ("nfs_apply_E", "nfs_apply_EH", "nfs_apply_EHE"):
                 getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
             L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
+            L.nfs_cg_solve_resident.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
             L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
             L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
@@ -82,7 +83,7 @@ def lib():
                          "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read",
                          "nfs_encode_backward", "nfs_workspace_bytes_batched", "nfs_cg_solve_batched",
                          "nfs_set_graphs", "nfs_tune_workspace_bytes", "nfs_autotune", "nfs_tuned_shape",
-                         "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched"):
+                         "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -217,6 +218,24 @@ def cg_solve(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int
     _check(lib().nfs_cg_solve(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
                               float(tol), int(replace_every), int(reorth), PRECISIONS[precision], _ptr(hist),
                               _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
+    return rho, hist, info
+
+
+def cg_solve_resident(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int = 0,
+                      precision: str = "fp16", reorth: bool = False, out=None, hist=None, info=None):
+    """cg_solve in the non-split form: P = exp(i phi) built once per solve
+    (2 K L x 4 bytes of workspace) and streamed by every E and E^H.  FP16
+    operands only (see include/nfs.h)."""
+    m = _c64(m, prob.device)
+    rho = out if out is not None else torch.empty(prob.L, dtype=torch.complex64, device=prob.device)
+    if hist is None:
+        hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=prob.device)
+    if info is None:
+        info = torch.zeros(2, dtype=torch.int32, device=prob.device)
+    ws = prob.workspace("CG_RESIDENT", precision, n_iter, reorth)
+    _check(lib().nfs_cg_solve_resident(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
+                                       float(tol), int(replace_every), int(reorth), PRECISIONS[precision],
+                                       _ptr(hist), _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
     return rho, hist, info
 
 

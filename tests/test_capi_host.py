@@ -121,7 +121,13 @@ def test_workspace_bytes(L):
         for prec in range(3):
             assert L.nfs_workspace_bytes(None, ctypes.byref(pr), op, prec, 10, 0, ctypes.byref(n)) == 0
             assert n.value > 0 and n.value % 256 == 0
-    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 4, 0, 0, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 5, 0, 0, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
+    # the resident (non-split) CG: FP16 only, and 2 K L x 4 bytes more than CG
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 4, 0, 10, 0, ctypes.byref(n)) == nfs.NFS_EUNSUPPORTED
+    assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 4, 2, 10, 0, ctypes.byref(n)) == 0
+    res = n.value
+    L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 2, 10, 0, ctypes.byref(n))
+    assert res >= n.value + 2 * 1008 * 784 * 4
     assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 0, 7, 0, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
     assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 3, 0, -1, 0, ctypes.byref(n)) == nfs.NFS_EINVAL
     assert L.nfs_workspace_bytes(None, ctypes.byref(pr), 0, 0, 0, 0, None) == nfs.NFS_EINVAL
@@ -215,3 +221,15 @@ def test_autotune_batched_validation(L):
     assert g(c, 2, arr, 2, A, n.value - 256, None) == nfs.NFS_EWORKSPACE
     assert g(c, 2, (nfs.nfs_problem * 2)(prob(), prob(t=None)), 2, A, n.value, None) == nfs.NFS_EINVAL
     assert g(c, 0, arr, 2, A, 0, None) == 0  # an empty batch has nothing to tune
+
+
+def test_resident_cg_validation(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    pr = prob()
+    f = L.nfs_cg_solve_resident
+    assert f(None, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 2, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A, 1 << 40, None) == nfs.NFS_EUNSUPPORTED
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 1, None, None, A, 1 << 40, None) == nfs.NFS_EUNSUPPORTED
+    assert f(c, ctypes.byref(pr), A, A, -1, 0.0, 0, 0, 2, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 2, None, None, A, 1, None) == nfs.NFS_EWORKSPACE
+    assert f(c, ctypes.byref(prob(G=0)), A, A, 5, 0.0, 0, 0, 2, None, None, A, 1 << 40, None) == nfs.NFS_ESHAPE
