@@ -56,6 +56,7 @@ def parse():
     ap.add_argument("--no-3d", action="store_true", help="skip the 3D 96x96x48 / 32-coil solve measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default encode shapes instead of autotuned ones")
     ap.add_argument("--no-resident", action="store_true", help="skip the resident-P (non-split) solve measurement")
+    ap.add_argument("--no-stopping", action="store_true", help="skip the 250-iteration L-curve / SSIM run")
     ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
@@ -351,6 +352,27 @@ def main():
         prob._ws.pop(("CG_RESIDENT", args.precision, 1, not args.plain), None)
         torch.cuda.empty_cache()
 
+    stopping = None
+    if not args.no_stopping:
+        # the paper's stopping-criteria study: 250 iterations, L-curve corner
+        # and SSIM of every iterate against the phantom
+        n_long = 250
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        _, h_long, i_long, its = nfs.cg_solve_traced(prob, m, n_long, precision=args.precision,
+                                                     reorth=not args.plain)
+        ev[1].record()
+        ss = nfs.ssim(its[1:], torch.from_numpy(d["rho_true"]), d["dims"])
+        ev[2].record()
+        torch.cuda.synchronize()
+        ss = ss.cpu().numpy()
+        corner, _ = nfs.lcurve_corner(h_long)
+        stopping = dict(iterations=n_long, ms_solve=ev[0].elapsed_time(ev[1]), ms_ssim_all=ev[1].elapsed_time(ev[2]),
+                        peak_ssim=float(ss.max()), peak_ssim_iteration=int(np.argmax(ss)) + 1,
+                        ssim_at=dict((str(k), float(ss[k - 1])) for k in (5, 10, 30, 100, 250)),
+                        lcurve_corner_iteration=corner, cg_info=i_long.cpu().tolist())
+        del its
+
     batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
     threed = None if args.no_3d else threed_run(nfs, synth, torch, dev, args)
 
@@ -383,6 +405,7 @@ def main():
         "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
         "roofline": roofline,
         "resident_P": resident,
+        "stopping_criteria": stopping,
         "batched": batched,
         "3d": threed,
         "wall_s_timed": wall,

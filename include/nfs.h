@@ -173,6 +173,42 @@ int nfs_cg_solve_resident(nfs_ctx* ctx, const nfs_problem* prob, const float* m,
                           double tol, int replace_every, int reorth, int precision, double* hist, int* info,
                           void* ws, size_t ws_bytes, void* stream);
 
+/* Stopping-criteria instrumentation (the paper's study of the CG iteration
+ * count: L-curve and SSIM over up to 250 iterations).
+ *
+ * nfs_cg_solve_traced: nfs_cg_solve that also stores every iterate:
+ *   iterates: device [n_iter+1][L] complex; row n = rho_n (row 0 = 0), with
+ *             the intensity correction applied as to the output; rows past
+ *             the last iteration are left untouched.
+ * Workspace: NFS_OP_CG.                                                    */
+int nfs_cg_solve_traced(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter, double tol,
+                        int replace_every, int reorth, int precision, double* hist, int* info, float* iterates,
+                        void* ws, size_t ws_bytes, void* stream);
+
+/* Mean SSIM (Wang, Bovik, Sheikh, Simoncelli 2004, as cited by the paper)
+ * of the magnitude of each of n_img images against the magnitude of `ref`:
+ * Gaussian window sigma 1.5 truncated to 11 taps per axis and normalised,
+ * C1 = (0.01 D)^2, C2 = (0.03 D)^2 with D = max - min of |ref|, window-
+ * weighted statistics without sample-size correction, averaged over the
+ * window positions fully inside the image.  Float64 throughout.
+ *   imgs: device [n_img][L] complex, ref: device [L] complex, L = nx ny nz,
+ *         voxel index x + nx (y + ny z); nx, ny >= 11, nz == 1 (2D) or >= 11
+ *   out:  device double [n_img]
+ * Workspace: nfs_ssim_workspace_bytes (256-byte aligned).                 */
+int nfs_ssim_workspace_bytes(int n_img, int nx, int ny, int nz, size_t* bytes);
+int nfs_ssim(nfs_ctx* ctx, const float* imgs, int n_img, const float* ref, int nx, int ny, int nz, double* out,
+             void* ws, size_t ws_bytes, void* stream);
+
+/* Corner of the L-curve (log ||rho_n||, log ||d_n||) from a CG history:
+ * HOST arrays.  hist: [n_rows][3] as written by the CG solves (||r_n||,
+ * ||rho_n||, ||d_n||^2); rows whose ||rho_n|| or ||d_n||^2 is not positive
+ * and finite are left out.  The curvature of an interior point is that of
+ * the circle through it and its two neighbours (signed, counter-clockwise
+ * positive); *corner = the row of largest curvature, or -1 with fewer than
+ * three usable rows.  kappa: host double [n_rows] or NULL (NaN where
+ * undefined).                                                              */
+int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, double* kappa);
+
 /* Many independent reconstructions (slices with uneven L, K and G) solved
  * together: each slice runs exactly the nfs_cg_solve sequence (same kernels,
  * so each slice's result is bit-identical to its single solve), forked from

@@ -526,7 +526,7 @@ static int check_cg_args(const nfs_ctx* ctx, const nfs_problem* prob, const floa
 // E^H instead of rebuilding the phase tiles
 static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const float* m, float* rho, int n_iter,
                   double tol, int replace_every, int reorth, double* hist, int* info, void* ws, hipStream_t s,
-                  bool resident = false) {
+                  bool resident = false, float* iterates = nullptr) {
   int rc;
   CgState st;
   st.r = at<float2>(ws, y.o_r);
@@ -541,6 +541,8 @@ static int run_cg(nfs_ctx* ctx, const nfs_problem* prob, const Layout& y, const 
   st.stop = at<int>(ws, y.o_stop);
   st.V = reorth ? at<float2>(ws, y.o_V) : nullptr;
   st.rn = reorth ? at<float2>(ws, y.o_rn) : nullptr;
+  st.iters = reinterpret_cast<float2*>(iterates);
+  st.icorr = prob->icorr;
   st.rpart = reorth ? at<double>(ws, y.o_rpart) : nullptr;
   const bool f16ops = scaled_prec(y.prec);  // f16 operand fragments, power-of-two scaled
   st.smax = f16ops ? at<float>(ws, y.o_smax) : nullptr;
@@ -702,6 +704,102 @@ extern "C" int nfs_cg_solve_resident(nfs_ctx* ctx, const nfs_problem* prob, cons
   return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
     return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st, true);
   });
+}
+
+extern "C" int nfs_cg_solve_traced(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                                   double tol, int replace_every, int reorth, int precision, double* hist, int* info,
+                                   float* iterates, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_cg_solve_traced";
+  int rc = check_cg_args(ctx, prob, m, rho, n_iter, tol, replace_every, reorth, precision, hist, info, fn);
+  if (rc) return rc;
+  if ((rc = check_vec(iterates, (int64_t)(n_iter + 1) * prob->n_vox, fn, "iterates"))) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_CG, precision, n_iter, reorth);
+  if ((rc = check_ws(y, ws, ws_bytes, fn))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  const void* ptrs[5] = {m, rho, hist, info, iterates};
+  const std::string key =
+      graph_key(ctx, "cgt", prob, 1, ptrs, 5, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
+  return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
+    return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st, false, iterates);
+  });
+}
+
+// ---------------------------------------------------------------------------
+// Stopping-criteria instrumentation: SSIM of iterates against a reference,
+// and the L-curve corner.
+static int check_ssim_dims(int n_img, int nx, int ny, int nz, const char* fn) {
+  if (n_img < 0) return fail(NFS_EINVAL, "%s: n_img %d < 0", fn, n_img);
+  if (nx < 11 || ny < 11 || !(nz == 1 || nz >= 11))
+    return fail(NFS_ESHAPE, "%s: image %d x %d x %d: needs nx, ny >= 11 and nz == 1 or >= 11", fn, nx, ny, nz);
+  if ((int64_t)nx * ny * nz > ((int64_t)1 << 26)) return fail(NFS_ESHAPE, "%s: image too large", fn);
+  return NFS_OK;
+}
+
+extern "C" int nfs_ssim_workspace_bytes(int n_img, int nx, int ny, int nz, size_t* bytes) {
+  const char* fn = "nfs_ssim_workspace_bytes";
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  int rc = check_ssim_dims(n_img, nx, ny, nz, fn);
+  if (rc) return rc;
+  *bytes = ssim_workspace_bytes(n_img, nx, ny, nz);
+  return NFS_OK;
+}
+
+extern "C" int nfs_ssim(nfs_ctx* ctx, const float* imgs, int n_img, const float* ref, int nx, int ny, int nz,
+                        double* out, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_ssim";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_ssim_dims(n_img, nx, ny, nz, fn);
+  if (rc) return rc;
+  const int64_t L = (int64_t)nx * ny * nz;
+  if ((rc = check_vec(imgs, (int64_t)n_img * L, fn, "imgs"))) return rc;
+  if ((rc = check_vec(ref, L, fn, "ref"))) return rc;
+  if (n_img > 0 && !out) return fail(NFS_EINVAL, "%s: out is NULL", fn);
+  if (misaligned(out, 8)) return fail(NFS_EINVAL, "%s: out not 8-byte aligned", fn);
+  const size_t need = ssim_workspace_bytes(n_img, nx, ny, nz);
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  if (ws_bytes < need) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, need);
+  NFS_TRY(launch_ssim(reinterpret_cast<const float2*>(imgs), n_img, reinterpret_cast<const float2*>(ref), nx, ny, nz,
+                      out, ws, (hipStream_t)stream),
+          "ssim");
+  return NFS_OK;
+}
+
+extern "C" int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, double* kappa) {
+  const char* fn = "nfs_lcurve_corner";
+  if (n_rows < 0) return fail(NFS_EINVAL, "%s: n_rows %d < 0", fn, n_rows);
+  if ((n_rows > 0 && !hist) || !corner) return fail(NFS_EINVAL, "%s: NULL argument", fn);
+  // usable rows: ||rho_n|| and ||d_n||^2 positive and finite
+  std::vector<int> rows;
+  for (int n = 0; n < n_rows; ++n) {
+    const double xr = hist[3 * n + 1], d2 = hist[3 * n + 2];
+    if (std::isfinite(xr) && std::isfinite(d2) && xr > 0.0 && d2 > 0.0) rows.push_back(n);
+  }
+  if (kappa)
+    for (int n = 0; n < n_rows; ++n) kappa[n] = std::nan("");
+  *corner = -1;
+  double best = 0.0;
+  for (size_t j = 1; j + 1 < rows.size(); ++j) {
+    double px[3], py[3];
+    for (int t = 0; t < 3; ++t) {
+      const int n = rows[j - 1 + t];
+      px[t] = std::log(hist[3 * n + 1]);
+      py[t] = 0.5 * std::log(hist[3 * n + 2]);
+    }
+    const double ax = px[1] - px[0], ay = py[1] - py[0];
+    const double bx = px[2] - px[1], by = py[2] - py[1];
+    const double cx = px[2] - px[0], cy = py[2] - py[0];
+    const double cross = ax * by - ay * bx;
+    const double den = std::hypot(ax, ay) * std::hypot(bx, by) * std::hypot(cx, cy);
+    if (!(den > 0.0)) continue;
+    const double k = 2.0 * cross / den;
+    if (kappa) kappa[rows[j]] = k;
+    if (*corner < 0 || k > best) {
+      best = k;
+      *corner = rows[j];
+    }
+  }
+  return NFS_OK;
 }
 
 // ---------------------------------------------------------------------------

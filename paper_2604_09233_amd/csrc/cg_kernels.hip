@@ -109,6 +109,7 @@ __global__ __launch_bounds__(256) void cg_init_kernel(CgState st, const float2* 
     st.r[l] = v;
     st.p[l] = v;
     rho[l] = make_float2(0.f, 0.f);
+    if (st.iters) st.iters[l] = make_float2(0.f, 0.f);
     a += (double)v.x * v.x + (double)v.y * v.y;
     if (st.smax) mx = fmaxf(mx, st.smax[l] * sqrtf(v.x * v.x + v.y * v.y));
   }
@@ -221,6 +222,10 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
       r.y = fmaf(-gf, q.y, r.y);
       rho[l] = x;
       rout[l] = r;
+      if (st.iters) {
+        const float j = st.icorr ? st.icorr[l] : 1.f;
+        st.iters[(size_t)(n + 1) * L + l] = make_float2(x.x * j, x.y * j);
+      }
       a += (double)r.x * r.x + (double)r.y * r.y;
       xx += (double)x.x * x.x + (double)x.y * x.y;
     }

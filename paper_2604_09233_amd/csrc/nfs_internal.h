@@ -122,6 +122,14 @@ hipError_t launch_grad_b0(const float2* hpart, int nsplit, int64_t HC16, int64_t
 hipError_t launch_grad_kcoef(const float* epart, int nsplit, int64_t HC16, int NB, const float* unscale,
                              const float2* grad_m, int64_t K, int G, int P, int b, float* out, hipStream_t s);
 
+// ---- stopping-criteria instrumentation (quality_kernels.hip) ------------------
+// mean SSIM of |imgs[i]| against |ref| for i < n_img into out[i] (float64);
+// images [n_img][L] complex, L = nx ny nz (x fastest); needs nx, ny >= 11 and
+// nz == 1 or nz >= 11
+size_t ssim_workspace_bytes(int n_img, int nx, int ny, int nz);
+hipError_t launch_ssim(const float2* imgs, int n_img, const float2* ref, int nx, int ny, int nz, double* out, void* ws,
+                       hipStream_t s);
+
 // ---- CG (cg_kernels.hip) -----------------------------------------------------
 struct CgState {
   float2* r;        // [L]
@@ -136,6 +144,8 @@ struct CgState {
   int* stop;        // [1]
   float2* V;        // [n_iter + 1][L] normalised residuals (re-orthogonalisation) or NULL
   float2* rn;       // [L] the updated residual before re-orthogonalisation, or NULL
+  float2* iters;    // [n_iter + 1][L] every iterate rho_n (traced solves), or NULL
+  const float* icorr;  // [L] intensity correction applied to stored iterates, or NULL
   double* rpart;    // [n_iter + 1][2][kCgBlocks] partial dot products v_j^H r
   const float* smax;  // [L] max_c |S[c][l]| (FP16 operands) or NULL
   float* bmax;        // [kBmaxBlocks] bound on the next E operand (with smax)

@@ -64,6 +64,10 @@ def lib():
                 getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
             L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
             L.nfs_cg_solve_resident.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
+            L.nfs_cg_solve_traced.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, vp, sz, vp]
+            L.nfs_ssim_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
+            L.nfs_ssim.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp, sz, vp]
+            L.nfs_lcurve_corner.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
             L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
             L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
@@ -83,7 +87,8 @@ def lib():
                          "nfs_apply_EHE", "nfs_cg_solve", "nfs_version", "nfs_profile_enable", "nfs_profile_read",
                          "nfs_encode_backward", "nfs_workspace_bytes_batched", "nfs_cg_solve_batched",
                          "nfs_set_graphs", "nfs_tune_workspace_bytes", "nfs_autotune", "nfs_tuned_shape",
-                         "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident"):
+                         "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident",
+                         "nfs_cg_solve_traced", "nfs_ssim_workspace_bytes", "nfs_ssim", "nfs_lcurve_corner"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -237,6 +242,60 @@ def cg_solve_resident(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_e
                                        float(tol), int(replace_every), int(reorth), PRECISIONS[precision],
                                        _ptr(hist), _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
     return rho, hist, info
+
+
+def cg_solve_traced(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int = 0,
+                    precision: str = "fp32", reorth: bool = False):
+    """cg_solve that also returns every iterate: (rho, hist, info, iterates
+    [n_iter+1][L] complex64, row n = rho_n)."""
+    m = _c64(m, prob.device)
+    dev = prob.device
+    rho = torch.empty(prob.L, dtype=torch.complex64, device=dev)
+    hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
+    info = torch.zeros(2, dtype=torch.int32, device=dev)
+    its = torch.full((n_iter + 1, prob.L), float("nan"), dtype=torch.complex64, device=dev)
+    ws = prob.workspace("CG", precision, n_iter, reorth)
+    _check(lib().nfs_cg_solve_traced(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
+                                     float(tol), int(replace_every), int(reorth), PRECISIONS[precision], _ptr(hist),
+                                     _ptr(info), _ptr(its), _ptr(ws), ws.numel(), prob._stream()))
+    return rho, hist, info, its
+
+
+def ssim(imgs, ref, dims, device: int = 0):
+    """Mean SSIM of |imgs[i]| against |ref| (see include/nfs.h) for a stack
+    imgs [n][L] (or one image [L]) of device complex64 tensors; dims (nx, ny)
+    or (nx, ny, nz), x fastest.  Returns a float64 device tensor [n]."""
+    dev = torch.device("cuda", device)
+    imgs = _c64(imgs, dev)
+    one = imgs.dim() == 1
+    imgs = imgs.reshape(1, -1) if one else imgs
+    ref = _c64(ref, dev)
+    nx, ny = int(dims[0]), int(dims[1])
+    nz = int(dims[2]) if len(dims) > 2 else 1
+    n = imgs.shape[0]
+    nbytes = ctypes.c_size_t()
+    _check(lib().nfs_ssim_workspace_bytes(n, nx, ny, nz, ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    out = torch.empty(n, dtype=torch.float64, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().nfs_ssim(context(device), _ptr(imgs), n, _ptr(ref), nx, ny, nz, _ptr(out),
+                          ctypes.c_void_p(ws.data_ptr() + off), nbytes.value, stream))
+    return out
+
+
+def lcurve_corner(hist):
+    """(corner row, curvature per row) of the L-curve of a CG history
+    [n+1][3] (host computation on a host copy; see include/nfs.h)."""
+    import numpy as np
+
+    h = np.ascontiguousarray(hist.cpu().numpy() if hasattr(hist, "cpu") else hist, dtype=np.float64)
+    n = h.shape[0]
+    kap = np.empty(n, dtype=np.float64)
+    c = ctypes.c_int()
+    _check(lib().nfs_lcurve_corner(h.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(c),
+                                   kap.ctypes.data_as(ctypes.c_void_p)))
+    return c.value, kap
 
 
 def encode_backward(prob: Problem, rho, grad_m, precision: str = "fp32", need_rho: bool = True,

@@ -233,3 +233,58 @@ def test_resident_cg_validation(L):
     assert f(c, ctypes.byref(pr), A, A, -1, 0.0, 0, 0, 2, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
     assert f(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 2, None, None, A, 1, None) == nfs.NFS_EWORKSPACE
     assert f(c, ctypes.byref(prob(G=0)), A, A, 5, 0.0, 0, 0, 2, None, None, A, 1 << 40, None) == nfs.NFS_ESHAPE
+
+
+def test_lcurve_corner_host_function_matches_oracle():
+    """nfs_lcurve_corner is host arithmetic over the CG history: it must pick
+    the oracle's corner and reproduce its curvatures."""
+    import numpy as np
+
+    from oracle import quality as Q
+
+    rng = np.random.default_rng(12)
+    for trial in range(5):
+        n = 40
+        # a noisy L shape: ||d|| falls fast then flattens while ||rho|| grows
+        t = np.arange(1, n + 1, dtype=np.float64)
+        lx = np.log(1 + t) + 0.01 * rng.standard_normal(n)
+        ly = -2.5 * np.tanh(t / (4 + trial)) + 0.003 * rng.standard_normal(n)
+        hist = np.zeros((n + 1, 3))
+        hist[0] = [1.0, 0.0, 1.0]
+        hist[1:, 0] = 1.0
+        hist[1:, 1] = np.exp(lx)
+        hist[1:, 2] = np.exp(2 * ly)
+        if trial == 3:
+            hist[17, 2] = -1e-3  # a recurrence value gone negative: left out
+        corner, kap = nfs.lcurve_corner(hist)
+        c_ref, k_ref = Q.lcurve_corner(hist)
+        assert corner == c_ref
+        ok = np.isfinite(k_ref)
+        assert np.array_equal(ok, np.isfinite(kap))
+        assert np.allclose(kap[ok], k_ref[ok], rtol=1e-12, atol=1e-14)
+    c = ctypes.c_int()
+    assert nfs.lib().nfs_lcurve_corner(None, 3, ctypes.byref(c), None) == nfs.NFS_EINVAL
+    assert nfs.lib().nfs_lcurve_corner(None, 0, ctypes.byref(c), None) == 0 and c.value == -1
+
+
+def test_ssim_and_traced_validation(L):
+    n = ctypes.c_size_t()
+    f = L.nfs_ssim_workspace_bytes
+    assert f(3, 20, 20, 1, ctypes.byref(n)) == 0 and n.value > 0
+    assert f(3, 10, 20, 1, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert f(3, 20, 20, 5, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert f(-1, 20, 20, 1, ctypes.byref(n)) == nfs.NFS_EINVAL
+    assert f(3, 20, 20, 1, None) == nfs.NFS_EINVAL
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    g = L.nfs_ssim
+    f(2, 20, 20, 1, ctypes.byref(n))
+    assert g(None, A, 2, A, 20, 20, 1, A, A, n.value, None) == nfs.NFS_EINVAL
+    assert g(c, None, 2, A, 20, 20, 1, A, A, n.value, None) == nfs.NFS_EINVAL
+    assert g(c, A, 2, A, 20, 20, 1, None, A, n.value, None) == nfs.NFS_EINVAL
+    assert g(c, A, 2, A, 20, 20, 1, A, A, n.value - 8, None) == nfs.NFS_EWORKSPACE
+    assert g(c, A, 2, A, 20, 20, 1, A, A + 64, n.value, None) == nfs.NFS_EWORKSPACE
+    t = L.nfs_cg_solve_traced
+    pr = prob()
+    assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A + 4, A, 1 << 40, None) == nfs.NFS_EINVAL
+    assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A, A, 1, None) == nfs.NFS_EWORKSPACE
