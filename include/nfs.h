@@ -209,6 +209,27 @@ int nfs_ssim(nfs_ctx* ctx, const float* imgs, int n_img, const float* ref, int n
  * undefined).                                                              */
 int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, double* kappa);
 
+/* k-space filter (Methods, "Computation of k-space filters"; last line of
+ * both reconstruction listings): rho_f = IFFT(FFT(rho) o f) on an image grid
+ * nx x ny x nz (voxel index x + nx (y + ny z)), f real [L] in the same index
+ * order, bin (u, v, w) standing for the signed frequency u (if u < ceil(nx/2),
+ * else u - nx) and so on, in cycles per field of view.  Applied on the GPU as
+ * (1/L) E^H diag(f) E rho with E the DFT of the grid, built from the
+ * library's own encoding operator (FP32-grade operands); rho, out: device
+ * [L] complex; f: device float [L].  Workspace:
+ * nfs_kspace_filter_workspace_bytes.                                      */
+int nfs_kspace_filter_workspace_bytes(const nfs_ctx* ctx, int nx, int ny, int nz, size_t* bytes);
+int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* out, int nx, int ny, int nz, const float* f,
+                            void* ws, size_t ws_bytes, void* stream);
+/* The filter itself: f = 1 on the bins inside the convex hull of the K
+ * first-order k-space positions kpos (HOST double [K][dim], cycles per field
+ * of view), 0 elsewhere; bins on the hull count as inside.  Host
+ * computation (convex hull by Andrew's monotone chain, then an edge test per
+ * bin); only 2D grids (dim 2, nz 1), NFS_EUNSUPPORTED otherwise.
+ * mask: HOST uint8 [L]; *n_inside (may be NULL): number of bins set.      */
+int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int ny, int nz, unsigned char* mask,
+                           int64_t* n_inside);
+
 /* Many independent reconstructions (slices with uneven L, K and G) solved
  * together: each slice runs exactly the nfs_cg_solve sequence (same kernels,
  * so each slice's result is bit-identical to its single solve), forked from

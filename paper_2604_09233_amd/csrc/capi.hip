@@ -421,13 +421,15 @@ static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const
 }
 
 // E^H E: p -> hpart; the E^H operand is packed straight from the E partials
-static int seq_EHE(const Ctx& c, const float2* p, bool bmax_ready = false) {
+// (optionally weighted per sample: E^H diag(wgt * wmul) E)
+static int seq_EHE(const Ctx& c, const float2* p, bool bmax_ready = false, const float* wgt = nullptr,
+                   float wmul = 1.f) {
   const Layout& y = c.y;
   int rc = seq_E(c, p, nullptr, bmax_ready);
   if (rc) return rc;
   float* us = at<float>(c.ws, y.o_unscale);
   NFS_TRY(launch_pack_EH_from_epart(y.prec, at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L,
-                                    us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
+                                    wgt, wmul, us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
           "pack_EH_from_epart");
   return timed_encode(c, 1, [&] {
     if (c.PH)
@@ -803,6 +805,141 @@ extern "C" int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, do
 }
 
 // ---------------------------------------------------------------------------
+// k-space filter: rho_f = (1 / L) E^H diag(f) E rho on the DFT problem of the
+// image grid (written into the workspace), FP32-grade operands.
+struct FilterLayout {
+  nfs_problem pr;
+  size_t o_sens, o_fields, o_b0, o_kcoef, o_t, o_enc, total;
+  Layout y;
+};
+
+static FilterLayout filter_layout(const nfs_ctx* ctx, int nx, int ny, int nz, void* ws) {
+  FilterLayout f{};
+  const int64_t L = (int64_t)nx * ny * nz;
+  const int P = nz > 1 ? 3 : 2;
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += al(bytes);
+    return at;
+  };
+  f.o_sens = take((size_t)L * 8);
+  f.o_fields = take((size_t)P * L * 4);
+  f.o_b0 = take((size_t)L * 4);
+  f.o_kcoef = take((size_t)L * P * 4);
+  f.o_t = take((size_t)L * 4);
+  f.o_enc = o;
+  char* b = static_cast<char*>(ws);
+  f.pr = nfs_problem{L, L, 1, P, (const float*)(b + f.o_sens), (const float*)(b + f.o_fields),
+                     (const float*)(b + f.o_b0), (const float*)(b + f.o_kcoef), (const float*)(b + f.o_t), nullptr};
+  f.y = make_layout(ctx, &f.pr, NFS_OP_EHE, NFS_FP32, 0, 0);
+  f.total = f.o_enc + f.y.total;
+  return f;
+}
+
+static int check_filter_dims(int nx, int ny, int nz, const char* fn) {
+  if (nx < 1 || ny < 1 || nz < 1) return fail(NFS_ESHAPE, "%s: grid %d x %d x %d", fn, nx, ny, nz);
+  if ((int64_t)nx * ny * nz > ((int64_t)1 << 26)) return fail(NFS_ESHAPE, "%s: grid too large", fn);
+  return NFS_OK;
+}
+
+extern "C" int nfs_kspace_filter_workspace_bytes(const nfs_ctx* ctx, int nx, int ny, int nz, size_t* bytes) {
+  const char* fn = "nfs_kspace_filter_workspace_bytes";
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  int rc = check_filter_dims(nx, ny, nz, fn);
+  if (rc) return rc;
+  *bytes = filter_layout(ctx, nx, ny, nz, nullptr).total;
+  return NFS_OK;
+}
+
+extern "C" int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* out, int nx, int ny, int nz,
+                                       const float* f, void* ws, size_t ws_bytes, void* stream) {
+  const char* fn = "nfs_apply_kspace_filter";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_filter_dims(nx, ny, nz, fn);
+  if (rc) return rc;
+  const int64_t L = (int64_t)nx * ny * nz;
+  if ((rc = check_vec(rho, L, fn, "rho"))) return rc;
+  if ((rc = check_vec(out, L, fn, "out"))) return rc;
+  if (!f) return fail(NFS_EINVAL, "%s: f is NULL", fn);
+  if (misaligned(f, 4)) return fail(NFS_EINVAL, "%s: f not 4-byte aligned", fn);
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  const FilterLayout fl = filter_layout(ctx, nx, ny, nz, ws);
+  if (ws_bytes < fl.total) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, fl.total);
+  hipStream_t s = (hipStream_t)stream;
+  char* b = static_cast<char*>(ws);
+  NFS_TRY(launch_dft_problem(nx, ny, nz, (float2*)(b + fl.o_sens), (float*)(b + fl.o_fields), (float*)(b + fl.o_b0),
+                             (float*)(b + fl.o_kcoef), (float*)(b + fl.o_t), s),
+          "dft_problem");
+  void* enc = b + fl.o_enc;
+  Ctx c{ctx, fl.y, &fl.pr, reinterpret_cast<const float2*>(fl.pr.sens), enc, s, nullptr};
+  if ((rc = seq_pack_coefs(c, true, true))) return rc;
+  if ((rc = seq_EHE(c, reinterpret_cast<const float2*>(rho), false, f, (float)(1.0 / (double)L)))) return rc;
+  NFS_TRY(launch_finish_EH(at<float2>(enc, fl.y.o_hpart), fl.y.shH.nsplit, fl.y.LC * 16, L, unscale_slot(c, 1),
+                           reinterpret_cast<float2*>(out), s),
+          "finish_EH");
+  return NFS_OK;
+}
+
+// Filter mask from the first-order k-space positions (host arithmetic):
+// Andrew's monotone chain builds the convex hull; a bin is inside when it is
+// on the inner side of (or on) every hull edge, up to a relative tolerance.
+extern "C" int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int ny, int nz,
+                                      unsigned char* mask, int64_t* n_inside) {
+  const char* fn = "nfs_kspace_filter_mask";
+  if (dim != 2 || nz != 1) return fail(NFS_EUNSUPPORTED, "%s: only 2D grids (dim 2, nz 1) are supported", fn);
+  int rc = check_filter_dims(nx, ny, nz, fn);
+  if (rc) return rc;
+  if (K < 0 || (K > 0 && !kpos) || !mask) return fail(NFS_EINVAL, "%s: NULL or negative argument", fn);
+  const int64_t L = (int64_t)nx * ny;
+  std::vector<std::pair<double, double>> pts;
+  pts.reserve((size_t)K);
+  double scale = 0.0;
+  for (int64_t k = 0; k < K; ++k) {
+    const double x = kpos[2 * k], y = kpos[2 * k + 1];
+    if (!std::isfinite(x) || !std::isfinite(y)) return fail(NFS_EINVAL, "%s: non-finite position %lld", fn, (long long)k);
+    pts.emplace_back(x, y);
+    scale = std::max(scale, std::max(std::fabs(x), std::fabs(y)));
+  }
+  std::sort(pts.begin(), pts.end());
+  pts.erase(std::unique(pts.begin(), pts.end()), pts.end());
+  auto cross = [](const std::pair<double, double>& o, const std::pair<double, double>& a,
+                  const std::pair<double, double>& b) {
+    return (a.first - o.first) * (b.second - o.second) - (a.second - o.second) * (b.first - o.first);
+  };
+  std::vector<std::pair<double, double>> hull;
+  if (pts.size() >= 3) {
+    std::vector<std::pair<double, double>> h(2 * pts.size());
+    size_t k = 0;
+    for (size_t i = 0; i < pts.size(); ++i) {
+      while (k >= 2 && cross(h[k - 2], h[k - 1], pts[i]) <= 0) --k;
+      h[k++] = pts[i];
+    }
+    for (size_t i = pts.size() - 1, t = k + 1; i-- > 0;) {
+      while (k >= t && cross(h[k - 2], h[k - 1], pts[i]) <= 0) --k;
+      h[k++] = pts[i];
+    }
+    h.resize(k - 1);  // counter-clockwise, first point not repeated
+    hull = h;
+  }
+  const double eps = 1e-12 * (scale > 1.0 ? scale * scale : 1.0);
+  int64_t count = 0;
+  for (int64_t l = 0; l < L; ++l) {
+    const int ix = (int)(l % nx), iy = (int)(l / nx);
+    const std::pair<double, double> p((double)(ix < (nx + 1) / 2 ? ix : ix - nx),
+                                      (double)(iy < (ny + 1) / 2 ? iy : iy - ny));
+    bool in = hull.size() >= 3;
+    for (size_t e = 0; in && e < hull.size(); ++e)
+      if (cross(hull[e], hull[(e + 1) % hull.size()], p) < -eps) in = false;
+    mask[l] = in ? 1 : 0;
+    count += in;
+  }
+  if (n_inside) *n_inside = count;
+  return NFS_OK;
+}
+
+// ---------------------------------------------------------------------------
 // Batched solves: independent slices, forked from the caller's stream onto
 // the context's streams (longest-processing-time assignment by L*K*G) and
 // joined back.
@@ -1067,8 +1204,8 @@ static int tune_pass(const nfs_ctx* ctx, const TuneSlice& t, const int* ovE, con
     NFS_TRY(launch_encode(sh, at<void>(ws, y.o_sB), at<void>(ws, y.o_vA), at<void>(ws, y.o_dataE), epart, sens, y.L,
                           y.G, tmax, y.P + 1, nullptr, s),
             "encode E (tuning)");
-    NFS_TRY(launch_pack_EH_from_epart(y.prec, epart, sh.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L, us, us + 1, y.KC,
-                                      at<void>(ws, y.o_dataH), nullptr, s),
+    NFS_TRY(launch_pack_EH_from_epart(y.prec, epart, sh.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L, nullptr, 1.f, us,
+                                      us + 1, y.KC, at<void>(ws, y.o_dataH), nullptr, s),
             "pack_EH_from_epart (tuning)");
   }
   if (ovH) {

@@ -300,9 +300,12 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
 // pass over the E output, and *unscale_out = *unscale_in / scale.  (Values
 // far below the bound only leave float16's normal range 29 binades under
 // it.)
+// An optional real weight per sample, times wmul, multiplies the E output
+// first (|weight * wmul| <= 1 keeps the scale bound).
 template <int PREC>
 __global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __restrict__ epart, int nsplit,
                                                                  int64_t HC16, int NB, int64_t K, int G, float scale,
+                                                                 const float* __restrict__ wgt, float wmul,
                                                                  const float* __restrict__ unscale_in,
                                                                  float* __restrict__ unscale_out, int64_t nchunks,
                                                                  void* __restrict__ out, const int* stop) {
@@ -330,8 +333,9 @@ __global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __
         v.x += w.x;
         v.y += w.y;
       }
-      v.x *= scale;
-      v.y *= scale;
+      const float w = wgt ? wgt[item] * wmul : wmul;
+      v.x *= scale * w;
+      v.y *= scale * w;
     }
     vals[2 * j] = reim ? v.y : v.x;
     vals[2 * j + 1] = reim ? -v.x : v.y;
@@ -977,8 +981,8 @@ hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, in
 }
 
 hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
-                                     int64_t L, const float* unscale_in, float* unscale_out, int64_t nchunks, void* out,
-                                     const int* stop, hipStream_t s) {
+                                     int64_t L, const float* wgt, float wmul, const float* unscale_in,
+                                     float* unscale_out, int64_t nchunks, void* out, const int* stop, hipStream_t s) {
   const int64_t total = nchunks * NB * 64;
   if (total == 0) return hipSuccess;
   int lg = 0;
@@ -986,8 +990,8 @@ hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, i
   const float scale = prec != PREC_BF16 ? ldexpf(1.f, -(lg + 1)) : 1.f;
   const dim3 gr = grid1(total), bl(256);
 #define NFS_PACKH(P_)                                                                                           \
-  hipLaunchKernelGGL(pack_EH_from_epart_kernel<P_>, gr, bl, 0, s, epart, nsplit, HC16, NB, K, G, scale, unscale_in, \
-                     unscale_out, nchunks, out, stop)
+  hipLaunchKernelGGL(pack_EH_from_epart_kernel<P_>, gr, bl, 0, s, epart, nsplit, HC16, NB, K, G, scale, wgt, wmul, \
+                     unscale_in, unscale_out, nchunks, out, stop)
   if (prec == PREC_FP32) NFS_PACKH(PREC_FP32);
   else if (prec == PREC_BF16) NFS_PACKH(PREC_BF16);
   else NFS_PACKH(PREC_FP16);

@@ -108,9 +108,10 @@ hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, in
 // E^H data operand of the samples straight from the E partials (E^H E):
 // value(k, c) = sum_s epart[s][k][2c] + i epart[s][k][2c+1]; for FP16 scaled
 // by 2^-(ceil(log2 L) + 1) with *unscale_out = *unscale_in times the inverse
+// wgt (per sample, or NULL) times wmul multiplies the E output first
 hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
-                                     int64_t L, const float* unscale_in, float* unscale_out, int64_t nchunks, void* out,
-                                     const int* stop, hipStream_t s);
+                                     int64_t L, const float* wgt, float wmul, const float* unscale_in,
+                                     float* unscale_out, int64_t nchunks, void* out, const int* stop, hipStream_t s);
 // sum E^H partials -> x[L] times *unscale
 hipError_t launch_finish_EH(const float2* hpart, int nsplit, int64_t HC16, int64_t L,
                             const float* unscale, float2* x, hipStream_t s);
@@ -129,6 +130,16 @@ hipError_t launch_grad_kcoef(const float* epart, int nsplit, int64_t HC16, int N
 size_t ssim_workspace_bytes(int n_img, int nx, int ny, int nz);
 hipError_t launch_ssim(const float2* imgs, int n_img, const float2* ref, int nx, int ny, int nz, double* out, void* ws,
                        hipStream_t s);
+
+// ---- k-space filter (postproc_kernels.hip) ------------------------------------
+// The DFT of an nx x ny x nz grid as an encoding problem: voxel l and sample
+// k index the same grid (x fastest); fields[d][l] = centred pixel index
+// (index - n_d / 2) along axis d, kcoef[k][d] = -2 pi (signed frequency of
+// bin k along d) / n_d, t = b0 = 0, sens = 1 (one coil); P = 2 (nz == 1) or
+// 3.  Then E rho = FFT(rho) up to a sign per bin, and E^H diag(w) E rho =
+// L IFFT(w o FFT(rho)).
+hipError_t launch_dft_problem(int nx, int ny, int nz, float2* sens, float* fields, float* b0, float* kcoef, float* t,
+                              hipStream_t s);
 
 // ---- CG (cg_kernels.hip) -----------------------------------------------------
 struct CgState {

@@ -68,6 +68,10 @@ def lib():
             L.nfs_ssim_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_ssim.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp, sz, vp]
             L.nfs_lcurve_corner.argtypes = [vp, i32, ctypes.POINTER(i32), vp]
+            L.nfs_kspace_filter_workspace_bytes.argtypes = [vp, i32, i32, i32, ctypes.POINTER(sz)]
+            L.nfs_apply_kspace_filter.argtypes = [vp, vp, vp, i32, i32, i32, vp, vp, sz, vp]
+            L.nfs_kspace_filter_mask.argtypes = [vp, ctypes.c_int64, i32, i32, i32, i32, vp,
+                                                 ctypes.POINTER(ctypes.c_int64)]
             L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
             L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
@@ -88,7 +92,8 @@ def lib():
                          "nfs_encode_backward", "nfs_workspace_bytes_batched", "nfs_cg_solve_batched",
                          "nfs_set_graphs", "nfs_tune_workspace_bytes", "nfs_autotune", "nfs_tuned_shape",
                          "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident",
-                         "nfs_cg_solve_traced", "nfs_ssim_workspace_bytes", "nfs_ssim", "nfs_lcurve_corner"):
+                         "nfs_cg_solve_traced", "nfs_ssim_workspace_bytes", "nfs_ssim", "nfs_lcurve_corner",
+                         "nfs_kspace_filter_workspace_bytes", "nfs_apply_kspace_filter", "nfs_kspace_filter_mask"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -296,6 +301,43 @@ def lcurve_corner(hist):
     _check(lib().nfs_lcurve_corner(h.ctypes.data_as(ctypes.c_void_p), n, ctypes.byref(c),
                                    kap.ctypes.data_as(ctypes.c_void_p)))
     return c.value, kap
+
+
+def kspace_filter_mask(kpos, dims):
+    """k-space filter f (float32 numpy [L], 0/1) of the bins inside the convex
+    hull of the first-order k positions kpos [K][2] (cycles per FOV); host
+    computation, 2D grids only (see include/nfs.h)."""
+    import numpy as np
+
+    k = np.ascontiguousarray(kpos, dtype=np.float64)
+    nx, ny = int(dims[0]), int(dims[1])
+    nz = int(dims[2]) if len(dims) > 2 else 1
+    mask = np.empty(nx * ny * nz, dtype=np.uint8)
+    cnt = ctypes.c_int64()
+    _check(lib().nfs_kspace_filter_mask(k.ctypes.data_as(ctypes.c_void_p), k.shape[0], k.shape[1], nx, ny, nz,
+                                        mask.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)))
+    return mask.astype(np.float32)
+
+
+def apply_kspace_filter(rho, f, dims, device: int = 0):
+    """IFFT(FFT(rho) o f) on the image grid dims (x fastest), on the GPU
+    through the library's encoding operator (see include/nfs.h)."""
+    dev = torch.device("cuda", device)
+    rho = _c64(rho, dev)
+    f = f.to(device=dev, dtype=torch.float32).contiguous() if torch.is_tensor(f) else \
+        torch.as_tensor(f, dtype=torch.float32, device=dev)
+    nx, ny = int(dims[0]), int(dims[1])
+    nz = int(dims[2]) if len(dims) > 2 else 1
+    nbytes = ctypes.c_size_t()
+    ctx = context(device)
+    _check(lib().nfs_kspace_filter_workspace_bytes(ctx, nx, ny, nz, ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    out = torch.empty_like(rho)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().nfs_apply_kspace_filter(ctx, _ptr(rho), _ptr(out), nx, ny, nz, _ptr(f),
+                                         ctypes.c_void_p(ws.data_ptr() + off), nbytes.value, stream))
+    return out
 
 
 def encode_backward(prob: Problem, rho, grad_m, precision: str = "fp32", need_rho: bool = True,

@@ -288,3 +288,42 @@ def test_ssim_and_traced_validation(L):
     assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, None, A, 1 << 40, None) == nfs.NFS_EINVAL
     assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A + 4, A, 1 << 40, None) == nfs.NFS_EINVAL
     assert t(c, ctypes.byref(pr), A, A, 5, 0.0, 0, 0, 0, None, None, A, A, 1, None) == nfs.NFS_EWORKSPACE
+
+
+def test_kspace_filter_mask_host_function_matches_oracle():
+    """nfs_kspace_filter_mask (host geometry) against the oracle's Delaunay
+    point location, bit for bit except for bins within 1e-6 of the hull
+    boundary (where both answers are valid)."""
+    import numpy as np
+
+    import synth
+    from oracle import postproc as PP
+
+    for cfg, seed in (("c1", 0), (None, 1), (None, 2)):
+        if cfg:
+            d = synth.make_config(cfg, with_noise=False)
+            dims = d["dims"]
+            kpos = d["kcoef"][:, 1:3].astype(np.float64) / np.pi
+        else:
+            rng = np.random.default_rng(seed)
+            dims = (40, 34)
+            kpos = rng.uniform(-14, 14, size=(300, 2)) * np.array([1.0, 0.7])
+        f = nfs.kspace_filter_mask(kpos, dims)
+        ref = PP.kspace_filter_mask(kpos, dims)
+        from scipy.spatial import ConvexHull
+        hull = ConvexHull(kpos)
+        fr = PP.grid_frequencies(dims)
+        # distance of every bin to the hull boundary (max over facet equations)
+        dist = np.max(fr @ hull.equations[:, :2].T + hull.equations[:, 2], axis=1)
+        clear = np.abs(dist) > 1e-6
+        assert np.array_equal(f[clear], ref[clear]), cfg
+        assert f.sum() > 0
+    c = ctypes.c_int64()
+    m = (ctypes.c_uint8 * 16)()
+    k = (ctypes.c_double * 6)(0, 0, 1, 0, 0, 1)
+    assert nfs.lib().nfs_kspace_filter_mask(k, 3, 3, 4, 4, 1, m, ctypes.byref(c)) == nfs.NFS_EUNSUPPORTED
+    assert nfs.lib().nfs_kspace_filter_mask(k, 3, 2, 4, 4, 2, m, ctypes.byref(c)) == nfs.NFS_EUNSUPPORTED
+    assert nfs.lib().nfs_kspace_filter_mask(None, 3, 2, 4, 4, 1, m, ctypes.byref(c)) == nfs.NFS_EINVAL
+    n = ctypes.c_size_t()
+    assert nfs.lib().nfs_kspace_filter_workspace_bytes(None, 0, 4, 1, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert nfs.lib().nfs_kspace_filter_workspace_bytes(None, 32, 32, 1, ctypes.byref(n)) == 0 and n.value > 0
