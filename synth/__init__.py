@@ -15,4 +15,5 @@ from .inputs import (  # noqa: F401
     dft_problem,
     unit_noise,
     batched_slices,
+    prescan,
 )

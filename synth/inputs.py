@@ -345,3 +345,37 @@ def batched_slices(n_slices: int = 24, seed: int = 0, n_range=(96, 160), g_range
             noise=unit_noise(rs[4], (G, t.size)),
         ))
     return out
+
+
+def prescan(dims=(64, 64), n_coil=8, n_echo=6, delta_te=1.0e-3, b0_hz=120.0, beta=0.2, snr=40.0, seed=0):
+    """Multi-echo prescan images for the map-estimation step (Methods,
+    "Computation of sensitivity maps" and "... of B0 maps"): per coil and
+    echo n, S_c(r) rho(r) exp(i (omega(r) n dTE + beta mod(n, 2))) plus
+    complex Gaussian noise (per-component sigma = max|rho S| / (snr sqrt 2)).
+    Also the two masks the estimation takes as inputs (their segmentation
+    is outside this work): M_R = the object support dilated by 2 voxels,
+    M_T = the object support eroded by 2 voxels (so that every object
+    carries trusted data).
+    Returns imgs [G][n_echo][L] complex64, S_true [G][L], omega_true [L]
+    (rad/s), beta, mask_T / mask_R [L] float32, rho [L], dims, delta_te."""
+    from scipy.ndimage import binary_dilation, binary_erosion
+
+    ss = np.random.default_rng(np.random.SeedSequence([_SEED_BASE + 7, seed]))
+    rs = [np.random.default_rng(s) for s in ss.bit_generator.seed_seq.spawn(5)]
+    x, y, z = grid_coords(dims)
+    three_d = len(dims) == 3
+    S = _sensitivities(n_coil, rs[0], x, y, z, three_d)
+    cfg = dict(dims=dims, b0_kind="bump" if not three_d else "gaussians", b0_hz=b0_hz)
+    omega = _b0_map(cfg, rs[1], x, y, z)
+    rho = np.abs(_phantom(rs[2], x, y, z, three_d))
+    shape = tuple(reversed(dims))
+    supp = (rho > 0).reshape(shape)
+    mask_R = binary_dilation(supp, iterations=2).ravel().astype(np.float32)
+    mask_T = binary_erosion(supp, iterations=2).ravel().astype(np.float32)
+    sigma = np.abs(S * rho[None, :]).max() / (snr * np.sqrt(2.0))
+    imgs = np.empty((n_coil, n_echo, x.size), dtype=np.complex64)
+    for n in range(n_echo):
+        ph = np.exp(1j * (omega * n * delta_te + beta * (n % 2)))
+        imgs[:, n, :] = S * (rho * ph)[None, :] + sigma * unit_noise(rs[3], (n_coil, x.size))
+    return dict(imgs=imgs, S_true=S.astype(np.complex64), omega_true=omega, beta=beta, mask_T=mask_T,
+                mask_R=mask_R, rho=rho, dims=tuple(dims), delta_te=delta_te, n_coil=n_coil, n_echo=n_echo)

@@ -1,0 +1,94 @@
+"""Pins of the FP64 map-estimation oracle (oracle/maps.py)."""
+import numpy as np
+import pytest
+
+from oracle import maps as M
+
+
+def test_difference_operators_on_polynomials():
+    """D2 of x^2 along x is 2 at every interior row, D1 of x is 1; both
+    vanish along the other axis; rows sit where the neighbours exist."""
+    dims = (7, 5, 4)
+    L = 7 * 5 * 4
+    idx = np.arange(L)
+    ix = idx % 7
+    D2, r2 = M._diff_matrix(dims, 0, 2)
+    D1, r1 = M._diff_matrix(dims, 0, 1)
+    assert np.allclose(D2 @ (ix.astype(float) ** 2), 2.0)
+    assert np.allclose(D1 @ ix.astype(float), 1.0)
+    assert len(r2) == 5 * 5 * 4 and len(r1) == 6 * 5 * 4
+    D2y, _ = M._diff_matrix(dims, 1, 2)
+    D1z, _ = M._diff_matrix(dims, 2, 1)
+    assert np.allclose(D2y @ (ix.astype(float) ** 2), 0.0)
+    assert np.allclose(D1z @ ix.astype(float), 0.0)
+
+
+def test_initial_sensitivities_of_rank_one_data():
+    """x[c, n, l] = s_l[c] e_l[n]: the first left singular vector is s_l / |s_l|
+    up to phase; with the coil-sum convention it is fixed exactly."""
+    rng = np.random.default_rng(1)
+    G, ne, L = 6, 5, 40
+    s = rng.standard_normal((G, L)) + 1j * rng.standard_normal((G, L))
+    e = rng.standard_normal((ne, L)) + 1j * rng.standard_normal((ne, L))
+    X = s[:, None, :] * e[None, :, :]
+    got = M.sens_initial(X)
+    t = s.sum(axis=0)
+    want = s / np.linalg.norm(s, axis=0) * (np.conj(t) / np.abs(t))
+    assert np.allclose(got, want, atol=1e-12)
+    assert np.allclose(np.imag(got.sum(axis=0)), 0.0, atol=1e-12) and np.all(np.real(got.sum(axis=0)) > 0)
+
+
+def test_sensitivity_smoothing_keeps_data_without_penalty():
+    dims = (9, 8)
+    L = 72
+    rng = np.random.default_rng(2)
+    s = (1 + rng.random((3, L))) * np.exp(1j * rng.uniform(-3, 3, (3, L)))
+    got = M.smooth_sens(s, np.ones(L), np.ones(L), dims, 0.0)
+    assert np.allclose(got, s, atol=1e-12)
+
+
+def test_sensitivity_smoothing_extrapolates_affine_maps_exactly():
+    """|S^| affine and phase constant: both parts have zero second
+    differences, so the solution equals S^ on all of M_R, also where M_T has
+    no data."""
+    dims = (16, 14)
+    L = 16 * 14
+    ix = np.arange(L) % 16
+    iy = np.arange(L) // 16
+    mag = 2.0 + 0.05 * ix - 0.03 * iy
+    s = np.stack([mag * np.exp(0.7j), (3.0 - 0.02 * ix + 0.04 * iy) * np.exp(-1.1j)])
+    mR = ((ix >= 2) & (ix <= 13) & (iy >= 1) & (iy <= 12)).astype(float)
+    mT = ((ix >= 5) & (ix <= 10) & (iy >= 4) & (iy <= 9)).astype(float)
+    got = M.smooth_sens(s, mT, mR, dims, 3.0)
+    inner = (ix >= 2) & (ix <= 13) & (iy >= 1) & (iy <= 12)
+    assert np.allclose(got[:, inner], s[:, inner], atol=1e-9)
+
+
+def test_b0_fit_recovers_exact_phases_with_wraps():
+    """Noise-free echoes with per-echo steps up to 0.9 pi (several wraps over
+    the echo train) and an even/odd offset: slope, offset and zero residual."""
+    rng = np.random.default_rng(3)
+    G, ne, L, dte = 4, 7, 50, 1e-3
+    S = rng.standard_normal((G, L)) + 1j * rng.standard_normal((G, L))
+    w = rng.uniform(-0.9 * np.pi, 0.9 * np.pi, L) / dte
+    beta = 0.3
+    rho = rng.uniform(0.5, 2.0, L) * np.exp(1j * rng.uniform(-np.pi, np.pi, L))
+    X = np.stack([S * (rho * np.exp(1j * (w * n * dte + beta * (n % 2))))[None, :] for n in range(ne)], axis=1)
+    b0, b, eps = M.b0_initial(X, S, dte)
+    assert np.allclose(b0, w, rtol=1e-10, atol=1e-7)
+    assert np.allclose(b, beta, atol=1e-10)
+    assert np.allclose(eps, 0.0, atol=1e-10)
+
+
+def test_b0_smoothing_special_cases():
+    dims = (10, 9)
+    L = 90
+    rng = np.random.default_rng(4)
+    b = rng.standard_normal(L)
+    assert np.allclose(M.smooth_b0(b, np.zeros(L), dims, 5.0), b, atol=1e-12)
+    c = np.full(L, 3.7)
+    assert np.allclose(M.smooth_b0(c, rng.random(L), dims, 5.0), c, atol=1e-12)
+    # larger eps smooths more: the result moves towards the mean
+    s1 = M.smooth_b0(b, np.full(L, 0.1), dims, 5.0)
+    s2 = M.smooth_b0(b, np.full(L, 1.0), dims, 5.0)
+    assert np.std(s2) < np.std(s1) < np.std(b)
