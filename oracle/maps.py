@@ -7,11 +7,14 @@ Methods, "Computation of sensitivity maps" and "Computation of B0 maps":
   values; its first left singular vector (numpy's SVD) gives the initial
   estimate of every coil's sensitivity at that voxel.  Singular vectors are
   defined up to a complex phase; it is fixed here (a reading) by rotating
-  each voxel's vector so that its coil sum is real and non-negative;
+  each voxel's vector so that its coil sum is real and non-negative; a
+  voxel whose prescan values are all zero gets the zero vector (a reading:
+  without data there is no estimate);
 * smoothing and extrapolation (the sensitivity-smoothing equation): per coil
   the least-squares solution of
       [diag(M_T); sqrt(a) diag(M_R) D2x; sqrt(a) diag(M_R) D2y; ...] S = [S^; 0; ...],
-  i.e. (diag(M_T) + a sum_d D2_d^T diag(M_R) D2_d) S = M_T S^, solved
+  i.e. the normal equations
+      (diag(M_T^2) + a sum_d D2_d^T diag(M_R^2) D2_d) S = M_T o S^, solved
   directly (scipy sparse LU); magnitude |S^| and the magnitude-normalised
   S^/|S^| are solved separately and recombined as |S|_s * n_s / |n_s|;
 * initial B0: the SENSE combination of each echo, c_n = sum_c conj(S_c) x_cn /
@@ -68,6 +71,8 @@ def sens_initial(imgs):
     G, ne, L = X.shape
     out = np.zeros((G, L), dtype=np.complex128)
     for l in range(L):
+        if not np.any(X[:, :, l]):
+            continue
         u, s, vh = np.linalg.svd(X[:, :, l], full_matrices=False)
         u1 = u[:, 0]
         t = u1.sum()
@@ -110,8 +115,8 @@ def smooth_sens(shat, mask_T, mask_R, dims, alpha):
     for s in np.asarray(shat, dtype=np.complex128):
         mag = np.abs(s)
         nrm = np.where(mag > 0, s / np.where(mag > 0, mag, 1.0), 0.0)
-        mag_s = solve(mT * mT * mag)
-        nrm_s = solve(mT * mT * nrm.real) + 1j * solve(mT * mT * nrm.imag)
+        mag_s = solve(mT * mag)
+        nrm_s = solve(mT * nrm.real) + 1j * solve(mT * nrm.imag)
         a = np.abs(nrm_s)
         out.append(np.where(a > 0, mag_s * nrm_s / np.where(a > 0, a, 1.0), 0.0))
     return np.array(out)

@@ -347,18 +347,34 @@ def batched_slices(n_slices: int = 24, seed: int = 0, n_range=(96, 160), g_range
     return out
 
 
-def prescan(dims=(64, 64), n_coil=8, n_echo=6, delta_te=1.0e-3, b0_hz=120.0, beta=0.2, snr=40.0, seed=0):
+def _head_phantom(x, y, z, three_d):
+    """Piecewise-constant head for the prescan: a low-intensity scalp shell
+    (0.12) around a brain (0.8) holding two low-intensity ventricles (0.25).
+    In 3D the head is an elongated ellipsoid cut by the slab, so every slice
+    holds tissue as in an axial slab through the brain."""
+    zz = (z / 2.5) ** 2 if three_d else 0.0
+    head = (x / 0.84) ** 2 + (y / 0.92) ** 2 + zz <= 1.0
+    brain = (x / 0.70) ** 2 + (y / 0.78) ** 2 + zz <= 1.0
+    vent = np.zeros_like(head)
+    for cx in (-0.17, 0.17):
+        vent |= ((x - cx) / 0.09) ** 2 + ((y + 0.05) / 0.26) ** 2 + (z / 1.2 if three_d else 0.0) ** 2 <= 1.0
+    rho = np.where(head, 0.12, 0.0)
+    rho = np.where(brain, 0.8 + 0.1 * np.cos(6.0 * x) * np.cos(5.0 * y), rho)
+    return np.where(brain & vent, 0.25, rho)
+
+
+def prescan(dims=(64, 64), n_coil=8, n_echo=6, delta_te=2.3e-3, b0_hz=100.0, beta=0.2, snr=40.0, seed=0):
     """Multi-echo prescan images for the map-estimation step (Methods,
     "Computation of sensitivity maps" and "... of B0 maps"): per coil and
     echo n, S_c(r) rho(r) exp(i (omega(r) n dTE + beta mod(n, 2))) plus
-    complex Gaussian noise (per-component sigma = max|rho S| / (snr sqrt 2)).
-    Also the two masks the estimation takes as inputs (their segmentation
-    is outside this work): M_R = the object support dilated by 2 voxels,
-    M_T = the object support eroded by 2 voxels (so that every object
-    carries trusted data).
+    complex Gaussian noise (per-component sigma = max|rho S| / (snr sqrt 2)),
+    on the head phantom above.  Also the two masks the estimation takes as
+    inputs (their segmentation is outside this work): M_R = the head
+    dilated by 2 voxels, M_T = brain tissue of intensity above 0.5 (the
+    scalp and the ventricles are left to the extrapolation).
     Returns imgs [G][n_echo][L] complex64, S_true [G][L], omega_true [L]
     (rad/s), beta, mask_T / mask_R [L] float32, rho [L], dims, delta_te."""
-    from scipy.ndimage import binary_dilation, binary_erosion
+    from scipy.ndimage import binary_dilation
 
     ss = np.random.default_rng(np.random.SeedSequence([_SEED_BASE + 7, seed]))
     rs = [np.random.default_rng(s) for s in ss.bit_generator.seed_seq.spawn(5)]
@@ -367,11 +383,10 @@ def prescan(dims=(64, 64), n_coil=8, n_echo=6, delta_te=1.0e-3, b0_hz=120.0, bet
     S = _sensitivities(n_coil, rs[0], x, y, z, three_d)
     cfg = dict(dims=dims, b0_kind="bump" if not three_d else "gaussians", b0_hz=b0_hz)
     omega = _b0_map(cfg, rs[1], x, y, z)
-    rho = np.abs(_phantom(rs[2], x, y, z, three_d))
+    rho = _head_phantom(x, y, z, three_d)
     shape = tuple(reversed(dims))
-    supp = (rho > 0).reshape(shape)
-    mask_R = binary_dilation(supp, iterations=2).ravel().astype(np.float32)
-    mask_T = binary_erosion(supp, iterations=2).ravel().astype(np.float32)
+    mask_R = binary_dilation((rho > 0).reshape(shape), iterations=2).ravel().astype(np.float32)
+    mask_T = (rho > 0.5).astype(np.float32)
     sigma = np.abs(S * rho[None, :]).max() / (snr * np.sqrt(2.0))
     imgs = np.empty((n_coil, n_echo, x.size), dtype=np.complex64)
     for n in range(n_echo):

@@ -92,3 +92,21 @@ def test_b0_smoothing_special_cases():
     s1 = M.smooth_b0(b, np.full(L, 0.1), dims, 5.0)
     s2 = M.smooth_b0(b, np.full(L, 1.0), dims, 5.0)
     assert np.std(s2) < np.std(s1) < np.std(b)
+
+
+def test_sensitivity_smoothing_weights_data_by_the_trusted_mask():
+    """Without penalty the data rows read diag(M_T) S = S^, so a mask of
+    constant value m gives S = S^ / m."""
+    dims = (6, 5)
+    rng = np.random.default_rng(5)
+    s = (1 + rng.random((2, 30))) * np.exp(1j * rng.uniform(-3, 3, (2, 30)))
+    got = M.smooth_sens(s, np.full(30, 0.5), np.ones(30), dims, 0.0)
+    assert np.allclose(got, 2.0 * s, atol=1e-12)
+
+
+def test_initial_sensitivities_of_an_empty_voxel_are_zero():
+    X = np.zeros((3, 4, 5), dtype=np.complex128)
+    X[:, :, 2] = np.arange(12).reshape(3, 4) + 1j
+    got = M.sens_initial(X)
+    assert np.all(got[:, [0, 1, 3, 4]] == 0)
+    assert abs(np.linalg.norm(got[:, 2]) - 1.0) < 1e-12
