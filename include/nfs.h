@@ -316,6 +316,77 @@ int nfs_encode_backward(nfs_ctx* ctx, const nfs_problem* prob, const float* rho,
 int nfs_profile_enable(nfs_ctx* ctx, int on);
 int nfs_profile_read(nfs_ctx* ctx, int kind, int* count, double* total_ms);
 
+/* ------------------------------------------------------------------------
+ * Map estimation from multi-echo prescan data (Methods, "Computation of
+ * sensitivity maps" and "Computation of B0 maps").  Float64 arithmetic.
+ * Prescan images: imgs [G][n_echo][L] complex, coil c and echo n of voxel l
+ * at imgs[(c n_echo + n) L + l]; grid nx x ny x nz (nz = 1 in 2D), voxel
+ * index x + nx (y + ny z).  The two smoothing calls solve their normal
+ * equations by Jacobi-preconditioned CG (float64 vectors and scalars, fixed-
+ * order reductions, one CG per right-hand side) until ||r|| <= tol ||b|| or
+ * max_iter iterations; they SYNCHRONISE the stream (every 32 iterations, to
+ * read the convergence flags) and so must not be captured into a graph.
+ * info: HOST int [2] or NULL: (largest iteration count over the right-hand
+ * sides, status as enum nfs_cg_status: NFS_CG_TOL when all converged,
+ * NFS_CG_EXACT when all right-hand sides were 0 or hit r == 0,
+ * NFS_CG_MAXITER if any ran out, NFS_CG_BREAKDOWN if any broke down).     */
+enum nfs_map_kind { NFS_MAP_SENS = 0, NFS_MAP_B0 = 1 };
+
+/* Workspace bytes of nfs_sens_maps (kind NFS_MAP_SENS) or nfs_b0_map
+ * (NFS_MAP_B0) for n_coil coils on an nx x ny x nz grid.                  */
+int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, int nz, size_t* bytes);
+
+/* Initial sensitivities S^: per voxel the first left singular vector of the
+ * n_coil x n_echo matrix of prescan values (rows coils, columns echoes),
+ * computed as the dominant eigenvector of its Gram matrix on the float64
+ * matrix cores, with the phase fixed so that its coil sum is real and
+ * non-negative; voxels whose values are all zero get 0.  Where the two
+ * largest singular values coincide the vector is not unique and any unit
+ * vector of the top eigenspace may be returned.
+ *   imgs: device complex [G][n_echo][L]; 1 <= G <= 16, 1 <= n_echo <= 1024
+ *   shat: device complex float64 (interleaved double pairs) [G][L]
+ * Needs no workspace; asynchronous.                                       */
+int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, int64_t n_vox, double* shat,
+                     void* stream);
+
+/* Sensitivity maps: S^ as above, then per coil the least-squares solution
+ * of the sensitivity-smoothing equation, i.e. the normal equations
+ *   (diag(M_T^2) + alpha sum_d D2_d^T diag(M_R^2) D2_d) s = M_T o s^
+ * for s^ = |S^| and for the real and imaginary parts of S^/|S^| (0 where
+ * S^ = 0), recombined as S = |S|_s n_s / |n_s| (0 where n_s = 0).  D2_d
+ * has one row (x[i-1] - 2 x[i] + x[i+1]) per voxel i whose two neighbours
+ * along axis d exist, weighted by M_R at i.  Rows of the system without
+ * any entry (voxels neither in M_T nor reached by a penalty row) give 0.
+ *   mask_T, mask_R: device float [L] (M_T, M_R; normally 0/1)
+ *   alpha >= 0; tol >= 0; max_iter >= 0
+ *   sens: device complex [G][L] or NULL; sens64: device complex float64
+ *   [G][L] or NULL (not both NULL); shat: device complex float64 [G][L] to
+ *   receive S^, or NULL (then S^ stays in the workspace)
+ * Workspace: nfs_maps_workspace_bytes(NFS_MAP_SENS, ...).                 */
+int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* mask_T, const float* mask_R,
+                  int nx, int ny, int nz, double alpha, double tol, int max_iter, float* sens, double* sens64,
+                  double* shat, int* info, void* ws, size_t ws_bytes, void* stream);
+
+/* B0 map: the prescan echoes combined with the sensitivities,
+ * c_n = sum_c conj(S_c) x_cn / sum_c |S_c|^2 (0 where the sum is 0), the
+ * phase of c_n conj(c_0) (0 for n = 0) unwrapped along the echoes (a jump
+ * of at least pi is taken modulo 2 pi into (-pi, pi]), the least-squares
+ * fit phi_n = a n + beta mod(n, 2), B0^ = a / delta_te (rad/s) and eps =
+ * the root mean square residual (the B0-fit equation); then the solution
+ * of the B0-smoothing equation's normal equations
+ *   (I + alpha sum_d D1_d^T diag(eps^2) D1_d) B0 = B0^,
+ * D1_d with one row (x[i+1] - x[i]) per voxel i whose next neighbour along
+ * axis d exists, weighted by eps at i.
+ *   sens: device complex [G][L]; 1 <= G <= 64; 3 <= n_echo <= 64;
+ *   delta_te > 0 (s); alpha, tol, max_iter as above
+ *   b0: device float [L] or NULL; b064: device double [L] or NULL;
+ *   fit: device double [3][L] (B0^, beta, eps) or NULL; at least one given.
+ *   With b0 and b064 both NULL only the fit runs (info = (0, 0)).
+ * Workspace: nfs_maps_workspace_bytes(NFS_MAP_B0, ...).                   */
+int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* sens, int nx, int ny, int nz,
+               double delta_te, double alpha, double tol, int max_iter, float* b0, double* b064, double* fit,
+               int* info, void* ws, size_t ws_bytes, void* stream);
+
 /* Message for the last non-OK status returned on the calling thread. */
 const char* nfs_last_error(void);
 

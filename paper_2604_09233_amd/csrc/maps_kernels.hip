@@ -1,0 +1,689 @@
+// Sensitivity and B0 map estimation from multi-echo prescan data (Methods,
+// "Computation of sensitivity maps" and "Computation of B0 maps"), float64
+// throughout.
+//
+// Initial sensitivities.  Per voxel the coil x echo matrix X (G <= 16 rows)
+// has as first left singular vector the dominant eigenvector of the
+// Hermitian Gram matrix X X^H.  The Gram matrix is formed on the float64
+// matrix cores (16x16x4 tiles, echoes as the contraction index) and its
+// dominant eigenvector isolated by repeated squaring: B <- B^2 / ||B||_F
+// converges to the rank-one projector u u^H at the rate (l2 / l1)^(2^k).
+// Because B is Hermitian, the operand layouts of the 16x16x4 instruction line
+// up with its result layout (register r of a lane holds row lane/16 + 4 r of
+// column lane % 16, which is, conjugated, the A operand and, as is, the B
+// operand of the r-th four-wide slice of the contraction), so every squaring
+// stays in registers.  u is read off the column of the largest diagonal entry and
+// rotated so that its coil sum is real and non-negative.
+//
+// Smoothing.  Both smoothing equations are least-squares problems whose
+// normal equations A x = b have a stencil matrix:
+//   sensitivities: A = diag(t) + a sum_d D2_d^T diag(w) D2_d, t = M_T^2,
+//                  w = M_R^2, b = M_T o (|S^|, Re n, Im n), n = S^/|S^|;
+//   B0:            A = I + a sum_d D1_d^T diag(w) D1_d, w = eps^2, b = B0^.
+// D2 along an axis has a row centred at every voxel whose two neighbours
+// along it exist; D1 a row at every voxel whose next neighbour exists, the
+// row weight taken at that voxel.  A is applied matrix-free and the systems
+// (3G sensitivity right-hand sides share one A) are solved by Jacobi-
+// preconditioned CG with float64 vectors and scalars, per right-hand side,
+// with fixed-order reductions.  The search direction p = D^-1 r + beta p is
+// not stored between the two passes of an iteration: the apply pass forms
+// it at each stencil point from r and the previous p (the same expression
+// everywhere, so the stored value and the one used in A p agree bitwise).
+//
+// B0 fit.  Per voxel the echoes are combined with the sensitivities,
+// c_n = sum_c conj(S_c) x_cn / sum_c |S_c|^2, the phase of c_n conj(c_0)
+// is unwrapped along n (a jump of at least pi between neighbouring echoes is
+// taken modulo 2 pi into (-pi, pi]), and phi_n = a n + b mod(n, 2) is fitted
+// by least squares (2x2 normal equations); B0^ = a / dTE, eps = the root mean
+// square fit residual.
+#include "nfs_internal.h"
+
+namespace nfs {
+
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+constexpr int kVoxPerBlock = 16;  // voxels staged per workgroup, 4 per wave
+constexpr int kEchoChunk = 16;    // echoes staged per pass
+constexpr int kStageStride = kVoxPerBlock + 1;
+constexpr int kMaxSquarings = 24;
+constexpr double kProjTol = 1e-13;  // trace(B) - 1 below this: one more squaring, then stop
+
+__device__ __forceinline__ double wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
+// acc += Y Y^H for the 16 x 4 complex block Y held one entry per lane (row
+// lane % 16, column lane / 16); acc in the 16x16x4 result layout.
+__device__ __forceinline__ void herm_rank4(double yr, double yi, dbl4& ar, dbl4& ai) {
+  ar = __builtin_amdgcn_mfma_f64_16x16x4f64(yr, yr, ar, 0, 0, 0);
+  ar = __builtin_amdgcn_mfma_f64_16x16x4f64(yi, yi, ar, 0, 0, 0);
+  ai = __builtin_amdgcn_mfma_f64_16x16x4f64(yi, yr, ai, 0, 0, 0);
+  ai = __builtin_amdgcn_mfma_f64_16x16x4f64(-yr, yi, ai, 0, 0, 0);
+}
+
+// Row of the 16x16x4 float64 result held in register r of a lane (its
+// column is lane % 16).
+__device__ __forceinline__ int result_row(int lane, int r) { return (lane >> 4) + 4 * r; }
+
+// Frobenius norm squared and trace of the Hermitian matrix held in the
+// result layout (every lane gets both).
+__device__ __forceinline__ void norm_trace(const dbl4& cr, const dbl4& ci, int lane, double& f2, double& tr) {
+  const int col = lane & 15;
+  double f = 0.0, t = 0.0;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    f += cr[r] * cr[r] + ci[r] * ci[r];
+    if (result_row(lane, r) == col) t += cr[r];
+  }
+  f2 = wave_sum(f);
+  tr = wave_sum(t);
+}
+
+__global__ void __launch_bounds__(256) sens_initial_kernel(const float2* __restrict__ X, int G, int ne, int64_t L,
+                                                           double2* __restrict__ shat) {
+  __shared__ float2 stage[kMaxSvdCoils * kEchoChunk * kStageStride];
+  __shared__ double2 proj[4][16 * 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int64_t l0 = (int64_t)blockIdx.x * kVoxPerBlock;
+  const int row_i = lane & 15, kslot = lane >> 4;
+
+  dbl4 cr[4], ci[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    cr[v] = dbl4{0.0, 0.0, 0.0, 0.0};
+    ci[v] = dbl4{0.0, 0.0, 0.0, 0.0};
+  }
+  // Gram matrices of the wave's four voxels, echo chunk by echo chunk
+  for (int n0 = 0; n0 < ne; n0 += kEchoChunk) {
+    __syncthreads();
+    for (int idx = tid; idx < G * kEchoChunk * kVoxPerBlock; idx += 256) {
+      const int v = idx % kVoxPerBlock, rowe = idx / kVoxPerBlock;  // rowe = coil * kEchoChunk + echo
+      const int g = rowe / kEchoChunk, n = n0 + rowe % kEchoChunk;
+      const int64_t l = l0 + v;
+      float2 x = make_float2(0.f, 0.f);
+      if (n < ne && l < L) x = X[((int64_t)g * ne + n) * L + l];
+      stage[rowe * kStageStride + v] = x;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int vox = wave * 4 + v;
+#pragma unroll
+      for (int kb = 0; kb < 4; ++kb) {
+        float2 y = make_float2(0.f, 0.f);
+        if (row_i < G) y = stage[(row_i * kEchoChunk + 4 * kb + kslot) * kStageStride + vox];
+        herm_rank4((double)y.x, (double)y.y, cr[v], ci[v]);
+      }
+    }
+  }
+  // normalise, then square until every voxel's projector has converged
+  bool live[4], last[4];
+  double tr[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    double f2;
+    norm_trace(cr[v], ci[v], lane, f2, tr[v]);
+    live[v] = f2 > 0.0;  // a voxel without data keeps the zero estimate
+    last[v] = false;
+    const double s = live[v] ? 1.0 / sqrt(f2) : 0.0;
+    cr[v] *= s;
+    ci[v] *= s;
+    tr[v] *= s;
+  }
+  for (int k = 0; k < kMaxSquarings; ++k) {
+    bool any = false;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (live[v] && !last[v] && tr[v] - 1.0 < kProjTol) last[v] = true;
+      else if (live[v] && last[v]) live[v] = false;  // converged and squared once more
+      any |= live[v];
+    }
+    if (!any) break;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      if (!live[v]) continue;
+      dbl4 nr = {0.0, 0.0, 0.0, 0.0}, ni = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < 4; ++r) herm_rank4(cr[v][r], -ci[v][r], nr, ni);
+      double f2, t;
+      norm_trace(nr, ni, lane, f2, t);
+      const double s = 1.0 / sqrt(f2);
+      cr[v] = nr * s;
+      ci[v] = ni * s;
+      tr[v] = t * s;
+    }
+  }
+  // read u off the column of the largest diagonal entry
+  double2* B = proj[wave];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int64_t l = l0 + wave * 4 + v;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) B[result_row(lane, r) * 16 + row_i] = make_double2(cr[v][r], ci[v][r]);
+    __syncthreads();  // every wave runs this loop the same number of times
+    int jm = 0;
+    double dm = B[0].x;
+    for (int j = 1; j < 16; ++j)
+      if (B[j * 16 + j].x > dm) {
+        dm = B[j * 16 + j].x;
+        jm = j;
+      }
+    double ur = 0.0, ui = 0.0;
+    if (dm > 0.0) {
+      const double s = 1.0 / sqrt(dm);
+      const double2 b = B[row_i * 16 + jm];
+      ur = b.x * s;
+      ui = b.y * s;
+    }
+    // coil sum over the 16 rows (lanes 0..15 hold them, as do the other groups)
+    double tr_ = ur, ti = ui;
+    for (int off = 8; off > 0; off >>= 1) {
+      tr_ += __shfl_xor(tr_, off);
+      ti += __shfl_xor(ti, off);
+    }
+    const double ta = hypot(tr_, ti);
+    if (ta > 0.0) {
+      const double cr_ = tr_ / ta, ci_ = -ti / ta;  // conj(t) / |t|
+      const double vr = ur * cr_ - ui * ci_, vi = ur * ci_ + ui * cr_;
+      ur = vr;
+      ui = vi;
+    }
+    if (lane < G && l < L) shat[(int64_t)lane * L + l] = make_double2(ur, ui);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- smoothing
+
+struct Grid3 {
+  int n[3];
+  int64_t s[3];
+};
+
+__device__ __forceinline__ void coords(const Grid3& g, int64_t j, int c[3]) {
+  c[0] = (int)(j % g.n[0]);
+  const int64_t q = j / g.n[0];
+  c[1] = (int)(q % g.n[1]);
+  c[2] = (int)(q / g.n[1]);
+}
+
+// Search direction at voxel i: D^-1 r + beta p_old (one expression for every
+// use, so stored and recomputed values agree bitwise).
+__device__ __forceinline__ double dir_at(const double* __restrict__ dinv, const double* __restrict__ r,
+                                         const double* __restrict__ po, double beta, int64_t i) {
+  return fma(beta, po[i], dinv[i] * r[i]);
+}
+
+// Row j of A applied to a vector given by the accessor V (SENS: D2 penalty,
+// B0: D1 penalty); also the diagonal of A when V is the unit-vector probe.
+template <int OP, class V>
+__device__ __forceinline__ double apply_row(const Grid3& g, const double* __restrict__ t, const double* __restrict__ w,
+                                            double alpha, int64_t j, const int c[3], V val) {
+  const double v0 = val(j);
+  double pen = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int n = g.n[d], cd = c[d];
+    const int64_t s = g.s[d];
+    if (OP == MAP_SENS) {
+      if (n < 3) continue;
+      const double vm1 = cd >= 1 ? val(j - s) : 0.0;
+      const double vp1 = cd <= n - 2 ? val(j + s) : 0.0;
+      if (cd >= 2) pen += w[j - s] * (val(j - 2 * s) - 2.0 * vm1 + v0);
+      if (cd >= 1 && cd <= n - 2) pen -= 2.0 * w[j] * (vm1 - 2.0 * v0 + vp1);
+      if (cd <= n - 3) pen += w[j + s] * (v0 - 2.0 * vp1 + val(j + 2 * s));
+    } else {
+      if (n < 2) continue;
+      if (cd >= 1) pen += w[j - s] * (v0 - val(j - s));
+      if (cd <= n - 2) pen -= w[j] * (val(j + s) - v0);
+    }
+  }
+  const double tj = OP == MAP_SENS ? t[j] : 1.0;
+  return fma(alpha, pen, tj * v0);
+}
+
+template <int OP>
+__device__ __forceinline__ double diag_row(const Grid3& g, const double* __restrict__ t, const double* __restrict__ w,
+                                           double alpha, int64_t j, const int c[3]) {
+  double pen = 0.0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const int n = g.n[d], cd = c[d];
+    const int64_t s = g.s[d];
+    if (OP == MAP_SENS) {
+      if (n < 3) continue;
+      if (cd >= 2) pen += w[j - s];
+      if (cd >= 1 && cd <= n - 2) pen += 4.0 * w[j];
+      if (cd <= n - 3) pen += w[j + s];
+    } else {
+      if (n < 2) continue;
+      if (cd >= 1) pen += w[j - s];
+      if (cd <= n - 2) pen += w[j];
+    }
+  }
+  const double tj = OP == MAP_SENS ? t[j] : 1.0;
+  return fma(alpha, pen, tj);
+}
+
+// Sum of v over the workgroup (256 threads) in a fixed tree; valid in thread 0.
+__device__ __forceinline__ double block_total(double v, double* red) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) red[wave] = v;
+  __syncthreads();
+  return (red[0] + red[1]) + (red[2] + red[3]);
+}
+
+// Weights and the inverse diagonal: SENS t = mT^2, w = mR^2 (float masks);
+// B0 w = eps^2 (float64 eps, t unused).
+template <int OP>
+__global__ void __launch_bounds__(256) smooth_setup_kernel(Grid3 g, int64_t L, const float* __restrict__ mT,
+                                                           const float* __restrict__ mR,
+                                                           const double* __restrict__ eps, double alpha,
+                                                           double* __restrict__ t, double* __restrict__ w) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  if (OP == MAP_SENS) {
+    const double a = mT[j], b = mR[j];
+    t[j] = a * a;
+    w[j] = b * b;
+  } else {
+    const double e = eps[j];
+    w[j] = e * e;
+  }
+}
+
+template <int OP>
+__global__ void __launch_bounds__(256) smooth_dinv_kernel(Grid3 g, int64_t L, const double* __restrict__ t,
+                                                          const double* __restrict__ w, double alpha,
+                                                          double* __restrict__ dinv) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  int c[3];
+  coords(g, j, c);
+  const double d = diag_row<OP>(g, t, w, alpha, j, c);
+  dinv[j] = d > 0.0 ? 1.0 / d : 0.0;
+}
+
+// x = 0, r = b, p = 0; partials of b.b and r.(D^-1 r).
+__global__ void __launch_bounds__(256) pcg_init_kernel(PcgState st, const double* __restrict__ b) {
+  __shared__ double red[4];
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int rhs = blockIdx.y;
+  const size_t o = (size_t)rhs * st.Lp;
+  double bb = 0.0, rz = 0.0;
+  if (j < st.L) {
+    const double bj = b[o + j];
+    st.x[o + j] = 0.0;
+    st.r[o + j] = bj;
+    st.p[0][o + j] = 0.0;
+    bb = bj * bj;
+    rz = bj * (st.dinv[j] * bj);
+  }
+  bb = block_total(bb, red);
+  rz = block_total(rz, red);
+  if (threadIdx.x == 0) {
+    st.part0[(size_t)rhs * st.nblk + blockIdx.x] = bb;
+    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+  }
+}
+
+__device__ __forceinline__ double sum_parts(const double* part, int nblk, double* red) {
+  double s = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += 256) s += part[i];
+  return block_total(s, red);
+}
+
+__global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  const double bb = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double rz = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
+  if (threadIdx.x == 0) {
+    st.bb[rhs] = bb;
+    st.rr[rhs] = bb;
+    st.rz[rhs] = rz;
+    st.beta[rhs] = 0.0;
+    st.alpha[rhs] = 0.0;
+    st.iters[rhs] = 0;
+    st.status[rhs] = bb > 0.0 ? 0 : PCG_EXACT;
+  }
+}
+
+// p_new = D^-1 r + beta p_old (stored), q = A p_new; partial p_new.q.
+template <int OP>
+__global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, const double* __restrict__ t,
+                                                        const double* __restrict__ w, double alpha, int pin) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.y;
+  if (st.status[rhs]) return;  // uniform per workgroup
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t o = (size_t)rhs * st.Lp;
+  const double* r = st.r + o;
+  const double* po = st.p[pin] + o;
+  const double beta = st.beta[rhs];
+  const double* dinv = st.dinv;
+  double pq = 0.0;
+  if (j < st.L) {
+    int c[3];
+    coords(g, j, c);
+    auto val = [&](int64_t i) { return dir_at(dinv, r, po, beta, i); };
+    const double pj = val(j);
+    const double qj = apply_row<OP>(g, t, w, alpha, j, c, val);
+    st.p[pin ^ 1][o + j] = pj;
+    st.q[o + j] = qj;
+    pq = pj * qj;
+  }
+  pq = block_total(pq, red);
+  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = pq;
+}
+
+__global__ void __launch_bounds__(256) pcg_alpha_kernel(PcgState st) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  if (st.status[rhs]) return;
+  const double pq = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
+  if (threadIdx.x == 0) {
+    const double a = st.rz[rhs] / pq;
+    if (!(pq > 0.0) || !isfinite(a)) {
+      st.status[rhs] = PCG_BREAKDOWN;
+      st.alpha[rhs] = 0.0;
+    } else {
+      st.alpha[rhs] = a;
+    }
+  }
+}
+
+// x += alpha p, r -= alpha q; partials of r.(D^-1 r) and r.r.
+__global__ void __launch_bounds__(256) pcg_update_kernel(PcgState st, int pnew) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.y;
+  if (st.status[rhs]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t o = (size_t)rhs * st.Lp;
+  const double a = st.alpha[rhs];
+  double rz = 0.0, rr = 0.0;
+  if (j < st.L) {
+    const double pj = st.p[pnew][o + j];
+    st.x[o + j] = fma(a, pj, st.x[o + j]);
+    const double rj = fma(-a, st.q[o + j], st.r[o + j]);
+    st.r[o + j] = rj;
+    rz = rj * (st.dinv[j] * rj);
+    rr = rj * rj;
+  }
+  rz = block_total(rz, red);
+  rr = block_total(rr, red);
+  if (threadIdx.x == 0) {
+    st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = rr;
+  }
+}
+
+__global__ void __launch_bounds__(256) pcg_beta_kernel(PcgState st, double tol2) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.x;
+  if (st.status[rhs]) return;
+  const double rz = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double rr = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
+  if (threadIdx.x == 0) {
+    st.iters[rhs] += 1;
+    st.rr[rhs] = rr;
+    const double bt = rz / st.rz[rhs];
+    if (rr == 0.0) st.status[rhs] = PCG_EXACT;
+    else if (rr <= tol2 * st.bb[rhs]) st.status[rhs] = PCG_TOL;
+    else if (!isfinite(bt)) st.status[rhs] = PCG_BREAKDOWN;
+    st.beta[rhs] = bt;
+    st.rz[rhs] = rz;
+  }
+}
+
+// Right-hand sides of the sensitivity smoothing from S^ [G][L]:
+// rows c, G + c, 2G + c = mT |S^|, mT Re(S^/|S^|), mT Im(S^/|S^|).
+__global__ void __launch_bounds__(256) sens_rhs_kernel(const double2* __restrict__ shat, const float* __restrict__ mT,
+                                                       int G, int64_t L, int64_t Lp, double* __restrict__ b) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (j >= L) return;
+  const double2 s = shat[(int64_t)c * L + j];
+  const double m = hypot(s.x, s.y);
+  const double nr = m > 0.0 ? s.x / m : 0.0, ni = m > 0.0 ? s.y / m : 0.0;
+  const double wt = mT[j];
+  b[(size_t)c * Lp + j] = wt * m;
+  b[(size_t)(G + c) * Lp + j] = wt * nr;
+  b[(size_t)(2 * G + c) * Lp + j] = wt * ni;
+}
+
+// S = |S|_s n_s / |n_s| from the smoothed components.
+__global__ void __launch_bounds__(256) sens_combine_kernel(const double* __restrict__ x, int G, int64_t L, int64_t Lp,
+                                                           float2* __restrict__ s32, double2* __restrict__ s64) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (j >= L) return;
+  const double m = x[(size_t)c * Lp + j];
+  const double nr = x[(size_t)(G + c) * Lp + j], ni = x[(size_t)(2 * G + c) * Lp + j];
+  const double a = hypot(nr, ni);
+  double sr = 0.0, si = 0.0;
+  if (a > 0.0) {
+    sr = (m * nr) / a;
+    si = (m * ni) / a;
+  }
+  if (s32) s32[(int64_t)c * L + j] = make_float2((float)sr, (float)si);
+  if (s64) s64[(int64_t)c * L + j] = make_double2(sr, si);
+}
+
+// Float64 modulo with the sign of the divisor (floor modulo).
+__device__ __forceinline__ double floor_mod(double a, double b) {
+  double m = fmod(a, b);
+  if (m != 0.0 && ((b < 0.0) != (m < 0.0))) m += b;
+  return m;
+}
+
+__global__ void __launch_bounds__(256) b0_fit_kernel(const float2* __restrict__ X, const float2* __restrict__ S, int G,
+                                                     int ne, int64_t L, double dte, double* __restrict__ b0hat,
+                                                     double* __restrict__ beta, double* __restrict__ eps) {
+  const int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (l >= L) return;
+  double wsum = 0.0;
+  for (int g = 0; g < G; ++g) {
+    const float2 s = S[(int64_t)g * L + l];
+    wsum += (double)s.x * s.x + (double)s.y * s.y;
+  }
+  const double winv = 1.0 / (wsum > 0.0 ? wsum : 1.0);
+  const double pi = 3.14159265358979311600, two_pi = 2.0 * pi;
+  double c0r = 0.0, c0i = 0.0, prev = 0.0, corr = 0.0;
+  double snp = 0.0, smp = 0.0, snn = 0.0, snm = 0.0, smm = 0.0;
+  // first pass: unwrapped phases and the fit sums; second pass: residuals
+  double phis[kMaxFitEchoes];
+  for (int n = 0; n < ne; ++n) {
+    double cr = 0.0, ci = 0.0;
+    for (int g = 0; g < G; ++g) {
+      const float2 s = S[(int64_t)g * L + l];
+      const float2 x = X[((int64_t)g * ne + n) * L + l];
+      const double sr = s.x, si = s.y, xr = x.x, xi = x.y;
+      cr += sr * xr + si * xi;  // conj(s) x
+      ci += sr * xi - si * xr;
+    }
+    cr *= winv;
+    ci *= winv;
+    if (n == 0) {
+      c0r = cr;
+      c0i = ci;
+    }
+    // phase of c_n conj(c_0)
+    const double pr = cr * c0r + ci * c0i, pim = ci * c0r - cr * c0i;
+    const double ph = n > 0 ? atan2(pim, pr) : 0.0;  // the first echo's phase is the reference
+    double up = ph;
+    if (n > 0) {
+      const double dd = ph - prev;
+      double dm = floor_mod(dd + pi, two_pi) - pi;
+      if (dm == -pi && dd > 0.0) dm = pi;
+      if (fabs(dd) >= pi) corr += dm - dd;
+      up = ph + corr;
+    }
+    prev = ph;
+    phis[n] = up;
+    const double dn = n, dmn = n & 1;
+    snp += dn * up;
+    smp += dmn * up;
+    snn += dn * dn;
+    snm += dn * dmn;
+    smm += dmn * dmn;
+  }
+  const double det = snn * smm - snm * snm;
+  const double a = (smm * snp - snm * smp) / det;
+  const double bcoef = (snn * smp - snm * snp) / det;
+  double ss = 0.0;
+  for (int n = 0; n < ne; ++n) {
+    const double res = phis[n] - (a * n + bcoef * (n & 1));
+    ss += res * res;
+  }
+  b0hat[l] = a / dte;
+  beta[l] = bcoef;
+  eps[l] = sqrt(ss / ne);
+}
+
+__global__ void __launch_bounds__(256) b0_store_kernel(const double* __restrict__ x, int64_t L, float* __restrict__ b0,
+                                                       double* __restrict__ b064) {
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  if (b0) b0[j] = (float)x[j];
+  if (b064) b064[j] = x[j];
+}
+
+Grid3 make_grid(int nx, int ny, int nz) {
+  Grid3 g;
+  g.n[0] = nx;
+  g.n[1] = ny;
+  g.n[2] = nz;
+  g.s[0] = 1;
+  g.s[1] = nx;
+  g.s[2] = (int64_t)nx * ny;
+  return g;
+}
+
+unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+}  // namespace
+
+size_t pcg_state_bytes(int nrhs, int64_t L) {
+  const int64_t Lp = (L + 63) & ~(int64_t)63;
+  const int64_t nblk = (L + 255) / 256;
+  size_t b = 0;
+  auto add = [&](size_t n) { b += (n + 255) & ~(size_t)255; };
+  for (int i = 0; i < 5; ++i) add((size_t)nrhs * Lp * 8);  // x r p0 p1 q
+  add((size_t)Lp * 8);                                       // dinv
+  add((size_t)nrhs * nblk * 8);                              // part0
+  add((size_t)nrhs * nblk * 8);                              // part1
+  for (int i = 0; i < 6; ++i) add((size_t)nrhs * 8);         // rz alpha beta bb rr + iters/status
+  add((size_t)nrhs * 8);
+  return b;
+}
+
+PcgState pcg_state(void* base, int nrhs, int64_t L) {
+  PcgState st;
+  st.L = L;
+  st.Lp = (L + 63) & ~(int64_t)63;
+  st.nblk = (int)((L + 255) / 256);
+  st.nrhs = nrhs;
+  char* p = static_cast<char*>(base);
+  auto take = [&](size_t n) {
+    char* q = p;
+    p += (n + 255) & ~(size_t)255;
+    return q;
+  };
+  const size_t vec = (size_t)nrhs * st.Lp * 8;
+  st.x = (double*)take(vec);
+  st.r = (double*)take(vec);
+  st.p[0] = (double*)take(vec);
+  st.p[1] = (double*)take(vec);
+  st.q = (double*)take(vec);
+  st.dinv = (double*)take((size_t)st.Lp * 8);
+  st.part0 = (double*)take((size_t)nrhs * st.nblk * 8);
+  st.part1 = (double*)take((size_t)nrhs * st.nblk * 8);
+  st.rz = (double*)take((size_t)nrhs * 8);
+  st.alpha = (double*)take((size_t)nrhs * 8);
+  st.beta = (double*)take((size_t)nrhs * 8);
+  st.bb = (double*)take((size_t)nrhs * 8);
+  st.rr = (double*)take((size_t)nrhs * 8);
+  st.iters = (int*)take((size_t)nrhs * 8);
+  st.status = (int*)take((size_t)nrhs * 8);
+  return st;
+}
+
+hipError_t launch_sens_initial(const float2* X, int G, int ne, int64_t L, double2* shat, hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(sens_initial_kernel, dim3(cdiv_u(L, kVoxPerBlock)), dim3(256), 0, s, X, G, ne, L, shat);
+  return hipGetLastError();
+}
+
+hipError_t launch_sens_rhs(const double2* shat, const float* mT, int G, int64_t L, int64_t Lp, double* b,
+                           hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(sens_rhs_kernel, dim3(cdiv_u(L, 256), G), dim3(256), 0, s, shat, mT, G, L, Lp, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_sens_combine(const double* x, int G, int64_t L, int64_t Lp, float2* s32, double2* s64,
+                               hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(sens_combine_kernel, dim3(cdiv_u(L, 256), G), dim3(256), 0, s, x, G, L, Lp, s32, s64);
+  return hipGetLastError();
+}
+
+hipError_t launch_b0_fit(const float2* X, const float2* S, int G, int ne, int64_t L, double dte, double* b0hat,
+                         double* beta, double* eps, hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(b0_fit_kernel, dim3(cdiv_u(L, 256)), dim3(256), 0, s, X, S, G, ne, L, dte, b0hat, beta, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_b0_store(const double* x, int64_t L, float* b0, double* b064, hipStream_t s) {
+  if (L == 0) return hipSuccess;
+  hipLaunchKernelGGL(b0_store_kernel, dim3(cdiv_u(L, 256)), dim3(256), 0, s, x, L, b0, b064);
+  return hipGetLastError();
+}
+
+hipError_t launch_smooth_setup(int op, int nx, int ny, int nz, const float* mT, const float* mR, const double* eps,
+                               double alpha, double* t, double* w, const PcgState& st, hipStream_t s) {
+  const Grid3 g = make_grid(nx, ny, nz);
+  const int64_t L = st.L;
+  if (L == 0) return hipSuccess;
+  const dim3 grid(cdiv_u(L, 256));
+  if (op == MAP_SENS) {
+    hipLaunchKernelGGL(smooth_setup_kernel<MAP_SENS>, grid, dim3(256), 0, s, g, L, mT, mR, eps, alpha, t, w);
+    hipLaunchKernelGGL(smooth_dinv_kernel<MAP_SENS>, grid, dim3(256), 0, s, g, L, t, w, alpha, st.dinv);
+  } else {
+    hipLaunchKernelGGL(smooth_setup_kernel<MAP_B0>, grid, dim3(256), 0, s, g, L, mT, mR, eps, alpha, t, w);
+    hipLaunchKernelGGL(smooth_dinv_kernel<MAP_B0>, grid, dim3(256), 0, s, g, L, t, w, alpha, st.dinv);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(const PcgState& st, const double* b, hipStream_t s) {
+  if (st.L == 0 || st.nrhs == 0) return hipSuccess;
+  hipLaunchKernelGGL(pcg_init_kernel, dim3(st.nblk, st.nrhs), dim3(256), 0, s, st, b);
+  hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_iteration(int op, const PcgState& st, int nx, int ny, int nz, const double* t, const double* w,
+                                double alpha, double tol2, int it, hipStream_t s) {
+  if (st.L == 0 || st.nrhs == 0) return hipSuccess;
+  const Grid3 g = make_grid(nx, ny, nz);
+  const int pin = it & 1;
+  const dim3 grid(st.nblk, st.nrhs);
+  if (op == MAP_SENS)
+    hipLaunchKernelGGL(pcg_apply_kernel<MAP_SENS>, grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+  else
+    hipLaunchKernelGGL(pcg_apply_kernel<MAP_B0>, grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+  hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+  hipLaunchKernelGGL(pcg_update_kernel, grid, dim3(256), 0, s, st, pin ^ 1);
+  hipLaunchKernelGGL(pcg_beta_kernel, dim3(st.nrhs), dim3(256), 0, s, st, tol2);
+  return hipGetLastError();
+}
+
+}  // namespace nfs

@@ -189,4 +189,54 @@ hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
 hipError_t launch_cg_reorth_apply(const CgState& st, int nv, bool from_rn, hipStream_t s);
 hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, int64_t L, hipStream_t s);
 
+
+// ---- map estimation (sensitivity and B0 maps from prescan data) ----
+constexpr int kMaxSvdCoils = 16;   // coils of the per-voxel SVD (one 16x16 matrix-core tile)
+constexpr int kMaxFitEchoes = 64;  // echoes of the B0 fit
+enum { MAP_SENS = 0, MAP_B0 = 1 };
+// PCG status per right-hand side (0 = running), same codes as the CG solve
+enum { PCG_TOL = 2, PCG_EXACT = 3, PCG_BREAKDOWN = 4 };
+
+// Jacobi-preconditioned CG over nrhs float64 right-hand sides of length L
+// (each stored with stride Lp), all in the caller's workspace.
+struct PcgState {
+  double* x;
+  double* r;
+  double* p[2];  // ping-pong: iteration n reads p[n & 1], writes p[(n & 1) ^ 1]
+  double* q;
+  double* dinv;  // [Lp] inverse diagonal (0 on rows without entries)
+  double* part0;  // [nrhs][nblk] workgroup partials
+  double* part1;
+  double* rz;     // [nrhs] r.(D^-1 r)
+  double* alpha;
+  double* beta;
+  double* bb;     // [nrhs] b.b
+  double* rr;     // [nrhs] r.r of the last iteration
+  int* iters;     // [nrhs] iterations run
+  int* status;    // [nrhs] 0 running, else PCG_*
+  int64_t L, Lp;
+  int nblk, nrhs;
+};
+size_t pcg_state_bytes(int nrhs, int64_t L);
+PcgState pcg_state(void* base, int nrhs, int64_t L);
+
+// S^ [G][L] (complex float64) from prescan X [G][ne][L] (complex float32), G <= 16
+hipError_t launch_sens_initial(const float2* X, int G, int ne, int64_t L, double2* shat, hipStream_t s);
+// b [3G][Lp]: mT |S^|, mT Re(S^/|S^|), mT Im(S^/|S^|)
+hipError_t launch_sens_rhs(const double2* shat, const float* mT, int G, int64_t L, int64_t Lp, double* b,
+                           hipStream_t s);
+// S [G][L] = x_mag * x_n / |x_n| from the smoothed components x [3G][Lp]; either output may be NULL
+hipError_t launch_sens_combine(const double* x, int G, int64_t L, int64_t Lp, float2* s32, double2* s64,
+                               hipStream_t s);
+// B0^ (rad/s), beta, eps [L] from prescan X and sensitivities S [G][L], ne <= kMaxFitEchoes
+hipError_t launch_b0_fit(const float2* X, const float2* S, int G, int ne, int64_t L, double dte, double* b0hat,
+                         double* beta, double* eps, hipStream_t s);
+hipError_t launch_b0_store(const double* x, int64_t L, float* b0, double* b064, hipStream_t s);
+// weights t, w [L] and st.dinv of the MAP_SENS (masks) or MAP_B0 (eps) system
+hipError_t launch_smooth_setup(int op, int nx, int ny, int nz, const float* mT, const float* mR, const double* eps,
+                               double alpha, double* t, double* w, const PcgState& st, hipStream_t s);
+hipError_t launch_pcg_init(const PcgState& st, const double* b, hipStream_t s);
+hipError_t launch_pcg_iteration(int op, const PcgState& st, int nx, int ny, int nz, const double* t, const double* w,
+                                double alpha, double tol2, int it, hipStream_t s);
+
 }  // namespace nfs

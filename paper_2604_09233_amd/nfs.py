@@ -84,6 +84,12 @@ def lib():
             L.nfs_autotune_batched.argtypes = [vp, i32, pp, i32, vp, sz, vp]
             L.nfs_profile_enable.argtypes = [vp, i32]
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+            L.nfs_maps_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+            L.nfs_sens_initial.argtypes = [vp, vp, i32, i32, ctypes.c_int64, vp, vp]
+            L.nfs_sens_maps.argtypes = [vp, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp, vp,
+                                        ctypes.POINTER(i32), vp, sz, vp]
+            L.nfs_b0_map.argtypes = [vp, vp, i32, i32, vp, i32, i32, i32, dbl, dbl, dbl, i32, vp, vp, vp,
+                                     ctypes.POINTER(i32), vp, sz, vp]
             L.nfs_last_error.restype = ctypes.c_char_p
             L.nfs_last_error.argtypes = []
             L.nfs_version.argtypes = []
@@ -93,7 +99,8 @@ def lib():
                          "nfs_set_graphs", "nfs_tune_workspace_bytes", "nfs_autotune", "nfs_tuned_shape",
                          "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident",
                          "nfs_cg_solve_traced", "nfs_ssim_workspace_bytes", "nfs_ssim", "nfs_lcurve_corner",
-                         "nfs_kspace_filter_workspace_bytes", "nfs_apply_kspace_filter", "nfs_kspace_filter_mask"):
+                         "nfs_kspace_filter_workspace_bytes", "nfs_apply_kspace_filter", "nfs_kspace_filter_mask",
+                         "nfs_maps_workspace_bytes", "nfs_sens_initial", "nfs_sens_maps", "nfs_b0_map"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -456,3 +463,73 @@ def profile_read(device: int, kind: str):
     ms = ctypes.c_double()
     _check(lib().nfs_profile_read(context(device), {"E": 0, "EH": 1}[kind], ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+MAP_KINDS = {"sens": 0, "b0": 1}
+
+
+def _grid(dims):
+    nx, ny = int(dims[0]), int(dims[1])
+    return nx, ny, int(dims[2]) if len(dims) > 2 else 1
+
+
+def _map_workspace(kind, n_coil, dims, dev):
+    nbytes = ctypes.c_size_t()
+    _check(lib().nfs_maps_workspace_bytes(MAP_KINDS[kind], n_coil, *_grid(dims), ctypes.byref(nbytes)))
+    ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+    off = (-ws.data_ptr()) % 256
+    return ctypes.c_void_p(ws.data_ptr() + off), nbytes.value, ws
+
+
+def sens_initial(imgs, device: int = 0):
+    """Initial sensitivities S^ [G][L] (complex128 device tensor) from prescan
+    images imgs [G][n_echo][L] complex64 (see include/nfs.h)."""
+    dev = torch.device("cuda", device)
+    X = _c64(torch.as_tensor(imgs), dev)
+    G, ne, L = X.shape
+    out = torch.empty(G, L, dtype=torch.complex128, device=dev)
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().nfs_sens_initial(context(device), _ptr(X), G, ne, L, _ptr(out), stream))
+    return out
+
+
+def sens_maps(imgs, mask_T, mask_R, dims, alpha: float, tol: float = 1e-10, max_iter: int = 100000,
+              device: int = 0):
+    """Smoothed and extrapolated sensitivity maps from prescan images
+    imgs [G][n_echo][L] and the masks M_T, M_R [L] on the grid dims.
+    Returns (S complex64 [G][L], S complex128 [G][L], S^ complex128 [G][L],
+    (iterations, status))."""
+    dev = torch.device("cuda", device)
+    X = _c64(torch.as_tensor(imgs), dev)
+    G, ne, L = X.shape
+    mT = _f32(torch.as_tensor(mask_T), dev)
+    mR = _f32(torch.as_tensor(mask_R), dev)
+    s32 = torch.empty(G, L, dtype=torch.complex64, device=dev)
+    s64 = torch.empty(G, L, dtype=torch.complex128, device=dev)
+    shat = torch.empty(G, L, dtype=torch.complex128, device=dev)
+    ws, nb, keep = _map_workspace("sens", G, dims, dev)
+    info = (ctypes.c_int * 2)()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().nfs_sens_maps(context(device), _ptr(X), G, ne, _ptr(mT), _ptr(mR), *_grid(dims), float(alpha),
+                               float(tol), int(max_iter), _ptr(s32), _ptr(s64), _ptr(shat), info, ws, nb, stream))
+    return s32, s64, shat, (info[0], info[1])
+
+
+def b0_map(imgs, sens, dims, delta_te: float, alpha: float, tol: float = 1e-10, max_iter: int = 100000,
+           device: int = 0):
+    """B0 map (rad/s) from prescan images imgs [G][n_echo][L] and
+    sensitivities sens [G][L] complex64.  Returns (B0 float32 [L], B0 float64
+    [L], fit float64 [3][L] = (B0^, beta, eps), (iterations, status))."""
+    dev = torch.device("cuda", device)
+    X = _c64(torch.as_tensor(imgs), dev)
+    G, ne, L = X.shape
+    S = _c64(torch.as_tensor(sens), dev)
+    b0 = torch.empty(L, dtype=torch.float32, device=dev)
+    b064 = torch.empty(L, dtype=torch.float64, device=dev)
+    fit = torch.empty(3, L, dtype=torch.float64, device=dev)
+    ws, nb, keep = _map_workspace("b0", G, dims, dev)
+    info = (ctypes.c_int * 2)()
+    stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
+    _check(lib().nfs_b0_map(context(device), _ptr(X), G, ne, _ptr(S), *_grid(dims), float(delta_te), float(alpha),
+                            float(tol), int(max_iter), _ptr(b0), _ptr(b064), _ptr(fit), info, ws, nb, stream))
+    return b0, b064, fit, (info[0], info[1])

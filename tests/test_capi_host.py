@@ -327,3 +327,65 @@ def test_kspace_filter_mask_host_function_matches_oracle():
     n = ctypes.c_size_t()
     assert nfs.lib().nfs_kspace_filter_workspace_bytes(None, 0, 4, 1, ctypes.byref(n)) == nfs.NFS_ESHAPE
     assert nfs.lib().nfs_kspace_filter_workspace_bytes(None, 32, 32, 1, ctypes.byref(n)) == 0 and n.value > 0
+
+
+# ---- map estimation: argument checks (nothing reaches a device) ----
+
+def _ctx():
+    return ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+
+
+def _sens_maps(L, G=8, ne=6, dims=(20, 16, 1), alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40, out=A,
+               masks=A):
+    info = (ctypes.c_int * 2)()
+    return L.nfs_sens_maps(_ctx(), A, G, ne, masks, masks, *dims, alpha, tol, max_iter, out, None, None, info, A,
+                           ws_bytes, None)
+
+
+def _b0_map(L, G=8, ne=6, dims=(20, 16, 1), dte=2.3e-3, alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40):
+    info = (ctypes.c_int * 2)()
+    return L.nfs_b0_map(_ctx(), A, G, ne, A, *dims, dte, alpha, tol, max_iter, A, None, None, info, A, ws_bytes,
+                        None)
+
+
+def test_map_workspace_sizes(L):
+    sz = ctypes.c_size_t()
+    assert L.nfs_maps_workspace_bytes(0, 8, 20, 16, 1, ctypes.byref(sz)) == 0
+    small = sz.value
+    assert L.nfs_maps_workspace_bytes(0, 8, 40, 16, 3, ctypes.byref(sz)) == 0
+    assert sz.value > small
+    # sensitivities: 3G float64 CG systems of 5 vectors each at least
+    assert sz.value >= 3 * 8 * 40 * 16 * 3 * 8 * 5
+    assert L.nfs_maps_workspace_bytes(1, 8, 20, 16, 1, ctypes.byref(sz)) == 0
+    assert sz.value >= 20 * 16 * 8 * 8
+    assert L.nfs_maps_workspace_bytes(2, 8, 20, 16, 1, ctypes.byref(sz)) == nfs.NFS_EINVAL
+    assert L.nfs_maps_workspace_bytes(0, 17, 20, 16, 1, ctypes.byref(sz)) == nfs.NFS_ESHAPE
+    assert L.nfs_maps_workspace_bytes(1, 64, 20, 16, 1, ctypes.byref(sz)) == 0
+    assert L.nfs_maps_workspace_bytes(0, 8, 0, 16, 1, ctypes.byref(sz)) == nfs.NFS_ESHAPE
+
+
+def test_map_argument_checks(L):
+    assert _sens_maps(L, G=17) == nfs.NFS_ESHAPE
+    assert _sens_maps(L, G=0) == nfs.NFS_ESHAPE
+    assert _sens_maps(L, ne=0) == nfs.NFS_ESHAPE
+    assert _sens_maps(L, dims=(20, 0, 1)) == nfs.NFS_ESHAPE
+    assert _sens_maps(L, alpha=-1.0) == nfs.NFS_EINVAL
+    assert _sens_maps(L, alpha=math.inf) == nfs.NFS_EINVAL
+    assert _sens_maps(L, tol=math.nan) == nfs.NFS_EINVAL
+    assert _sens_maps(L, max_iter=-1) == nfs.NFS_EINVAL
+    assert _sens_maps(L, out=None) == nfs.NFS_EINVAL
+    assert _sens_maps(L, masks=None) == nfs.NFS_EINVAL
+    assert _sens_maps(L, masks=A + 2) == nfs.NFS_EINVAL
+    assert _sens_maps(L, ws_bytes=1024) == nfs.NFS_EWORKSPACE
+    assert "workspace" in L.nfs_last_error().decode()
+    assert _b0_map(L, ne=2) == nfs.NFS_ESHAPE
+    assert _b0_map(L, ne=65) == nfs.NFS_ESHAPE
+    assert _b0_map(L, G=65) == nfs.NFS_ESHAPE
+    assert _b0_map(L, dte=0.0) == nfs.NFS_EINVAL
+    assert _b0_map(L, dte=-1e-3) == nfs.NFS_EINVAL
+    assert _b0_map(L, alpha=-0.5) == nfs.NFS_EINVAL
+    assert _b0_map(L, ws_bytes=64) == nfs.NFS_EWORKSPACE
+    assert L.nfs_sens_initial(None, A, 8, 6, 100, A, None) == nfs.NFS_EINVAL
+    assert L.nfs_sens_initial(_ctx(), A, 17, 6, 100, A, None) == nfs.NFS_ESHAPE
+    assert L.nfs_sens_initial(_ctx(), A, 8, 6, -1, A, None) == nfs.NFS_ESHAPE
+    assert L.nfs_sens_initial(_ctx(), A, 8, 6, 100, None, None) == nfs.NFS_EINVAL

@@ -1,0 +1,171 @@
+"""Map estimation on the GPU against the FP64 oracle (oracle/maps.py):
+initial sensitivities (per-voxel dominant singular vector), the smoothed and
+extrapolated sensitivity maps, the B0 fit and the eps-weighted B0 smoothing.
+
+Tolerances.  The initial sensitivities are float64 on both sides; where the
+two largest singular values are separated (ratio below 0.95) the vector is
+unique and both sides agree to rounding (1e-9 asserted); elsewhere any unit
+vector of the top eigenspace is valid and the test checks unit norm, the
+phase convention and the Rayleigh quotient instead.  The smoothing solves run
+CG to ||r|| <= 1e-12 ||b||; the error to the direct solution of the oracle is
+then at most kappa * 1e-12 with kappa (Jacobi-scaled) below 1e5 on these
+grids, so 1e-6 relative is asserted (observed ~1e-12)."""
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import maps as M
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def nfs():
+    from paper_2604_09233_amd import nfs as mod
+
+    assert torch.cuda.is_available()
+    return mod
+
+
+def rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def top_two(X):
+    s = np.linalg.svd(np.moveaxis(X, 2, 0), compute_uv=False)  # [L][min(G, ne)]
+    s2 = s[:, 1] if s.shape[1] > 1 else np.zeros(s.shape[0])
+    return s[:, 0], s2
+
+
+def check_initial(X, got):
+    X = np.asarray(X, dtype=np.complex128)
+    want = M.sens_initial(X)
+    s1, s2 = top_two(X)
+    sep = s2 < 0.95 * s1
+    err = np.abs(got - want).max(axis=0)
+    print(f"  separated voxels {sep.sum()}/{sep.size}: max error {err[sep].max() if sep.any() else 0:.2e}")
+    assert np.all(err[sep] < 1e-9)
+    nz = s1 > 0
+    assert np.all(np.abs(np.linalg.norm(got[:, nz], axis=0) - 1.0) < 1e-12)
+    cs = got.sum(axis=0)
+    assert np.all(np.abs(cs.imag[nz]) <= 1e-12 * np.abs(cs[nz]) + 1e-300)
+    assert np.all(cs.real[nz] >= 0)
+    # Rayleigh quotient of the Gram matrix reaches its largest eigenvalue
+    ray = np.einsum("gl,gnl,hnl,hl->l", np.conj(got), X, np.conj(X), got).real
+    assert np.all(ray[nz] >= s1[nz] ** 2 * (1 - 1e-9))
+    assert np.all(got[:, ~nz] == 0)
+
+
+@pytest.mark.parametrize("dims,G,ne", [((41, 35), 8, 6), ((21, 18, 9), 16, 16), ((37, 29), 3, 20),
+                                       ((13, 11), 16, 33)])
+def test_initial_sensitivities_match_oracle(nfs, dims, G, ne):
+    d = synth.prescan(dims=dims, n_coil=G, n_echo=ne, seed=1)
+    X = d["imgs"].copy()
+    X[:, :, 5] = 0  # a voxel without data
+    X[:, :, -1] = 0
+    got = nfs.sens_initial(torch.from_numpy(X)).cpu().numpy()
+    print(f"S^ {dims} G={G} ne={ne}")
+    check_initial(X, got)
+
+
+def test_initial_sensitivities_of_rank_one_data(nfs):
+    rng = np.random.default_rng(4)
+    G, ne, L = 16, 8, 203
+    s = (rng.standard_normal((G, L)) + 1j * rng.standard_normal((G, L))).astype(np.complex64)
+    e = (rng.standard_normal((ne, L)) + 1j * rng.standard_normal((ne, L))).astype(np.complex64)
+    X = (s[:, None, :] * e[None, :, :]).astype(np.complex64)
+    got = nfs.sens_initial(torch.from_numpy(X)).cpu().numpy()
+    # closed form of the float32 data's dominant vector is that of the exact
+    # rank-one product up to the float32 rounding of X (relative ~1e-7)
+    sd = s.astype(np.complex128)
+    t = sd.sum(axis=0)
+    want = sd / np.linalg.norm(sd, axis=0) * (np.conj(t) / np.abs(t))
+    assert np.abs(got - want).max() < 1e-5
+    check_initial(X, got)
+
+
+@pytest.mark.parametrize("dims,G,alpha", [((41, 35), 4, 10.0), ((20, 18, 9), 4, 3.0), ((33, 2), 2, 5.0),
+                                          ((19, 17), 3, 0.0)])
+def test_sensitivity_maps_match_oracle(nfs, dims, G, alpha):
+    d = synth.prescan(dims=dims, n_coil=G, n_echo=6, seed=2)
+    X = d["imgs"]
+    mT, mR = d["mask_T"], d["mask_R"]
+    if dims == (33, 2):  # a degenerate grid: no second differences along y
+        mT = (np.arange(66) % 33 > 8).astype(np.float32) * (np.arange(66) % 33 < 25)
+        mR = np.ones(66, dtype=np.float32)
+    s32, s64, shat, info = nfs.sens_maps(torch.from_numpy(X), mT, mR, dims, alpha, tol=1e-12, max_iter=50000)
+    want = M.smooth_sens(M.sens_initial(X), mT, mR, dims, alpha)
+    e = rel(s64.cpu().numpy(), want)
+    print(f"S {dims} G={G} alpha={alpha}: CG iterations {info[0]} status {info[1]}, relative error {e:.2e}")
+    assert info[1] in (2, 3)  # converged to tol, or exactly
+    assert e < 1e-6
+    assert np.array_equal(s32.cpu().numpy(), s64.cpu().numpy().astype(np.complex64))
+    assert torch.equal(shat, nfs.sens_initial(torch.from_numpy(X)))
+
+
+def test_sensitivity_maps_without_penalty_keep_the_trusted_data(nfs):
+    d = synth.prescan(dims=(24, 20), n_coil=4, n_echo=5, seed=3)
+    mT = d["mask_T"]
+    _, s64, shat, info = nfs.sens_maps(torch.from_numpy(d["imgs"]), mT, d["mask_R"], (24, 20), 0.0, tol=1e-14)
+    s64, shat = s64.cpu().numpy(), shat.cpu().numpy()
+    inside = mT > 0
+    assert np.abs(s64[:, inside] - shat[:, inside]).max() < 1e-13
+    assert np.all(s64[:, ~inside] == 0)
+
+
+@pytest.mark.parametrize("dims,G,ne", [((41, 35), 4, 6), ((20, 18, 9), 8, 16), ((30, 3), 2, 3)])
+def test_b0_map_matches_oracle(nfs, dims, G, ne):
+    d = synth.prescan(dims=dims, n_coil=G, n_echo=ne, seed=5)
+    X, S = d["imgs"], d["S_true"]
+    S = S.copy()
+    S[:, 7] = 0  # a voxel without sensitivity
+    alpha = 50.0
+    b0, b064, fit, info = nfs.b0_map(torch.from_numpy(X), torch.from_numpy(S), dims, d["delta_te"], alpha, tol=1e-12)
+    bh, bb, ee = M.b0_initial(X, S, d["delta_te"])
+    fit = fit.cpu().numpy()
+    scale = np.abs(bh).max()
+    print(f"B0 {dims}: fit errors {np.abs(fit[0] - bh).max() / scale:.1e} {np.abs(fit[1] - bb).max():.1e} "
+          f"{np.abs(fit[2] - ee).max():.1e}; CG iterations {info[0]} status {info[1]}")
+    assert np.abs(fit[0] - bh).max() <= 1e-10 * scale
+    assert np.abs(fit[1] - bb).max() <= 1e-10
+    assert np.abs(fit[2] - ee).max() <= 1e-10
+    assert fit[0][7] == 0 and fit[2][7] == 0
+    want = M.smooth_b0(bh, ee, dims, alpha)
+    e = rel(b064.cpu().numpy(), want)
+    print(f"  smoothed: relative error {e:.2e}")
+    assert e < 1e-6
+    assert np.array_equal(b0.cpu().numpy(), b064.cpu().numpy().astype(np.float32))
+
+
+def test_b0_fit_recovers_noise_free_phases_with_wraps(nfs):
+    """Per-echo phase steps up to 0.9 pi (several wraps over 9 echoes) and an
+    even/odd offset: the fit returns them exactly (to float32 data rounding)."""
+    rng = np.random.default_rng(6)
+    G, ne, L, dte = 6, 9, 500, 1e-3
+    S = (rng.standard_normal((G, L)) + 1j * rng.standard_normal((G, L))).astype(np.complex64)
+    w = rng.uniform(-0.9 * np.pi, 0.9 * np.pi, L) / dte
+    rho = rng.uniform(0.5, 2.0, L) * np.exp(1j * rng.uniform(-np.pi, np.pi, L))
+    X = np.stack([S * (rho * np.exp(1j * (w * n * dte + 0.3 * (n % 2))))[None, :] for n in range(ne)], axis=1)
+    X = X.astype(np.complex64)
+    _, _, fit, _ = nfs.b0_map(torch.from_numpy(X), torch.from_numpy(S), (25, 20), dte, 0.0)
+    fit = fit.cpu().numpy()
+    assert np.abs(fit[0] - w).max() < 1e-5 / dte
+    assert np.abs(fit[1] - 0.3).max() < 1e-5
+    assert fit[2].max() < 1e-5
+
+
+def test_b0_smoothing_without_weights_is_identity(nfs):
+    """eps = 0 (noise-free data) leaves B0^ unchanged whatever alpha."""
+    rng = np.random.default_rng(7)
+    G, ne, L, dte = 3, 4, 300, 2e-3
+    S = (1 + rng.random((G, L))).astype(np.complex64)
+    w = rng.uniform(-200, 200, L)
+    X = np.stack([S * np.exp(1j * w * n * dte)[None, :] for n in range(ne)], axis=1).astype(np.complex64)
+    _, b064, fit, info = nfs.b0_map(torch.from_numpy(X), torch.from_numpy(S), (20, 15), dte, 1e4, tol=1e-13)
+    fit = fit.cpu().numpy()
+    want = M.smooth_b0(fit[0], fit[2], (20, 15), 1e4)
+    assert rel(b064.cpu().numpy(), want) < 1e-9
+    assert rel(b064.cpu().numpy(), fit[0]) < 1e-6
