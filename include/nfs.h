@@ -361,11 +361,13 @@ int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, in
  *   alpha >= 0; tol >= 0; max_iter >= 0
  *   sens: device complex [G][L] or NULL; sens64: device complex float64
  *   [G][L] or NULL (not both NULL); shat: device complex float64 [G][L] to
- *   receive S^, or NULL (then S^ stays in the workspace)
+ *   receive S^, or NULL (then S^ stays in the workspace); parts: device
+ *   double [3G][L] to receive the three smoothed components (|S|_s per
+ *   coil, then Re n_s, then Im n_s), or NULL
  * Workspace: nfs_maps_workspace_bytes(NFS_MAP_SENS, ...).                 */
 int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* mask_T, const float* mask_R,
                   int nx, int ny, int nz, double alpha, double tol, int max_iter, float* sens, double* sens64,
-                  double* shat, int* info, void* ws, size_t ws_bytes, void* stream);
+                  double* shat, double* parts, int* info, void* ws, size_t ws_bytes, void* stream);
 
 /* B0 map: the prescan echoes combined with the sensitivities,
  * c_n = sum_c conj(S_c) x_cn / sum_c |S_c|^2 (0 where the sum is 0), the

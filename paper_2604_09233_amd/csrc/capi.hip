@@ -1577,8 +1577,8 @@ extern "C" int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int
 
 extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* mask_T,
                              const float* mask_R, int nx, int ny, int nz, double alpha, double tol, int max_iter,
-                             float* sens, double* sens64, double* shat, int* info, void* ws, size_t ws_bytes,
-                             void* stream) {
+                             float* sens, double* sens64, double* shat, double* parts, int* info, void* ws,
+                             size_t ws_bytes, void* stream) {
   const char* fn = "nfs_sens_maps";
   if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
   if (n_coil < 1 || n_coil > kMaxSvdCoils) return fail(NFS_ESHAPE, "%s: n_coil %d outside [1, %d]", fn, n_coil, kMaxSvdCoils);
@@ -1591,7 +1591,7 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
   if (!mask_T || !mask_R) return fail(NFS_EINVAL, "%s: mask is NULL", fn);
   if (misaligned(mask_T, 4) || misaligned(mask_R, 4)) return fail(NFS_EINVAL, "%s: mask not 4-byte aligned", fn);
   if (!sens && !sens64) return fail(NFS_EINVAL, "%s: both outputs are NULL", fn);
-  if (misaligned(sens, 8) || misaligned(sens64, 16) || misaligned(shat, 16))
+  if (misaligned(sens, 8) || misaligned(sens64, 16) || misaligned(shat, 16) || misaligned(parts, 8))
     return fail(NFS_EINVAL, "%s: output misaligned", fn);
   const MapLayout m = map_layout(NFS_MAP_SENS, n_coil, L);
   if ((rc = check_map_ws(m, ws, ws_bytes, fn))) return rc;
@@ -1608,6 +1608,8 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
   NFS_TRY(launch_sens_combine(st.x, n_coil, L, st.Lp, reinterpret_cast<float2*>(sens),
                               reinterpret_cast<double2*>(sens64), s),
           fn);
+  if (parts && L > 0)
+    NFS_TRY(hipMemcpy2DAsync(parts, L * 8, st.x, st.Lp * 8, L * 8, 3 * n_coil, hipMemcpyDeviceToDevice, s), fn);
   return NFS_OK;
 }
 

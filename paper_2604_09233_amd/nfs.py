@@ -86,7 +86,7 @@ def lib():
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
             L.nfs_maps_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_sens_initial.argtypes = [vp, vp, i32, i32, ctypes.c_int64, vp, vp]
-            L.nfs_sens_maps.argtypes = [vp, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp, vp,
+            L.nfs_sens_maps.argtypes = [vp, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp, vp, vp,
                                         ctypes.POINTER(i32), vp, sz, vp]
             L.nfs_b0_map.argtypes = [vp, vp, i32, i32, vp, i32, i32, i32, dbl, dbl, dbl, i32, vp, vp, vp,
                                      ctypes.POINTER(i32), vp, sz, vp]
@@ -494,11 +494,12 @@ def sens_initial(imgs, device: int = 0):
 
 
 def sens_maps(imgs, mask_T, mask_R, dims, alpha: float, tol: float = 1e-10, max_iter: int = 100000,
-              device: int = 0):
+              device: int = 0, parts: bool = False):
     """Smoothed and extrapolated sensitivity maps from prescan images
     imgs [G][n_echo][L] and the masks M_T, M_R [L] on the grid dims.
     Returns (S complex64 [G][L], S complex128 [G][L], S^ complex128 [G][L],
-    (iterations, status))."""
+    (iterations, status)), and with parts=True also the smoothed components
+    float64 [3G][L] (|S|_s, Re n_s, Im n_s) as a fifth item."""
     dev = torch.device("cuda", device)
     X = _c64(torch.as_tensor(imgs), dev)
     G, ne, L = X.shape
@@ -507,11 +508,15 @@ def sens_maps(imgs, mask_T, mask_R, dims, alpha: float, tol: float = 1e-10, max_
     s32 = torch.empty(G, L, dtype=torch.complex64, device=dev)
     s64 = torch.empty(G, L, dtype=torch.complex128, device=dev)
     shat = torch.empty(G, L, dtype=torch.complex128, device=dev)
+    comp = torch.empty(3 * G, L, dtype=torch.float64, device=dev) if parts else None
     ws, nb, keep = _map_workspace("sens", G, dims, dev)
     info = (ctypes.c_int * 2)()
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     _check(lib().nfs_sens_maps(context(device), _ptr(X), G, ne, _ptr(mT), _ptr(mR), *_grid(dims), float(alpha),
-                               float(tol), int(max_iter), _ptr(s32), _ptr(s64), _ptr(shat), info, ws, nb, stream))
+                               float(tol), int(max_iter), _ptr(s32), _ptr(s64), _ptr(shat), _ptr(comp), info, ws, nb,
+                               stream))
+    if parts:
+        return s32, s64, shat, (info[0], info[1]), comp
     return s32, s64, shat, (info[0], info[1])
 
 

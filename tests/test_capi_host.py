@@ -338,8 +338,8 @@ def _ctx():
 def _sens_maps(L, G=8, ne=6, dims=(20, 16, 1), alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40, out=A,
                masks=A):
     info = (ctypes.c_int * 2)()
-    return L.nfs_sens_maps(_ctx(), A, G, ne, masks, masks, *dims, alpha, tol, max_iter, out, None, None, info, A,
-                           ws_bytes, None)
+    return L.nfs_sens_maps(_ctx(), A, G, ne, masks, masks, *dims, alpha, tol, max_iter, out, None, None, None, info,
+                           A, ws_bytes, None)
 
 
 def _b0_map(L, G=8, ne=6, dims=(20, 16, 1), dte=2.3e-3, alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40):

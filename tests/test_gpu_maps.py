@@ -169,3 +169,50 @@ def test_b0_smoothing_without_weights_is_identity(nfs):
     want = M.smooth_b0(fit[0], fit[2], (20, 15), 1e4)
     assert rel(b064.cpu().numpy(), want) < 1e-9
     assert rel(b064.cpu().numpy(), fit[0]) < 1e-6
+
+
+def test_maps_at_the_prescan_size(nfs):
+    """The paper's prescan geometry (219x219x22 voxels, 16 coils, 16 echoes)
+    with the benchmark's settings: S^ on sampled voxels against the oracle's
+    per-voxel SVD; the normal-equation residual of sampled smoothing systems
+    evaluated on the CPU with the oracle's sparse matrices (an independent
+    operator), which CG's stopping rule bounds by tol (2 tol asserted, for
+    the drift between recurrence and true residual); the B0 fit on sampled
+    voxels against the oracle's fit, and the B0 smoothing residual."""
+    dims, G, ne, tol = (219, 219, 22), 16, 16, 1e-6
+    d = synth.prescan(dims=dims, n_coil=G, n_echo=ne)
+    L = int(np.prod(dims))
+    X = torch.from_numpy(d["imgs"]).cuda()
+    s32, s64, shat, info, parts = nfs.sens_maps(X, d["mask_T"], d["mask_R"], dims, 10.0, tol=tol, parts=True)
+    print(f"prescan {dims}: sensitivity CG iterations {info[0]} status {info[1]}")
+    assert info[1] == 2
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(L, 400, replace=False))
+    Xs = d["imgs"][:, :, idx].astype(np.complex128)
+    want = M.sens_initial(Xs)
+    s1, s2 = top_two(Xs)
+    sep = s2 < 0.95 * s1
+    got = shat.cpu().numpy()[:, idx]
+    assert np.abs(got - want)[:, sep].max() < 1e-9
+    A = M.smoothing_matrix(dims, d["mask_T"], d["mask_R"], 10.0, 2).tocsr()
+    parts = parts.cpu().numpy()
+    sh = shat.cpu().numpy()
+    mT = d["mask_T"].astype(np.float64)
+    for c in (0, 7, G + 3, 2 * G + 11):  # magnitudes, real and imaginary parts
+        k, comp = c % G, c // G
+        mag = np.abs(sh[k])
+        n = np.where(mag > 0, sh[k] / np.where(mag > 0, mag, 1.0), 0.0)
+        b = mT * (mag, n.real, n.imag)[comp]
+        r = np.linalg.norm(b - A @ parts[c]) / np.linalg.norm(b)
+        print(f"  system {c}: relative normal-equation residual {r:.2e}")
+        assert r < 2 * tol
+    b0, b064, fit, info_b = nfs.b0_map(X, s32, dims, d["delta_te"], 10.0, tol=tol)
+    assert info_b[1] == 2
+    bh, bb, ee = M.b0_initial(Xs.astype(np.complex64), s32.cpu().numpy()[:, idx], d["delta_te"])
+    fit = fit.cpu().numpy()
+    assert np.abs(fit[0][idx] - bh).max() <= 1e-9 * np.abs(bh).max()
+    assert np.abs(fit[2][idx] - ee).max() <= 1e-9
+    A = M.smoothing_matrix(dims, np.ones(L), fit[2], 10.0, 1).tocsr()
+    r = np.linalg.norm(fit[0] - A @ b064.cpu().numpy()) / np.linalg.norm(fit[0])
+    print(f"  B0: CG iterations {info_b[0]}, relative residual {r:.2e}")
+    assert r < 2 * tol
