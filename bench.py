@@ -214,11 +214,35 @@ def maps_run(nfs, synth, torch, dev):
         torch.cuda.synchronize()
         return time.perf_counter() - t, r
 
-    t0, _ = wall(lambda: nfs.sens_maps(X, mT, mR, dims, MAP_ALPHA_S, tol=0.0, max_iter=0))
-    t1, _ = wall(lambda: nfs.sens_maps(X, mT, mR, dims, MAP_ALPHA_S, tol=0.0, max_iter=128))
-    ms_it = (t1 - t0) / 128 * 1e3
+    def per_iteration(precond, n):
+        t0, _ = wall(lambda: nfs.sens_maps(X, mT, mR, dims, MAP_ALPHA_S, tol=0.0, max_iter=0, precond=precond))
+        t1, _ = wall(lambda: nfs.sens_maps(X, mT, mR, dims, MAP_ALPHA_S, tol=0.0, max_iter=n, precond=precond))
+        return (t1 - t0) / n * 1e3
+
     nrhs = 3 * MAP_COILS
-    it_bytes = nrhs * L * 80 + L * 16  # apply: r, p in, p, q out; update: x, p, r, q in, x, r out; D^-1 twice
+    # algorithmic bytes per iteration and right-hand side.  Jacobi: apply
+    # (r, p in; p, q out) + update (x, p, r, q in; x, r out) = 80 B per voxel.
+    # Multigrid: apply (z, p in; p, q out) + update + r.z = 96 B per fine
+    # voxel, and per voxel of every level above the coarsest the V-cycle's
+    # stencil passes: first sweep 16, second sweep 24, residual 24, restriction
+    # 8, prolongation 16, two sweeps 48 = 136 B.
+    lv = [L]
+    dd = list(dims)
+    while lv[-1] > 64:
+        c = [n // 2 + 1 if n >= 3 else n for n in dd]
+        if c == dd:
+            break
+        dd = c
+        lv.append(int(np.prod(dd)))
+    bytes_jac = nrhs * L * 80
+    bytes_mg = nrhs * (96 * L + 136 * sum(lv[:-1]))
+    ms_jac = per_iteration("jacobi", 128)
+    ms_mg = per_iteration("mg", 16)
+
+    def roof(nbytes, ms):
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        return dict(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
+
     ts, (s32, s64, shat, info_s) = wall(lambda: nfs.sens_maps(X, mT, mR, dims, MAP_ALPHA_S, tol=MAP_TOL,
                                                                max_iter=100000))
     tb, (b0, b064, fit, info_b) = wall(lambda: nfs.b0_map(X, s32, dims, d["delta_te"], MAP_ALPHA_B, tol=MAP_TOL,
@@ -236,7 +260,6 @@ def maps_run(nfs, synth, torch, dev):
     om = d["omega_true"][inside]
     b_err0 = float(np.sqrt(np.mean((fit[0].cpu().numpy()[inside] - om) ** 2)))
     b_err = float(np.sqrt(np.mean((b064.cpu().numpy()[inside] - om) ** 2)))
-    gbs = it_bytes / (ms_it * 1e-3) / 1e9
     out = dict(workload=f"prescan {dims[0]}x{dims[1]}x{dims[2]}, {MAP_COILS} coils, {MAP_ECHOES} echoes, "
                         f"dTE {d['delta_te'] * 1e3:.1f} ms, alpha_S {MAP_ALPHA_S}, alpha_B {MAP_ALPHA_B}, "
                         f"CG tol {MAP_TOL}",
@@ -244,9 +267,9 @@ def maps_run(nfs, synth, torch, dev):
                ms_sens_initial=ms_init,
                sens_initial_GBs=(X.numel() * 8 + MAP_COILS * L * 16) / (ms_init * 1e-3) / 1e9,
                s_sens_maps=ts, sens_cg_iterations=info_s[0], sens_cg_status=nfs.CG_STATUS.get(info_s[1], info_s[1]),
-               ms_per_pcg_iteration=ms_it, pcg_iteration_roofline=dict(bound="hbm", achieved=gbs,
-                                                                       peak=HBM_PEAK_GBS, unit="GB/s",
-                                                                       frac=gbs / HBM_PEAK_GBS),
+               preconditioner="multigrid V(2,2), %d levels" % len(lv),
+               ms_per_iteration=dict(multigrid=ms_mg, jacobi=ms_jac),
+               iteration_roofline=dict(multigrid=roof(bytes_mg, ms_mg), jacobi=roof(bytes_jac, ms_jac)),
                s_b0_map=tb, b0_cg_iterations=info_b[0], b0_cg_status=nfs.CG_STATUS.get(info_b[1], info_b[1]),
                sens_rel_err_vs_truth_in_MT=dict(initial=s0_err, smoothed=s_err),
                b0_rms_err_vs_truth_in_MT_rad_s=dict(initial=b_err0, smoothed=b_err))

@@ -322,9 +322,10 @@ int nfs_profile_read(nfs_ctx* ctx, int kind, int* count, double* total_ms);
  * Prescan images: imgs [G][n_echo][L] complex, coil c and echo n of voxel l
  * at imgs[(c n_echo + n) L + l]; grid nx x ny x nz (nz = 1 in 2D), voxel
  * index x + nx (y + ny z).  The two smoothing calls solve their normal
- * equations by Jacobi-preconditioned CG (float64 vectors and scalars, fixed-
- * order reductions, one CG per right-hand side) until ||r|| <= tol ||b|| or
- * max_iter iterations; they SYNCHRONISE the stream (every 32 iterations, to
+ * equations by preconditioned CG (float64 vectors and scalars, fixed-order
+ * reductions, one CG per right-hand side; the paper suggests an incomplete-
+ * Cholesky preconditioner, here Jacobi or multigrid, see nfs_precond) until
+ * ||r|| <= tol ||b|| or max_iter iterations; they SYNCHRONISE the stream (every 32 iterations, to
  * read the convergence flags) and so must not be captured into a graph.
  * info: HOST int [2] or NULL: (largest iteration count over the right-hand
  * sides, status as enum nfs_cg_status: NFS_CG_TOL when all converged,
@@ -332,9 +333,23 @@ int nfs_profile_read(nfs_ctx* ctx, int kind, int* count, double* total_ms);
  * NFS_CG_MAXITER if any ran out, NFS_CG_BREAKDOWN if any broke down).     */
 enum nfs_map_kind { NFS_MAP_SENS = 0, NFS_MAP_B0 = 1 };
 
+/* Preconditioner of the smoothing solves.
+ *  NFS_PRECOND_JACOBI: the inverse diagonal.
+ *  NFS_PRECOND_MG:     one symmetric multigrid V-cycle: levels that halve
+ *      every axis longer than 2 (coarse point I at fine point 2I) down to
+ *      at most 64 unknowns, the same stencil on each level with its weights
+ *      averaged by the interpolation weights and alpha divided by 16 (second
+ *      differences) or 4 (first differences), multilinear prolongation,
+ *      restriction by its transpose over 2^(axes halved), two damped Jacobi
+ *      sweeps (weight 0.6) before and after the coarse correction, and the
+ *      explicit inverse on the coarsest level.  Far fewer iterations on the
+ *      poorly conditioned sensitivity system.                              */
+enum nfs_precond { NFS_PRECOND_JACOBI = 0, NFS_PRECOND_MG = 1 };
+
 /* Workspace bytes of nfs_sens_maps (kind NFS_MAP_SENS) or nfs_b0_map
- * (NFS_MAP_B0) for n_coil coils on an nx x ny x nz grid.                  */
-int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, int nz, size_t* bytes);
+ * (NFS_MAP_B0) for n_coil coils on an nx x ny x nz grid with preconditioner
+ * precond.                                                                 */
+int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, int nz, int precond, size_t* bytes);
 
 /* Initial sensitivities S^: per voxel the first left singular vector of the
  * n_coil x n_echo matrix of prescan values (rows coils, columns echoes),
@@ -358,7 +373,7 @@ int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, in
  * along axis d exist, weighted by M_R at i.  Rows of the system without
  * any entry (voxels neither in M_T nor reached by a penalty row) give 0.
  *   mask_T, mask_R: device float [L] (M_T, M_R; normally 0/1)
- *   alpha >= 0; tol >= 0; max_iter >= 0
+ *   alpha >= 0; tol >= 0; max_iter >= 0; precond: enum nfs_precond
  *   sens: device complex [G][L] or NULL; sens64: device complex float64
  *   [G][L] or NULL (not both NULL); shat: device complex float64 [G][L] to
  *   receive S^, or NULL (then S^ stays in the workspace); parts: device
@@ -366,8 +381,8 @@ int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, in
  *   coil, then Re n_s, then Im n_s), or NULL
  * Workspace: nfs_maps_workspace_bytes(NFS_MAP_SENS, ...).                 */
 int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* mask_T, const float* mask_R,
-                  int nx, int ny, int nz, double alpha, double tol, int max_iter, float* sens, double* sens64,
-                  double* shat, double* parts, int* info, void* ws, size_t ws_bytes, void* stream);
+                  int nx, int ny, int nz, double alpha, double tol, int max_iter, int precond, float* sens,
+                  double* sens64, double* shat, double* parts, int* info, void* ws, size_t ws_bytes, void* stream);
 
 /* B0 map: the prescan echoes combined with the sensitivities,
  * c_n = sum_c conj(S_c) x_cn / sum_c |S_c|^2 (0 where the sum is 0), the
@@ -386,8 +401,8 @@ int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const
  *   With b0 and b064 both NULL only the fit runs (info = (0, 0)).
  * Workspace: nfs_maps_workspace_bytes(NFS_MAP_B0, ...).                   */
 int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* sens, int nx, int ny, int nz,
-               double delta_te, double alpha, double tol, int max_iter, float* b0, double* b064, double* fit,
-               int* info, void* ws, size_t ws_bytes, void* stream);
+               double delta_te, double alpha, double tol, int max_iter, int precond, float* b0, double* b064,
+               double* fit, int* info, void* ws, size_t ws_bytes, void* stream);
 
 /* Message for the last non-OK status returned on the calling thread. */
 const char* nfs_last_error(void);

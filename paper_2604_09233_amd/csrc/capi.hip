@@ -1453,14 +1453,16 @@ extern "C" int nfs_tuned_shape(const nfs_ctx* ctx, const nfs_problem* prob, int 
 
 namespace {
 
-constexpr int kPcgChunk = 32;  // iterations enqueued between two status reads
 constexpr int kMaxMapEchoes = 1024;
 
 struct MapLayout {
-  size_t shat = 0, b = 0, t = 0, w = 0, fit = 0, pcg = 0, total = 0;
+  size_t shat = 0, b = 0, t = 0, w = 0, fit = 0, pcg = 0, mg = 0, total = 0;
 };
 
-MapLayout map_layout(int kind, int G, int64_t L) {
+MapLayout map_layout(int kind, int G, int nx, int ny, int nz, int precond) {
+  const int64_t L = (int64_t)nx * ny * nz;
+  const bool mg = precond == NFS_PRECOND_MG;
+  const int nrhs = kind == NFS_MAP_SENS ? 3 * G : 1;
   MapLayout m;
   const int64_t Lp = (L + 63) & ~(int64_t)63;
   size_t off = 0;
@@ -1474,12 +1476,12 @@ MapLayout map_layout(int kind, int G, int64_t L) {
     m.b = take((size_t)3 * G * Lp * 8);
     m.t = take((size_t)Lp * 8);
     m.w = take((size_t)Lp * 8);
-    m.pcg = take(pcg_state_bytes(3 * G, L));
   } else {
     m.fit = take((size_t)3 * Lp * 8);  // B0^, beta, eps
     m.w = take((size_t)Lp * 8);
-    m.pcg = take(pcg_state_bytes(1, L));
   }
+  m.pcg = take(pcg_state_bytes(nrhs, L, mg));
+  if (mg) m.mg = take(mg_bytes(nrhs, nx, ny, nz));
   m.total = off;
   return m;
 }
@@ -1492,7 +1494,9 @@ int check_map_grid(int nx, int ny, int nz, const char* fn, int64_t* L) {
   return NFS_OK;
 }
 
-int check_solver_args(double alpha, double tol, int max_iter, const char* fn) {
+int check_solver_args(double alpha, double tol, int max_iter, int precond, const char* fn) {
+  if (precond != NFS_PRECOND_JACOBI && precond != NFS_PRECOND_MG)
+    return fail(NFS_EINVAL, "%s: unknown preconditioner %d", fn, precond);
   if (!std::isfinite(alpha) || alpha < 0.0) return fail(NFS_EINVAL, "%s: alpha %g not finite and >= 0", fn, alpha);
   if (!std::isfinite(tol) || tol < 0.0) return fail(NFS_EINVAL, "%s: tol %g not finite and >= 0", fn, tol);
   if (max_iter < 0) return fail(NFS_EINVAL, "%s: max_iter %d < 0", fn, max_iter);
@@ -1506,27 +1510,14 @@ int check_map_ws(const MapLayout& m, void* ws, size_t ws_bytes, const char* fn) 
   return NFS_OK;
 }
 
-// Enqueue PCG iterations in chunks until every right-hand side has stopped
-// or max_iter is reached; info (host, may be NULL) = (largest iteration
-// count, status).
-int run_pcg(int op, const PcgState& st, const double* b, int nx, int ny, int nz, const double* t, const double* w,
-            double alpha, double tol, int max_iter, int* info, hipStream_t s, const char* fn) {
-  NFS_TRY(launch_pcg_init(st, b, s), fn);
+// Solve, then info (host, may be NULL) = (largest iteration count, status).
+int run_pcg(int op, int precond, const PcgState& st, void* mg_ws, const double* b, int nx, int ny, int nz,
+            const double* t, const double* w, double alpha, double tol, int max_iter, int* info, hipStream_t s,
+            const char* fn) {
   std::vector<int> status(st.nrhs), iters(st.nrhs);
-  const double tol2 = tol * tol;
-  int it = 0;
-  for (;;) {
-    NFS_TRY(hipMemcpyAsync(status.data(), st.status, st.nrhs * sizeof(int), hipMemcpyDeviceToHost, s), fn);
-    NFS_TRY(hipStreamSynchronize(s), fn);
-    bool all = true;
-    for (int v : status) all = all && v != 0;
-    if (all || it >= max_iter) break;
-    const int n = std::min(kPcgChunk, max_iter - it);
-    for (int k = 0; k < n; ++k) NFS_TRY(launch_pcg_iteration(op, st, nx, ny, nz, t, w, alpha, tol2, it + k, s), fn);
-    it += n;
-  }
+  NFS_TRY(pcg_solve(op, precond, st, mg_ws, b, nx, ny, nz, t, w, alpha, tol, max_iter, status.data(), iters.data(), s),
+          fn);
   if (info) {
-    NFS_TRY(hipMemcpy(iters.data(), st.iters, st.nrhs * sizeof(int), hipMemcpyDeviceToHost), fn);
     int most = 0, worst = NFS_CG_EXACT;
     bool any_running = false, any_break = false, any_tol = false;
     for (int i = 0; i < st.nrhs; ++i) {
@@ -1539,14 +1530,14 @@ int run_pcg(int op, const PcgState& st, const double* b, int nx, int ny, int nz,
     else if (any_running) worst = NFS_CG_MAXITER;
     else if (any_tol) worst = NFS_CG_TOL;
     info[0] = most;
-    info[1] = st.nrhs ? worst : NFS_CG_EXACT;
+    info[1] = worst;
   }
   return NFS_OK;
 }
 
 }  // namespace
 
-extern "C" int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, int nz, size_t* bytes) {
+extern "C" int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, int nz, int precond, size_t* bytes) {
   const char* fn = "nfs_maps_workspace_bytes";
   if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
   if (kind != NFS_MAP_SENS && kind != NFS_MAP_B0) return fail(NFS_EINVAL, "%s: unknown kind %d", fn, kind);
@@ -1555,7 +1546,9 @@ extern "C" int nfs_maps_workspace_bytes(int kind, int n_coil, int nx, int ny, in
   int64_t L;
   int rc = check_map_grid(nx, ny, nz, fn, &L);
   if (rc) return rc;
-  *bytes = map_layout(kind, n_coil, L).total;
+  if (precond != NFS_PRECOND_JACOBI && precond != NFS_PRECOND_MG)
+    return fail(NFS_EINVAL, "%s: unknown preconditioner %d", fn, precond);
+  *bytes = map_layout(kind, n_coil, nx, ny, nz, precond).total;
   return NFS_OK;
 }
 
@@ -1577,8 +1570,8 @@ extern "C" int nfs_sens_initial(nfs_ctx* ctx, const float* imgs, int n_coil, int
 
 extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* mask_T,
                              const float* mask_R, int nx, int ny, int nz, double alpha, double tol, int max_iter,
-                             float* sens, double* sens64, double* shat, double* parts, int* info, void* ws,
-                             size_t ws_bytes, void* stream) {
+                             int precond, float* sens, double* sens64, double* shat, double* parts, int* info,
+                             void* ws, size_t ws_bytes, void* stream) {
   const char* fn = "nfs_sens_maps";
   if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
   if (n_coil < 1 || n_coil > kMaxSvdCoils) return fail(NFS_ESHAPE, "%s: n_coil %d outside [1, %d]", fn, n_coil, kMaxSvdCoils);
@@ -1586,17 +1579,18 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
   int64_t L;
   int rc = check_map_grid(nx, ny, nz, fn, &L);
   if (rc) return rc;
-  if ((rc = check_solver_args(alpha, tol, max_iter, fn))) return rc;
+  if ((rc = check_solver_args(alpha, tol, max_iter, precond, fn))) return rc;
   if ((rc = check_vec(imgs, (int64_t)n_coil * n_echo * L, fn, "imgs"))) return rc;
   if (!mask_T || !mask_R) return fail(NFS_EINVAL, "%s: mask is NULL", fn);
   if (misaligned(mask_T, 4) || misaligned(mask_R, 4)) return fail(NFS_EINVAL, "%s: mask not 4-byte aligned", fn);
   if (!sens && !sens64) return fail(NFS_EINVAL, "%s: both outputs are NULL", fn);
   if (misaligned(sens, 8) || misaligned(sens64, 16) || misaligned(shat, 16) || misaligned(parts, 8))
     return fail(NFS_EINVAL, "%s: output misaligned", fn);
-  const MapLayout m = map_layout(NFS_MAP_SENS, n_coil, L);
+  const MapLayout m = map_layout(NFS_MAP_SENS, n_coil, nx, ny, nz, precond);
   if ((rc = check_map_ws(m, ws, ws_bytes, fn))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const PcgState st = pcg_state(at<char>(ws, m.pcg), 3 * n_coil, L);
+  const bool mg = precond == NFS_PRECOND_MG;
+  const PcgState st = pcg_state(at<char>(ws, m.pcg), 3 * n_coil, L, mg);
   double2* sh = shat ? reinterpret_cast<double2*>(shat) : at<double2>(ws, m.shat);
   double* b = at<double>(ws, m.b);
   double* t = at<double>(ws, m.t);
@@ -1604,7 +1598,9 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
   NFS_TRY(launch_sens_initial(reinterpret_cast<const float2*>(imgs), n_coil, n_echo, L, sh, s), fn);
   NFS_TRY(launch_sens_rhs(sh, mask_T, n_coil, L, st.Lp, b, s), fn);
   NFS_TRY(launch_smooth_setup(MAP_SENS, nx, ny, nz, mask_T, mask_R, nullptr, alpha, t, w, st, s), fn);
-  if ((rc = run_pcg(MAP_SENS, st, b, nx, ny, nz, t, w, alpha, tol, max_iter, info, s, fn))) return rc;
+  if ((rc = run_pcg(MAP_SENS, precond, st, mg ? at<char>(ws, m.mg) : nullptr, b, nx, ny, nz, t, w, alpha, tol,
+                    max_iter, info, s, fn)))
+    return rc;
   NFS_TRY(launch_sens_combine(st.x, n_coil, L, st.Lp, reinterpret_cast<float2*>(sens),
                               reinterpret_cast<double2*>(sens64), s),
           fn);
@@ -1614,8 +1610,8 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
 }
 
 extern "C" int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_echo, const float* sens, int nx, int ny,
-                          int nz, double delta_te, double alpha, double tol, int max_iter, float* b0, double* b064,
-                          double* fit, int* info, void* ws, size_t ws_bytes, void* stream) {
+                          int nz, double delta_te, double alpha, double tol, int max_iter, int precond, float* b0,
+                          double* b064, double* fit, int* info, void* ws, size_t ws_bytes, void* stream) {
   const char* fn = "nfs_b0_map";
   if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
   if (n_coil < 1 || n_coil > 64) return fail(NFS_ESHAPE, "%s: n_coil %d outside [1, 64]", fn, n_coil);
@@ -1624,16 +1620,17 @@ extern "C" int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_ech
   int64_t L;
   int rc = check_map_grid(nx, ny, nz, fn, &L);
   if (rc) return rc;
-  if ((rc = check_solver_args(alpha, tol, max_iter, fn))) return rc;
+  if ((rc = check_solver_args(alpha, tol, max_iter, precond, fn))) return rc;
   if (!std::isfinite(delta_te) || !(delta_te > 0.0)) return fail(NFS_EINVAL, "%s: delta_te %g not > 0", fn, delta_te);
   if ((rc = check_vec(imgs, (int64_t)n_coil * n_echo * L, fn, "imgs"))) return rc;
   if ((rc = check_vec(sens, (int64_t)n_coil * L, fn, "sens"))) return rc;
   if (!b0 && !b064 && !fit) return fail(NFS_EINVAL, "%s: every output is NULL", fn);
   if (misaligned(b0, 4) || misaligned(b064, 8) || misaligned(fit, 8)) return fail(NFS_EINVAL, "%s: output misaligned", fn);
-  const MapLayout m = map_layout(NFS_MAP_B0, n_coil, L);
+  const MapLayout m = map_layout(NFS_MAP_B0, n_coil, nx, ny, nz, precond);
   if ((rc = check_map_ws(m, ws, ws_bytes, fn))) return rc;
   hipStream_t s = (hipStream_t)stream;
-  const PcgState st = pcg_state(at<char>(ws, m.pcg), 1, L);
+  const bool mg = precond == NFS_PRECOND_MG;
+  const PcgState st = pcg_state(at<char>(ws, m.pcg), 1, L, mg);
   double* f = at<double>(ws, m.fit);
   double *b0hat = f, *beta = f + st.Lp, *eps = f + 2 * st.Lp;
   double* w = at<double>(ws, m.w);
@@ -1650,7 +1647,9 @@ extern "C" int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_ech
     return NFS_OK;
   }
   NFS_TRY(launch_smooth_setup(MAP_B0, nx, ny, nz, nullptr, nullptr, eps, alpha, nullptr, w, st, s), fn);
-  if ((rc = run_pcg(MAP_B0, st, b0hat, nx, ny, nz, nullptr, w, alpha, tol, max_iter, info, s, fn))) return rc;
+  if ((rc = run_pcg(MAP_B0, precond, st, mg ? at<char>(ws, m.mg) : nullptr, b0hat, nx, ny, nz, nullptr, w, alpha, tol,
+                    max_iter, info, s, fn)))
+    return rc;
   NFS_TRY(launch_b0_store(st.x, L, b0, b064, s), fn);
   return NFS_OK;
 }

@@ -36,7 +36,10 @@
 // taken modulo 2 pi into (-pi, pi]), and phi_n = a n + b mod(n, 2) is fitted
 // by least squares (2x2 normal equations); B0^ = a / dTE, eps = the root mean
 // square fit residual.
+#include "nfs.h"
 #include "nfs_internal.h"
+
+#include <algorithm>
 
 namespace nfs {
 
@@ -210,13 +213,6 @@ __device__ __forceinline__ void coords(const Grid3& g, int64_t j, int c[3]) {
   c[2] = (int)(q / g.n[1]);
 }
 
-// Search direction at voxel i: D^-1 r + beta p_old (one expression for every
-// use, so stored and recomputed values agree bitwise).
-__device__ __forceinline__ double dir_at(const double* __restrict__ dinv, const double* __restrict__ r,
-                                         const double* __restrict__ po, double beta, int64_t i) {
-  return fma(beta, po[i], dinv[i] * r[i]);
-}
-
 // Row j of A applied to a vector given by the accessor V (SENS: D2 penalty,
 // B0: D1 penalty); also the diagonal of A when V is the unit-vector probe.
 template <int OP, class V>
@@ -309,7 +305,19 @@ __global__ void __launch_bounds__(256) smooth_dinv_kernel(Grid3 g, int64_t L, co
   dinv[j] = d > 0.0 ? 1.0 / d : 0.0;
 }
 
-// x = 0, r = b, p = 0; partials of b.b and r.(D^-1 r).
+// Search direction at voxel i: z_i + beta p_old_i with z = D^-1 r (Jacobi)
+// or the stored multigrid output (one expression for every use, so stored
+// and recomputed values agree bitwise).
+template <bool MG>
+__device__ __forceinline__ double dir_at(const double* __restrict__ dinv, const double* __restrict__ r,
+                                         const double* __restrict__ z, const double* __restrict__ po, double beta,
+                                         int64_t i) {
+  return MG ? fma(beta, po[i], z[i]) : fma(beta, po[i], dinv[i] * r[i]);
+}
+
+// x = 0, r = b, p = 0; partials of b.b (part1) and, for Jacobi, r.(D^-1 r)
+// (part0); the status of every right-hand side cleared.
+template <bool MG>
 __global__ void __launch_bounds__(256) pcg_init_kernel(PcgState st, const double* __restrict__ b) {
   __shared__ double red[4];
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -322,13 +330,14 @@ __global__ void __launch_bounds__(256) pcg_init_kernel(PcgState st, const double
     st.r[o + j] = bj;
     st.p[0][o + j] = 0.0;
     bb = bj * bj;
-    rz = bj * (st.dinv[j] * bj);
+    if (!MG) rz = bj * (st.dinv[j] * bj);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) st.status[rhs] = 0;
   bb = block_total(bb, red);
-  rz = block_total(rz, red);
+  if (!MG) rz = block_total(rz, red);
   if (threadIdx.x == 0) {
-    st.part0[(size_t)rhs * st.nblk + blockIdx.x] = bb;
-    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = bb;
+    if (!MG) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
   }
 }
 
@@ -338,11 +347,35 @@ __device__ __forceinline__ double sum_parts(const double* part, int nblk, double
   return block_total(s, red);
 }
 
+// Multigrid form: z is cleared on the rows of A without entries (voxels the
+// system does not see, whose solution is 0; prolongation would otherwise
+// carry coarse corrections into them, where CG cannot remove them), which
+// keeps the preconditioner symmetric on the active rows; partials of r.z
+// into part0.
+__global__ void __launch_bounds__(256) pcg_dot_kernel(PcgState st) {
+  __shared__ double red[4];
+  const int rhs = blockIdx.y;
+  if (st.status[rhs]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const size_t o = (size_t)rhs * st.Lp;
+  double rz = 0.0;
+  if (j < st.L) {
+    double zj = st.z[o + j];
+    if (st.dinv[j] == 0.0) {
+      zj = 0.0;
+      st.z[o + j] = 0.0;
+    }
+    rz = st.r[o + j] * zj;
+  }
+  rz = block_total(rz, red);
+  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+}
+
 __global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st) {
   __shared__ double red[4];
   const int rhs = blockIdx.x;
-  const double bb = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
-  const double rz = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double rz = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double bb = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
   if (threadIdx.x == 0) {
     st.bb[rhs] = bb;
     st.rr[rhs] = bb;
@@ -354,8 +387,8 @@ __global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st) {
   }
 }
 
-// p_new = D^-1 r + beta p_old (stored), q = A p_new; partial p_new.q.
-template <int OP>
+// p_new = z + beta p_old (stored), q = A p_new; partial p_new.q.
+template <int OP, bool MG>
 __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, const double* __restrict__ t,
                                                         const double* __restrict__ w, double alpha, int pin) {
   __shared__ double red[4];
@@ -364,6 +397,7 @@ __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, co
   const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const size_t o = (size_t)rhs * st.Lp;
   const double* r = st.r + o;
+  const double* z = MG ? st.z + o : nullptr;
   const double* po = st.p[pin] + o;
   const double beta = st.beta[rhs];
   const double* dinv = st.dinv;
@@ -371,7 +405,7 @@ __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, co
   if (j < st.L) {
     int c[3];
     coords(g, j, c);
-    auto val = [&](int64_t i) { return dir_at(dinv, r, po, beta, i); };
+    auto val = [&](int64_t i) { return dir_at<MG>(dinv, r, z, po, beta, i); };
     const double pj = val(j);
     const double qj = apply_row<OP>(g, t, w, alpha, j, c, val);
     st.p[pin ^ 1][o + j] = pj;
@@ -398,7 +432,9 @@ __global__ void __launch_bounds__(256) pcg_alpha_kernel(PcgState st) {
   }
 }
 
-// x += alpha p, r -= alpha q; partials of r.(D^-1 r) and r.r.
+// x += alpha p, r -= alpha q; partials of r.r (part1) and, for Jacobi,
+// r.(D^-1 r) (part0).
+template <bool MG>
 __global__ void __launch_bounds__(256) pcg_update_kernel(PcgState st, int pnew) {
   __shared__ double red[4];
   const int rhs = blockIdx.y;
@@ -412,13 +448,13 @@ __global__ void __launch_bounds__(256) pcg_update_kernel(PcgState st, int pnew) 
     st.x[o + j] = fma(a, pj, st.x[o + j]);
     const double rj = fma(-a, st.q[o + j], st.r[o + j]);
     st.r[o + j] = rj;
-    rz = rj * (st.dinv[j] * rj);
+    if (!MG) rz = rj * (st.dinv[j] * rj);
     rr = rj * rj;
   }
-  rz = block_total(rz, red);
+  if (!MG) rz = block_total(rz, red);
   rr = block_total(rr, red);
   if (threadIdx.x == 0) {
-    st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+    if (!MG) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
     st.part1[(size_t)rhs * st.nblk + blockIdx.x] = rr;
   }
 }
@@ -438,6 +474,219 @@ __global__ void __launch_bounds__(256) pcg_beta_kernel(PcgState st, double tol2)
     else if (!isfinite(bt)) st.status[rhs] = PCG_BREAKDOWN;
     st.beta[rhs] = bt;
     st.rz[rhs] = rz;
+  }
+}
+
+// ------------------------------------------------------ multigrid V-cycle
+//
+// Levels are rediscretisations of the same normal equations: each coarser
+// grid keeps every axis of length <= 2 and halves the others (coarse point
+// I at fine point 2I), its weights t, w are the interpolation-weighted
+// averages of the finer ones and its penalty weight alpha is divided by 16
+// (second differences) or 4 (first differences), the factor by which the
+// Galerkin product P^T A P scales those terms.  Prolongation P is
+// multilinear interpolation, restriction P^T divided by the constant 2^(axes
+// halved), so the cycle is symmetric; smoothing is damped Jacobi (the same
+// number of sweeps before and after); the coarsest level (at most
+// kMgCoarseMax unknowns) is solved with its explicit inverse.
+
+struct AxisMap {
+  int n[2];
+  double wt[2];
+  int cnt;
+};
+
+// coarse neighbours of fine coordinate i along an axis of fine length n and
+// coarse length nc (nc == n: axis not coarsened)
+__device__ __forceinline__ AxisMap fine_to_coarse(int i, int n, int nc) {
+  AxisMap m;
+  if (nc == n) {
+    m.n[0] = i;
+    m.wt[0] = 1.0;
+    m.cnt = 1;
+  } else if ((i & 1) == 0) {
+    m.n[0] = i >> 1;
+    m.wt[0] = 1.0;
+    m.cnt = 1;
+  } else {
+    m.n[0] = i >> 1;
+    m.wt[0] = 0.5;
+    m.cnt = 1;
+    if ((i >> 1) + 1 < nc) {
+      m.n[1] = (i >> 1) + 1;
+      m.wt[1] = 0.5;
+      m.cnt = 2;
+    }
+  }
+  return m;
+}
+
+// fine neighbours of coarse coordinate I (fine length n, coarse length nc)
+__device__ __forceinline__ int coarse_to_fine(int I, int n, int nc, int* idx, double* wt) {
+  if (nc == n) {
+    idx[0] = I;
+    wt[0] = 1.0;
+    return 1;
+  }
+  int k = 0;
+  for (int d = -1; d <= 1; ++d) {
+    const int i = 2 * I + d;
+    if (i < 0 || i >= n) continue;
+    idx[k] = i;
+    wt[k] = d == 0 ? 1.0 : 0.5;
+    ++k;
+  }
+  return k;
+}
+
+// interpolation-weighted averages of the fine weights on the coarse grid
+template <int OP>
+__global__ void __launch_bounds__(256) mg_coarsen_kernel(Grid3 gf, Grid3 gc, int64_t Lc, const double* __restrict__ tf,
+                                                         const double* __restrict__ wf, double* __restrict__ tc,
+                                                         double* __restrict__ wc) {
+  const int64_t J = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (J >= Lc) return;
+  int C[3];
+  coords(gc, J, C);
+  int ix[3][3], n[3];
+  double wx[3][3];
+  for (int d = 0; d < 3; ++d) n[d] = coarse_to_fine(C[d], gf.n[d], gc.n[d], ix[d], wx[d]);
+  double st = 0.0, sw = 0.0, s = 0.0;
+  for (int a = 0; a < n[2]; ++a)
+    for (int b = 0; b < n[1]; ++b)
+      for (int c = 0; c < n[0]; ++c) {
+        const double wgt = wx[2][a] * wx[1][b] * wx[0][c];
+        const int64_t i = ix[0][c] + gf.s[1] * ix[1][b] + gf.s[2] * ix[2][a];
+        if (OP == MAP_SENS) st += wgt * tf[i];
+        sw += wgt * wf[i];
+        s += wgt;
+      }
+  if (OP == MAP_SENS) tc[J] = st / s;
+  wc[J] = sw / s;
+}
+
+// x = omega D^-1 b (the first sweep from x = 0)
+__global__ void __launch_bounds__(256) mg_sweep0_kernel(const int* __restrict__ status, int64_t L, int64_t Lp,
+                                                        const double* __restrict__ dinv, double omega,
+                                                        const double* __restrict__ b, double* __restrict__ x) {
+  const int rhs = blockIdx.y;
+  if (status[rhs]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  const size_t o = (size_t)rhs * Lp;
+  x[o + j] = omega * (dinv[j] * b[o + j]);
+}
+
+// MODE 0: y = x + omega D^-1 (b - A x) (a Jacobi sweep); MODE 1: y = b - A x
+template <int OP, int MODE>
+__global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__ status, Grid3 g, int64_t L,
+                                                         int64_t Lp, const double* __restrict__ t,
+                                                         const double* __restrict__ w, double alpha,
+                                                         const double* __restrict__ dinv, double omega,
+                                                         const double* __restrict__ b, const double* __restrict__ x,
+                                                         double* __restrict__ y) {
+  const int rhs = blockIdx.y;
+  if (status[rhs]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= L) return;
+  const size_t o = (size_t)rhs * Lp;
+  const double* xv = x + o;
+  int c[3];
+  coords(g, j, c);
+  const double ax = apply_row<OP>(g, t, w, alpha, j, c, [&](int64_t i) { return xv[i]; });
+  const double res = b[o + j] - ax;
+  y[o + j] = MODE == 0 ? fma(omega, dinv[j] * res, xv[j]) : res;
+}
+
+// bc = P^T r / fac
+__global__ void __launch_bounds__(256) mg_restrict_kernel(const int* __restrict__ status, Grid3 gf, Grid3 gc,
+                                                          int64_t Lc, int64_t Lpf, int64_t Lpc, double inv_fac,
+                                                          const double* __restrict__ r, double* __restrict__ bc) {
+  const int rhs = blockIdx.y;
+  if (status[rhs]) return;
+  const int64_t J = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (J >= Lc) return;
+  int C[3];
+  coords(gc, J, C);
+  int ix[3][3], n[3];
+  double wx[3][3];
+  for (int d = 0; d < 3; ++d) n[d] = coarse_to_fine(C[d], gf.n[d], gc.n[d], ix[d], wx[d]);
+  const double* rv = r + (size_t)rhs * Lpf;
+  double s = 0.0;
+  for (int a = 0; a < n[2]; ++a)
+    for (int b = 0; b < n[1]; ++b)
+      for (int c = 0; c < n[0]; ++c)
+        s += (wx[2][a] * wx[1][b] * wx[0][c]) * rv[ix[0][c] + gf.s[1] * ix[1][b] + gf.s[2] * ix[2][a]];
+  bc[(size_t)rhs * Lpc + J] = s * inv_fac;
+}
+
+// x += P xc
+__global__ void __launch_bounds__(256) mg_prolong_kernel(const int* __restrict__ status, Grid3 gf, Grid3 gc,
+                                                         int64_t Lf, int64_t Lpf, int64_t Lpc,
+                                                         const double* __restrict__ xc, double* __restrict__ x) {
+  const int rhs = blockIdx.y;
+  if (status[rhs]) return;
+  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (j >= Lf) return;
+  int c[3];
+  coords(gf, j, c);
+  AxisMap m[3];
+  for (int d = 0; d < 3; ++d) m[d] = fine_to_coarse(c[d], gf.n[d], gc.n[d]);
+  const double* cv = xc + (size_t)rhs * Lpc;
+  double s = 0.0;
+  for (int a = 0; a < m[2].cnt; ++a)
+    for (int b = 0; b < m[1].cnt; ++b)
+      for (int e = 0; e < m[0].cnt; ++e)
+        s += (m[2].wt[a] * m[1].wt[b] * m[0].wt[e]) * cv[m[0].n[e] + gc.s[1] * m[1].n[b] + gc.s[2] * m[2].n[a]];
+  x[(size_t)rhs * Lpf + j] += s;
+}
+
+// Explicit inverse of the coarsest operator (n <= kMgCoarseMax unknowns; a
+// row without entries gets a unit diagonal), Gauss-Jordan in LDS.
+template <int OP>
+__global__ void __launch_bounds__(256) mg_coarsest_kernel(Grid3 g, int n, const double* __restrict__ t,
+                                                          const double* __restrict__ w, double alpha,
+                                                          double* __restrict__ ainv) {
+  __shared__ double M[kMgCoarseMax][2 * kMgCoarseMax + 1];
+  __shared__ double col[kMgCoarseMax];
+  if (n > kMgCoarseMax) return;  // the host never builds such a hierarchy
+  for (int e = threadIdx.x; e < n * n; e += 256) {
+    const int i = e / n, jj = e % n;
+    int c[3];
+    coords(g, i, c);
+    M[i][jj] = apply_row<OP>(g, t, w, alpha, i, c, [&](int64_t k) { return k == jj ? 1.0 : 0.0; });
+    M[i][n + jj] = i == jj ? 1.0 : 0.0;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < n; i += 256)
+    if (M[i][i] == 0.0) M[i][i] = 1.0;
+  __syncthreads();
+  for (int k = 0; k < n; ++k) {
+    const double piv = M[k][k];
+    __syncthreads();
+    for (int jj = threadIdx.x; jj < 2 * n; jj += 256) M[k][jj] /= piv;
+    __syncthreads();
+    for (int i = threadIdx.x; i < n; i += 256) col[i] = M[i][k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < n * 2 * n; e += 256) {
+      const int i = e / (2 * n), jj = e % (2 * n);
+      if (i != k) M[i][jj] = fma(-col[i], M[k][jj], M[i][jj]);
+    }
+    __syncthreads();
+  }
+  for (int e = threadIdx.x; e < n * n; e += 256) ainv[e] = M[e / n][n + e % n];
+}
+
+__global__ void __launch_bounds__(64) mg_coarse_solve_kernel(const int* __restrict__ status, int n, int64_t Lp,
+                                                             const double* __restrict__ ainv,
+                                                             const double* __restrict__ b, double* __restrict__ x) {
+  const int rhs = blockIdx.x;
+  if (status[rhs]) return;
+  const double* bv = b + (size_t)rhs * Lp;
+  for (int i = threadIdx.x; i < n; i += 64) {
+    double s = 0.0;
+    for (int k = 0; k < n; ++k) s = fma(ainv[i * n + k], bv[k], s);
+    x[(size_t)rhs * Lp + i] = s;
   }
 }
 
@@ -569,21 +818,20 @@ unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 }  // namespace
 
-size_t pcg_state_bytes(int nrhs, int64_t L) {
+size_t pcg_state_bytes(int nrhs, int64_t L, bool with_z) {
   const int64_t Lp = (L + 63) & ~(int64_t)63;
   const int64_t nblk = (L + 255) / 256;
   size_t b = 0;
   auto add = [&](size_t n) { b += (n + 255) & ~(size_t)255; };
-  for (int i = 0; i < 5; ++i) add((size_t)nrhs * Lp * 8);  // x r p0 p1 q
-  add((size_t)Lp * 8);                                       // dinv
-  add((size_t)nrhs * nblk * 8);                              // part0
-  add((size_t)nrhs * nblk * 8);                              // part1
-  for (int i = 0; i < 6; ++i) add((size_t)nrhs * 8);         // rz alpha beta bb rr + iters/status
-  add((size_t)nrhs * 8);
+  for (int i = 0; i < (with_z ? 6 : 5); ++i) add((size_t)nrhs * Lp * 8);  // x r p0 p1 q (z)
+  add((size_t)Lp * 8);                                                      // dinv
+  add((size_t)nrhs * nblk * 8);                                             // part0
+  add((size_t)nrhs * nblk * 8);                                             // part1
+  for (int i = 0; i < 7; ++i) add((size_t)nrhs * 8);  // rz alpha beta bb rr iters status
   return b;
 }
 
-PcgState pcg_state(void* base, int nrhs, int64_t L) {
+PcgState pcg_state(void* base, int nrhs, int64_t L, bool with_z) {
   PcgState st;
   st.L = L;
   st.Lp = (L + 63) & ~(int64_t)63;
@@ -601,6 +849,7 @@ PcgState pcg_state(void* base, int nrhs, int64_t L) {
   st.p[0] = (double*)take(vec);
   st.p[1] = (double*)take(vec);
   st.q = (double*)take(vec);
+  st.z = with_z ? (double*)take(vec) : nullptr;
   st.dinv = (double*)take((size_t)st.Lp * 8);
   st.part0 = (double*)take((size_t)nrhs * st.nblk * 8);
   st.part1 = (double*)take((size_t)nrhs * st.nblk * 8);
@@ -612,6 +861,221 @@ PcgState pcg_state(void* base, int nrhs, int64_t L) {
   st.iters = (int*)take((size_t)nrhs * 8);
   st.status = (int*)take((size_t)nrhs * 8);
   return st;
+}
+
+namespace {
+
+constexpr int kMgMaxLevels = 24;
+constexpr double kMgOmega = 0.6;  // damped Jacobi weight
+constexpr int kMgSweeps = 2;      // sweeps before and after the coarse correction
+
+struct MgLevel {
+  Grid3 g;
+  int64_t L, Lp;
+  double alpha;
+  const double* t;
+  const double* w;
+  const double* dinv;
+  const double* b;
+  double* x[2];
+  double* tw[3];  // coarse levels: t, w, dinv storage
+};
+
+struct MgHierarchy {
+  int nlev = 0;
+  MgLevel lev[kMgMaxLevels];
+  double* ainv = nullptr;
+};
+
+// Grid sizes of the levels (fine first).
+int mg_dims(int nx, int ny, int nz, int dims[][3]) {
+  int n = 0;
+  int d[3] = {nx, ny, nz};
+  for (;;) {
+    dims[n][0] = d[0];
+    dims[n][1] = d[1];
+    dims[n][2] = d[2];
+    ++n;
+    const int64_t L = (int64_t)d[0] * d[1] * d[2];
+    if (L <= kMgCoarseMax || n == kMgMaxLevels) break;
+    int c[3];
+    for (int k = 0; k < 3; ++k) c[k] = d[k] >= 3 ? d[k] / 2 + 1 : d[k];
+    if (c[0] == d[0] && c[1] == d[1] && c[2] == d[2]) break;
+    for (int k = 0; k < 3; ++k) d[k] = c[k];
+  }
+  return n;
+}
+
+size_t mg_layout(void* base, int nrhs, int nx, int ny, int nz, MgHierarchy* h) {
+  int dims[kMgMaxLevels][3];
+  const int nlev = mg_dims(nx, ny, nz, dims);
+  char* p = static_cast<char*>(base);
+  size_t off = 0;
+  auto take = [&](size_t n) {
+    char* q = p ? p + off : nullptr;
+    off += (n + 255) & ~(size_t)255;
+    return (double*)q;
+  };
+  if (h) h->nlev = nlev;
+  for (int l = 0; l < nlev; ++l) {
+    const int64_t L = (int64_t)dims[l][0] * dims[l][1] * dims[l][2];
+    const int64_t Lp = (L + 63) & ~(int64_t)63;
+    MgLevel lv{};
+    lv.g = make_grid(dims[l][0], dims[l][1], dims[l][2]);
+    lv.L = L;
+    lv.Lp = Lp;
+    if (l == 0) {
+      lv.x[1] = take((size_t)nrhs * Lp * 8);
+    } else {
+      for (int k = 0; k < 3; ++k) lv.tw[k] = take((size_t)Lp * 8);
+      lv.b = take((size_t)nrhs * Lp * 8);
+      lv.x[0] = take((size_t)nrhs * Lp * 8);
+      lv.x[1] = take((size_t)nrhs * Lp * 8);
+    }
+    if (h) h->lev[l] = lv;
+  }
+  double* ainv = take((size_t)kMgCoarseMax * kMgCoarseMax * 8);
+  if (h) h->ainv = ainv;
+  return off;
+}
+
+// Coarse weights, inverse diagonals and the coarsest inverse.
+template <int OP>
+hipError_t mg_setup(MgHierarchy& h, const PcgState& st, const double* t, const double* w, double alpha,
+                    hipStream_t s) {
+  const double shrink = OP == MAP_SENS ? 1.0 / 16.0 : 1.0 / 4.0;
+  MgLevel& f = h.lev[0];
+  f.alpha = alpha;
+  f.t = t;
+  f.w = w;
+  f.dinv = st.dinv;
+  f.b = st.r;
+  f.x[0] = st.z;
+  for (int l = 1; l < h.nlev; ++l) {
+    MgLevel& c = h.lev[l];
+    const MgLevel& p = h.lev[l - 1];
+    c.alpha = p.alpha * shrink;
+    c.t = c.tw[0];
+    c.w = c.tw[1];
+    c.dinv = c.tw[2];
+    hipLaunchKernelGGL(mg_coarsen_kernel<OP>, dim3(cdiv_u(c.L, 256)), dim3(256), 0, s, p.g, c.g, c.L, p.t, p.w,
+                       c.tw[0], c.tw[1]);
+    hipLaunchKernelGGL(smooth_dinv_kernel<OP>, dim3(cdiv_u(c.L, 256)), dim3(256), 0, s, c.g, c.L, c.t, c.w, c.alpha,
+                       c.tw[2]);
+  }
+  const MgLevel& z = h.lev[h.nlev - 1];
+  hipLaunchKernelGGL(mg_coarsest_kernel<OP>, dim3(1), dim3(256), 0, s, z.g, (int)z.L, z.t, z.w, z.alpha, h.ainv);
+  return hipGetLastError();
+}
+
+// z = M^-1 r (one V-cycle for every running right-hand side).
+template <int OP>
+hipError_t mg_vcycle(const MgHierarchy& h, const PcgState& st, hipStream_t s) {
+  const int nr = st.nrhs;
+  int cur[kMgMaxLevels];
+  for (int l = 0; l + 1 < h.nlev; ++l) {
+    const MgLevel& v = h.lev[l];
+    const dim3 grid(cdiv_u(v.L, 256), nr);
+    hipLaunchKernelGGL(mg_sweep0_kernel, grid, dim3(256), 0, s, st.status, v.L, v.Lp, v.dinv, kMgOmega, v.b, v.x[1]);
+    int c = 1;
+    for (int k = 1; k < kMgSweeps; ++k, c ^= 1)
+      hipLaunchKernelGGL((mg_stencil_kernel<OP, 0>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
+                         v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
+    cur[l] = c;
+    hipLaunchKernelGGL((mg_stencil_kernel<OP, 1>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
+                       v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
+    const MgLevel& n = h.lev[l + 1];
+    double fac = 1.0;
+    for (int d = 0; d < 3; ++d) fac *= n.g.n[d] != v.g.n[d] ? 2.0 : 1.0;
+    hipLaunchKernelGGL(mg_restrict_kernel, dim3(cdiv_u(n.L, 256), nr), dim3(256), 0, s, st.status, v.g, n.g, n.L,
+                       v.Lp, n.Lp, 1.0 / fac, v.x[c ^ 1], const_cast<double*>(n.b));
+  }
+  const MgLevel& z = h.lev[h.nlev - 1];
+  hipLaunchKernelGGL(mg_coarse_solve_kernel, dim3(nr), dim3(64), 0, s, st.status, (int)z.L, z.Lp, h.ainv, z.b,
+                     z.x[0]);
+  for (int l = h.nlev - 2; l >= 0; --l) {
+    const MgLevel& v = h.lev[l];
+    const MgLevel& n = h.lev[l + 1];
+    const dim3 grid(cdiv_u(v.L, 256), nr);
+    int c = cur[l];
+    hipLaunchKernelGGL(mg_prolong_kernel, grid, dim3(256), 0, s, st.status, v.g, n.g, v.L, v.Lp, n.Lp, n.x[0], v.x[c]);
+    for (int k = 0; k < kMgSweeps; ++k, c ^= 1)
+      hipLaunchKernelGGL((mg_stencil_kernel<OP, 0>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
+                         v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
+    // 1 + (kMgSweeps - 1) + kMgSweeps buffer changes end every level in x[0]
+  }
+  return hipGetLastError();
+}
+
+template <int OP>
+hipError_t pcg_run(int precond, const PcgState& st, void* mg_ws, const double* b, int nx, int ny, int nz,
+                   const double* t, const double* w, double alpha, double tol, int max_iter, int* status, int* iters,
+                   hipStream_t s) {
+  const bool mg = precond == NFS_PRECOND_MG;
+  const Grid3 g = make_grid(nx, ny, nz);
+  const dim3 grid(st.nblk, st.nrhs);
+  MgHierarchy h;
+  hipError_t e;
+  if (mg) {
+    mg_layout(mg_ws, st.nrhs, nx, ny, nz, &h);
+    if (h.lev[h.nlev - 1].L > kMgCoarseMax) return hipErrorInvalidValue;
+    if ((e = mg_setup<OP>(h, st, t, w, alpha, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(pcg_init_kernel<true>, grid, dim3(256), 0, s, st, b);
+    if ((e = mg_vcycle<OP>(h, st, s)) != hipSuccess) return e;
+    hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
+  } else {
+    hipLaunchKernelGGL(pcg_init_kernel<false>, grid, dim3(256), 0, s, st, b);
+  }
+  hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+  if ((e = hipGetLastError()) != hipSuccess) return e;
+  const double tol2 = tol * tol;
+  int it = 0;
+  for (;;) {
+    if ((e = hipMemcpyAsync(status, st.status, st.nrhs * sizeof(int), hipMemcpyDeviceToHost, s)) != hipSuccess)
+      return e;
+    if ((e = hipStreamSynchronize(s)) != hipSuccess) return e;
+    bool all = true;
+    for (int k = 0; k < st.nrhs; ++k) all = all && status[k] != 0;
+    if (all || it >= max_iter) break;
+    const int n = std::min(kPcgChunk, max_iter - it);
+    for (int k = 0; k < n; ++k, ++it) {
+      const int pin = it & 1;
+      if (mg) {
+        hipLaunchKernelGGL((pcg_apply_kernel<OP, true>), grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+        hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+        hipLaunchKernelGGL(pcg_update_kernel<true>, grid, dim3(256), 0, s, st, pin ^ 1);
+        if ((e = mg_vcycle<OP>(h, st, s)) != hipSuccess) return e;
+        hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
+      } else {
+        hipLaunchKernelGGL((pcg_apply_kernel<OP, false>), grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+        hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+        hipLaunchKernelGGL(pcg_update_kernel<false>, grid, dim3(256), 0, s, st, pin ^ 1);
+      }
+      hipLaunchKernelGGL(pcg_beta_kernel, dim3(st.nrhs), dim3(256), 0, s, st, tol2);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  return hipMemcpy(iters, st.iters, st.nrhs * sizeof(int), hipMemcpyDeviceToHost);
+}
+
+}  // namespace
+
+size_t mg_bytes(int nrhs, int nx, int ny, int nz) { return mg_layout(nullptr, nrhs, nx, ny, nz, nullptr); }
+
+hipError_t pcg_solve(int op, int precond, const PcgState& st, void* mg_ws, const double* b, int nx, int ny, int nz,
+                     const double* t, const double* w, double alpha, double tol, int max_iter, int* status,
+                     int* iters, hipStream_t s) {
+  if (st.L == 0 || st.nrhs == 0) {
+    for (int k = 0; k < st.nrhs; ++k) {
+      status[k] = PCG_EXACT;
+      iters[k] = 0;
+    }
+    return hipSuccess;
+  }
+  return op == MAP_SENS ? pcg_run<MAP_SENS>(precond, st, mg_ws, b, nx, ny, nz, t, w, alpha, tol, max_iter, status,
+                                            iters, s)
+                        : pcg_run<MAP_B0>(precond, st, mg_ws, b, nx, ny, nz, t, w, alpha, tol, max_iter, status,
+                                          iters, s);
 }
 
 hipError_t launch_sens_initial(const float2* X, int G, int ne, int64_t L, double2* shat, hipStream_t s) {
@@ -660,29 +1124,6 @@ hipError_t launch_smooth_setup(int op, int nx, int ny, int nz, const float* mT, 
     hipLaunchKernelGGL(smooth_setup_kernel<MAP_B0>, grid, dim3(256), 0, s, g, L, mT, mR, eps, alpha, t, w);
     hipLaunchKernelGGL(smooth_dinv_kernel<MAP_B0>, grid, dim3(256), 0, s, g, L, t, w, alpha, st.dinv);
   }
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_init(const PcgState& st, const double* b, hipStream_t s) {
-  if (st.L == 0 || st.nrhs == 0) return hipSuccess;
-  hipLaunchKernelGGL(pcg_init_kernel, dim3(st.nblk, st.nrhs), dim3(256), 0, s, st, b);
-  hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_iteration(int op, const PcgState& st, int nx, int ny, int nz, const double* t, const double* w,
-                                double alpha, double tol2, int it, hipStream_t s) {
-  if (st.L == 0 || st.nrhs == 0) return hipSuccess;
-  const Grid3 g = make_grid(nx, ny, nz);
-  const int pin = it & 1;
-  const dim3 grid(st.nblk, st.nrhs);
-  if (op == MAP_SENS)
-    hipLaunchKernelGGL(pcg_apply_kernel<MAP_SENS>, grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
-  else
-    hipLaunchKernelGGL(pcg_apply_kernel<MAP_B0>, grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
-  hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
-  hipLaunchKernelGGL(pcg_update_kernel, grid, dim3(256), 0, s, st, pin ^ 1);
-  hipLaunchKernelGGL(pcg_beta_kernel, dim3(st.nrhs), dim3(256), 0, s, st, tol2);
   return hipGetLastError();
 }
 

@@ -193,6 +193,8 @@ hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, 
 // ---- map estimation (sensitivity and B0 maps from prescan data) ----
 constexpr int kMaxSvdCoils = 16;   // coils of the per-voxel SVD (one 16x16 matrix-core tile)
 constexpr int kMaxFitEchoes = 64;  // echoes of the B0 fit
+constexpr int kMgCoarseMax = 64;   // unknowns of the coarsest multigrid level (explicit inverse)
+constexpr int kPcgChunk = 32;      // PCG iterations enqueued between two reads of the status flags
 enum { MAP_SENS = 0, MAP_B0 = 1 };
 // PCG status per right-hand side (0 = running), same codes as the CG solve
 enum { PCG_TOL = 2, PCG_EXACT = 3, PCG_BREAKDOWN = 4 };
@@ -204,6 +206,7 @@ struct PcgState {
   double* r;
   double* p[2];  // ping-pong: iteration n reads p[n & 1], writes p[(n & 1) ^ 1]
   double* q;
+  double* z;     // multigrid output M^-1 r (NULL with the Jacobi preconditioner)
   double* dinv;  // [Lp] inverse diagonal (0 on rows without entries)
   double* part0;  // [nrhs][nblk] workgroup partials
   double* part1;
@@ -217,8 +220,17 @@ struct PcgState {
   int64_t L, Lp;
   int nblk, nrhs;
 };
-size_t pcg_state_bytes(int nrhs, int64_t L);
-PcgState pcg_state(void* base, int nrhs, int64_t L);
+size_t pcg_state_bytes(int nrhs, int64_t L, bool with_z);
+PcgState pcg_state(void* base, int nrhs, int64_t L, bool with_z);
+// workspace of the multigrid hierarchy for nrhs right-hand sides on an nx x ny x nz grid
+size_t mg_bytes(int nrhs, int nx, int ny, int nz);
+// Solve the MAP_SENS / MAP_B0 normal equations for st.nrhs right-hand sides b
+// [nrhs][Lp] into st.x with the NFS_PRECOND_* preconditioner (mg_ws: mg_bytes
+// of workspace, multigrid only); synchronises the stream every kPcgChunk
+// iterations.  status, iters: host [nrhs].
+hipError_t pcg_solve(int op, int precond, const PcgState& st, void* mg_ws, const double* b, int nx, int ny, int nz,
+                     const double* t, const double* w, double alpha, double tol, int max_iter, int* status,
+                     int* iters, hipStream_t s);
 
 // S^ [G][L] (complex float64) from prescan X [G][ne][L] (complex float32), G <= 16
 hipError_t launch_sens_initial(const float2* X, int G, int ne, int64_t L, double2* shat, hipStream_t s);
@@ -235,8 +247,5 @@ hipError_t launch_b0_store(const double* x, int64_t L, float* b0, double* b064, 
 // weights t, w [L] and st.dinv of the MAP_SENS (masks) or MAP_B0 (eps) system
 hipError_t launch_smooth_setup(int op, int nx, int ny, int nz, const float* mT, const float* mR, const double* eps,
                                double alpha, double* t, double* w, const PcgState& st, hipStream_t s);
-hipError_t launch_pcg_init(const PcgState& st, const double* b, hipStream_t s);
-hipError_t launch_pcg_iteration(int op, const PcgState& st, int nx, int ny, int nz, const double* t, const double* w,
-                                double alpha, double tol2, int it, hipStream_t s);
 
 }  // namespace nfs

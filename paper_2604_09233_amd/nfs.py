@@ -84,11 +84,11 @@ def lib():
             L.nfs_autotune_batched.argtypes = [vp, i32, pp, i32, vp, sz, vp]
             L.nfs_profile_enable.argtypes = [vp, i32]
             L.nfs_profile_read.argtypes = [vp, i32, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
-            L.nfs_maps_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
+            L.nfs_maps_workspace_bytes.argtypes = [i32, i32, i32, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_sens_initial.argtypes = [vp, vp, i32, i32, ctypes.c_int64, vp, vp]
-            L.nfs_sens_maps.argtypes = [vp, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, vp, vp, vp, vp,
-                                        ctypes.POINTER(i32), vp, sz, vp]
-            L.nfs_b0_map.argtypes = [vp, vp, i32, i32, vp, i32, i32, i32, dbl, dbl, dbl, i32, vp, vp, vp,
+            L.nfs_sens_maps.argtypes = [vp, vp, i32, i32, vp, vp, i32, i32, i32, dbl, dbl, i32, i32, vp, vp, vp,
+                                        vp, ctypes.POINTER(i32), vp, sz, vp]
+            L.nfs_b0_map.argtypes = [vp, vp, i32, i32, vp, i32, i32, i32, dbl, dbl, dbl, i32, i32, vp, vp, vp,
                                      ctypes.POINTER(i32), vp, sz, vp]
             L.nfs_last_error.restype = ctypes.c_char_p
             L.nfs_last_error.argtypes = []
@@ -466,6 +466,7 @@ def profile_read(device: int, kind: str):
 
 
 MAP_KINDS = {"sens": 0, "b0": 1}
+PRECONDS = {"jacobi": 0, "mg": 1}
 
 
 def _grid(dims):
@@ -473,9 +474,10 @@ def _grid(dims):
     return nx, ny, int(dims[2]) if len(dims) > 2 else 1
 
 
-def _map_workspace(kind, n_coil, dims, dev):
+def _map_workspace(kind, n_coil, dims, precond, dev):
     nbytes = ctypes.c_size_t()
-    _check(lib().nfs_maps_workspace_bytes(MAP_KINDS[kind], n_coil, *_grid(dims), ctypes.byref(nbytes)))
+    _check(lib().nfs_maps_workspace_bytes(MAP_KINDS[kind], n_coil, *_grid(dims), PRECONDS[precond],
+                                          ctypes.byref(nbytes)))
     ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
     off = (-ws.data_ptr()) % 256
     return ctypes.c_void_p(ws.data_ptr() + off), nbytes.value, ws
@@ -494,7 +496,7 @@ def sens_initial(imgs, device: int = 0):
 
 
 def sens_maps(imgs, mask_T, mask_R, dims, alpha: float, tol: float = 1e-10, max_iter: int = 100000,
-              device: int = 0, parts: bool = False):
+              device: int = 0, parts: bool = False, precond: str = "mg"):
     """Smoothed and extrapolated sensitivity maps from prescan images
     imgs [G][n_echo][L] and the masks M_T, M_R [L] on the grid dims.
     Returns (S complex64 [G][L], S complex128 [G][L], S^ complex128 [G][L],
@@ -509,19 +511,19 @@ def sens_maps(imgs, mask_T, mask_R, dims, alpha: float, tol: float = 1e-10, max_
     s64 = torch.empty(G, L, dtype=torch.complex128, device=dev)
     shat = torch.empty(G, L, dtype=torch.complex128, device=dev)
     comp = torch.empty(3 * G, L, dtype=torch.float64, device=dev) if parts else None
-    ws, nb, keep = _map_workspace("sens", G, dims, dev)
+    ws, nb, keep = _map_workspace("sens", G, dims, precond, dev)
     info = (ctypes.c_int * 2)()
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     _check(lib().nfs_sens_maps(context(device), _ptr(X), G, ne, _ptr(mT), _ptr(mR), *_grid(dims), float(alpha),
-                               float(tol), int(max_iter), _ptr(s32), _ptr(s64), _ptr(shat), _ptr(comp), info, ws, nb,
-                               stream))
+                               float(tol), int(max_iter), PRECONDS[precond], _ptr(s32), _ptr(s64), _ptr(shat),
+                               _ptr(comp), info, ws, nb, stream))
     if parts:
         return s32, s64, shat, (info[0], info[1]), comp
     return s32, s64, shat, (info[0], info[1])
 
 
 def b0_map(imgs, sens, dims, delta_te: float, alpha: float, tol: float = 1e-10, max_iter: int = 100000,
-           device: int = 0):
+           device: int = 0, precond: str = "mg"):
     """B0 map (rad/s) from prescan images imgs [G][n_echo][L] and
     sensitivities sens [G][L] complex64.  Returns (B0 float32 [L], B0 float64
     [L], fit float64 [3][L] = (B0^, beta, eps), (iterations, status))."""
@@ -532,9 +534,10 @@ def b0_map(imgs, sens, dims, delta_te: float, alpha: float, tol: float = 1e-10, 
     b0 = torch.empty(L, dtype=torch.float32, device=dev)
     b064 = torch.empty(L, dtype=torch.float64, device=dev)
     fit = torch.empty(3, L, dtype=torch.float64, device=dev)
-    ws, nb, keep = _map_workspace("b0", G, dims, dev)
+    ws, nb, keep = _map_workspace("b0", G, dims, precond, dev)
     info = (ctypes.c_int * 2)()
     stream = ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)
     _check(lib().nfs_b0_map(context(device), _ptr(X), G, ne, _ptr(S), *_grid(dims), float(delta_te), float(alpha),
-                            float(tol), int(max_iter), _ptr(b0), _ptr(b064), _ptr(fit), info, ws, nb, stream))
+                            float(tol), int(max_iter), PRECONDS[precond], _ptr(b0), _ptr(b064), _ptr(fit), info, ws,
+                            nb, stream))
     return b0, b064, fit, (info[0], info[1])

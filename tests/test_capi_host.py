@@ -336,32 +336,38 @@ def _ctx():
 
 
 def _sens_maps(L, G=8, ne=6, dims=(20, 16, 1), alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40, out=A,
-               masks=A):
+               masks=A, precond=1):
     info = (ctypes.c_int * 2)()
-    return L.nfs_sens_maps(_ctx(), A, G, ne, masks, masks, *dims, alpha, tol, max_iter, out, None, None, None, info,
-                           A, ws_bytes, None)
+    return L.nfs_sens_maps(_ctx(), A, G, ne, masks, masks, *dims, alpha, tol, max_iter, precond, out, None, None,
+                           None, info, A, ws_bytes, None)
 
 
-def _b0_map(L, G=8, ne=6, dims=(20, 16, 1), dte=2.3e-3, alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40):
+def _b0_map(L, G=8, ne=6, dims=(20, 16, 1), dte=2.3e-3, alpha=1.0, tol=1e-8, max_iter=10, ws_bytes=1 << 40,
+            precond=1):
     info = (ctypes.c_int * 2)()
-    return L.nfs_b0_map(_ctx(), A, G, ne, A, *dims, dte, alpha, tol, max_iter, A, None, None, info, A, ws_bytes,
-                        None)
+    return L.nfs_b0_map(_ctx(), A, G, ne, A, *dims, dte, alpha, tol, max_iter, precond, A, None, None, info, A,
+                        ws_bytes, None)
 
 
 def test_map_workspace_sizes(L):
     sz = ctypes.c_size_t()
-    assert L.nfs_maps_workspace_bytes(0, 8, 20, 16, 1, ctypes.byref(sz)) == 0
+    assert L.nfs_maps_workspace_bytes(0, 8, 20, 16, 1, 0, ctypes.byref(sz)) == 0
     small = sz.value
-    assert L.nfs_maps_workspace_bytes(0, 8, 40, 16, 3, ctypes.byref(sz)) == 0
+    assert L.nfs_maps_workspace_bytes(0, 8, 40, 16, 3, 0, ctypes.byref(sz)) == 0
     assert sz.value > small
     # sensitivities: 3G float64 CG systems of 5 vectors each at least
     assert sz.value >= 3 * 8 * 40 * 16 * 3 * 8 * 5
-    assert L.nfs_maps_workspace_bytes(1, 8, 20, 16, 1, ctypes.byref(sz)) == 0
+    jac = sz.value
+    # multigrid: a sixth fine vector, a fine scratch vector and the coarse levels
+    assert L.nfs_maps_workspace_bytes(0, 8, 40, 16, 3, 1, ctypes.byref(sz)) == 0
+    assert sz.value >= jac + 2 * 3 * 8 * 40 * 16 * 3 * 8
+    assert L.nfs_maps_workspace_bytes(1, 8, 20, 16, 1, 0, ctypes.byref(sz)) == 0
     assert sz.value >= 20 * 16 * 8 * 8
-    assert L.nfs_maps_workspace_bytes(2, 8, 20, 16, 1, ctypes.byref(sz)) == nfs.NFS_EINVAL
-    assert L.nfs_maps_workspace_bytes(0, 17, 20, 16, 1, ctypes.byref(sz)) == nfs.NFS_ESHAPE
-    assert L.nfs_maps_workspace_bytes(1, 64, 20, 16, 1, ctypes.byref(sz)) == 0
-    assert L.nfs_maps_workspace_bytes(0, 8, 0, 16, 1, ctypes.byref(sz)) == nfs.NFS_ESHAPE
+    assert L.nfs_maps_workspace_bytes(2, 8, 20, 16, 1, 0, ctypes.byref(sz)) == nfs.NFS_EINVAL
+    assert L.nfs_maps_workspace_bytes(0, 8, 20, 16, 1, 2, ctypes.byref(sz)) == nfs.NFS_EINVAL
+    assert L.nfs_maps_workspace_bytes(0, 17, 20, 16, 1, 0, ctypes.byref(sz)) == nfs.NFS_ESHAPE
+    assert L.nfs_maps_workspace_bytes(1, 64, 20, 16, 1, 1, ctypes.byref(sz)) == 0
+    assert L.nfs_maps_workspace_bytes(0, 8, 0, 16, 1, 0, ctypes.byref(sz)) == nfs.NFS_ESHAPE
 
 
 def test_map_argument_checks(L):
@@ -373,6 +379,8 @@ def test_map_argument_checks(L):
     assert _sens_maps(L, alpha=math.inf) == nfs.NFS_EINVAL
     assert _sens_maps(L, tol=math.nan) == nfs.NFS_EINVAL
     assert _sens_maps(L, max_iter=-1) == nfs.NFS_EINVAL
+    assert _sens_maps(L, precond=2) == nfs.NFS_EINVAL
+    assert _b0_map(L, precond=-1) == nfs.NFS_EINVAL
     assert _sens_maps(L, out=None) == nfs.NFS_EINVAL
     assert _sens_maps(L, masks=None) == nfs.NFS_EINVAL
     assert _sens_maps(L, masks=A + 2) == nfs.NFS_EINVAL

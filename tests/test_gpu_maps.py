@@ -87,19 +87,23 @@ def test_initial_sensitivities_of_rank_one_data(nfs):
     check_initial(X, got)
 
 
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
 @pytest.mark.parametrize("dims,G,alpha", [((41, 35), 4, 10.0), ((20, 18, 9), 4, 3.0), ((33, 2), 2, 5.0),
-                                          ((19, 17), 3, 0.0)])
-def test_sensitivity_maps_match_oracle(nfs, dims, G, alpha):
+                                          ((19, 17), 3, 0.0), ((7, 6), 2, 4.0)])
+def test_sensitivity_maps_match_oracle(nfs, dims, G, alpha, precond):
     d = synth.prescan(dims=dims, n_coil=G, n_echo=6, seed=2)
     X = d["imgs"]
     mT, mR = d["mask_T"], d["mask_R"]
     if dims == (33, 2):  # a degenerate grid: no second differences along y
         mT = (np.arange(66) % 33 > 8).astype(np.float32) * (np.arange(66) % 33 < 25)
         mR = np.ones(66, dtype=np.float32)
-    s32, s64, shat, info = nfs.sens_maps(torch.from_numpy(X), mT, mR, dims, alpha, tol=1e-12, max_iter=50000)
+    s32, s64, shat, info = nfs.sens_maps(torch.from_numpy(X), mT, mR, dims, alpha, tol=1e-12, max_iter=50000,
+                                         precond=precond)
     want = M.smooth_sens(M.sens_initial(X), mT, mR, dims, alpha)
     e = rel(s64.cpu().numpy(), want)
-    print(f"S {dims} G={G} alpha={alpha}: CG iterations {info[0]} status {info[1]}, relative error {e:.2e}")
+    print(f"S {dims} G={G} alpha={alpha} {precond}: CG iterations {info[0]} status {info[1]}, relative error {e:.2e}")
+    if precond == "mg" and int(np.prod(dims)) <= 64:
+        assert info[0] <= 2  # one level: the preconditioner is the exact inverse
     assert info[1] in (2, 3)  # converged to tol, or exactly
     assert e < 1e-6
     assert np.array_equal(s32.cpu().numpy(), s64.cpu().numpy().astype(np.complex64))
@@ -116,14 +120,16 @@ def test_sensitivity_maps_without_penalty_keep_the_trusted_data(nfs):
     assert np.all(s64[:, ~inside] == 0)
 
 
+@pytest.mark.parametrize("precond", ["mg", "jacobi"])
 @pytest.mark.parametrize("dims,G,ne", [((41, 35), 4, 6), ((20, 18, 9), 8, 16), ((30, 3), 2, 3)])
-def test_b0_map_matches_oracle(nfs, dims, G, ne):
+def test_b0_map_matches_oracle(nfs, dims, G, ne, precond):
     d = synth.prescan(dims=dims, n_coil=G, n_echo=ne, seed=5)
     X, S = d["imgs"], d["S_true"]
     S = S.copy()
     S[:, 7] = 0  # a voxel without sensitivity
     alpha = 50.0
-    b0, b064, fit, info = nfs.b0_map(torch.from_numpy(X), torch.from_numpy(S), dims, d["delta_te"], alpha, tol=1e-12)
+    b0, b064, fit, info = nfs.b0_map(torch.from_numpy(X), torch.from_numpy(S), dims, d["delta_te"], alpha, tol=1e-12,
+                                     precond=precond)
     bh, bb, ee = M.b0_initial(X, S, d["delta_te"])
     fit = fit.cpu().numpy()
     scale = np.abs(bh).max()
@@ -135,7 +141,7 @@ def test_b0_map_matches_oracle(nfs, dims, G, ne):
     assert fit[0][7] == 0 and fit[2][7] == 0
     want = M.smooth_b0(bh, ee, dims, alpha)
     e = rel(b064.cpu().numpy(), want)
-    print(f"  smoothed: relative error {e:.2e}")
+    print(f"  smoothed ({precond}): relative error {e:.2e}")
     assert e < 1e-6
     assert np.array_equal(b0.cpu().numpy(), b064.cpu().numpy().astype(np.float32))
 
@@ -196,6 +202,8 @@ def test_maps_at_the_prescan_size(nfs):
     assert np.abs(got - want)[:, sep].max() < 1e-9
     A = M.smoothing_matrix(dims, d["mask_T"], d["mask_R"], 10.0, 2).tocsr()
     parts = parts.cpu().numpy()
+    empty = A.diagonal() == 0  # rows without entries: the solution is 0 there
+    assert empty.any() and np.all(parts[:, empty] == 0)
     sh = shat.cpu().numpy()
     mT = d["mask_T"].astype(np.float64)
     for c in (0, 7, G + 3, 2 * G + 11):  # magnitudes, real and imaginary parts
