@@ -1480,7 +1480,7 @@ MapLayout map_layout(int kind, int G, int nx, int ny, int nz, int precond) {
     m.fit = take((size_t)3 * Lp * 8);  // B0^, beta, eps
     m.w = take((size_t)Lp * 8);
   }
-  m.pcg = take(pcg_state_bytes(nrhs, L, mg));
+  m.pcg = take(pcg_state_bytes(nrhs, nx, ny, nz, mg));
   if (mg) m.mg = take(mg_bytes(nrhs, nx, ny, nz));
   m.total = off;
   return m;
@@ -1590,7 +1590,7 @@ extern "C" int nfs_sens_maps(nfs_ctx* ctx, const float* imgs, int n_coil, int n_
   if ((rc = check_map_ws(m, ws, ws_bytes, fn))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const bool mg = precond == NFS_PRECOND_MG;
-  const PcgState st = pcg_state(at<char>(ws, m.pcg), 3 * n_coil, L, mg);
+  const PcgState st = pcg_state(at<char>(ws, m.pcg), 3 * n_coil, nx, ny, nz, mg);
   double2* sh = shat ? reinterpret_cast<double2*>(shat) : at<double2>(ws, m.shat);
   double* b = at<double>(ws, m.b);
   double* t = at<double>(ws, m.t);
@@ -1630,7 +1630,7 @@ extern "C" int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_ech
   if ((rc = check_map_ws(m, ws, ws_bytes, fn))) return rc;
   hipStream_t s = (hipStream_t)stream;
   const bool mg = precond == NFS_PRECOND_MG;
-  const PcgState st = pcg_state(at<char>(ws, m.pcg), 1, L, mg);
+  const PcgState st = pcg_state(at<char>(ws, m.pcg), 1, nx, ny, nz, mg);
   double* f = at<double>(ws, m.fit);
   double *b0hat = f, *beta = f + st.Lp, *eps = f + 2 * st.Lp;
   double* w = at<double>(ws, m.w);

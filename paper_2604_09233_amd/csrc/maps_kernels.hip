@@ -213,12 +213,14 @@ __device__ __forceinline__ void coords(const Grid3& g, int64_t j, int c[3]) {
   c[2] = (int)(q / g.n[1]);
 }
 
-// Row j of A applied to a vector given by the accessor V (SENS: D2 penalty,
-// B0: D1 penalty); also the diagonal of A when V is the unit-vector probe.
+// Row j of A applied to a vector given by the accessor val(d, k) (its value
+// at offset k along axis d from voxel j; val(0, 0) at j itself).  SENS: D2
+// penalty, B0: D1 penalty.  Offsets are only asked for where they lie on
+// the grid.
 template <int OP, class V>
 __device__ __forceinline__ double apply_row(const Grid3& g, const double* __restrict__ t, const double* __restrict__ w,
-                                            double alpha, int64_t j, const int c[3], V val) {
-  const double v0 = val(j);
+                                            double alpha, int64_t j, const int c[3], V&& val) {
+  const double v0 = val(0, 0);
   double pen = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
@@ -226,19 +228,90 @@ __device__ __forceinline__ double apply_row(const Grid3& g, const double* __rest
     const int64_t s = g.s[d];
     if (OP == MAP_SENS) {
       if (n < 3) continue;
-      const double vm1 = cd >= 1 ? val(j - s) : 0.0;
-      const double vp1 = cd <= n - 2 ? val(j + s) : 0.0;
-      if (cd >= 2) pen += w[j - s] * (val(j - 2 * s) - 2.0 * vm1 + v0);
+      const double vm1 = cd >= 1 ? val(d, -1) : 0.0;
+      const double vp1 = cd <= n - 2 ? val(d, 1) : 0.0;
+      if (cd >= 2) pen += w[j - s] * (val(d, -2) - 2.0 * vm1 + v0);
       if (cd >= 1 && cd <= n - 2) pen -= 2.0 * w[j] * (vm1 - 2.0 * v0 + vp1);
-      if (cd <= n - 3) pen += w[j + s] * (v0 - 2.0 * vp1 + val(j + 2 * s));
+      if (cd <= n - 3) pen += w[j + s] * (v0 - 2.0 * vp1 + val(d, 2));
     } else {
       if (n < 2) continue;
-      if (cd >= 1) pen += w[j - s] * (v0 - val(j - s));
-      if (cd <= n - 2) pen -= w[j] * (val(j + s) - v0);
+      if (cd >= 1) pen += w[j - s] * (v0 - val(d, -1));
+      if (cd <= n - 2) pen -= w[j] * (val(d, 1) - v0);
     }
   }
   const double tj = OP == MAP_SENS ? t[j] : 1.0;
   return fma(alpha, pen, tj * v0);
+}
+
+// ---- z-marching tiles: a workgroup owns a kTileX x kTileY column of the
+// grid and walks it along z, holding planes z-2 .. z+2 of the vector it
+// reads (with a two-voxel halo in x and y) in an LDS ring, so that each
+// value is read from memory about (36 x 12) / (32 x 8) = 1.7 times instead
+// of once per stencil point.
+constexpr int kTileX = 32, kTileY = 8, kHalo = 2;
+constexpr int kPlaneX = kTileX + 2 * kHalo, kPlaneY = kTileY + 2 * kHalo, kPlane = kPlaneX * kPlaneY;
+constexpr int kRing = 2 * kHalo + 1;
+
+__host__ __device__ __forceinline__ int tile_count(const Grid3& g) {
+  return ((g.n[0] + kTileX - 1) / kTileX) * ((g.n[1] + kTileY - 1) / kTileY);
+}
+
+// load(i, interior, x, y, z): value of voxel i at (x, y, z) (interior: i
+// belongs to this tile);
+// row(j, c, val): the output of voxel j at coordinates c from the accessor.
+// The plane two ahead is fetched into registers while the current plane is
+// computed, so the loads of one plane overlap the arithmetic of the last.
+template <class Load, class Row>
+__device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], Load&& load, Row&& row) {
+  const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
+  const int ntx = (nx + kTileX - 1) / kTileX;
+  const int x0 = (int)(blockIdx.x % ntx) * kTileX, y0 = (int)(blockIdx.x / ntx) * kTileY;
+  // plane entries of this thread: e0 and e1 = e0 + 256 (kPlane < 512)
+  const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
+  const bool has1 = e1 < kPlane;
+  auto fetch = [&](int z, int e) -> double {
+    const int lx = e % kPlaneX, ly = e / kPlaneX;
+    const int gx = x0 - kHalo + lx, gy = y0 - kHalo + ly;
+    if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) return 0.0;
+    const bool interior = lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo && ly < kHalo + kTileY;
+    return load(gx + g.s[1] * gy + g.s[2] * z, interior, gx, gy, z);
+  };
+  const int lx = threadIdx.x % kTileX, ly = threadIdx.x / kTileX;
+  const int gx = x0 + lx, gy = y0 + ly;
+  const bool mine = gx < nx && gy < ny;
+  const int ctr = (ly + kHalo) * kPlaneX + lx + kHalo;
+  for (int z = 0; z < kHalo && z < nz; ++z) {
+    ring[z % kRing][e0] = fetch(z, e0);
+    if (has1) ring[z % kRing][e1] = fetch(z, e1);
+  }
+  double n0 = 0.0, n1 = 0.0;
+  if (kHalo < nz) {
+    n0 = fetch(kHalo, e0);
+    if (has1) n1 = fetch(kHalo, e1);
+  }
+  for (int z = 0; z < nz; ++z) {
+    if (z + kHalo < nz) {
+      ring[(z + kHalo) % kRing][e0] = n0;
+      if (has1) ring[(z + kHalo) % kRing][e1] = n1;
+    }
+    __syncthreads();
+    if (z + kHalo + 1 < nz) {
+      n0 = fetch(z + kHalo + 1, e0);
+      if (has1) n1 = fetch(z + kHalo + 1, e1);
+    }
+    if (mine) {
+      const int c[3] = {gx, gy, z};
+      const int64_t j = gx + g.s[1] * gy + g.s[2] * z;
+      const double* here = ring[z % kRing];
+      auto val = [&](int d, int k) -> double {
+        if (d == 0) return here[ctr + k];
+        if (d == 1) return here[ctr + k * kPlaneX];
+        return ring[(z + k + kRing) % kRing][ctr];
+      };
+      row(j, c, val);
+    }
+    __syncthreads();
+  }
 }
 
 template <int OP>
@@ -336,8 +409,8 @@ __global__ void __launch_bounds__(256) pcg_init_kernel(PcgState st, const double
   bb = block_total(bb, red);
   if (!MG) rz = block_total(rz, red);
   if (threadIdx.x == 0) {
-    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = bb;
-    if (!MG) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+    st.part1[(size_t)rhs * st.npart + blockIdx.x] = bb;
+    if (!MG) st.part0[(size_t)rhs * st.npart + blockIdx.x] = rz;
   }
 }
 
@@ -347,10 +420,8 @@ __device__ __forceinline__ double sum_parts(const double* part, int nblk, double
   return block_total(s, red);
 }
 
-// Multigrid form: z is cleared on the rows of A without entries (voxels the
-// system does not see, whose solution is 0; prolongation would otherwise
-// carry coarse corrections into them, where CG cannot remove them), which
-// keeps the preconditioner symmetric on the active rows; partials of r.z
+// Single-level multigrid (the explicit inverse alone): z cleared on the
+// rows of A without entries as in the last sweep below; partials of r.z
 // into part0.
 __global__ void __launch_bounds__(256) pcg_dot_kernel(PcgState st) {
   __shared__ double red[4];
@@ -368,14 +439,15 @@ __global__ void __launch_bounds__(256) pcg_dot_kernel(PcgState st) {
     rz = st.r[o + j] * zj;
   }
   rz = block_total(rz, red);
-  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
+  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.npart + blockIdx.x] = rz;
 }
 
-__global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st) {
+// n0: number of part0 partials (r.z from the vector or the stencil kernels)
+__global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st, int n0) {
   __shared__ double red[4];
   const int rhs = blockIdx.x;
-  const double rz = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
-  const double bb = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double rz = sum_parts(st.part0 + (size_t)rhs * st.npart, n0, red);
+  const double bb = sum_parts(st.part1 + (size_t)rhs * st.npart, st.nblk, red);
   if (threadIdx.x == 0) {
     st.bb[rhs] = bb;
     st.rr[rhs] = bb;
@@ -387,40 +459,45 @@ __global__ void __launch_bounds__(256) pcg_init_scalars_kernel(PcgState st) {
   }
 }
 
-// p_new = z + beta p_old (stored), q = A p_new; partial p_new.q.
+// p_new = z + beta p_old (stored), q = A p_new; partial p_new.q.  Grid
+// (tiles, right-hand sides).
 template <int OP, bool MG>
 __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, const double* __restrict__ t,
                                                         const double* __restrict__ w, double alpha, int pin) {
+  __shared__ double ring[kRing][kPlane];
   __shared__ double red[4];
   const int rhs = blockIdx.y;
   if (st.status[rhs]) return;  // uniform per workgroup
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
   const size_t o = (size_t)rhs * st.Lp;
   const double* r = st.r + o;
   const double* z = MG ? st.z + o : nullptr;
   const double* po = st.p[pin] + o;
+  double* pn = st.p[pin ^ 1] + o;
+  double* q = st.q + o;
   const double beta = st.beta[rhs];
   const double* dinv = st.dinv;
   double pq = 0.0;
-  if (j < st.L) {
-    int c[3];
-    coords(g, j, c);
-    auto val = [&](int64_t i) { return dir_at<MG>(dinv, r, z, po, beta, i); };
-    const double pj = val(j);
-    const double qj = apply_row<OP>(g, t, w, alpha, j, c, val);
-    st.p[pin ^ 1][o + j] = pj;
-    st.q[o + j] = qj;
-    pq = pj * qj;
-  }
+  march(
+      g, ring,
+      [&](int64_t i, bool interior, int, int, int) {
+        const double v = dir_at<MG>(dinv, r, z, po, beta, i);
+        if (interior) pn[i] = v;
+        return v;
+      },
+      [&](int64_t j, const int c[3], auto& val) {
+        const double qj = apply_row<OP>(g, t, w, alpha, j, c, val);
+        q[j] = qj;
+        pq += val(0, 0) * qj;
+      });
   pq = block_total(pq, red);
-  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = pq;
+  if (threadIdx.x == 0) st.part0[(size_t)rhs * st.npart + blockIdx.x] = pq;
 }
 
 __global__ void __launch_bounds__(256) pcg_alpha_kernel(PcgState st) {
   __shared__ double red[4];
   const int rhs = blockIdx.x;
   if (st.status[rhs]) return;
-  const double pq = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double pq = sum_parts(st.part0 + (size_t)rhs * st.npart, st.ntile, red);
   if (threadIdx.x == 0) {
     const double a = st.rz[rhs] / pq;
     if (!(pq > 0.0) || !isfinite(a)) {
@@ -454,17 +531,17 @@ __global__ void __launch_bounds__(256) pcg_update_kernel(PcgState st, int pnew) 
   if (!MG) rz = block_total(rz, red);
   rr = block_total(rr, red);
   if (threadIdx.x == 0) {
-    if (!MG) st.part0[(size_t)rhs * st.nblk + blockIdx.x] = rz;
-    st.part1[(size_t)rhs * st.nblk + blockIdx.x] = rr;
+    if (!MG) st.part0[(size_t)rhs * st.npart + blockIdx.x] = rz;
+    st.part1[(size_t)rhs * st.npart + blockIdx.x] = rr;
   }
 }
 
-__global__ void __launch_bounds__(256) pcg_beta_kernel(PcgState st, double tol2) {
+__global__ void __launch_bounds__(256) pcg_beta_kernel(PcgState st, double tol2, int n0) {
   __shared__ double red[4];
   const int rhs = blockIdx.x;
   if (st.status[rhs]) return;
-  const double rz = sum_parts(st.part0 + (size_t)rhs * st.nblk, st.nblk, red);
-  const double rr = sum_parts(st.part1 + (size_t)rhs * st.nblk, st.nblk, red);
+  const double rz = sum_parts(st.part0 + (size_t)rhs * st.npart, n0, red);
+  const double rr = sum_parts(st.part1 + (size_t)rhs * st.npart, st.nblk, red);
   if (threadIdx.x == 0) {
     st.iters[rhs] += 1;
     st.rr[rhs] = rr;
@@ -490,53 +567,83 @@ __global__ void __launch_bounds__(256) pcg_beta_kernel(PcgState st, double tol2)
 // number of sweeps before and after); the coarsest level (at most
 // kMgCoarseMax unknowns) is solved with its explicit inverse.
 
+// Coarse neighbours of fine coordinate i along an axis of fine length n and
+// coarse length nc (nc == n: axis not coarsened): indices n0, n1 with
+// weights w0, w1 (w1 = 0 and n1 = n0 where there is one).  Fixed size, so
+// that loops over them unroll into registers.
 struct AxisMap {
-  int n[2];
-  double wt[2];
-  int cnt;
+  int n0, n1;
+  double w0, w1;
 };
 
-// coarse neighbours of fine coordinate i along an axis of fine length n and
-// coarse length nc (nc == n: axis not coarsened)
 __device__ __forceinline__ AxisMap fine_to_coarse(int i, int n, int nc) {
   AxisMap m;
   if (nc == n) {
-    m.n[0] = i;
-    m.wt[0] = 1.0;
-    m.cnt = 1;
+    m.n0 = m.n1 = i;
+    m.w0 = 1.0;
+    m.w1 = 0.0;
   } else if ((i & 1) == 0) {
-    m.n[0] = i >> 1;
-    m.wt[0] = 1.0;
-    m.cnt = 1;
+    m.n0 = m.n1 = i >> 1;
+    m.w0 = 1.0;
+    m.w1 = 0.0;
   } else {
-    m.n[0] = i >> 1;
-    m.wt[0] = 0.5;
-    m.cnt = 1;
-    if ((i >> 1) + 1 < nc) {
-      m.n[1] = (i >> 1) + 1;
-      m.wt[1] = 0.5;
-      m.cnt = 2;
-    }
+    m.n0 = i >> 1;
+    m.w0 = 0.5;
+    const bool two = (i >> 1) + 1 < nc;
+    m.n1 = two ? (i >> 1) + 1 : m.n0;
+    m.w1 = two ? 0.5 : 0.0;
   }
   return m;
 }
 
-// fine neighbours of coarse coordinate I (fine length n, coarse length nc)
-__device__ __forceinline__ int coarse_to_fine(int I, int n, int nc, int* idx, double* wt) {
+// Fine neighbours of coarse coordinate I (fine length n, coarse length nc):
+// indices f[0..2] with weights wt[0..2] (0 where absent, the index then
+// clamped onto the axis: the last coarse point of an even axis lies one
+// past its end).
+struct FineMap {
+  int f[3];
+  double wt[3];
+};
+
+__device__ __forceinline__ FineMap coarse_to_fine(int I, int n, int nc) {
+  FineMap m;
   if (nc == n) {
-    idx[0] = I;
-    wt[0] = 1.0;
-    return 1;
+    m.f[0] = m.f[1] = m.f[2] = I;
+    m.wt[0] = m.wt[2] = 0.0;
+    m.wt[1] = 1.0;
+    return m;
   }
-  int k = 0;
+#pragma unroll
   for (int d = -1; d <= 1; ++d) {
     const int i = 2 * I + d;
-    if (i < 0 || i >= n) continue;
-    idx[k] = i;
-    wt[k] = d == 0 ? 1.0 : 0.5;
-    ++k;
+    const bool in = i >= 0 && i < n;
+    m.f[d + 1] = in ? i : (i < 0 ? 0 : n - 1);  // absent: any valid index, weight 0
+    m.wt[d + 1] = in ? (d == 0 ? 1.0 : 0.5) : 0.0;
   }
-  return k;
+  return m;
+}
+
+// sum over the coarse neighbours of fine voxel (xi, yi, zi) of weight x value
+__device__ __forceinline__ double interpolate(const double* __restrict__ cv, const Grid3& gf, const Grid3& gc, int xi,
+                                              int yi, int zi) {
+  const AxisMap mx = fine_to_coarse(xi, gf.n[0], gc.n[0]);
+  const AxisMap my = fine_to_coarse(yi, gf.n[1], gc.n[1]);
+  const AxisMap mz = fine_to_coarse(zi, gf.n[2], gc.n[2]);
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const int zc = a ? mz.n1 : mz.n0;
+    const double wz = a ? mz.w1 : mz.w0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b) {
+      const int yc = b ? my.n1 : my.n0;
+      const double wzy = wz * (b ? my.w1 : my.w0);
+      const double* line = cv + (int64_t)zc * gc.s[2] + (int64_t)yc * gc.s[1];
+      s += (wzy * mx.w0) * line[mx.n0];
+      s += (wzy * mx.w1) * line[mx.n1];
+    }
+  }
+  return s;
 }
 
 // interpolation-weighted averages of the fine weights on the coarse grid
@@ -548,15 +655,18 @@ __global__ void __launch_bounds__(256) mg_coarsen_kernel(Grid3 gf, Grid3 gc, int
   if (J >= Lc) return;
   int C[3];
   coords(gc, J, C);
-  int ix[3][3], n[3];
-  double wx[3][3];
-  for (int d = 0; d < 3; ++d) n[d] = coarse_to_fine(C[d], gf.n[d], gc.n[d], ix[d], wx[d]);
+  const FineMap mx = coarse_to_fine(C[0], gf.n[0], gc.n[0]);
+  const FineMap my = coarse_to_fine(C[1], gf.n[1], gc.n[1]);
+  const FineMap mz = coarse_to_fine(C[2], gf.n[2], gc.n[2]);
   double st = 0.0, sw = 0.0, s = 0.0;
-  for (int a = 0; a < n[2]; ++a)
-    for (int b = 0; b < n[1]; ++b)
-      for (int c = 0; c < n[0]; ++c) {
-        const double wgt = wx[2][a] * wx[1][b] * wx[0][c];
-        const int64_t i = ix[0][c] + gf.s[1] * ix[1][b] + gf.s[2] * ix[2][a];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b)
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const double wgt = mz.wt[a] * my.wt[b] * mx.wt[c];
+        const int64_t i = mx.f[c] + gf.s[1] * my.f[b] + gf.s[2] * mz.f[a];
         if (OP == MAP_SENS) st += wgt * tf[i];
         sw += wgt * wf[i];
         s += wgt;
@@ -565,80 +675,99 @@ __global__ void __launch_bounds__(256) mg_coarsen_kernel(Grid3 gf, Grid3 gc, int
   wc[J] = sw / s;
 }
 
-// x = omega D^-1 b (the first sweep from x = 0)
-__global__ void __launch_bounds__(256) mg_sweep0_kernel(const int* __restrict__ status, int64_t L, int64_t Lp,
-                                                        const double* __restrict__ dinv, double omega,
-                                                        const double* __restrict__ b, double* __restrict__ x) {
-  const int rhs = blockIdx.y;
-  if (status[rhs]) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= L) return;
-  const size_t o = (size_t)rhs * Lp;
-  x[o + j] = omega * (dinv[j] * b[o + j]);
-}
+// Grid (tiles, right-hand sides).  MODE
+//   MG_SWEEP:    y = x + omega D^-1 (b - A x), one damped Jacobi sweep;
+//   MG_RESIDUAL: y = b - A x;
+//   MG_PRE:      the two sweeps from x = 0: x0 = omega D^-1 b (formed while
+//                loading), y = x0 + omega D^-1 (b - A x0);
+//   MG_POST:     a sweep from x + P xc (the coarse correction added while
+//                loading; xc on the grid gc);
+//   MG_LAST:     a sweep whose result is cleared on the rows without entries
+//                (voxels the system does not see, whose solution is 0;
+//                prolongation would otherwise carry coarse corrections there,
+//                where CG cannot remove them; clearing keeps the
+//                preconditioner symmetric on the active rows), with the
+//                partial b.y per workgroup into part (the finest level:
+//                b = r, y = z).
+enum { MG_SWEEP = 0, MG_RESIDUAL = 1, MG_PRE = 2, MG_POST = 3, MG_LAST = 4 };
 
-// MODE 0: y = x + omega D^-1 (b - A x) (a Jacobi sweep); MODE 1: y = b - A x
 template <int OP, int MODE>
-__global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__ status, Grid3 g, int64_t L,
-                                                         int64_t Lp, const double* __restrict__ t,
-                                                         const double* __restrict__ w, double alpha,
-                                                         const double* __restrict__ dinv, double omega,
+__global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__ status, Grid3 g, int64_t Lp,
+                                                         const double* __restrict__ t, const double* __restrict__ w,
+                                                         double alpha, const double* __restrict__ dinv, double omega,
                                                          const double* __restrict__ b, const double* __restrict__ x,
-                                                         double* __restrict__ y) {
+                                                         double* __restrict__ y, Grid3 gc, int64_t Lpc,
+                                                         const double* __restrict__ xc, double* __restrict__ part,
+                                                         int npart) {
+  __shared__ double ring[kRing][kPlane];
+  __shared__ double red[4];
   const int rhs = blockIdx.y;
   if (status[rhs]) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= L) return;
   const size_t o = (size_t)rhs * Lp;
   const double* xv = x + o;
-  int c[3];
-  coords(g, j, c);
-  const double ax = apply_row<OP>(g, t, w, alpha, j, c, [&](int64_t i) { return xv[i]; });
-  const double res = b[o + j] - ax;
-  y[o + j] = MODE == 0 ? fma(omega, dinv[j] * res, xv[j]) : res;
+  const double* bv = b + o;
+  const double* cv = MODE == MG_POST ? xc + (size_t)rhs * Lpc : nullptr;
+  double* yv = y + o;
+  double dot = 0.0;
+  march(
+      g, ring,
+      [&](int64_t i, bool, int xi, int yi, int zi) -> double {
+        if (MODE == MG_PRE) return omega * (dinv[i] * bv[i]);
+        if (MODE != MG_POST) return xv[i];
+        return xv[i] + interpolate(cv, g, gc, xi, yi, zi);
+      },
+      [&](int64_t j, const int c[3], auto& val) {
+        const double res = bv[j] - apply_row<OP>(g, t, w, alpha, j, c, val);
+        if (MODE == MG_RESIDUAL) {
+          yv[j] = res;
+          return;
+        }
+        const double dj = dinv[j];
+        double yj = fma(omega, dj * res, val(0, 0));
+        if (MODE == MG_LAST) {
+          if (dj == 0.0) yj = 0.0;
+          dot += bv[j] * yj;
+        }
+        yv[j] = yj;
+      });
+  if (MODE == MG_LAST) {
+    dot = block_total(dot, red);
+    if (threadIdx.x == 0) part[(size_t)rhs * npart + blockIdx.x] = dot;
+  }
 }
 
-// bc = P^T r / fac
-__global__ void __launch_bounds__(256) mg_restrict_kernel(const int* __restrict__ status, Grid3 gf, Grid3 gc,
-                                                          int64_t Lc, int64_t Lpf, int64_t Lpc, double inv_fac,
-                                                          const double* __restrict__ r, double* __restrict__ bc) {
-  const int rhs = blockIdx.y;
+// Grid of the transfer kernels: (x chunks of 64, rows y + ny z strided by
+// gridDim.y, right-hand sides); one wave per workgroup, coordinates from the
+// block indices.
+constexpr int kRowChunk = 64;
+
+// bc = P^T r / fac on the coarse grid
+__global__ void __launch_bounds__(64) mg_restrict_kernel(const int* __restrict__ status, Grid3 gf, Grid3 gc,
+                                                         int64_t Lpf, int64_t Lpc, double inv_fac,
+                                                         const double* __restrict__ r, double* __restrict__ bc) {
+  const int rhs = blockIdx.z;
   if (status[rhs]) return;
-  const int64_t J = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (J >= Lc) return;
-  int C[3];
-  coords(gc, J, C);
-  int ix[3][3], n[3];
-  double wx[3][3];
-  for (int d = 0; d < 3; ++d) n[d] = coarse_to_fine(C[d], gf.n[d], gc.n[d], ix[d], wx[d]);
+  const int X = blockIdx.x * kRowChunk + threadIdx.x;
+  if (X >= gc.n[0]) return;
+  const FineMap mx = coarse_to_fine(X, gf.n[0], gc.n[0]);
   const double* rv = r + (size_t)rhs * Lpf;
-  double s = 0.0;
-  for (int a = 0; a < n[2]; ++a)
-    for (int b = 0; b < n[1]; ++b)
-      for (int c = 0; c < n[0]; ++c)
-        s += (wx[2][a] * wx[1][b] * wx[0][c]) * rv[ix[0][c] + gf.s[1] * ix[1][b] + gf.s[2] * ix[2][a]];
-  bc[(size_t)rhs * Lpc + J] = s * inv_fac;
-}
-
-// x += P xc
-__global__ void __launch_bounds__(256) mg_prolong_kernel(const int* __restrict__ status, Grid3 gf, Grid3 gc,
-                                                         int64_t Lf, int64_t Lpf, int64_t Lpc,
-                                                         const double* __restrict__ xc, double* __restrict__ x) {
-  const int rhs = blockIdx.y;
-  if (status[rhs]) return;
-  const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (j >= Lf) return;
-  int c[3];
-  coords(gf, j, c);
-  AxisMap m[3];
-  for (int d = 0; d < 3; ++d) m[d] = fine_to_coarse(c[d], gf.n[d], gc.n[d]);
-  const double* cv = xc + (size_t)rhs * Lpc;
-  double s = 0.0;
-  for (int a = 0; a < m[2].cnt; ++a)
-    for (int b = 0; b < m[1].cnt; ++b)
-      for (int e = 0; e < m[0].cnt; ++e)
-        s += (m[2].wt[a] * m[1].wt[b] * m[0].wt[e]) * cv[m[0].n[e] + gc.s[1] * m[1].n[b] + gc.s[2] * m[2].n[a]];
-  x[(size_t)rhs * Lpf + j] += s;
+  double* bv = bc + (size_t)rhs * Lpc;
+  for (int row = blockIdx.y; row < gc.n[1] * gc.n[2]; row += gridDim.y) {
+    const int Y = row % gc.n[1], Z = row / gc.n[1];
+    const FineMap my = coarse_to_fine(Y, gf.n[1], gc.n[1]);
+    const FineMap mz = coarse_to_fine(Z, gf.n[2], gc.n[2]);
+    double s = 0.0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b) {
+        const double* line = rv + (int64_t)mz.f[a] * gf.s[2] + (int64_t)my.f[b] * gf.s[1];
+        const double wzy = mz.wt[a] * my.wt[b];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) s += (wzy * mx.wt[c]) * line[mx.f[c]];
+      }
+    bv[X + (int64_t)Y * gc.s[1] + (int64_t)Z * gc.s[2]] = s * inv_fac;
+  }
 }
 
 // Explicit inverse of the coarsest operator (n <= kMgCoarseMax unknowns; a
@@ -654,7 +783,7 @@ __global__ void __launch_bounds__(256) mg_coarsest_kernel(Grid3 g, int n, const 
     const int i = e / n, jj = e % n;
     int c[3];
     coords(g, i, c);
-    M[i][jj] = apply_row<OP>(g, t, w, alpha, i, c, [&](int64_t k) { return k == jj ? 1.0 : 0.0; });
+    M[i][jj] = apply_row<OP>(g, t, w, alpha, i, c, [&](int d, int k) { return i + k * g.s[d] == jj ? 1.0 : 0.0; });
     M[i][n + jj] = i == jj ? 1.0 : 0.0;
   }
   __syncthreads();
@@ -816,11 +945,17 @@ Grid3 make_grid(int nx, int ny, int nz) {
 
 unsigned cdiv_u(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
+dim3 row_grid(const Grid3& g, int nrhs) {
+  const int64_t rows = (int64_t)g.n[1] * g.n[2];
+  return dim3(cdiv_u(g.n[0], kRowChunk), (unsigned)std::min<int64_t>(rows, 65535), nrhs);
+}
+
 }  // namespace
 
-size_t pcg_state_bytes(int nrhs, int64_t L, bool with_z) {
+size_t pcg_state_bytes(int nrhs, int nx, int ny, int nz, bool with_z) {
+  const int64_t L = (int64_t)nx * ny * nz;
   const int64_t Lp = (L + 63) & ~(int64_t)63;
-  const int64_t nblk = (L + 255) / 256;
+  const int64_t nblk = std::max<int64_t>((L + 255) / 256, tile_count(make_grid(nx, ny, nz)));
   size_t b = 0;
   auto add = [&](size_t n) { b += (n + 255) & ~(size_t)255; };
   for (int i = 0; i < (with_z ? 6 : 5); ++i) add((size_t)nrhs * Lp * 8);  // x r p0 p1 q (z)
@@ -831,11 +966,14 @@ size_t pcg_state_bytes(int nrhs, int64_t L, bool with_z) {
   return b;
 }
 
-PcgState pcg_state(void* base, int nrhs, int64_t L, bool with_z) {
+PcgState pcg_state(void* base, int nrhs, int nx, int ny, int nz, bool with_z) {
   PcgState st;
+  const int64_t L = (int64_t)nx * ny * nz;
   st.L = L;
   st.Lp = (L + 63) & ~(int64_t)63;
   st.nblk = (int)((L + 255) / 256);
+  st.ntile = tile_count(make_grid(nx, ny, nz));
+  st.npart = std::max(st.nblk, st.ntile);
   st.nrhs = nrhs;
   char* p = static_cast<char*>(base);
   auto take = [&](size_t n) {
@@ -851,8 +989,8 @@ PcgState pcg_state(void* base, int nrhs, int64_t L, bool with_z) {
   st.q = (double*)take(vec);
   st.z = with_z ? (double*)take(vec) : nullptr;
   st.dinv = (double*)take((size_t)st.Lp * 8);
-  st.part0 = (double*)take((size_t)nrhs * st.nblk * 8);
-  st.part1 = (double*)take((size_t)nrhs * st.nblk * 8);
+  st.part0 = (double*)take((size_t)nrhs * st.npart * 8);
+  st.part1 = (double*)take((size_t)nrhs * st.npart * 8);
   st.rz = (double*)take((size_t)nrhs * 8);
   st.alpha = (double*)take((size_t)nrhs * 8);
   st.beta = (double*)take((size_t)nrhs * 8);
@@ -968,27 +1106,27 @@ hipError_t mg_setup(MgHierarchy& h, const PcgState& st, const double* t, const d
   return hipGetLastError();
 }
 
-// z = M^-1 r (one V-cycle for every running right-hand side).
+// z = M^-1 r (one V-cycle for every running right-hand side): per level the
+// two pre-sweeps in one pass, the residual, its restriction; the coarsest
+// solve; per level the prolongation inside the first post-sweep and the
+// second post-sweep (on the finest level also clearing the rows without
+// entries and forming r.z).  Every level ends in x[0] (st.z on the finest).
+static_assert(kMgSweeps == 2, "the fused passes are two sweeps before and after");
 template <int OP>
 hipError_t mg_vcycle(const MgHierarchy& h, const PcgState& st, hipStream_t s) {
   const int nr = st.nrhs;
-  int cur[kMgMaxLevels];
   for (int l = 0; l + 1 < h.nlev; ++l) {
     const MgLevel& v = h.lev[l];
-    const dim3 grid(cdiv_u(v.L, 256), nr);
-    hipLaunchKernelGGL(mg_sweep0_kernel, grid, dim3(256), 0, s, st.status, v.L, v.Lp, v.dinv, kMgOmega, v.b, v.x[1]);
-    int c = 1;
-    for (int k = 1; k < kMgSweeps; ++k, c ^= 1)
-      hipLaunchKernelGGL((mg_stencil_kernel<OP, 0>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
-                         v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
-    cur[l] = c;
-    hipLaunchKernelGGL((mg_stencil_kernel<OP, 1>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
-                       v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
     const MgLevel& n = h.lev[l + 1];
+    const dim3 tg(tile_count(v.g), nr);
+    hipLaunchKernelGGL((mg_stencil_kernel<OP, MG_PRE>), tg, dim3(256), 0, s, st.status, v.g, v.Lp, v.t, v.w, v.alpha,
+                       v.dinv, kMgOmega, v.b, v.x[0], v.x[0], n.g, n.Lp, nullptr, nullptr, 0);
+    hipLaunchKernelGGL((mg_stencil_kernel<OP, MG_RESIDUAL>), tg, dim3(256), 0, s, st.status, v.g, v.Lp, v.t, v.w,
+                       v.alpha, v.dinv, kMgOmega, v.b, v.x[0], v.x[1], n.g, n.Lp, nullptr, nullptr, 0);
     double fac = 1.0;
     for (int d = 0; d < 3; ++d) fac *= n.g.n[d] != v.g.n[d] ? 2.0 : 1.0;
-    hipLaunchKernelGGL(mg_restrict_kernel, dim3(cdiv_u(n.L, 256), nr), dim3(256), 0, s, st.status, v.g, n.g, n.L,
-                       v.Lp, n.Lp, 1.0 / fac, v.x[c ^ 1], const_cast<double*>(n.b));
+    hipLaunchKernelGGL(mg_restrict_kernel, row_grid(n.g, nr), dim3(kRowChunk), 0, s, st.status, v.g, n.g, v.Lp, n.Lp,
+                       1.0 / fac, v.x[1], const_cast<double*>(n.b));
   }
   const MgLevel& z = h.lev[h.nlev - 1];
   hipLaunchKernelGGL(mg_coarse_solve_kernel, dim3(nr), dim3(64), 0, s, st.status, (int)z.L, z.Lp, h.ainv, z.b,
@@ -996,13 +1134,15 @@ hipError_t mg_vcycle(const MgHierarchy& h, const PcgState& st, hipStream_t s) {
   for (int l = h.nlev - 2; l >= 0; --l) {
     const MgLevel& v = h.lev[l];
     const MgLevel& n = h.lev[l + 1];
-    const dim3 grid(cdiv_u(v.L, 256), nr);
-    int c = cur[l];
-    hipLaunchKernelGGL(mg_prolong_kernel, grid, dim3(256), 0, s, st.status, v.g, n.g, v.L, v.Lp, n.Lp, n.x[0], v.x[c]);
-    for (int k = 0; k < kMgSweeps; ++k, c ^= 1)
-      hipLaunchKernelGGL((mg_stencil_kernel<OP, 0>), grid, dim3(256), 0, s, st.status, v.g, v.L, v.Lp, v.t, v.w,
-                         v.alpha, v.dinv, kMgOmega, v.b, v.x[c], v.x[c ^ 1]);
-    // 1 + (kMgSweeps - 1) + kMgSweeps buffer changes end every level in x[0]
+    const dim3 tg(tile_count(v.g), nr);
+    hipLaunchKernelGGL((mg_stencil_kernel<OP, MG_POST>), tg, dim3(256), 0, s, st.status, v.g, v.Lp, v.t, v.w, v.alpha,
+                       v.dinv, kMgOmega, v.b, v.x[0], v.x[1], n.g, n.Lp, n.x[0], nullptr, 0);
+    if (l > 0)
+      hipLaunchKernelGGL((mg_stencil_kernel<OP, MG_SWEEP>), tg, dim3(256), 0, s, st.status, v.g, v.Lp, v.t, v.w,
+                         v.alpha, v.dinv, kMgOmega, v.b, v.x[1], v.x[0], n.g, n.Lp, nullptr, nullptr, 0);
+    else
+      hipLaunchKernelGGL((mg_stencil_kernel<OP, MG_LAST>), tg, dim3(256), 0, s, st.status, v.g, v.Lp, v.t, v.w,
+                         v.alpha, v.dinv, kMgOmega, v.b, v.x[1], v.x[0], n.g, n.Lp, nullptr, st.part0, st.npart);
   }
   return hipGetLastError();
 }
@@ -1013,7 +1153,7 @@ hipError_t pcg_run(int precond, const PcgState& st, void* mg_ws, const double* b
                    hipStream_t s) {
   const bool mg = precond == NFS_PRECOND_MG;
   const Grid3 g = make_grid(nx, ny, nz);
-  const dim3 grid(st.nblk, st.nrhs);
+  const dim3 grid(st.nblk, st.nrhs), tgrid(st.ntile, st.nrhs);
   MgHierarchy h;
   hipError_t e;
   if (mg) {
@@ -1022,11 +1162,13 @@ hipError_t pcg_run(int precond, const PcgState& st, void* mg_ws, const double* b
     if ((e = mg_setup<OP>(h, st, t, w, alpha, s)) != hipSuccess) return e;
     hipLaunchKernelGGL(pcg_init_kernel<true>, grid, dim3(256), 0, s, st, b);
     if ((e = mg_vcycle<OP>(h, st, s)) != hipSuccess) return e;
-    hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
+    if (h.nlev == 1) hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
   } else {
     hipLaunchKernelGGL(pcg_init_kernel<false>, grid, dim3(256), 0, s, st, b);
   }
-  hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
+  // part0 holds r.z from the vector kernels (nblk) or the last sweep (ntile)
+  const int n0 = mg && h.nlev > 1 ? st.ntile : st.nblk;
+  hipLaunchKernelGGL(pcg_init_scalars_kernel, dim3(st.nrhs), dim3(256), 0, s, st, n0);
   if ((e = hipGetLastError()) != hipSuccess) return e;
   const double tol2 = tol * tol;
   int it = 0;
@@ -1041,17 +1183,17 @@ hipError_t pcg_run(int precond, const PcgState& st, void* mg_ws, const double* b
     for (int k = 0; k < n; ++k, ++it) {
       const int pin = it & 1;
       if (mg) {
-        hipLaunchKernelGGL((pcg_apply_kernel<OP, true>), grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+        hipLaunchKernelGGL((pcg_apply_kernel<OP, true>), tgrid, dim3(256), 0, s, st, g, t, w, alpha, pin);
         hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
         hipLaunchKernelGGL(pcg_update_kernel<true>, grid, dim3(256), 0, s, st, pin ^ 1);
         if ((e = mg_vcycle<OP>(h, st, s)) != hipSuccess) return e;
-        hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
+        if (h.nlev == 1) hipLaunchKernelGGL(pcg_dot_kernel, grid, dim3(256), 0, s, st);
       } else {
-        hipLaunchKernelGGL((pcg_apply_kernel<OP, false>), grid, dim3(256), 0, s, st, g, t, w, alpha, pin);
+        hipLaunchKernelGGL((pcg_apply_kernel<OP, false>), tgrid, dim3(256), 0, s, st, g, t, w, alpha, pin);
         hipLaunchKernelGGL(pcg_alpha_kernel, dim3(st.nrhs), dim3(256), 0, s, st);
         hipLaunchKernelGGL(pcg_update_kernel<false>, grid, dim3(256), 0, s, st, pin ^ 1);
       }
-      hipLaunchKernelGGL(pcg_beta_kernel, dim3(st.nrhs), dim3(256), 0, s, st, tol2);
+      hipLaunchKernelGGL(pcg_beta_kernel, dim3(st.nrhs), dim3(256), 0, s, st, tol2, n0);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
   }

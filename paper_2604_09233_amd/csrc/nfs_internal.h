@@ -218,10 +218,13 @@ struct PcgState {
   int* iters;     // [nrhs] iterations run
   int* status;    // [nrhs] 0 running, else PCG_*
   int64_t L, Lp;
-  int nblk, nrhs;
+  int nblk;   // workgroups of the vector kernels (256 voxels each)
+  int ntile;  // workgroups of the stencil kernels (z-marching tiles)
+  int npart;  // stride of part0 / part1: max(nblk, ntile)
+  int nrhs;
 };
-size_t pcg_state_bytes(int nrhs, int64_t L, bool with_z);
-PcgState pcg_state(void* base, int nrhs, int64_t L, bool with_z);
+size_t pcg_state_bytes(int nrhs, int nx, int ny, int nz, bool with_z);
+PcgState pcg_state(void* base, int nrhs, int nx, int ny, int nz, bool with_z);
 // workspace of the multigrid hierarchy for nrhs right-hand sides on an nx x ny x nz grid
 size_t mg_bytes(int nrhs, int nx, int ny, int nz);
 // Solve the MAP_SENS / MAP_B0 normal equations for st.nrhs right-hand sides b
