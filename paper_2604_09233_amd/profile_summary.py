@@ -59,7 +59,7 @@ def summarize(path, title, command, note=""):
            "Per-kernel statistics from rocprofv3 (`--kernel-trace --stats`), durations in microseconds.", "",
            "| kernel | calls | total us | average us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in rows:
-        name = r["Name"].split("(")[0].replace("void ", "")
+        name = _short(r["Name"])
         out.append(f"| `{name}` | {r['Calls']} | {float(r['TotalDurationNs']) / 1e3:.1f} | "
                    f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                    f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
@@ -69,6 +69,9 @@ def summarize(path, title, command, note=""):
 
 
 def _short(name):
+    """Kernel name without its parameter list ('(anonymous namespace)::'
+    dropped first, so that it is not taken for the parameter list)."""
+    name = name.replace("(anonymous namespace)::", "")
     return name.split("(")[0].replace("void ", "").strip()
 
 
