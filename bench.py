@@ -45,6 +45,12 @@ N_CU, SIMD_PER_CU, TRANS_LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 8, 2.4
 TRANS_PEAK = N_CU * SIMD_PER_CU * TRANS_LANES_PER_SIMD * CLOCK_GHZ * 1e9
 
 
+def progress(msg):
+    """One line on stderr as each measurement leg starts (the JSON result is
+    the only stdout line)."""
+    print(f"bench: {msg}", file=sys.stderr, flush=True)
+
+
 def parse():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -166,20 +172,33 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
     if not args.no_tune:
         nfs.autotune_batched(probs, "bf16")
     work = sum((n_iter + 0.5) * d["L"] * d["K"] * d["n_coil"] for d in sl)
-    nfs.set_graphs(0, True)
-    outs, hists, infos = nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True)
-    torch.cuda.synchronize()
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    for _ in range(steps):
-        nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True, outs=outs, hists=hists, infos=infos)
-    ev1.record()
-    torch.cuda.synchronize()
-    nfs.set_graphs(0, False)
-    t = ev0.elapsed_time(ev1) / steps
+
+    def timed(mode):
+        nfs.set_batch_mode(0, mode)
+        nfs.set_graphs(0, True)
+        outs, hists, infos = nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True)
+        torch.cuda.synchronize()
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        for _ in range(steps):
+            nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True, outs=outs, hists=hists,
+                                 infos=infos)
+        ev1.record()
+        torch.cuda.synchronize()
+        nfs.set_graphs(0, False)
+        return ev0.elapsed_time(ev1) / steps, outs
+
+    t_p, out_p = timed("persistent")
+    t, out_s = timed("streams")
+    same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
     return dict(workload="24 slices, 2D 96..160 square, 8..32 coils, 8000..30000 samples, 16 terms, per-slice B0, "
-                         "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch",
+                         "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch (slices' solves "
+                         "forked over 8 streams)",
                 ms_per_batch=t, value=work / (t * 1e-3), unit="voxel*sample*coil/s",
+                persistent_form=dict(ms_per_batch=t_p, value=work / (t_p * 1e-3),
+                                     form="lock-step; per iteration one persistent E and one persistent E^H launch "
+                                          "per coil class over all slices"),
+                persistent_equals_streams=same,
                 pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps, tuned=not args.no_tune)
 
 
@@ -222,10 +241,11 @@ def maps_run(nfs, synth, torch, dev):
     nrhs = 3 * MAP_COILS
     # algorithmic bytes per iteration and right-hand side.  Jacobi: apply
     # (r, p in; p, q out) + update (x, p, r, q in; x, r out) = 80 B per voxel.
-    # Multigrid: apply (z, p in; p, q out) + update + r.z = 96 B per fine
-    # voxel, and per voxel of every level above the coarsest the V-cycle's
-    # stencil passes: first sweep 16, second sweep 24, residual 24, restriction
-    # 8, prolongation 16, two sweeps 48 = 136 B.
+    # Multigrid: apply (z, p in; p, q out) + update = 80 B per fine voxel, and
+    # per voxel of every level above the coarsest the V-cycle's passes: the
+    # two pre-sweeps (b in, x out) 16, residual (x, b in; r out) 24,
+    # restriction 8, post-sweep with prolongation (x, b in; x out) 24, last
+    # sweep (x, b in; x out; r.z on the finest level) 24 = 96 B.
     lv = [L]
     dd = list(dims)
     while lv[-1] > 64:
@@ -235,7 +255,7 @@ def maps_run(nfs, synth, torch, dev):
         dd = c
         lv.append(int(np.prod(dd)))
     bytes_jac = nrhs * L * 80
-    bytes_mg = nrhs * (96 * L + 136 * sum(lv[:-1]))
+    bytes_mg = nrhs * (80 * L + 96 * sum(lv[:-1]))
     ms_jac = per_iteration("jacobi", 128)
     ms_mg = per_iteration("mg", 16)
 
@@ -300,6 +320,7 @@ def main():
     m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
     torch.cuda.synchronize()
 
+    progress("autotune and the c2 solve")
     tuned = {}
     if not args.no_tune:
         for prec in {args.precision, "fp32", "bf16"}:
@@ -471,6 +492,7 @@ def main():
                         lcurve_corner_iteration=corner, cg_info=i_long.cpu().tolist())
         del its
 
+    progress("operand forms, stopping study, k-space filter")
     # the paper's k-space filter on the reconstruction: bins inside the hull
     # of the first-order k positions (linear x, y terms; kcoef / pi in
     # cycles per FOV for the normalised coordinates), IFFT(FFT(rho) o f)
@@ -491,8 +513,11 @@ def main():
         kf = dict(bins_inside=int(f.sum()), bins=int(f.size), ms_apply=e0.elapsed_time(e1),
                   ssim_vs_phantom_before=s_before, ssim_vs_phantom_after=s_after)
 
+    progress("batched leg")
     batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
+    progress("3D leg")
     threed = None if args.no_3d else threed_run(nfs, synth, torch, dev, args)
+    progress("maps leg")
     maps = None if args.no_maps else maps_run(nfs, synth, torch, dev)
 
     st = info.cpu().tolist()
@@ -532,6 +557,7 @@ def main():
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
+        progress("CPU oracle baseline")
         out["cpu_baseline"] = cpu_baseline(d)
     print(json.dumps(out))
 

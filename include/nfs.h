@@ -256,6 +256,23 @@ int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, c
  * is on.  Graphs live until nfs_destroy.  Default off.                    */
 int nfs_set_graphs(nfs_ctx* ctx, int on);
 
+/* How nfs_cg_solve_batched runs the slices (default NFS_BATCH_STREAMS).
+ *  NFS_BATCH_STREAMS: each slice runs its own complete solve; slices are
+ *      spread over 8 library streams (longest first) and joined, so the
+ *      slices' kernels overlap freely.
+ *  NFS_BATCH_PERSISTENT: all slices step through CG in lock-step; per
+ *      iteration the E and the E^H contractions of every slice are one
+ *      persistent launch per shape class (column blocks, held tiles),
+ *      whose fixed grid walks a work list of all its slices' tile blocks
+ *      (slices of different L and K in the same launch; the classes run
+ *      side by side on the library streams); the per-slice packing and CG
+ *      vector kernels between them are forked over the streams.  Used when
+ *      every slice has FP16 or BF16 operands, at most 20 field terms and
+ *      at most 32 coils; otherwise the call runs as NFS_BATCH_STREAMS.
+ * Either way each slice's result is bit-identical to its nfs_cg_solve.     */
+enum nfs_batch_mode { NFS_BATCH_STREAMS = 0, NFS_BATCH_PERSISTENT = 1 };
+int nfs_set_batch_mode(nfs_ctx* ctx, int mode);
+
 /* Tile-shape autotuning of the fused encode kernel (the kernel that builds
  * the phase tiles of the signal model, takes their sine/cosine and applies
  * them, for E and for E^H).  For this problem's shape class (L, K, G, P and

@@ -21,6 +21,7 @@ struct nfs_ctx {
   int n_cu;
   bool profiling = false;
   bool graphs = false;
+  int batch_mode = NFS_BATCH_STREAMS;
   std::unordered_map<std::string, hipGraphExec_t> graph_cache;
   std::vector<hipStream_t> bstreams;  // batched solves: forked streams (default priority)
   std::vector<hipEvent_t> bevents;    // ... and their join events
@@ -382,15 +383,47 @@ static float* unscale_slot(const Ctx& c, int which) {
   return scaled_prec(c.y.prec) ? at<float>(c.ws, c.y.o_unscale) + which : nullptr;
 }
 
-// E part: rho -> epart (partials) via packed Q = S o rho (o wgt);
-// bmax_ready: the FP16 scale bound of Q is already in bmax
-static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr, bool bmax_ready = false) {
+// The E operand: packed Q = S o rho (o wgt); bmax_ready: the FP16 scale
+// bound of Q is already in bmax
+static int pre_E(const Ctx& c, const float2* rho, bool bmax_ready, const float* wgt = nullptr) {
   const Layout& y = c.y;
   float* bmax = at<float>(c.ws, y.o_bmax);
   if (scaled_prec(y.prec) && !bmax_ready) NFS_TRY(launch_absmax(rho, c.sens, wgt, y.L, 1, 0, y.G, bmax, c.stop, c.s), "absmax(Q)");
   NFS_TRY(launch_pack_data(OP_E, y.prec, rho, c.sens, wgt, y.L, 1, 0, y.G, y.NB, y.LC, at<void>(c.ws, y.o_dataE),
                            bmax, at<float>(c.ws, y.o_unscale), c.stop, c.s),
           "pack_data(E)");
+  return NFS_OK;
+}
+
+// The E^H operand from src (m [G][K]) (o wgt)
+static int pre_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr) {
+  const Layout& y = c.y;
+  float* bmax = at<float>(c.ws, y.o_bmax);
+  if (scaled_prec(y.prec))
+    NFS_TRY(launch_absmax(src, nullptr, wgt, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
+  NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, wgt, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
+                           bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
+          "pack_data(EH)");
+  return NFS_OK;
+}
+
+// The E^H operand of E^H E, packed straight from the E partials
+// (optionally weighted per sample: E^H diag(wgt * wmul) E)
+static int mid_EHE(const Ctx& c, const float* wgt = nullptr, float wmul = 1.f) {
+  const Layout& y = c.y;
+  float* us = at<float>(c.ws, y.o_unscale);
+  NFS_TRY(launch_pack_EH_from_epart(y.prec, at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L,
+                                    wgt, wmul, us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
+          "pack_EH_from_epart");
+  return NFS_OK;
+}
+
+// E part: rho -> epart (partials) via packed Q = S o rho (o wgt);
+// bmax_ready: the FP16 scale bound of Q is already in bmax
+static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr, bool bmax_ready = false) {
+  const Layout& y = c.y;
+  int rc = pre_E(c, rho, bmax_ready, wgt);
+  if (rc) return rc;
   return timed_encode(c, 0, [&] {
     if (c.PE)
       return launch_resident(y.shE, c.PE, at<void>(c.ws, y.o_dataE), at<float>(c.ws, y.o_epart), c.sens, y.L, y.G,
@@ -404,12 +437,8 @@ static int seq_E(const Ctx& c, const float2* rho, const float* wgt = nullptr, bo
 // E^H part: src (m [G][K]) (o wgt) -> hpart (coil-combined partials)
 static int seq_EH(const Ctx& c, const float2* src, int64_t is, int64_t cs, const float* wgt = nullptr) {
   const Layout& y = c.y;
-  float* bmax = at<float>(c.ws, y.o_bmax);
-  if (scaled_prec(y.prec))
-    NFS_TRY(launch_absmax(src, nullptr, wgt, y.K, is, cs, y.G, bmax, c.stop, c.s), "absmax(m)");
-  NFS_TRY(launch_pack_data(OP_EH, y.prec, src, nullptr, wgt, y.K, is, cs, y.G, y.NB, y.KC, at<void>(c.ws, y.o_dataH),
-                           bmax, at<float>(c.ws, y.o_unscale) + 1, c.stop, c.s),
-          "pack_data(EH)");
+  int rc = pre_EH(c, src, is, cs, wgt);
+  if (rc) return rc;
   return timed_encode(c, 1, [&] {
     if (c.PH)
       return launch_resident(y.shH, c.PH, at<void>(c.ws, y.o_dataH), at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G,
@@ -427,10 +456,7 @@ static int seq_EHE(const Ctx& c, const float2* p, bool bmax_ready = false, const
   const Layout& y = c.y;
   int rc = seq_E(c, p, nullptr, bmax_ready);
   if (rc) return rc;
-  float* us = at<float>(c.ws, y.o_unscale);
-  NFS_TRY(launch_pack_EH_from_epart(y.prec, at<float>(c.ws, y.o_epart), y.shE.nsplit, y.KC * 16, y.NB, y.K, y.G, y.L,
-                                    wgt, wmul, us, us + 1, y.KC, at<void>(c.ws, y.o_dataH), c.stop, c.s),
-          "pack_EH_from_epart");
+  if ((rc = mid_EHE(c, wgt, wmul))) return rc;
   return timed_encode(c, 1, [&] {
     if (c.PH)
       return launch_resident(y.shH, c.PH, at<void>(c.ws, y.o_dataH), at<float>(c.ws, y.o_hpart), c.sens, y.L, y.G,
@@ -1008,6 +1034,256 @@ extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, con
   return NFS_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Lock-step batched CG: every slice runs the nfs_cg_solve sequence, but the
+// E and E^H contractions of all slices go into one persistent encode launch
+// each (launch_encode_persistent), between which the per-slice packing and
+// CG vector kernels are forked over the library streams and joined.
+struct SliceRun {
+  const nfs_problem* pr;
+  const Layout* y;
+  void* ws;
+  CgState st;
+  const float2* sens;
+  float2* x;
+  const float* m;
+  double* hist;
+  int* info;
+};
+
+static EncodeItem encode_item(const SliceRun& r, int op) {
+  const Layout& y = *r.y;
+  const EncodeShape& sh = op == OP_E ? y.shE : y.shH;
+  EncodeItem e{};
+  e.heldcoef = at<void>(r.ws, op == OP_E ? y.o_sB : y.o_vB);
+  e.strmcoef = at<void>(r.ws, op == OP_E ? y.o_vA : y.o_sA);
+  e.sdata = at<void>(r.ws, op == OP_E ? y.o_dataE : y.o_dataH);
+  e.HC = sh.HC;
+  e.SC = sh.SC;
+  e.cps = sh.cps;
+  e.out_part = at<float>(r.ws, op == OP_E ? y.o_epart : y.o_hpart);
+  e.sens = r.sens;
+  e.L = y.L;
+  e.tmax = at<unsigned>(r.ws, y.o_tmax);
+  e.stop = r.st.stop;
+  e.G = y.G;
+  e.T = y.P + 1;
+  e.NB = sh.NB;
+  e.gx = (int)cdiv(sh.HC, (int64_t)kWaves * sh.MT);
+  return e;
+}
+
+// Whether the batch can run in lock-step with persistent launches: every
+// slice's shapes are ones the persistent kernel is built for.
+static bool lockstep_ok(int n, const std::vector<Layout>& ys) {
+  if (n < 1) return false;
+  for (int i = 0; i < n; ++i) {
+    const Layout& y = ys[i];
+    if (y.L == 0 || y.K == 0) return false;
+    for (const EncodeShape* sh : {&y.shE, &y.shH})
+      if (!persistent_supported(sh->prec, sh->NQ, sh->NB, sh->MT)) return false;
+  }
+  return true;
+}
+
+// The persistent encode launches of one direction (op OP_E or OP_EH) over
+// all slices: one launch per shape class (phase instructions, column
+// blocks, held tiles), at most kMaxBatchItems slices each.  The classes are
+// independent, so their launches go onto the library streams and run side
+// by side; each gets a grid of its resident workgroups (the encode kernel's
+// registers allow four per CU up to two column blocks, else two).
+static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, int op, hipStream_t s) {
+  std::map<int, std::vector<int>> groups;  // (NQ * 8 + NB) * 8 + MT -> slices
+  for (size_t i = 0; i < runs.size(); ++i) {
+    const EncodeShape& sh = op == OP_E ? runs[i].y->shE : runs[i].y->shH;
+    groups[(sh.NQ * 8 + sh.NB) * 8 + sh.MT].push_back((int)i);
+  }
+  std::vector<EncodeBatch> batches;
+  std::vector<int> keys;
+  for (const auto& g : groups)
+    for (size_t b0 = 0; b0 < g.second.size(); b0 += kMaxBatchItems) {
+      EncodeBatch b{};
+      int64_t first = 0;
+      for (size_t j = b0; j < g.second.size() && j < b0 + kMaxBatchItems; ++j) {
+        const SliceRun& r = runs[g.second[j]];
+        const EncodeShape& sh = op == OP_E ? r.y->shE : r.y->shH;
+        EncodeItem& e = b.it[b.n++];
+        e = encode_item(r, op);
+        e.first = first;
+        first += (int64_t)e.gx * sh.nsplit;
+      }
+      b.total = first;
+      batches.push_back(b);
+      keys.push_back(g.first);
+    }
+  const int nb = (int)batches.size();
+  const bool fork = nb > 1;
+  if (fork) NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
+  for (int k = 0; k < nb; ++k) {
+    const int key = keys[k];
+    const int MT = key % 8, NB = (key / 8) % 8, NQ = key / 64;
+    hipStream_t sk = fork ? ctx->bstreams[k % kBatchStreams] : s;
+    if (fork) NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
+    const int per_cu = NB <= 2 ? 4 : 2;
+    NFS_TRY(launch_encode_persistent(op, runs[0].y->prec, NQ, NB, MT, batches[k], per_cu * ctx->n_cu, sk),
+            "encode_persistent");
+  }
+  if (fork)
+    for (int k = 0; k < nb && k < kBatchStreams; ++k) {  // after every launch on that stream
+      NFS_TRY(hipEventRecord(ctx->bevents[k], ctx->bstreams[k]), "hipEventRecord");
+      NFS_TRY(hipStreamWaitEvent(s, ctx->bevents[k], 0), "hipStreamWaitEvent");
+    }
+  return NFS_OK;
+}
+
+// Run f(run, stream) for every slice, slices forked over the library
+// streams (lanes) and joined back into s.
+template <class F>
+static int fork_join(nfs_ctx* ctx, const std::vector<std::vector<int>>& lanes, std::vector<SliceRun>& runs,
+                     hipStream_t s, F&& f) {
+  NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
+  for (size_t k = 0; k < lanes.size(); ++k) {
+    hipStream_t sk = ctx->bstreams[k];
+    NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
+    for (int i : lanes[k]) {
+      const int rc = f(runs[i], sk);
+      if (rc) return rc;
+    }
+    NFS_TRY(hipEventRecord(ctx->bevents[k], sk), "hipEventRecord");
+    NFS_TRY(hipStreamWaitEvent(s, ctx->bevents[k], 0), "hipStreamWaitEvent");
+  }
+  return NFS_OK;
+}
+
+static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const std::vector<Layout>& ys,
+                           const std::vector<size_t>& offs, const float* const* m, float* const* rho, int n_iter,
+                           double tol, int replace_every, int reorth, double* const* hist, int* const* info, void* ws,
+                           const std::vector<std::vector<int>>& lanes, hipStream_t s) {
+  std::vector<SliceRun> runs(n);
+  for (int i = 0; i < n; ++i) {
+    SliceRun& r = runs[i];
+    const Layout& y = ys[i];
+    r.pr = &probs[i];
+    r.y = &ys[i];
+    r.ws = static_cast<char*>(ws) + offs[i];
+    r.x = reinterpret_cast<float2*>(rho[i]);
+    r.m = m[i];
+    r.hist = hist ? hist[i] : nullptr;
+    r.info = info ? info[i] : nullptr;
+    CgState& st = r.st;
+    st.r = at<float2>(r.ws, y.o_r);
+    st.p = at<float2>(r.ws, y.o_p);
+    st.q = at<float2>(r.ws, y.o_q);
+    st.b = at<float2>(r.ws, y.o_b);
+    st.part = at<double>(r.ws, y.o_part);
+    st.alpha = at<double>(r.ws, y.o_alpha);
+    st.scal = at<double>(r.ws, y.o_scal);
+    st.hist = r.hist ? r.hist : at<double>(r.ws, y.o_hist);
+    st.info = r.info ? r.info : at<int>(r.ws, y.o_info);
+    st.stop = at<int>(r.ws, y.o_stop);
+    st.V = reorth ? at<float2>(r.ws, y.o_V) : nullptr;
+    st.rn = reorth ? at<float2>(r.ws, y.o_rn) : nullptr;
+    st.iters = nullptr;
+    st.icorr = probs[i].icorr;
+    st.rpart = reorth ? at<double>(r.ws, y.o_rpart) : nullptr;
+    const bool f16ops = scaled_prec(y.prec);
+    st.smax = f16ops ? at<float>(r.ws, y.o_smax) : nullptr;
+    st.bmax = f16ops ? at<float>(r.ws, y.o_bmax) : nullptr;
+    st.L = y.L;
+    const int64_t nb = cdiv(y.L, 256);
+    st.nblk = (int)(nb < 1 ? 1 : (nb > kCgBlocks ? kCgBlocks : nb));
+    r.sens = probs[i].icorr ? at<float2>(r.ws, y.o_sensj) : reinterpret_cast<const float2*>(probs[i].sens);
+  }
+  auto ctx_of = [&](SliceRun& r, hipStream_t sk) {
+    return Ctx{ctx, *r.y, r.pr, r.sens, r.ws, sk, r.st.stop};
+  };
+  auto hs = [](const SliceRun& r) { return r.y->LC * 16; };
+  int rc;
+  // setup and the E^H packing of the data
+  rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+    const Layout& y = *r.y;
+    if (r.pr->icorr)
+      NFS_TRY(launch_scale_sens(reinterpret_cast<const float2*>(r.pr->sens), r.pr->icorr, y.G, y.L,
+                                const_cast<float2*>(r.sens), sk),
+              "scale_sens");
+    if (scaled_prec(y.prec)) NFS_TRY(launch_sens_absmax(r.sens, y.G, y.L, at<float>(r.ws, y.o_smax), sk), "sens_absmax");
+    NFS_TRY(launch_cg_reset(r.st, sk), "cg_reset");
+    Ctx c = ctx_of(r, sk);
+    int e = seq_pack_coefs(c, true, true);
+    if (e) return e;
+    NFS_TRY(launch_cg_norm_m(r.st, reinterpret_cast<const float2*>(r.m), (int64_t)y.G * y.K, sk), "cg_norm_m");
+    return pre_EH(c, reinterpret_cast<const float2*>(r.m), 1, y.K);
+  });
+  if (rc) return rc;
+  if ((rc = persistent_encode(ctx, runs, OP_EH, s))) return rc;
+  rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+    Ctx c = ctx_of(r, sk);
+    NFS_TRY(launch_cg_init(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1), r.x,
+                           r.y->L, sk),
+            "cg_init");
+    NFS_TRY(launch_cg_start(r.st, n_iter, sk), "cg_start");
+    if (reorth) NFS_TRY(launch_cg_store_v(r.st, 0, sk), "cg_store_v");
+    return NFS_OK;
+  });
+  if (rc) return rc;
+  // one E^H E of every slice's v (the direction, or the iterate for a
+  // residual replacement)
+  auto ehe_all = [&](bool of_x) -> int {
+    int e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+      Ctx c = ctx_of(r, sk);
+      return of_x ? pre_E(c, r.x, false) : pre_E(c, r.st.p, scaled_prec(r.y->prec));
+    });
+    if (e) return e;
+    if ((e = persistent_encode(ctx, runs, OP_E, s))) return e;
+    e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int { return mid_EHE(ctx_of(r, sk)); });
+    if (e) return e;
+    return persistent_encode(ctx, runs, OP_EH, s);
+  };
+  for (int it = 0; it < n_iter; ++it) {
+    if ((rc = ehe_all(false))) return rc;
+    const bool replace = replace_every > 0 && (it + 1) % replace_every == 0 && it + 1 < n_iter;
+    const int nv = reorth ? it + 1 : 0;
+    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+      Ctx c = ctx_of(r, sk);
+      NFS_TRY(launch_cg_beta(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1),
+                             r.y->L, sk),
+              "cg_beta");
+      NFS_TRY(launch_cg_update(r.st, r.x, r.y->L, it, replace ? 0 : nv, sk), "cg_update");
+      return NFS_OK;
+    });
+    if (rc) return rc;
+    if (replace) {
+      if ((rc = ehe_all(true))) return rc;
+      rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+        Ctx c = ctx_of(r, sk);
+        NFS_TRY(launch_cg_replace(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1),
+                                  r.y->L, nv, sk),
+                "cg_replace");
+        return NFS_OK;
+      });
+      if (rc) return rc;
+    }
+    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+      if (reorth) NFS_TRY(launch_cg_reorth_apply(r.st, nv, !replace, sk), "cg_reorth_apply");
+      NFS_TRY(launch_cg_direction(r.st, r.y->L, it, n_iter, tol, sk), "cg_direction");
+      return NFS_OK;
+    });
+    if (rc) return rc;
+  }
+  return fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+    NFS_TRY(launch_cg_finish(r.st, r.x, r.pr->icorr, r.y->L, sk), "cg_finish");
+    return NFS_OK;
+  });
+}
+
+extern "C" int nfs_set_batch_mode(nfs_ctx* ctx, int mode) {
+  if (!ctx) return fail(NFS_EINVAL, "nfs_set_batch_mode: ctx is NULL");
+  if (mode != NFS_BATCH_STREAMS && mode != NFS_BATCH_PERSISTENT)
+    return fail(NFS_EINVAL, "nfs_set_batch_mode: unknown mode %d", mode);
+  ctx->batch_mode = mode;
+  return NFS_OK;
+}
+
 extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, const float* const* m,
                                     float* const* rho, int n_iter, double tol, int replace_every, int reorth,
                                     int precision, double* const* hist, int* const* info, void* ws, size_t ws_bytes,
@@ -1038,8 +1314,14 @@ extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_proble
     ptrs.push_back(hist ? hist[i] : nullptr);
     ptrs.push_back(info ? info[i] : nullptr);
   }
-  const std::string key = graph_key(ctx, "cgb", probs, n_slices, ptrs.data(), (int)ptrs.size(), n_iter, tol,
-                                    replace_every, reorth, precision, ws, ws_bytes, stream);
+  const bool lockstep = ctx->batch_mode == NFS_BATCH_PERSISTENT && lockstep_ok(n_slices, ys);
+  const std::string key = graph_key(ctx, lockstep ? "cgbp" : "cgb", probs, n_slices, ptrs.data(), (int)ptrs.size(),
+                                    n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
+  if (lockstep)
+    return run_maybe_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> int {
+      return run_cg_lockstep(ctx, n_slices, probs, ys, offs, m, rho, n_iter, tol, replace_every, reorth, hist, info,
+                             ws, lanes, s);
+    });
   return run_maybe_graph(ctx, key, (hipStream_t)stream, [&](hipStream_t s) -> int {
     NFS_TRY(hipEventRecord(ctx->fork_event, s), "hipEventRecord");
     for (int k = 0; k < ns; ++k) {

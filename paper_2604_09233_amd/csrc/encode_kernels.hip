@@ -571,19 +571,15 @@ __device__ __forceinline__ void stream_range(const u4* __restrict__ strmcoef, co
   }
 }
 
+// One workgroup's share of an encode launch: held tiles
+// (bx * kWaves + wave) * MT ... of one problem, over split `split` of the
+// streamed chunks; st0, st1: the two LDS staging buffers.
 template <int OP, int PREC, int NQ, int NB, int MT>
-__global__ __launch_bounds__(256) void encode_kernel(
-    const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef, const void* __restrict__ sdata, int64_t HC,
-    int64_t SC, int64_t cps, float* __restrict__ out_part, const float2* __restrict__ sens, int64_t L, int G,
-    const unsigned* __restrict__ tmax, int T, const int* stop) {
-  if (stop && *stop) return;
-  const int64_t nblk = (int64_t)gridDim.x * gridDim.y;
-  int64_t b = blockIdx.x + (int64_t)gridDim.x * blockIdx.y;
-  const int64_t per = nblk / 8;
-  if (b < per * 8) b = (b % 8) * per + b / 8;
-  const int64_t bx = b % gridDim.x;
-  const int64_t split = b / gridDim.x;
-
+__device__ __forceinline__ void encode_block(const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef,
+                                             const void* __restrict__ sdata, int64_t HC, int64_t SC, int64_t cps,
+                                             float* __restrict__ out_part, const float2* __restrict__ sens,
+                                             int64_t L, int G, const unsigned* __restrict__ tmax, int T, int64_t bx,
+                                             int64_t split, u4* st0, u4* st1) {
   const int lane = threadIdx.x & 63;
   const int wave = threadIdx.x >> 6;
   const int64_t tile0 = (bx * kWaves + wave) * MT;
@@ -613,16 +609,60 @@ __global__ __launch_bounds__(256) void encode_kernel(
 
   // Streamed chunks are staged through LDS, double-buffered and shared by
   // the 4 waves.
-  __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
   const int64_t c0 = split * cps;
   const int64_t c1 = (c0 + cps < SC) ? c0 + cps : SC;
   const u4* sd = (const u4*)sdata;
   if (raw)
-    stream_range<PREC, NQ, NB, MT, false>(strmcoef, sd, c0, c1, hc, acc, stage[0], stage[1], wave, lane);
+    stream_range<PREC, NQ, NB, MT, false>(strmcoef, sd, c0, c1, hc, acc, st0, st1, wave, lane);
   else
-    stream_range<PREC, NQ, NB, MT, true>(strmcoef, sd, c0, c1, hc, acc, stage[0], stage[1], wave, lane);
+    stream_range<PREC, NQ, NB, MT, true>(strmcoef, sd, c0, c1, hc, acc, st0, st1, wave, lane);
 
   write_partials<OP, NB, MT>(acc, tile0, split, HC, out_part, sens, L, G, lane);
+}
+
+// XCD-aware order: block b of nblk goes to XCD b % 8 (round-robin dispatch);
+// renumbering makes each XCD take a contiguous range of blocks, which share
+// streamed chunks in that XCD's L2.
+__device__ __forceinline__ int64_t xcd_order(int64_t b, int64_t nblk) {
+  const int64_t per = nblk / 8;
+  return b < per * 8 ? (b % 8) * per + b / 8 : b;
+}
+
+template <int OP, int PREC, int NQ, int NB, int MT>
+__global__ __launch_bounds__(256) void encode_kernel(
+    const u4* __restrict__ heldcoef, const u4* __restrict__ strmcoef, const void* __restrict__ sdata, int64_t HC,
+    int64_t SC, int64_t cps, float* __restrict__ out_part, const float2* __restrict__ sens, int64_t L, int G,
+    const unsigned* __restrict__ tmax, int T, const int* stop) {
+  if (stop && *stop) return;
+  const int64_t b = xcd_order(blockIdx.x + (int64_t)gridDim.x * blockIdx.y, (int64_t)gridDim.x * gridDim.y);
+  __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
+  encode_block<OP, PREC, NQ, NB, MT>(heldcoef, strmcoef, sdata, HC, SC, cps, out_part, sens, L, G, tmax, T,
+                                     b % gridDim.x, b / gridDim.x, stage[0], stage[1]);
+}
+
+// Persistent form for many problems (slices) at once: a fixed grid walks the
+// work list of every slice's (held-tile block, split) items, item w at
+// workgroups w mod gridDim.x, in XCD order, so one launch covers slices of
+// different sizes (one launch per column-block count NB, which fixes the
+// kernel's registers).  Items of a slice whose stop flag is set are
+// skipped.  Every item runs exactly the code of the single-problem kernel,
+// so results are bit-identical to it.
+template <int OP, int PREC, int NQ, int NB, int MT>
+__global__ __launch_bounds__(256) void encode_persistent_kernel(EncodeBatch batch) {
+  __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
+  const int64_t total = batch.total;
+  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
+    const int64_t b = xcd_order(w, total);
+    int i = 0;
+    while (i + 1 < batch.n && b >= batch.it[i + 1].first) ++i;
+    const EncodeItem& e = batch.it[i];
+    __syncthreads();  // the previous item's reads of the staging buffers are done
+    if (e.stop && *e.stop) continue;
+    const int64_t lb = b - e.first;
+    encode_block<OP, PREC, NQ, NB, MT>((const u4*)e.heldcoef, (const u4*)e.strmcoef, e.sdata, e.HC, e.SC, e.cps,
+                                       e.out_part, e.sens, e.L, e.G, e.tmax, e.T, lb % e.gx, lb / e.gx, stage[0],
+                                       stage[1]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -926,6 +966,51 @@ hipError_t launch_encode(const EncodeShape& sh, const void* hc, const void* scf,
   return launch_encode_nq<OP_EH, PREC_FP16>(NFS_ENC_ARGS);
 }
 #undef NFS_ENC_ARGS
+
+template <int OP, int PREC, int NQ>
+static hipError_t launch_persistent_nb(const EncodeBatch& b, int NB, int MT, int grid, hipStream_t s) {
+  switch (NB * 8 + MT) {
+#define NFS_PERSIST(nb, mt)                                                                                       \
+  case nb * 8 + mt:                                                                                             \
+    hipLaunchKernelGGL((encode_persistent_kernel<OP, PREC, NQ, nb, mt>), dim3(grid), dim3(256), 0, s, b); \
+    break;
+    NFS_PERSIST(1, 2)
+    NFS_PERSIST(1, 4)
+    NFS_PERSIST(2, 2)
+    NFS_PERSIST(2, 4)
+    NFS_PERSIST(4, 2)
+    NFS_PERSIST(4, 4)
+#undef NFS_PERSIST
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <int OP, int PREC>
+static hipError_t launch_persistent_nq(const EncodeBatch& b, int NQ, int NB, int MT, int grid, hipStream_t s) {
+  if (NQ == 1) return launch_persistent_nb<OP, PREC, 1>(b, NB, MT, grid, s);
+  if (NQ == 2) return launch_persistent_nb<OP, PREC, 2>(b, NB, MT, grid, s);
+  return hipErrorInvalidValue;
+}
+
+bool persistent_supported(int prec, int NQ, int NB, int MT) {
+  return (prec == PREC_FP16 || prec == PREC_BF16) && (NQ == 1 || NQ == 2) && (NB == 1 || NB == 2 || NB == 4) &&
+         valid_held_tiles(NB, MT);
+}
+
+hipError_t launch_encode_persistent(int op, int prec, int NQ, int NB, int MT, const EncodeBatch& b, int grid,
+                                    hipStream_t s) {
+  if (b.total == 0) return hipSuccess;
+  if (b.n < 1 || b.n > kMaxBatchItems || grid < 1 || !persistent_supported(prec, NQ, NB, MT))
+    return hipErrorInvalidValue;
+  for (int i = 0; i < b.n; ++i)
+    if (b.it[i].NB != NB || b.it[i].T < 1 || b.it[i].T > kMaxTerms) return hipErrorInvalidValue;
+  if (op == OP_E)
+    return prec == PREC_BF16 ? launch_persistent_nq<OP_E, PREC_BF16>(b, NQ, NB, MT, grid, s)
+                             : launch_persistent_nq<OP_E, PREC_FP16>(b, NQ, NB, MT, grid, s);
+  return prec == PREC_BF16 ? launch_persistent_nq<OP_EH, PREC_BF16>(b, NQ, NB, MT, grid, s)
+                           : launch_persistent_nq<OP_EH, PREC_FP16>(b, NQ, NB, MT, grid, s);
+}
 
 hipError_t launch_build_P(int NQ, const void* heldcoef, const void* strmcoef, int64_t HC, int64_t SC,
                           const unsigned* tmax, int T, void* P, hipStream_t s) {

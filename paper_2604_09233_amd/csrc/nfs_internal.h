@@ -72,6 +72,37 @@ struct EncodeShape {
   int64_t cps;       // streamed chunks per split
 };
 
+// One problem (slice) of a persistent encode launch: the arguments of its
+// single-problem launch, its held-tile block count gx (the single launch's
+// grid x), and the index of its first item in the launch's work list
+// (items: gx * nsplit per slice, slices in list order).
+struct EncodeItem {
+  const void* heldcoef;
+  const void* strmcoef;
+  const void* sdata;
+  int64_t HC, SC, cps;
+  float* out_part;
+  const float2* sens;
+  int64_t L;
+  const unsigned* tmax;
+  const int* stop;
+  int64_t first;
+  int G, T, NB, gx;
+};
+constexpr int kMaxBatchItems = 24;  // slices per persistent launch (the list is a kernel argument)
+struct EncodeBatch {
+  EncodeItem it[kMaxBatchItems];
+  int n;
+  int64_t total;  // items in the work list
+};
+// Whether a persistent launch handles this operand form and shape
+// (FP16 / BF16 operands, NQ <= 2, NB in {1, 2, 4}).
+bool persistent_supported(int prec, int NQ, int NB, int MT);
+// All slices of b in one launch of `grid` workgroups (same op, precision,
+// NQ, NB and MT for every slice).
+hipError_t launch_encode_persistent(int op, int prec, int NQ, int NB, int MT, const EncodeBatch& b, int grid,
+                                    hipStream_t s);
+
 // ---- launchers (encode_kernels.hip) ---------------------------------------
 // per-term largest magnitudes of the phase coefficients, as float bits:
 // tmax[b] = max_k |a_b(k)| (a_0 = t, a_{b+1} = kcoef[.][b], before the 1/2pi

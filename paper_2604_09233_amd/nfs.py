@@ -77,6 +77,7 @@ def lib():
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
                                                i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]
             L.nfs_set_graphs.argtypes = [vp, i32]
+            L.nfs_set_batch_mode.argtypes = [vp, i32]
             L.nfs_tune_workspace_bytes.argtypes = [vp, pp, i32, ctypes.POINTER(sz)]
             L.nfs_autotune.argtypes = [vp, pp, i32, vp, sz, vp]
             L.nfs_tuned_shape.argtypes = [vp, pp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
@@ -100,7 +101,8 @@ def lib():
                          "nfs_tune_workspace_bytes_batched", "nfs_autotune_batched", "nfs_cg_solve_resident",
                          "nfs_cg_solve_traced", "nfs_ssim_workspace_bytes", "nfs_ssim", "nfs_lcurve_corner",
                          "nfs_kspace_filter_workspace_bytes", "nfs_apply_kspace_filter", "nfs_kspace_filter_mask",
-                         "nfs_maps_workspace_bytes", "nfs_sens_initial", "nfs_sens_maps", "nfs_b0_map"):
+                         "nfs_maps_workspace_bytes", "nfs_sens_initial", "nfs_sens_maps", "nfs_b0_map",
+                         "nfs_set_batch_mode"):
                 getattr(L, name).restype = ctypes.c_int
             _lib = L
         return _lib
@@ -412,6 +414,17 @@ def tuned_shape(prob: Problem, precision: str = "fp16"):
 def set_graphs(device: int, on: bool = True):
     """Capture repeated solves into hipGraphs and replay them (see include/nfs.h)."""
     _check(lib().nfs_set_graphs(context(device), int(on)))
+
+
+BATCH_MODES = {"streams": 0, "persistent": 1}
+
+
+def set_batch_mode(device: int, mode: str = "streams"):
+    """How cg_solve_batched runs its slices: "streams" (each slice's own
+    solve, spread over library streams; the default) or "persistent"
+    (lock-step, persistent E and E^H launches over all slices per
+    iteration); see include/nfs.h."""
+    _check(lib().nfs_set_batch_mode(context(device), BATCH_MODES[mode]))
 
 
 _batch_ws = {}

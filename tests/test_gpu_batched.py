@@ -39,8 +39,17 @@ def small_batch(nfs):
     return sl, probs, ms
 
 
+@pytest.fixture(params=["persistent", "streams"])
+def mode(nfs, request):
+    nfs.set_batch_mode(0, request.param)
+    yield request.param
+    nfs.set_batch_mode(0, "streams")
+
+
 @pytest.mark.parametrize("prec,reorth", [("fp16", True), ("fp32", True), ("bf16", False)])
-def test_batched_equals_single_solves(nfs, small_batch, prec, reorth):
+def test_batched_equals_single_solves(nfs, small_batch, prec, reorth, mode):
+    """Each slice of the batch is bit-identical to its single solve, in both
+    batch modes (FP32 operands run the streams form in either)."""
     sl, probs, ms = small_batch
     rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 12, precision=prec, reorth=reorth)
     torch.cuda.synchronize()
@@ -63,9 +72,10 @@ def test_batched_slice_matches_oracle(nfs, small_batch):
         assert err < 1e-4
 
 
-def test_batched_tolerance_freezes_slices_independently(nfs, small_batch):
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_batched_tolerance_freezes_slices_independently(nfs, small_batch, prec, mode):
     sl, probs, ms = small_batch
-    rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 40, tol=1e-2, precision="fp32",
+    rb, hb, ib = nfs.cg_solve_batched(probs, [torch.from_numpy(m) for m in ms], 40, tol=1e-2, precision=prec,
                                       reorth=True)
     torch.cuda.synchronize()
     for i in range(len(probs)):
@@ -117,3 +127,25 @@ def test_graph_replay_matches_eager(nfs, small_batch):
             torch.cuda.synchronize()
     finally:
         nfs.set_graphs(0, False)
+
+
+def test_persistent_batch_with_mixed_shapes_and_replacement(nfs):
+    """Slices of 4 to 32 coils (one to four column blocks), different held-
+    tile counts (untuned defaults, so several launch classes), residual
+    replacement every 4 iterations: the lock-step persistent batch equals
+    the single solves bit for bit."""
+    sl = synth.batched_slices(7, seed=11, n_range=(24, 48), g_range=(4, 32), k_range=(1000, 4000))
+    probs, ms = [], []
+    for d in sl:
+        probs.append(nfs.Problem(*args(d)))
+        ms.append(torch.from_numpy((d["noise"] * 0.1).astype(np.complex64)))
+    print("coils", [d["n_coil"] for d in sl], "samples", [d["K"] for d in sl])
+    nfs.set_batch_mode(0, "persistent")
+    rb, hb, ib = nfs.cg_solve_batched(probs, ms, 9, replace_every=4, precision="bf16", reorth=True)
+    torch.cuda.synchronize()
+    nfs.set_batch_mode(0, "streams")
+    for i, (p, m) in enumerate(zip(probs, ms)):
+        r1, h1, i1 = nfs.cg_solve(p, m, 9, replace_every=4, precision="bf16", reorth=True)
+        torch.cuda.synchronize()
+        assert torch.equal(rb[i].cpu(), r1.cpu()), i
+        assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
