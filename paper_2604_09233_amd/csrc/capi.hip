@@ -1091,7 +1091,8 @@ static bool lockstep_ok(int n, const std::vector<Layout>& ys) {
 // blocks, held tiles), at most kMaxBatchItems slices each.  The classes are
 // independent, so their launches go onto the library streams and run side
 // by side; each gets a grid of its resident workgroups (the encode kernel's
-// registers allow four per CU up to two column blocks, else two).
+// registers allow four per CU up to two column blocks or with two held
+// tiles, three for four column blocks with four held tiles).
 static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, int op, hipStream_t s) {
   std::map<int, std::vector<int>> groups;  // (NQ * 8 + NB) * 8 + MT -> slices
   for (size_t i = 0; i < runs.size(); ++i) {
@@ -1124,7 +1125,7 @@ static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, in
     const int MT = key % 8, NB = (key / 8) % 8, NQ = key / 64;
     hipStream_t sk = fork ? ctx->bstreams[k % kBatchStreams] : s;
     if (fork) NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
-    const int per_cu = NB <= 2 ? 4 : 2;
+    const int per_cu = NB <= 2 || MT == 2 ? 4 : 3;
     NFS_TRY(launch_encode_persistent(op, runs[0].y->prec, NQ, NB, MT, batches[k], per_cu * ctx->n_cu, sk),
             "encode_persistent");
   }
