@@ -214,33 +214,41 @@ __device__ __forceinline__ void coords(const Grid3& g, int64_t j, int c[3]) {
 }
 
 // Row j of A applied to a vector given by the accessor val(d, k) (its value
-// at offset k along axis d from voxel j; val(0, 0) at j itself).  SENS: D2
-// penalty, B0: D1 penalty.  Offsets are only asked for where they lie on
-// the grid.
-template <int OP, class V>
-__device__ __forceinline__ double apply_row(const Grid3& g, const double* __restrict__ t, const double* __restrict__ w,
-                                            double alpha, int64_t j, const int c[3], V&& val) {
+// at offset k along axis d from voxel j; val(0, 0) at j itself), with the
+// penalty weights from the accessor wt(d, k) (k in -1, 0, 1) and the data
+// weight tj.  SENS: D2 penalty, B0: D1 penalty (tj = 1).  Offsets are only
+// asked for where they lie on the grid.
+template <int OP, class V, class W>
+__device__ __forceinline__ double apply_row(const Grid3& g, double tj, double alpha, const int c[3], V&& val,
+                                            W&& wt) {
   const double v0 = val(0, 0);
   double pen = 0.0;
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
     const int n = g.n[d], cd = c[d];
-    const int64_t s = g.s[d];
     if (OP == MAP_SENS) {
       if (n < 3) continue;
       const double vm1 = cd >= 1 ? val(d, -1) : 0.0;
       const double vp1 = cd <= n - 2 ? val(d, 1) : 0.0;
-      if (cd >= 2) pen += w[j - s] * (val(d, -2) - 2.0 * vm1 + v0);
-      if (cd >= 1 && cd <= n - 2) pen -= 2.0 * w[j] * (vm1 - 2.0 * v0 + vp1);
-      if (cd <= n - 3) pen += w[j + s] * (v0 - 2.0 * vp1 + val(d, 2));
+      if (cd >= 2) pen += wt(d, -1) * (val(d, -2) - 2.0 * vm1 + v0);
+      if (cd >= 1 && cd <= n - 2) pen -= 2.0 * wt(0, 0) * (vm1 - 2.0 * v0 + vp1);
+      if (cd <= n - 3) pen += wt(d, 1) * (v0 - 2.0 * vp1 + val(d, 2));
     } else {
       if (n < 2) continue;
-      if (cd >= 1) pen += w[j - s] * (v0 - val(d, -1));
-      if (cd <= n - 2) pen -= w[j] * (val(d, 1) - v0);
+      if (cd >= 1) pen += wt(d, -1) * (v0 - val(d, -1));
+      if (cd <= n - 2) pen -= wt(0, 0) * (val(d, 1) - v0);
     }
   }
-  const double tj = OP == MAP_SENS ? t[j] : 1.0;
   return fma(alpha, pen, tj * v0);
+}
+
+// The same with the weights read from memory (w [L], t [L] or unused for B0).
+template <int OP, class V>
+__device__ __forceinline__ double apply_row_mem(const Grid3& g, const double* __restrict__ t,
+                                                const double* __restrict__ w, double alpha, int64_t j, const int c[3],
+                                                V&& val) {
+  return apply_row<OP>(g, OP == MAP_SENS ? t[j] : 1.0, alpha, c, val,
+                       [&](int d, int k) { return w[j + k * g.s[d]]; });
 }
 
 // ---- z-marching tiles: a workgroup owns a kTileX x kTileY column of the
@@ -257,24 +265,41 @@ __host__ __device__ __forceinline__ int tile_count(const Grid3& g) {
 }
 
 // load(i, interior, x, y, z): value of voxel i at (x, y, z) (interior: i
-// belongs to this tile);
-// row(j, c, val): the output of voxel j at coordinates c from the accessor.
-// The plane two ahead is fetched into registers while the current plane is
-// computed, so the loads of one plane overlap the arithmetic of the last.
+// belongs to this tile); row(j, c, val, wt): the output of voxel j at
+// coordinates c from the accessors of the vector and of the penalty weights
+// w, whose planes z-1 .. z+1 are held in a second LDS ring.  The vector's
+// plane two ahead and the weights' plane one ahead are fetched into
+// registers while the current plane is computed, so the loads of one plane
+// overlap the arithmetic of the last.
+constexpr int kWRing = 3;
+
 template <class Load, class Row>
-__device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], Load&& load, Row&& row) {
+__device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], double (*wring)[kPlane],
+                                      const double* __restrict__ w, Load&& load, Row&& row) {
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int ntx = (nx + kTileX - 1) / kTileX;
   const int x0 = (int)(blockIdx.x % ntx) * kTileX, y0 = (int)(blockIdx.x / ntx) * kTileY;
   // plane entries of this thread: e0 and e1 = e0 + 256 (kPlane < 512)
   const int e0 = threadIdx.x, e1 = threadIdx.x + 256;
   const bool has1 = e1 < kPlane;
-  auto fetch = [&](int z, int e) -> double {
+  auto at_e = [&](int e, int& gx, int& gy, bool& interior) {
     const int lx = e % kPlaneX, ly = e / kPlaneX;
-    const int gx = x0 - kHalo + lx, gy = y0 - kHalo + ly;
-    if (gx < 0 || gx >= nx || gy < 0 || gy >= ny) return 0.0;
-    const bool interior = lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo && ly < kHalo + kTileY;
+    gx = x0 - kHalo + lx;
+    gy = y0 - kHalo + ly;
+    interior = lx >= kHalo && lx < kHalo + kTileX && ly >= kHalo && ly < kHalo + kTileY;
+    return gx >= 0 && gx < nx && gy >= 0 && gy < ny;
+  };
+  auto fetch = [&](int z, int e) -> double {
+    int gx, gy;
+    bool interior;
+    if (!at_e(e, gx, gy, interior)) return 0.0;
     return load(gx + g.s[1] * gy + g.s[2] * z, interior, gx, gy, z);
+  };
+  auto fetch_w = [&](int z, int e) -> double {
+    int gx, gy;
+    bool interior;
+    if (!at_e(e, gx, gy, interior)) return 0.0;
+    return w[gx + g.s[1] * gy + g.s[2] * z];
   };
   const int lx = threadIdx.x % kTileX, ly = threadIdx.x / kTileX;
   const int gx = x0 + lx, gy = y0 + ly;
@@ -284,31 +309,51 @@ __device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], Lo
     ring[z % kRing][e0] = fetch(z, e0);
     if (has1) ring[z % kRing][e1] = fetch(z, e1);
   }
-  double n0 = 0.0, n1 = 0.0;
+  wring[0][e0] = fetch_w(0, e0);
+  if (has1) wring[0][e1] = fetch_w(0, e1);
+  double n0 = 0.0, n1 = 0.0, m0 = 0.0, m1 = 0.0;
   if (kHalo < nz) {
     n0 = fetch(kHalo, e0);
     if (has1) n1 = fetch(kHalo, e1);
+  }
+  if (1 < nz) {
+    m0 = fetch_w(1, e0);
+    if (has1) m1 = fetch_w(1, e1);
   }
   for (int z = 0; z < nz; ++z) {
     if (z + kHalo < nz) {
       ring[(z + kHalo) % kRing][e0] = n0;
       if (has1) ring[(z + kHalo) % kRing][e1] = n1;
     }
+    if (z + 1 < nz) {
+      wring[(z + 1) % kWRing][e0] = m0;
+      if (has1) wring[(z + 1) % kWRing][e1] = m1;
+    }
     __syncthreads();
     if (z + kHalo + 1 < nz) {
       n0 = fetch(z + kHalo + 1, e0);
       if (has1) n1 = fetch(z + kHalo + 1, e1);
     }
+    if (z + 2 < nz) {
+      m0 = fetch_w(z + 2, e0);
+      if (has1) m1 = fetch_w(z + 2, e1);
+    }
     if (mine) {
       const int c[3] = {gx, gy, z};
       const int64_t j = gx + g.s[1] * gy + g.s[2] * z;
       const double* here = ring[z % kRing];
+      const double* what = wring[z % kWRing];
       auto val = [&](int d, int k) -> double {
         if (d == 0) return here[ctr + k];
         if (d == 1) return here[ctr + k * kPlaneX];
         return ring[(z + k + kRing) % kRing][ctr];
       };
-      row(j, c, val);
+      auto wt = [&](int d, int k) -> double {
+        if (d == 0) return what[ctr + k];
+        if (d == 1) return what[ctr + k * kPlaneX];
+        return wring[(z + k + kWRing) % kWRing][ctr];
+      };
+      row(j, c, val, wt);
     }
     __syncthreads();
   }
@@ -465,6 +510,7 @@ template <int OP, bool MG>
 __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, const double* __restrict__ t,
                                                         const double* __restrict__ w, double alpha, int pin) {
   __shared__ double ring[kRing][kPlane];
+  __shared__ double wring[kWRing][kPlane];
   __shared__ double red[4];
   const int rhs = blockIdx.y;
   if (st.status[rhs]) return;  // uniform per workgroup
@@ -478,14 +524,14 @@ __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, co
   const double* dinv = st.dinv;
   double pq = 0.0;
   march(
-      g, ring,
+      g, ring, wring, w,
       [&](int64_t i, bool interior, int, int, int) {
         const double v = dir_at<MG>(dinv, r, z, po, beta, i);
         if (interior) pn[i] = v;
         return v;
       },
-      [&](int64_t j, const int c[3], auto& val) {
-        const double qj = apply_row<OP>(g, t, w, alpha, j, c, val);
+      [&](int64_t j, const int c[3], auto& val, auto& wt) {
+        const double qj = apply_row<OP>(g, OP == MAP_SENS ? t[j] : 1.0, alpha, c, val, wt);
         q[j] = qj;
         pq += val(0, 0) * qj;
       });
@@ -700,6 +746,7 @@ __global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__
                                                          const double* __restrict__ xc, double* __restrict__ part,
                                                          int npart) {
   __shared__ double ring[kRing][kPlane];
+  __shared__ double wring[kWRing][kPlane];
   __shared__ double red[4];
   const int rhs = blockIdx.y;
   if (status[rhs]) return;
@@ -710,14 +757,14 @@ __global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__
   double* yv = y + o;
   double dot = 0.0;
   march(
-      g, ring,
+      g, ring, wring, w,
       [&](int64_t i, bool, int xi, int yi, int zi) -> double {
         if (MODE == MG_PRE) return omega * (dinv[i] * bv[i]);
         if (MODE != MG_POST) return xv[i];
         return xv[i] + interpolate(cv, g, gc, xi, yi, zi);
       },
-      [&](int64_t j, const int c[3], auto& val) {
-        const double res = bv[j] - apply_row<OP>(g, t, w, alpha, j, c, val);
+      [&](int64_t j, const int c[3], auto& val, auto& wt) {
+        const double res = bv[j] - apply_row<OP>(g, OP == MAP_SENS ? t[j] : 1.0, alpha, c, val, wt);
         if (MODE == MG_RESIDUAL) {
           yv[j] = res;
           return;
@@ -783,7 +830,7 @@ __global__ void __launch_bounds__(256) mg_coarsest_kernel(Grid3 g, int n, const 
     const int i = e / n, jj = e % n;
     int c[3];
     coords(g, i, c);
-    M[i][jj] = apply_row<OP>(g, t, w, alpha, i, c, [&](int d, int k) { return i + k * g.s[d] == jj ? 1.0 : 0.0; });
+    M[i][jj] = apply_row_mem<OP>(g, t, w, alpha, i, c, [&](int d, int k) { return i + k * g.s[d] == jj ? 1.0 : 0.0; });
     M[i][n + jj] = i == jj ? 1.0 : 0.0;
   }
   __syncthreads();
