@@ -224,8 +224,12 @@ int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* out, int nx, 
 /* The filter itself: f = 1 on the bins inside the convex hull of the K
  * first-order k-space positions kpos (HOST double [K][dim], cycles per field
  * of view), 0 elsewhere; bins on the hull count as inside.  Host
- * computation (convex hull by Andrew's monotone chain, then an edge test per
- * bin); only 2D grids (dim 2, nz 1), NFS_EUNSUPPORTED otherwise.
+ * computation.  dim 2 (with nz 1): convex hull by Andrew's monotone chain,
+ * then an edge test per bin.  dim 3: convex hull by quickhull (on the
+ * positions joggled by at most 5e-10 of their largest coordinate, which
+ * keeps the visible regions of nearly coplanar trajectory samples simple),
+ * then per (x, y) column the z interval the face planes allow; NFS_EINVAL
+ * if the positions span no volume.
  * mask: HOST uint8 [L]; *n_inside (may be NULL): number of bins set.      */
 int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int ny, int nz, unsigned char* mask,
                            int64_t* n_inside);

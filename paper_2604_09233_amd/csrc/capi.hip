@@ -6,6 +6,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <array>
 #include <map>
 #include <string>
 #include <unordered_map>
@@ -911,13 +912,313 @@ extern "C" int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* ou
 // Filter mask from the first-order k-space positions (host arithmetic):
 // Andrew's monotone chain builds the convex hull; a bin is inside when it is
 // on the inner side of (or on) every hull edge, up to a relative tolerance.
+// ---------------------------------------------------------------------------
+// 3D convex hull (quickhull): the face planes n.x <= d (unit n) of the hull
+// of pts [n][3].  Points are assigned to a face they lie above (conflict
+// lists); the farthest point of a face is added by deleting the faces it
+// sees and joining the horizon edges to it.  Returns false for point sets
+// without volume (all points on a plane).
+namespace {
+
+struct HullFace {
+  int v[3];       // counter-clockwise seen from outside
+  int nb[3];      // face across edge v[i] -> v[(i + 1) % 3]
+  double n[3], d;
+  bool alive;
+  std::vector<int> pts;
+};
+
+struct Hull3 {
+  const double* P;
+  double eps;
+  std::vector<HullFace> F;
+  std::vector<int64_t> mark;  // visit stamps of the current step (2 r: visible, 2 r + 1: not)
+  int64_t round = 0;
+
+  const double* pt(int i) const { return P + 3 * (size_t)i; }
+  double dist(const HullFace& f, int i) const {
+    const double* q = pt(i);
+    return f.n[0] * q[0] + f.n[1] * q[1] + f.n[2] * q[2] - f.d;
+  }
+  int add_face(int a, int b, int c) {
+    HullFace f;
+    f.v[0] = a;
+    f.v[1] = b;
+    f.v[2] = c;
+    f.nb[0] = f.nb[1] = f.nb[2] = -1;
+    const double *A = pt(a), *B = pt(b), *C = pt(c);
+    const double u[3] = {B[0] - A[0], B[1] - A[1], B[2] - A[2]};
+    const double w[3] = {C[0] - A[0], C[1] - A[1], C[2] - A[2]};
+    double n[3] = {u[1] * w[2] - u[2] * w[1], u[2] * w[0] - u[0] * w[2], u[0] * w[1] - u[1] * w[0]};
+    const double len = std::sqrt(n[0] * n[0] + n[1] * n[1] + n[2] * n[2]);
+    for (int k = 0; k < 3; ++k) f.n[k] = len > 0 ? n[k] / len : 0.0;
+    f.d = f.n[0] * A[0] + f.n[1] * A[1] + f.n[2] * A[2];
+    f.alive = true;
+    F.push_back(std::move(f));
+    return (int)F.size() - 1;
+  }
+  // link faces sharing an edge (a -> b in one, b -> a in the other)
+  void link_all(const std::vector<int>& ids) {
+    std::map<std::pair<int, int>, std::pair<int, int>> edge;  // (a, b) -> (face, edge index)
+    for (int f : ids)
+      for (int e = 0; e < 3; ++e) edge[{F[f].v[e], F[f].v[(e + 1) % 3]}] = {f, e};
+    for (int f : ids)
+      for (int e = 0; e < 3; ++e) {
+        auto it = edge.find({F[f].v[(e + 1) % 3], F[f].v[e]});
+        if (it != edge.end()) F[f].nb[e] = it->second.first;
+      }
+  }
+
+  // Four points spanning a tetrahedron thicker than eps in every sense:
+  // the extremes along the axis of largest extent, the point farthest from
+  // their line, the point farthest from that plane; false if none exist.
+  bool simplex(int64_t n, int tv[4]) {
+    if (n < 4) return false;
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int64_t i = 1; i < n; ++i)
+      for (int k = 0; k < 3; ++k) {
+        if (pt((int)i)[k] < pt(lo[k])[k]) lo[k] = (int)i;
+        if (pt((int)i)[k] > pt(hi[k])[k]) hi[k] = (int)i;
+      }
+    int ax = 0;
+    for (int k = 1; k < 3; ++k)
+      if (pt(hi[k])[k] - pt(lo[k])[k] > pt(hi[ax])[ax] - pt(lo[ax])[ax]) ax = k;
+    const int i0 = lo[ax], i1 = hi[ax];
+    if (!(pt(i1)[ax] - pt(i0)[ax] > eps)) return false;
+    const double* a = pt(i0);
+    const double* b = pt(i1);
+    const double ab[3] = {b[0] - a[0], b[1] - a[1], b[2] - a[2]};
+    int i2 = -1;
+    double best = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double* q = pt((int)i);
+      const double aq[3] = {q[0] - a[0], q[1] - a[1], q[2] - a[2]};
+      const double c[3] = {ab[1] * aq[2] - ab[2] * aq[1], ab[2] * aq[0] - ab[0] * aq[2], ab[0] * aq[1] - ab[1] * aq[0]};
+      const double d2 = c[0] * c[0] + c[1] * c[1] + c[2] * c[2];
+      if (d2 > best) {
+        best = d2;
+        i2 = (int)i;
+      }
+    }
+    const double lab = std::sqrt(ab[0] * ab[0] + ab[1] * ab[1] + ab[2] * ab[2]);
+    if (i2 < 0 || !(std::sqrt(best) / lab > eps)) return false;
+    const int t = add_face(i0, i1, i2);
+    int i3 = -1;
+    best = 0.0;
+    for (int64_t i = 0; i < n; ++i) {
+      const double dd = std::fabs(dist(F[t], (int)i));
+      if (dd > best) {
+        best = dd;
+        i3 = (int)i;
+      }
+    }
+    F.clear();
+    if (i3 < 0 || !(best > eps)) return false;
+    tv[0] = i0;
+    tv[1] = i1;
+    tv[2] = i2;
+    tv[3] = i3;
+    return true;
+  }
+
+  bool build(int64_t n) {
+    int tv[4];
+    if (!simplex(n, tv)) return false;
+    const int i0 = tv[0], i1 = tv[1], i2 = tv[2], i3 = tv[3];
+    // the tetrahedron, every face oriented away from its centroid
+    double cen[3] = {0, 0, 0};
+    for (int q : tv)
+      for (int k = 0; k < 3; ++k) cen[k] += 0.25 * pt(q)[k];
+    const int fv[4][3] = {{0, 1, 2}, {0, 3, 1}, {1, 3, 2}, {2, 3, 0}};
+    std::vector<int> ids;
+    for (auto& f3 : fv) {
+      int id = add_face(tv[f3[0]], tv[f3[1]], tv[f3[2]]);
+      const HullFace& f = F[id];
+      if (f.n[0] * cen[0] + f.n[1] * cen[1] + f.n[2] * cen[2] - f.d > 0) {
+        F.pop_back();
+        id = add_face(tv[f3[0]], tv[f3[2]], tv[f3[1]]);
+      }
+      ids.push_back(id);
+    }
+    link_all(ids);
+    for (int64_t i = 0; i < n; ++i) {
+      if (i == i0 || i == i1 || i == i2 || i == i3) continue;
+      for (int f : ids)
+        if (dist(F[f], (int)i) > eps) {
+          F[f].pts.push_back((int)i);
+          break;
+        }
+    }
+    std::vector<int> work(ids);
+    while (!work.empty()) {
+      const int f0 = work.back();
+      work.pop_back();
+      if (!F[f0].alive || F[f0].pts.empty()) continue;
+      // farthest conflict point
+      int p = -1;
+      double far = -1.0;
+      for (int q : F[f0].pts) {
+        const double dd = dist(F[f0], q);
+        if (dd > far) {
+          far = dd;
+          p = q;
+        }
+      }
+      // faces visible from p (connected region around f0) and its horizon
+      std::vector<int> vis{f0}, stack{f0};
+      ++round;
+      if (mark.size() < F.size()) mark.resize(F.size() + F.size() / 2, 0);
+      auto seen = [&](int g) { return mark[g] == 2 * round ? 1 : mark[g] == 2 * round + 1 ? 2 : 0; };
+      mark[f0] = 2 * round;
+      std::vector<std::pair<int, int>> horizon;  // (visible face, edge index)
+      while (!stack.empty()) {
+        const int f = stack.back();
+        stack.pop_back();
+        for (int e = 0; e < 3; ++e) {
+          const int g = F[f].nb[e];
+          if (g < 0) return false;  // broken adjacency (degenerate input)
+          const int sg = seen(g);
+          if (sg == 1) continue;
+          if (sg == 2) {
+            horizon.push_back({f, e});
+            continue;
+          }
+          if (dist(F[g], p) > eps) {
+            mark[g] = 2 * round;
+            vis.push_back(g);
+            stack.push_back(g);
+          } else {
+            mark[g] = 2 * round + 1;
+            horizon.push_back({f, e});
+          }
+        }
+      }
+      // new faces (a, b, p) on the horizon edges a -> b
+      std::map<int, int> start, end;  // horizon vertex -> new face starting / ending there
+      std::vector<int> fresh;
+      for (auto& he : horizon) {
+        const int a = F[he.first].v[he.second], b = F[he.first].v[(he.second + 1) % 3];
+        const int g = F[he.first].nb[he.second];
+        const int nf = add_face(a, b, p);
+        F[nf].nb[0] = g;
+        for (int e = 0; e < 3; ++e)
+          if (F[g].v[e] == b && F[g].v[(e + 1) % 3] == a) F[g].nb[e] = nf;
+        if (start.count(a) || end.count(b)) return false;  // the horizon is not a simple cycle
+        start[a] = nf;
+        end[b] = nf;
+        fresh.push_back(nf);
+      }
+      for (int nf : fresh) {
+        const int a = F[nf].v[0], b = F[nf].v[1];
+        if (!start.count(b) || !end.count(a)) return false;
+        F[nf].nb[1] = start[b];  // across b -> p
+        F[nf].nb[2] = end[a];    // across p -> a
+      }
+      // hand the orphaned conflict points to the new faces
+      for (int f : vis) {
+        F[f].alive = false;
+        for (int q : F[f].pts) {
+          if (q == p) continue;
+          for (int nf : fresh)
+            if (dist(F[nf], q) > eps) {
+              F[nf].pts.push_back(q);
+              break;
+            }
+        }
+        std::vector<int>().swap(F[f].pts);
+      }
+      for (int nf : fresh) work.push_back(nf);
+    }
+    return true;
+  }
+};
+
+}  // namespace
+
+// Unit-normal face planes (n0, n1, n2, d) of the hull of pts [n][3]; false
+// if the points do not span a volume.  The points are first joggled by a
+// fixed pseudo-random offset of at most 5e-10 of their largest coordinate
+// (trajectory samples lie on smooth curves, many nearly coplanar with hull
+// faces, where the region a new point sees is otherwise not a disk); the
+// faces therefore move by at most that much.
+static bool convex_hull_3d(const double* pts, int64_t n, double scale, std::vector<std::array<double, 4>>* planes) {
+  const double s = scale > 1.0 ? scale : 1.0;
+  {
+    // the unjoggled points must span a volume well above the joggle
+    Hull3 h0;
+    h0.P = pts;
+    h0.eps = 1e-7 * s;
+    int tv[4];
+    if (!h0.simplex(n, tv)) return false;
+  }
+  std::vector<double> q(pts, pts + 3 * n);
+  uint64_t st = 88172645463325252ULL;  // xorshift64
+  for (double& x : q) {
+    st ^= st << 13;
+    st ^= st >> 7;
+    st ^= st << 17;
+    x += 1e-9 * s * ((double)(st >> 11) / 9007199254740992.0 - 0.5);
+  }
+  Hull3 h;
+  h.P = q.data();
+  h.eps = 1e-12 * s;
+  if (!h.build(n)) return false;
+  planes->clear();
+  for (const HullFace& f : h.F)
+    if (f.alive) planes->push_back({f.n[0], f.n[1], f.n[2], f.d});
+  return !planes->empty();
+}
+
+// Mask of the bins of an nx x ny x nz grid inside the hull planes: per
+// (x, y) column the planes bound z to one interval (tol: slack in the
+// plane distance, so that bins on the hull count as inside).
+static int64_t mask_from_planes(const std::vector<std::array<double, 4>>& planes, int nx, int ny, int nz, double tol,
+                                unsigned char* mask) {
+  auto freq = [](int i, int n) { return (double)(i < (n + 1) / 2 ? i : i - n); };
+  int64_t count = 0;
+  for (int iy = 0; iy < ny; ++iy)
+    for (int ix = 0; ix < nx; ++ix) {
+      const double u = freq(ix, nx), v = freq(iy, ny);
+      double zlo = -HUGE_VAL, zhi = HUGE_VAL;
+      bool ok = true;
+      for (const auto& pl : planes) {
+        const double rhs = pl[3] + tol - pl[0] * u - pl[1] * v;
+        if (pl[2] > 1e-12) zhi = std::min(zhi, rhs / pl[2]);
+        else if (pl[2] < -1e-12) zlo = std::max(zlo, rhs / pl[2]);
+        else if (rhs < 0) ok = false;
+      }
+      for (int iz = 0; iz < nz; ++iz) {
+        const double w = freq(iz, nz);
+        const bool in = ok && w >= zlo && w <= zhi;
+        mask[ix + (int64_t)nx * (iy + (int64_t)ny * iz)] = in ? 1 : 0;
+        count += in;
+      }
+    }
+  return count;
+}
+
 extern "C" int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int ny, int nz,
                                       unsigned char* mask, int64_t* n_inside) {
   const char* fn = "nfs_kspace_filter_mask";
-  if (dim != 2 || nz != 1) return fail(NFS_EUNSUPPORTED, "%s: only 2D grids (dim 2, nz 1) are supported", fn);
+  if (!(dim == 3 || (dim == 2 && nz == 1)))
+    return fail(NFS_EUNSUPPORTED, "%s: dim must be 3, or 2 with nz 1", fn);
   int rc = check_filter_dims(nx, ny, nz, fn);
   if (rc) return rc;
   if (K < 0 || (K > 0 && !kpos) || !mask) return fail(NFS_EINVAL, "%s: NULL or negative argument", fn);
+  if (dim == 3) {
+    double scale = 0.0;
+    for (int64_t k = 0; k < 3 * K; ++k) {
+      if (!std::isfinite(kpos[k])) return fail(NFS_EINVAL, "%s: non-finite position %lld", fn, (long long)(k / 3));
+      scale = std::max(scale, std::fabs(kpos[k]));
+    }
+    std::vector<std::array<double, 4>> planes;
+    if (!convex_hull_3d(kpos, K, scale, &planes))
+      return fail(NFS_EINVAL, "%s: the %lld positions span no volume (fewer than 4 or all on a plane)", fn,
+                  (long long)K);
+    const int64_t cnt = mask_from_planes(planes, nx, ny, nz, 1e-9 * (scale > 1.0 ? scale : 1.0), mask);
+    if (n_inside) *n_inside = cnt;
+    return NFS_OK;
+  }
   const int64_t L = (int64_t)nx * ny;
   std::vector<std::pair<double, double>> pts;
   pts.reserve((size_t)K);

@@ -314,8 +314,8 @@ def lcurve_corner(hist):
 
 def kspace_filter_mask(kpos, dims):
     """k-space filter f (float32 numpy [L], 0/1) of the bins inside the convex
-    hull of the first-order k positions kpos [K][2] (cycles per FOV); host
-    computation, 2D grids only (see include/nfs.h)."""
+    hull of the first-order k positions kpos [K][2] (2D grid) or [K][3] (3D
+    grid), in cycles per FOV; host computation (see include/nfs.h)."""
     import numpy as np
 
     k = np.ascontiguousarray(kpos, dtype=np.float64)

@@ -321,7 +321,7 @@ def test_kspace_filter_mask_host_function_matches_oracle():
     c = ctypes.c_int64()
     m = (ctypes.c_uint8 * 16)()
     k = (ctypes.c_double * 6)(0, 0, 1, 0, 0, 1)
-    assert nfs.lib().nfs_kspace_filter_mask(k, 3, 3, 4, 4, 1, m, ctypes.byref(c)) == nfs.NFS_EUNSUPPORTED
+    assert nfs.lib().nfs_kspace_filter_mask(k, 3, 4, 4, 4, 1, m, ctypes.byref(c)) == nfs.NFS_EUNSUPPORTED
     assert nfs.lib().nfs_kspace_filter_mask(k, 3, 2, 4, 4, 2, m, ctypes.byref(c)) == nfs.NFS_EUNSUPPORTED
     assert nfs.lib().nfs_kspace_filter_mask(None, 3, 2, 4, 4, 1, m, ctypes.byref(c)) == nfs.NFS_EINVAL
     n = ctypes.c_size_t()
@@ -397,3 +397,71 @@ def test_map_argument_checks(L):
     assert L.nfs_sens_initial(_ctx(), A, 17, 6, 100, A, None) == nfs.NFS_ESHAPE
     assert L.nfs_sens_initial(_ctx(), A, 8, 6, -1, A, None) == nfs.NFS_ESHAPE
     assert L.nfs_sens_initial(_ctx(), A, 8, 6, 100, None, None) == nfs.NFS_EINVAL
+
+
+def test_kspace_filter_mask_3d_matches_oracle():
+    """3D hull mask (host quickhull, per-column plane intervals) against the
+    oracle's Delaunay point location, bit for bit except for bins within
+    1e-6 of the hull boundary: a cube (closed form), random ellipsoid clouds
+    and the first-order positions of the 3D spiral workload."""
+    import numpy as np
+
+    import synth
+    from oracle import postproc as PP
+    from scipy.spatial import ConvexHull
+
+    cube = np.array([[x, y, z] for x in (-3.5, 4.5) for y in (-2.5, 3.5) for z in (-1.5, 2.5)] + [[0.1, 0.2, 0.3]])
+    dims = (12, 10, 8)
+    f = nfs.kspace_filter_mask(cube, dims)
+    fr = PP.grid_frequencies(dims)
+    want = ((fr[:, 0] >= -3.5) & (fr[:, 0] <= 4.5) & (fr[:, 1] >= -2.5) & (fr[:, 1] <= 3.5)
+            & (fr[:, 2] >= -1.5) & (fr[:, 2] <= 2.5))
+    assert np.array_equal(f.astype(bool), want)
+    d = synth.make_config("c3s", with_noise=False)
+    # every 16th position: the oracle's 3D Delaunay of all 32000 takes minutes
+    cases = [(d["dims"], d["kcoef"][::16, 1:4].astype(np.float64) / np.pi)]
+    for seed in (1, 2):
+        rng = np.random.default_rng(seed)
+        v = rng.standard_normal((500, 3))
+        v *= (rng.random(500) ** (1 / 3) / np.linalg.norm(v, axis=1))[:, None]
+        cases.append(((20, 18, 14), v * np.array([9.0, 7.0, 5.0])))
+    for dims, kpos in cases:
+        f = nfs.kspace_filter_mask(kpos, dims)
+        ref = PP.kspace_filter_mask(kpos, dims)
+        hull = ConvexHull(kpos)
+        fr = PP.grid_frequencies(dims)
+        dist = np.max(fr @ hull.equations[:, :3].T + hull.equations[:, 3], axis=1)
+        clear = np.abs(dist) > 1e-6
+        print(f"3D mask {dims}, {len(kpos)} positions: {int(f.sum())} bins inside, "
+              f"{int((~clear).sum())} within 1e-6 of the hull")
+        assert np.array_equal(f[clear], ref[clear])
+        assert 0 < f.sum() < f.size
+    L = nfs.lib()
+    c = ctypes.c_int64()
+    m = (ctypes.c_uint8 * 64)()
+    flat = (ctypes.c_double * 15)(0, 0, 0, 1, 0, 0, 0, 1, 0, 1, 1, 0, 0.5, 0.5, 0)  # coplanar
+    assert L.nfs_kspace_filter_mask(flat, 5, 3, 4, 4, 4, m, ctypes.byref(c)) == nfs.NFS_EINVAL
+    assert L.nfs_kspace_filter_mask(flat, 3, 3, 4, 4, 4, m, ctypes.byref(c)) == nfs.NFS_EINVAL  # too few
+
+
+def test_kspace_filter_mask_3d_full_trajectory_sampled():
+    """All 572000 first-order positions of the 96x96x48 3D spiral workload:
+    sampled bins of the native mask against a half-space test with the face
+    equations of scipy's ConvexHull (an independent hull), off the 1e-6
+    boundary band."""
+    import numpy as np
+
+    import synth
+    from oracle import postproc as PP
+    from scipy.spatial import ConvexHull
+
+    d = synth.make_config("c3", with_noise=False)
+    kpos = d["kcoef"][:, 1:4].astype(np.float64) / np.pi
+    f = nfs.kspace_filter_mask(kpos, d["dims"])
+    eq = ConvexHull(kpos).equations
+    fr = PP.grid_frequencies(d["dims"])
+    idx = np.random.default_rng(0).choice(fr.shape[0], 3000, replace=False)
+    dist = np.max(fr[idx] @ eq[:, :3].T + eq[:, 3], axis=1)
+    clear = np.abs(dist) > 1e-6
+    assert np.array_equal(f[idx][clear].astype(bool), dist[clear] < 0)
+    assert 0.3 < f.mean() < 0.9
