@@ -110,3 +110,76 @@ def test_initial_sensitivities_of_an_empty_voxel_are_zero():
     got = M.sens_initial(X)
     assert np.all(got[:, [0, 1, 3, 4]] == 0)
     assert abs(np.linalg.norm(got[:, 2]) - 1.0) < 1e-12
+
+
+def _stacked_rows(dims, order):
+    """Rows of D_order along every axis, by explicit loops over voxels (no
+    shared code with the oracle's sparse assembly): list of (centre voxel,
+    {voxel: coefficient})."""
+    nx = dims[0]
+    ny = dims[1]
+    nz = dims[2] if len(dims) == 3 else 1
+    rows = []
+    for z in range(nz):
+        for y in range(ny):
+            for x in range(nx):
+                c = (x, y, z)
+                for ax, n in enumerate((nx, ny, nz)):
+                    def vid(o):
+                        q = list(c)
+                        q[ax] += o
+                        return q[0] + nx * (q[1] + ny * q[2])
+                    if order == 2 and 1 <= c[ax] <= n - 2:
+                        rows.append((vid(0), {vid(-1): 1.0, vid(0): -2.0, vid(1): 1.0}))
+                    if order == 1 and c[ax] <= n - 2:
+                        rows.append((vid(0), {vid(0): -1.0, vid(1): 1.0}))
+    return rows
+
+
+def _dense_lstsq(dims, data_w, data, pen_w, alpha, order):
+    """Least-squares solution of the stacked system as printed in the
+    smoothing equations: [diag(data_w); sqrt(alpha) diag(pen_w) D] x = [data; 0],
+    by numpy's dense lstsq."""
+    L = int(np.prod(dims))
+    rows = _stacked_rows(dims, order)
+    A = np.zeros((L + len(rows), L))
+    A[np.arange(L), np.arange(L)] = data_w
+    for r, (ctr, coefs) in enumerate(rows):
+        for v, cf in coefs.items():
+            A[L + r, v] = np.sqrt(alpha) * pen_w[ctr] * cf
+    b = np.concatenate([data, np.zeros(len(rows))])
+    return np.linalg.lstsq(A, b, rcond=None)[0], A
+
+
+@pytest.mark.parametrize("dims", [(9, 7), (5, 4, 4)])
+def test_sensitivity_smoothing_is_the_stacked_least_squares_solution(dims):
+    """Random non-binary masks (every voxel carries data, so the system has
+    full column rank): each smoothed component equals the dense lstsq
+    solution of the stacked system [diag(M_T); sqrt(a) diag(M_R) D2] S = [S^; 0]."""
+    rng = np.random.default_rng(8)
+    L = int(np.prod(dims))
+    mT = 0.3 + rng.random(L)
+    mR = rng.random(L)
+    s = (1 + rng.random((2, L))) * np.exp(1j * rng.uniform(-1, 1, (2, L)))
+    alpha = 2.5
+    got = M.smooth_sens(s, mT, mR, dims, alpha)
+    for c in range(2):
+        mag = np.abs(s[c])
+        nrm = s[c] / mag
+        m_s, _ = _dense_lstsq(dims, mT, mag, mR, alpha, 2)
+        re_s, _ = _dense_lstsq(dims, mT, nrm.real, mR, alpha, 2)
+        im_s, _ = _dense_lstsq(dims, mT, nrm.imag, mR, alpha, 2)
+        n_s = re_s + 1j * im_s
+        want = m_s * n_s / np.abs(n_s)
+        assert np.allclose(got[c], want, rtol=1e-9, atol=1e-12)
+
+
+@pytest.mark.parametrize("dims", [(8, 6), (4, 5, 3)])
+def test_b0_smoothing_is_the_stacked_least_squares_solution(dims):
+    rng = np.random.default_rng(9)
+    L = int(np.prod(dims))
+    b0 = rng.standard_normal(L) * 50
+    eps = rng.random(L)
+    got = M.smooth_b0(b0, eps, dims, 7.0)
+    want, _ = _dense_lstsq(dims, np.ones(L), b0, eps, 7.0, 1)
+    assert np.allclose(got, want, rtol=1e-10, atol=1e-10)
