@@ -1308,6 +1308,9 @@ static std::vector<std::vector<int>> assign_lanes(int n_slices, const nfs_proble
   return lanes;
 }
 
+// Slices' layouts one after another, then kBatchCounters work-list counters
+// of the persistent launches (the last offset in offs).
+constexpr int kBatchCounters = 256;
 static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs, int precision, int n_iter, int reorth,
                             std::vector<Layout>* ys, std::vector<size_t>* offs) {
   size_t tot = 0;
@@ -1317,7 +1320,8 @@ static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs,
     tot += al(y.total);
     if (ys) ys->push_back(y);
   }
-  return tot;
+  if (offs) offs->push_back(tot);
+  return tot + al(kBatchCounters * sizeof(int));
 }
 
 extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
@@ -1394,12 +1398,20 @@ static bool lockstep_ok(int n, const std::vector<Layout>& ys) {
 // by side; each gets a grid of its resident workgroups (the encode kernel's
 // registers allow four per CU up to two column blocks or with two held
 // tiles, three for four column blocks with four held tiles).
-static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, int op, hipStream_t s) {
+static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, int op, int* counters,
+                             hipStream_t s) {
   std::map<int, std::vector<int>> groups;  // (NQ * 8 + NB) * 8 + MT -> slices
   for (size_t i = 0; i < runs.size(); ++i) {
     const EncodeShape& sh = op == OP_E ? runs[i].y->shE : runs[i].y->shH;
     groups[(sh.NQ * 8 + sh.NB) * 8 + sh.MT].push_back((int)i);
   }
+  // longest items first: slices by streamed chunks per item, descending
+  for (auto& g : groups)
+    std::stable_sort(g.second.begin(), g.second.end(), [&](int a, int b) {
+      const EncodeShape& sa = op == OP_E ? runs[a].y->shE : runs[a].y->shH;
+      const EncodeShape& sb = op == OP_E ? runs[b].y->shE : runs[b].y->shH;
+      return sa.cps > sb.cps;
+    });
   std::vector<EncodeBatch> batches;
   std::vector<int> keys;
   for (const auto& g : groups)
@@ -1427,6 +1439,9 @@ static int persistent_encode(nfs_ctx* ctx, const std::vector<SliceRun>& runs, in
     hipStream_t sk = fork ? ctx->bstreams[k % kBatchStreams] : s;
     if (fork) NFS_TRY(hipStreamWaitEvent(sk, ctx->fork_event, 0), "hipStreamWaitEvent");
     const int per_cu = NB <= 2 || MT == 2 ? 4 : 3;
+    if (k >= kBatchCounters / 2) return fail(NFS_EINVAL, "encode_persistent: too many shape classes");
+    batches[k].counter = counters + (op == OP_E ? 0 : kBatchCounters / 2) + k;
+    NFS_TRY(launch_fill_zero(reinterpret_cast<float*>(batches[k].counter), 1, sk), "fill_zero(counter)");
     NFS_TRY(launch_encode_persistent(op, runs[0].y->prec, NQ, NB, MT, batches[k], per_cu * ctx->n_cu, sk),
             "encode_persistent");
   }
@@ -1461,6 +1476,7 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
                            const std::vector<size_t>& offs, const float* const* m, float* const* rho, int n_iter,
                            double tol, int replace_every, int reorth, double* const* hist, int* const* info, void* ws,
                            const std::vector<std::vector<int>>& lanes, hipStream_t s) {
+  int* counters = at<int>(ws, offs[n]);
   std::vector<SliceRun> runs(n);
   for (int i = 0; i < n; ++i) {
     SliceRun& r = runs[i];
@@ -1517,7 +1533,7 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
     return pre_EH(c, reinterpret_cast<const float2*>(r.m), 1, y.K);
   });
   if (rc) return rc;
-  if ((rc = persistent_encode(ctx, runs, OP_EH, s))) return rc;
+  if ((rc = persistent_encode(ctx, runs, OP_EH, counters, s))) return rc;
   rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
     Ctx c = ctx_of(r, sk);
     NFS_TRY(launch_cg_init(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1), r.x,
@@ -1536,10 +1552,10 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
       return of_x ? pre_E(c, r.x, false) : pre_E(c, r.st.p, scaled_prec(r.y->prec));
     });
     if (e) return e;
-    if ((e = persistent_encode(ctx, runs, OP_E, s))) return e;
+    if ((e = persistent_encode(ctx, runs, OP_E, counters, s))) return e;
     e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int { return mid_EHE(ctx_of(r, sk)); });
     if (e) return e;
-    return persistent_encode(ctx, runs, OP_EH, s);
+    return persistent_encode(ctx, runs, OP_EH, counters, s);
   };
   for (int it = 0; it < n_iter; ++it) {
     if ((rc = ehe_all(false))) return rc;

@@ -640,23 +640,29 @@ __global__ __launch_bounds__(256) void encode_kernel(
                                      b % gridDim.x, b / gridDim.x, stage[0], stage[1]);
 }
 
-// Persistent form for many problems (slices) at once: a fixed grid walks the
-// work list of every slice's (held-tile block, split) items, item w at
-// workgroups w mod gridDim.x, in XCD order, so one launch covers slices of
-// different sizes (one launch per column-block count NB, which fixes the
-// kernel's registers).  Items of a slice whose stop flag is set are
-// skipped.  Every item runs exactly the code of the single-problem kernel,
-// so results are bit-identical to it.
+// Persistent form for many problems (slices) at once: a fixed grid takes the
+// items of every slice's (held-tile block, split) work list in list order
+// from an atomic counter (the host puts the longest items first), so one
+// launch covers slices of different sizes (one launch per column-block
+// count NB, which fixes the kernel's registers) and balances their uneven
+// costs.  The loop ends for every workgroup once the counter passes the
+// list's end.  Items of a slice whose stop flag is set are skipped.  Every
+// item runs exactly the code of the single-problem kernel, so results are
+// bit-identical to it.
 template <int OP, int PREC, int NQ, int NB, int MT>
 __global__ __launch_bounds__(256) void encode_persistent_kernel(EncodeBatch batch) {
   __shared__ u4 stage[2][Stream<PREC, NB, NQ>::NBLK * 64];
+  __shared__ int next;
   const int64_t total = batch.total;
-  for (int64_t w = blockIdx.x; w < total; w += gridDim.x) {
-    const int64_t b = xcd_order(w, total);
+  for (;;) {
+    __syncthreads();  // the previous item's reads of the staging buffers and of `next` are done
+    if (threadIdx.x == 0) next = atomicAdd(batch.counter, 1);
+    __syncthreads();
+    const int64_t b = next;
+    if (b >= total) break;
     int i = 0;
     while (i + 1 < batch.n && b >= batch.it[i + 1].first) ++i;
     const EncodeItem& e = batch.it[i];
-    __syncthreads();  // the previous item's reads of the staging buffers are done
     if (e.stop && *e.stop) continue;
     const int64_t lb = b - e.first;
     encode_block<OP, PREC, NQ, NB, MT>((const u4*)e.heldcoef, (const u4*)e.strmcoef, e.sdata, e.HC, e.SC, e.cps,
@@ -1001,7 +1007,8 @@ bool persistent_supported(int prec, int NQ, int NB, int MT) {
 hipError_t launch_encode_persistent(int op, int prec, int NQ, int NB, int MT, const EncodeBatch& b, int grid,
                                     hipStream_t s) {
   if (b.total == 0) return hipSuccess;
-  if (b.n < 1 || b.n > kMaxBatchItems || grid < 1 || !persistent_supported(prec, NQ, NB, MT))
+  if (b.n < 1 || b.n > kMaxBatchItems || grid < 1 || !b.counter || !persistent_supported(prec, NQ, NB, MT) ||
+      b.total > INT32_MAX)
     return hipErrorInvalidValue;
   for (int i = 0; i < b.n; ++i)
     if (b.it[i].NB != NB || b.it[i].T < 1 || b.it[i].T > kMaxTerms) return hipErrorInvalidValue;

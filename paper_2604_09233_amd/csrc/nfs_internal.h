@@ -75,7 +75,8 @@ struct EncodeShape {
 // One problem (slice) of a persistent encode launch: the arguments of its
 // single-problem launch, its held-tile block count gx (the single launch's
 // grid x), and the index of its first item in the launch's work list
-// (items: gx * nsplit per slice, slices in list order).
+// (items: gx * nsplit per slice, slices in list order; workgroups take
+// items in list order from an atomic counter).
 struct EncodeItem {
   const void* heldcoef;
   const void* strmcoef;
@@ -94,6 +95,7 @@ struct EncodeBatch {
   EncodeItem it[kMaxBatchItems];
   int n;
   int64_t total;  // items in the work list
+  int* counter;   // next item to take (device int, zero at launch)
 };
 // Whether a persistent launch handles this operand form and shape
 // (FP16 / BF16 operands, NQ <= 2, NB in {1, 2, 4}).
