@@ -1534,6 +1534,13 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
   });
   if (rc) return rc;
   if ((rc = persistent_encode(ctx, runs, OP_EH, counters, s))) return rc;
+  // Per iteration two fork-joins: the E^H packing between the persistent E
+  // and E^H launches, and the CG vector updates together with the packing
+  // of the next iteration's E operand (a residual replacement adds one
+  // more E^H E of the iterate).
+  auto pre_E_dir = [&](SliceRun& r, hipStream_t sk) -> int {
+    return pre_E(ctx_of(r, sk), r.st.p, scaled_prec(r.y->prec));
+  };
   rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
     Ctx c = ctx_of(r, sk);
     NFS_TRY(launch_cg_init(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1), r.x,
@@ -1541,50 +1548,55 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
             "cg_init");
     NFS_TRY(launch_cg_start(r.st, n_iter, sk), "cg_start");
     if (reorth) NFS_TRY(launch_cg_store_v(r.st, 0, sk), "cg_store_v");
-    return NFS_OK;
+    return n_iter > 0 ? pre_E_dir(r, sk) : NFS_OK;
   });
   if (rc) return rc;
-  // one E^H E of every slice's v (the direction, or the iterate for a
-  // residual replacement)
-  auto ehe_all = [&](bool of_x) -> int {
-    int e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
-      Ctx c = ctx_of(r, sk);
-      return of_x ? pre_E(c, r.x, false) : pre_E(c, r.st.p, scaled_prec(r.y->prec));
-    });
+  // E (operand already packed), E^H packing, E^H
+  auto ehe_rest = [&]() -> int {
+    int e = persistent_encode(ctx, runs, OP_E, counters, s);
     if (e) return e;
-    if ((e = persistent_encode(ctx, runs, OP_E, counters, s))) return e;
     e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int { return mid_EHE(ctx_of(r, sk)); });
     if (e) return e;
     return persistent_encode(ctx, runs, OP_EH, counters, s);
   };
   for (int it = 0; it < n_iter; ++it) {
-    if ((rc = ehe_all(false))) return rc;
+    if ((rc = ehe_rest())) return rc;
     const bool replace = replace_every > 0 && (it + 1) % replace_every == 0 && it + 1 < n_iter;
+    const bool more = it + 1 < n_iter;
     const int nv = reorth ? it + 1 : 0;
-    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+    auto beta_update = [&](SliceRun& r, hipStream_t sk) -> int {
       Ctx c = ctx_of(r, sk);
       NFS_TRY(launch_cg_beta(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1),
                              r.y->L, sk),
               "cg_beta");
       NFS_TRY(launch_cg_update(r.st, r.x, r.y->L, it, replace ? 0 : nv, sk), "cg_update");
       return NFS_OK;
-    });
-    if (rc) return rc;
-    if (replace) {
-      if ((rc = ehe_all(true))) return rc;
-      rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
-        Ctx c = ctx_of(r, sk);
-        NFS_TRY(launch_cg_replace(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1),
-                                  r.y->L, nv, sk),
-                "cg_replace");
-        return NFS_OK;
-      });
-      if (rc) return rc;
-    }
-    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+    };
+    auto finish_iteration = [&](SliceRun& r, hipStream_t sk) -> int {
       if (reorth) NFS_TRY(launch_cg_reorth_apply(r.st, nv, !replace, sk), "cg_reorth_apply");
       NFS_TRY(launch_cg_direction(r.st, r.y->L, it, n_iter, tol, sk), "cg_direction");
-      return NFS_OK;
+      return more ? pre_E_dir(r, sk) : NFS_OK;
+    };
+    if (!replace) {
+      rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+        const int e = beta_update(r, sk);
+        return e ? e : finish_iteration(r, sk);
+      });
+      if (rc) return rc;
+      continue;
+    }
+    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+      const int e = beta_update(r, sk);
+      return e ? e : pre_E(ctx_of(r, sk), r.x, false);
+    });
+    if (rc) return rc;
+    if ((rc = ehe_rest())) return rc;
+    rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
+      Ctx c = ctx_of(r, sk);
+      NFS_TRY(launch_cg_replace(r.st, at<float2>(r.ws, r.y->o_hpart), r.y->shH.nsplit, hs(r), unscale_slot(c, 1),
+                                r.y->L, nv, sk),
+              "cg_replace");
+      return finish_iteration(r, sk);
     });
     if (rc) return rc;
   }
