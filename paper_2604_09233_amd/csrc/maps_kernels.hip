@@ -265,17 +265,20 @@ __host__ __device__ __forceinline__ int tile_count(const Grid3& g) {
 }
 
 // load(i, interior, x, y, z): value of voxel i at (x, y, z) (interior: i
-// belongs to this tile); row(j, c, val, wt): the output of voxel j at
-// coordinates c from the accessors of the vector and of the penalty weights
-// w, whose planes z-1 .. z+1 are held in a second LDS ring.  The vector's
-// plane two ahead and the weights' plane one ahead are fetched into
-// registers while the current plane is computed, so the loads of one plane
-// overlap the arithmetic of the last.
+// belongs to this tile); cload(j): the per-voxel values the output of voxel
+// j needs besides the stencil (right-hand side, inverse diagonal, data
+// weight); row(j, c, val, wt, cv): the output of voxel j at coordinates c
+// from the accessors of the vector and of the penalty weights w, whose
+// planes z-1 .. z+1 are held in a second LDS ring, and cv = cload(j).  The
+// vector's plane two ahead, the weights' plane one ahead and the next
+// plane's per-voxel values are fetched into registers while the current
+// plane is computed, so the loads of one plane overlap the arithmetic of
+// the last.
 constexpr int kWRing = 3;
 
-template <class Load, class Row>
+template <class Load, class CLoad, class Row>
 __device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], double (*wring)[kPlane],
-                                      const double* __restrict__ w, Load&& load, Row&& row) {
+                                      const double* __restrict__ w, Load&& load, CLoad&& cload, Row&& row) {
   const int nx = g.n[0], ny = g.n[1], nz = g.n[2];
   const int ntx = (nx + kTileX - 1) / kTileX;
   const int x0 = (int)(blockIdx.x % ntx) * kTileX, y0 = (int)(blockIdx.x / ntx) * kTileY;
@@ -312,6 +315,9 @@ __device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], do
   wring[0][e0] = fetch_w(0, e0);
   if (has1) wring[0][e1] = fetch_w(0, e1);
   double n0 = 0.0, n1 = 0.0, m0 = 0.0, m1 = 0.0;
+  auto at_ij = [&](int z) { return (int64_t)gx + g.s[1] * gy + g.s[2] * z; };
+  decltype(cload(int64_t(0))) cv{};
+  if (mine) cv = cload(at_ij(0));
   if (kHalo < nz) {
     n0 = fetch(kHalo, e0);
     if (has1) n1 = fetch(kHalo, e1);
@@ -338,9 +344,11 @@ __device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], do
       m0 = fetch_w(z + 2, e0);
       if (has1) m1 = fetch_w(z + 2, e1);
     }
+    decltype(cv) cn{};
+    if (mine && z + 1 < nz) cn = cload(at_ij(z + 1));
     if (mine) {
       const int c[3] = {gx, gy, z};
-      const int64_t j = gx + g.s[1] * gy + g.s[2] * z;
+      const int64_t j = at_ij(z);
       const double* here = ring[z % kRing];
       const double* what = wring[z % kWRing];
       auto val = [&](int d, int k) -> double {
@@ -353,8 +361,9 @@ __device__ __forceinline__ void march(const Grid3& g, double (*ring)[kPlane], do
         if (d == 1) return what[ctr + k * kPlaneX];
         return wring[(z + k + kWRing) % kWRing][ctr];
       };
-      row(j, c, val, wt);
+      row(j, c, val, wt, cv);
     }
+    cv = cn;
     __syncthreads();
   }
 }
@@ -530,8 +539,9 @@ __global__ void __launch_bounds__(256) pcg_apply_kernel(PcgState st, Grid3 g, co
         if (interior) pn[i] = v;
         return v;
       },
-      [&](int64_t j, const int c[3], auto& val, auto& wt) {
-        const double qj = apply_row<OP>(g, OP == MAP_SENS ? t[j] : 1.0, alpha, c, val, wt);
+      [&](int64_t j) { return OP == MAP_SENS ? t[j] : 1.0; },
+      [&](int64_t j, const int c[3], auto& val, auto& wt, double tj) {
+        const double qj = apply_row<OP>(g, tj, alpha, c, val, wt);
         q[j] = qj;
         pq += val(0, 0) * qj;
       });
@@ -763,17 +773,18 @@ __global__ void __launch_bounds__(256) mg_stencil_kernel(const int* __restrict__
         if (MODE != MG_POST) return xv[i];
         return xv[i] + interpolate(cv, g, gc, xi, yi, zi);
       },
-      [&](int64_t j, const int c[3], auto& val, auto& wt) {
-        const double res = bv[j] - apply_row<OP>(g, OP == MAP_SENS ? t[j] : 1.0, alpha, c, val, wt);
+      [&](int64_t j) { return double3{bv[j], MODE == MG_RESIDUAL ? 0.0 : dinv[j], OP == MAP_SENS ? t[j] : 1.0}; },
+      [&](int64_t j, const int c[3], auto& val, auto& wt, double3 cv) {
+        const double res = cv.x - apply_row<OP>(g, cv.z, alpha, c, val, wt);
         if (MODE == MG_RESIDUAL) {
           yv[j] = res;
           return;
         }
-        const double dj = dinv[j];
+        const double dj = cv.y;
         double yj = fma(omega, dj * res, val(0, 0));
         if (MODE == MG_LAST) {
           if (dj == 0.0) yj = 0.0;
-          dot += bv[j] * yj;
+          dot += cv.x * yj;
         }
         yv[j] = yj;
       });
