@@ -244,7 +244,9 @@ int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int n
  * nfs_cg_solve); hist, info: host arrays of device pointers, or NULL (and
  * individual entries may be NULL).  The workspace (256-byte aligned, at
  * least nfs_workspace_bytes_batched bytes) is split into one CG workspace
- * per slice.                                                               */
+ * per slice (each nfs_workspace_bytes of that slice, rounded up to 256) and
+ * a 1 KiB block of work-list counters for the persistent form; 0 bytes for
+ * n_slices 0, which returns NFS_OK without work.                          */
 int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
                                 int n_iter, int reorth, size_t* bytes);
 int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, const float* const* m,

@@ -1321,7 +1321,7 @@ static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs,
     if (ys) ys->push_back(y);
   }
   if (offs) offs->push_back(tot);
-  return tot + al(kBatchCounters * sizeof(int));
+  return n ? tot + al(kBatchCounters * sizeof(int)) : 0;
 }
 
 extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
@@ -1629,11 +1629,11 @@ extern "C" int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_proble
   }
   std::vector<Layout> ys;
   std::vector<size_t> offs;
+  if (n_slices == 0) return NFS_OK;
   const size_t need = batch_layouts(ctx, n_slices, probs, precision, n_iter, reorth, &ys, &offs);
   if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
   if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
   if (ws_bytes < need) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, need);
-  if (n_slices == 0) return NFS_OK;
   if ((rc = ensure_batch_streams(ctx))) return rc;
   const std::vector<std::vector<int>> lanes = assign_lanes(n_slices, probs);
   const int ns = (int)lanes.size();

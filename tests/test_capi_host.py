@@ -169,13 +169,17 @@ def test_batched_validation(L):
     ok = (nfs.nfs_problem * 2)(prob(), prob(L=64, K=99, G=3, P=16))
     assert f(c, 2, ok, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1, None) == nfs.NFS_EWORKSPACE
     assert f(c, 0, ok, ptrs, ptrs, 5, 0.0, 0, 0, 0, None, None, A, 1, None) == nfs.NFS_OK  # nothing to do
+    assert f(c, 0, None, None, None, 5, 0.0, 0, 0, 0, None, None, None, 0, None) == nfs.NFS_OK
     n = ctypes.c_size_t()
     assert L.nfs_workspace_bytes_batched(None, 2, ok, 2, 30, 1, ctypes.byref(n)) == 0
     one = ctypes.c_size_t()
     L.nfs_workspace_bytes(None, ctypes.byref(ok[0]), 3, 2, 30, 1, ctypes.byref(one))
     two = ctypes.c_size_t()
     L.nfs_workspace_bytes(None, ctypes.byref(ok[1]), 3, 2, 30, 1, ctypes.byref(two))
-    assert n.value == one.value + two.value
+    al = lambda b: (b + 255) // 256 * 256
+    assert n.value == al(one.value) + al(two.value) + 1024  # per-slice workspaces, then the work-list counters
+    z = ctypes.c_size_t(7)
+    assert L.nfs_workspace_bytes_batched(None, 0, None, 2, 30, 1, ctypes.byref(z)) == 0 and z.value == 0
     assert L.nfs_set_graphs(None, 1) == nfs.NFS_EINVAL
 
 
