@@ -69,6 +69,8 @@ def parse():
     ap.add_argument("--no-maps", action="store_true", help="skip the sensitivity / B0 map-estimation measurement")
     ap.add_argument("--profile-run", action="store_true",
                     help="one solve only (no side measurements, no CPU baseline), for counter collection")
+    ap.add_argument("--no-compress", action="store_true",
+                    help="solve with the full phase basis instead of its compressed form (nfs_compress_basis)")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every solve eagerly instead of replaying it from a captured hipGraph")
     return ap.parse_args()
@@ -338,21 +340,39 @@ def main():
     m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
     torch.cuda.synchronize()
 
+    # Phase-basis compression, once per geometry (like the shape tuning):
+    # the 16 solid harmonics on one slice span 10 functions, and the
+    # per-sample offset theta cancels in E^H E.  The solve then runs on the
+    # compressed problem with data exp(-i theta) m, the rotation inside the
+    # timed step.
+    prob_full = prob
+    theta, basis = None, None
+    if not args.no_compress:
+        prob, theta, cinfo = nfs.compress_basis(prob_full)
+        basis = dict(terms=d["n_basis"] + 1, compressed_terms=prob.P + 1, err_bound_rad=cinfo["err_bound"])
+    m_solve = m if theta is None else nfs.phase_shift(m, theta, -1)
+    m_buf = torch.empty_like(m)
+    torch.cuda.synchronize()
+
     progress("autotune and the c2 solve")
     tuned = {}
     if not args.no_tune:
         for prec in {args.precision, "fp32", "bf16"}:
             tuned[prec] = nfs.autotune(prob, prec)
 
-    def solve(prec, out, hist, info, reorth):
-        return nfs.cg_solve(prob, m, n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
+    def solve(prec, out, hist, info, reorth, p=None):
+        p = prob if p is None else p
+        data = m
+        if p is not prob_full:
+            data = nfs.phase_shift(m, theta, -1, out=m_buf)
+        return nfs.cg_solve(p, data, n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
 
-    def time_solves(prec, steps, warmup, profile=False, reorth=not args.plain):
+    def time_solves(prec, steps, warmup, profile=False, reorth=not args.plain, p=None):
         out = torch.empty(L, dtype=torch.complex64, device=dev)
         hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
         info = torch.zeros(2, dtype=torch.int32, device=dev)
         for _ in range(warmup):
-            solve(prec, out, hist, info, reorth)
+            solve(prec, out, hist, info, reorth, p)
         torch.cuda.synchronize()
         if profile:
             nfs.profile_enable(0, True)
@@ -362,7 +382,7 @@ def main():
         t0 = time.perf_counter()
         ev0.record()
         for _ in range(steps):
-            solve(prec, out, hist, info, reorth)
+            solve(prec, out, hist, info, reorth, p)
         ev1.record()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
@@ -419,6 +439,17 @@ def main():
         return dict(ms_per_step=ms_f, value=(n_iter + 0.5) * vsc / (ms_f * 1e-3),
                     rel_err_vs_oracle=rel(rho_f.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
 
+    full_basis = None
+    if basis is not None:
+        # the same solve on the uncompressed basis (17 terms: two phase
+        # instructions per tile)
+        if not args.no_tune:
+            nfs.autotune(prob_full, args.precision)
+        rho_u, _, _, ms_u, _, _ = time_solves(args.precision, max(1, args.steps // 2), 1, p=prob_full)
+        full_basis = dict(ms_per_step=ms_u, value=(n_iter + 0.5) * vsc / (ms_u * 1e-3),
+                          rel_err_vs_oracle=rel(rho_u.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
+        basis["full_basis_form"] = full_basis
+        del rho_u
     fp32 = form("fp32") if not args.no_fp32_form and args.precision != "fp32" else None
     bf16 = form("bf16") if not args.no_fp32_form and args.precision != "bf16" else None
     # plain recurrences, same precision, for reference
@@ -444,7 +475,7 @@ def main():
     # instructions, and per 16-column block of the 2G real columns one f16
     # 16x16x32 (fp16), two bf16 16x16x32 (bf16: hi and lo data parts) or
     # three f16 16x16x32 (fp32: split operands) contraction instructions
-    P = d["n_basis"]
+    P = prob.P  # terms of the basis the solve runs on
     nq = -(-3 * (P + 1) // 32)
     nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
     tiles = pairs / 256.0
@@ -470,11 +501,11 @@ def main():
             o = torch.empty(L, dtype=torch.complex64, device=dev)
             h = torch.full((n + 1, 3), float("nan"), dtype=torch.float64, device=dev)
             f = torch.zeros(2, dtype=torch.int32, device=dev)
-            nfs.cg_solve_resident(prob, m, n, reorth=not args.plain, out=o, hist=h, info=f)
+            nfs.cg_solve_resident(prob, m_solve, n, reorth=not args.plain, out=o, hist=h, info=f)
             torch.cuda.synchronize()
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
-            nfs.cg_solve_resident(prob, m, n, reorth=not args.plain, out=o, hist=h, info=f)
+            nfs.cg_solve_resident(prob, m_solve, n, reorth=not args.plain, out=o, hist=h, info=f)
             e1.record()
             torch.cuda.synchronize()
             return o, e0.elapsed_time(e1)
@@ -496,7 +527,7 @@ def main():
         n_long = 250
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
         ev[0].record()
-        _, h_long, i_long, its = nfs.cg_solve_traced(prob, m, n_long, precision=args.precision,
+        _, h_long, i_long, its = nfs.cg_solve_traced(prob, m_solve, n_long, precision=args.precision,
                                                      reorth=not args.plain)
         ev[1].record()
         ss = nfs.ssim(its[1:], torch.from_numpy(d["rho_true"]), d["dims"])
@@ -555,7 +586,8 @@ def main():
         "config": {"workload": f"{args.config}: 2D 128x128, 16 coils, 4x15000-sample R=4 spiral, 16 field terms, "
                                f"B0 +-100 Hz, {n_iter} CG iterations (one step = one CG solve)",
                    "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision,
-                   "cg": "plain" if args.plain else "re-orthogonalised", "hip_graphs": not args.no_graphs},
+                   "cg": "plain" if args.plain else "re-orthogonalised", "hip_graphs": not args.no_graphs,
+                   "phase_basis": basis, "phase_instructions_per_tile": nq},
         "rel_err_vs_oracle": err,
         "encode_shapes": {"tuned": not args.no_tune,
                           "held_tiles_nsplit": nfs.tuned_shape(prob, args.precision)},

@@ -234,6 +234,46 @@ int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* out, int nx, 
 int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int ny, int nz, unsigned char* mask,
                            int64_t* n_inside);
 
+/* Phase-basis compression (host computation on host arrays).  The phase of
+ * the signal model, phi(k, l) = t[k] b0[l] + sum_p kcoef[k][p] fields[p][l]
+ * (the encoding matrix as the product of the sample-side and voxel-side
+ * coefficient matrices), is rewritten as
+ *   phi(k, l) = theta[k] + t'[k] b0'[l] + sum_{p < P'} kcoef'[k][p] fields'[p][l]
+ * with P' + 1 <= P + 1 terms: each voxel-side row is scaled by its term's
+ * largest sample coefficient and centred (its mean goes into the per-sample
+ * offset theta), and the centred rows are replaced by their leading
+ * principal directions (double-precision Gram matrix, Jacobi eigenvectors),
+ * as many as make
+ *   max_l sum_b |residual_b(l)| <= rel_tol * sum_b max|a_b| max|h_b|,
+ * which bounds |phi' - phi| at every (k, l) by that fraction of the phase
+ * bound.  rel_tol <= 0 selects 2^-24.  A basis evaluated on a lower-
+ * dimensional set (16 solid harmonics up to third order on one slice span
+ * the 10 polynomials of degree <= 3 in two variables) loses its dependent
+ * terms, so every tile phase takes fewer matrix-core products.
+ * Since theta depends on the sample only, E^H E is unchanged; the original
+ * operators follow from the compressed ones as
+ *   E m = diag(exp(+i theta)) E' m,   E^H m = E'^H (diag(exp(-i theta)) m)
+ * (nfs_phase_shift), so a CG solve of the compressed problem on data
+ * exp(-i theta) m returns the solution of the original one.
+ * Inputs: HOST float arrays laid out as in nfs_problem (fields [P][L], b0 [L],
+ * kcoef [K][P], t [K]).  Outputs (HOST, caller-allocated at the input sizes):
+ * fields_out rows 0..P'-1 of [P][L], b0_out [L], kcoef_out the first K P'
+ * entries as [K][P'] (row-major, P' columns), t_out [K], theta [K] double
+ * (rad), *n_basis_out = P', *err_bound (may be NULL) = the residual bound
+ * reached (rad).  NFS_EINVAL for NULL or non-finite inputs or a negative
+ * rel_tol, NFS_ESHAPE for sizes outside those of nfs_problem.  The outputs
+ * go into an nfs_problem with n_basis P' and the original sens and icorr. */
+int nfs_compress_basis(const float* fields, const float* b0, const float* kcoef, const float* t, int64_t L,
+                       int64_t K, int P, double rel_tol, float* fields_out, float* b0_out, float* kcoef_out,
+                       float* t_out, double* theta, int* n_basis_out, double* err_bound);
+
+/* out[c][k] = m[c][k] exp(i sign theta[k]) for sign = +1 or -1 (the
+ * per-sample offset of nfs_compress_basis), rotation in double precision.
+ * m, out: DEVICE [G][K] complex (out == m allowed); theta: DEVICE [K]
+ * double.  Launched on `stream`.                                          */
+int nfs_phase_shift(nfs_ctx* ctx, const float* m, float* out, int n_coil, int64_t K, const double* theta, int sign,
+                    void* stream);
+
 /* Many independent reconstructions (slices with uneven L, K and G) solved
  * together: each slice runs exactly the nfs_cg_solve sequence (same kernels,
  * so each slice's result is bit-identical to its single solve), forked from

@@ -2265,3 +2265,195 @@ extern "C" int nfs_b0_map(nfs_ctx* ctx, const float* imgs, int n_coil, int n_ech
   NFS_TRY(launch_b0_store(st.x, L, b0, b064, s), fn);
   return NFS_OK;
 }
+
+// ---------------------------------------------------------------------------
+// Phase-basis compression (host).  phi(k, l) = sum_b a_b(k) h_b(l) over the
+// T = P + 1 terms (a_0 = t, h_0 = b0; a_{b+1} = kcoef[.][b], h_{b+1} =
+// fields[b]).  With s_b = max_k |a_b| and the scaled rows h^_b = s_b h_b,
+// mu_b = mean_l h^_b and A_b = h^_b - mu_b, the phase is exactly
+//   phi = theta(k) + sum_b (a_b / s_b)(k) A_b(l),  theta = sum_b (a_b / s_b) mu_b.
+// The rows A_b span a space of some numerical rank r <= T; with U the
+// eigenvectors of the Gram matrix A A^T (cyclic Jacobi, largest eigenvalue
+// first), direction j has voxel side h'_j = sum_b U_bj A_b and sample side
+// a'_j = sum_b (a_b / s_b) U_bj.  Directions are added in that order until
+// the residual E_b = A_b - sum_{j <= r} U_bj h'_j satisfies
+//   max_l sum_b |E_b(l)| <= rel_tol * sum_b max|a_b| max|h_b|,
+// which bounds the phase change at every (k, l), since |a_b / s_b| <= 1.
+// Everything runs in double precision; the outputs are rounded once.
+
+// eigenvalues (descending) and eigenvectors (columns of U, row-major T x T)
+// of the symmetric matrix S (row-major, overwritten), by cyclic Jacobi
+// rotations
+static void jacobi_eigen(std::vector<double>& S, int T, std::vector<double>* lam, std::vector<double>* U) {
+  std::vector<double> V((size_t)T * T, 0.0);
+  for (int i = 0; i < T; ++i) V[(size_t)i * T + i] = 1.0;
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0.0, diag = 0.0;
+    for (int p = 0; p < T; ++p) {
+      diag += S[(size_t)p * T + p] * S[(size_t)p * T + p];
+      for (int q = p + 1; q < T; ++q) off += S[(size_t)p * T + q] * S[(size_t)p * T + q];
+    }
+    if (off <= 1e-34 * diag || off == 0.0) break;
+    for (int p = 0; p < T; ++p)
+      for (int q = p + 1; q < T; ++q) {
+        const double apq = S[(size_t)p * T + q];
+        if (apq == 0.0) continue;
+        const double app = S[(size_t)p * T + p], aqq = S[(size_t)q * T + q];
+        // rotation angle that zeroes S[p][q]: tan(theta) = t, the smaller root
+        const double zeta = (aqq - app) / (2.0 * apq);
+        const double t = (zeta >= 0 ? 1.0 : -1.0) / (std::fabs(zeta) + std::sqrt(1.0 + zeta * zeta));
+        const double c = 1.0 / std::sqrt(1.0 + t * t), s = t * c;
+        for (int k = 0; k < T; ++k) {  // columns p, q
+          const double skp = S[(size_t)k * T + p], skq = S[(size_t)k * T + q];
+          S[(size_t)k * T + p] = c * skp - s * skq;
+          S[(size_t)k * T + q] = s * skp + c * skq;
+        }
+        for (int k = 0; k < T; ++k) {  // rows p, q
+          const double spk = S[(size_t)p * T + k], sqk = S[(size_t)q * T + k];
+          S[(size_t)p * T + k] = c * spk - s * sqk;
+          S[(size_t)q * T + k] = s * spk + c * sqk;
+        }
+        for (int k = 0; k < T; ++k) {
+          const double vkp = V[(size_t)k * T + p], vkq = V[(size_t)k * T + q];
+          V[(size_t)k * T + p] = c * vkp - s * vkq;
+          V[(size_t)k * T + q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  std::vector<int> order(T);
+  for (int i = 0; i < T; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return S[(size_t)x * T + x] > S[(size_t)y * T + y]; });
+  lam->assign(T, 0.0);
+  U->assign((size_t)T * T, 0.0);
+  for (int j = 0; j < T; ++j) {
+    (*lam)[j] = S[(size_t)order[j] * T + order[j]];
+    for (int b = 0; b < T; ++b) (*U)[(size_t)b * T + j] = V[(size_t)b * T + order[j]];
+  }
+}
+
+extern "C" int nfs_compress_basis(const float* fields, const float* b0, const float* kcoef, const float* t,
+                                  int64_t L, int64_t K, int P, double rel_tol, float* fields_out, float* b0_out,
+                                  float* kcoef_out, float* t_out, double* theta, int* n_basis_out,
+                                  double* err_bound) {
+  const char* fn = "nfs_compress_basis";
+  const int64_t lim = (int64_t)1 << 26;
+  if (L < 0 || L > lim || K < 0 || K > lim) return fail(NFS_ESHAPE, "%s: L or K outside [0, 2^26]", fn);
+  if (P < 0 || P > 31) return fail(NFS_ESHAPE, "%s: n_basis %d outside [0, 31]", fn, P);
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(NFS_EINVAL, "%s: rel_tol must be finite and >= 0", fn);
+  if ((L > 0 && (!b0 || !b0_out)) || (K > 0 && (!t || !t_out || !theta)) || !n_basis_out ||
+      (P > 0 && L > 0 && (!fields || !fields_out)) || (P > 0 && K > 0 && (!kcoef || !kcoef_out)))
+    return fail(NFS_EINVAL, "%s: NULL array", fn);
+  const double tol_rel = rel_tol > 0.0 ? rel_tol : std::ldexp(1.0, -24);
+  const int T = P + 1;
+  auto a_at = [&](int b, int64_t k) -> double { return b == 0 ? (double)t[k] : (double)kcoef[k * P + (b - 1)]; };
+  auto h_at = [&](int b, int64_t l) -> double { return b == 0 ? (double)b0[l] : (double)fields[(b - 1) * L + l]; };
+  std::vector<double> s(T, 0.0), hmax(T, 0.0);
+  for (int b = 0; b < T; ++b) {
+    for (int64_t k = 0; k < K; ++k) {
+      const double v = a_at(b, k);
+      if (!std::isfinite(v)) return fail(NFS_EINVAL, "%s: non-finite sample coefficient (term %d)", fn, b);
+      s[b] = std::max(s[b], std::fabs(v));
+    }
+    for (int64_t l = 0; l < L; ++l) {
+      const double v = h_at(b, l);
+      if (!std::isfinite(v)) return fail(NFS_EINVAL, "%s: non-finite voxel coefficient (term %d)", fn, b);
+      hmax[b] = std::max(hmax[b], std::fabs(v));
+    }
+  }
+  double bound = 0.0;
+  for (int b = 0; b < T; ++b) bound += s[b] * hmax[b];
+  const double tol = tol_rel * bound;
+  // scaled, centred voxel rows A_b and their means
+  std::vector<double> A((size_t)T * L), mu(T, 0.0);
+  for (int b = 0; b < T; ++b) {
+    double sum = 0.0;
+    for (int64_t l = 0; l < L; ++l) {
+      const double v = s[b] * h_at(b, l);
+      A[(size_t)b * L + l] = v;
+      sum += v;
+    }
+    mu[b] = L > 0 ? sum / (double)L : 0.0;
+    for (int64_t l = 0; l < L; ++l) A[(size_t)b * L + l] -= mu[b];
+  }
+  std::vector<double> S((size_t)T * T, 0.0);
+  for (int p = 0; p < T; ++p)
+    for (int q = p; q < T; ++q) {
+      double acc = 0.0;
+      for (int64_t l = 0; l < L; ++l) acc += A[(size_t)p * L + l] * A[(size_t)q * L + l];
+      S[(size_t)p * T + q] = S[(size_t)q * T + p] = acc;
+    }
+  std::vector<double> lam, U;
+  jacobi_eigen(S, T, &lam, &U);
+  // add directions until the residual bound holds
+  std::vector<double> E(A), H;  // E: residual rows; H: kept voxel sides, row j
+  auto resid = [&]() {
+    double worst = 0.0;
+    for (int64_t l = 0; l < L; ++l) {
+      double acc = 0.0;
+      for (int b = 0; b < T; ++b) acc += std::fabs(E[(size_t)b * L + l]);
+      worst = std::max(worst, acc);
+    }
+    return worst;
+  };
+  int r = 0;
+  double err = resid();
+  while (err > tol && r < T) {
+    std::vector<double> h(L, 0.0);
+    for (int b = 0; b < T; ++b) {
+      const double u = U[(size_t)b * T + r];
+      if (u != 0.0)
+        for (int64_t l = 0; l < L; ++l) h[l] += u * A[(size_t)b * L + l];
+    }
+    for (int b = 0; b < T; ++b) {
+      const double u = U[(size_t)b * T + r];
+      if (u != 0.0)
+        for (int64_t l = 0; l < L; ++l) E[(size_t)b * L + l] -= u * h[l];
+    }
+    H.insert(H.end(), h.begin(), h.end());
+    ++r;
+    err = resid();
+  }
+  // outputs: direction 0 in the (t, b0) slot, directions 1.. as field terms
+  const int Pn = r > 0 ? r - 1 : 0;
+  for (int64_t k = 0; k < K; ++k) {
+    double th = 0.0;
+    double as[32];
+    for (int b = 0; b < T; ++b) {
+      as[b] = s[b] > 0.0 ? a_at(b, k) / s[b] : 0.0;
+      th += as[b] * mu[b];
+    }
+    theta[k] = th;
+    for (int j = 0; j < std::max(r, 1); ++j) {
+      double v = 0.0;
+      if (j < r)
+        for (int b = 0; b < T; ++b) v += as[b] * U[(size_t)b * T + j];
+      if (j == 0)
+        t_out[k] = (float)v;
+      else
+        kcoef_out[k * Pn + (j - 1)] = (float)v;
+    }
+  }
+  for (int64_t l = 0; l < L; ++l) {
+    b0_out[l] = r > 0 ? (float)H[l] : 0.f;
+    for (int j = 1; j < r; ++j) fields_out[(j - 1) * L + l] = (float)H[(size_t)j * L + l];
+  }
+  *n_basis_out = Pn;
+  if (err_bound) *err_bound = err;
+  return NFS_OK;
+}
+
+extern "C" int nfs_phase_shift(nfs_ctx* ctx, const float* m, float* out, int n_coil, int64_t K, const double* theta,
+                               int sign, void* stream) {
+  const char* fn = "nfs_phase_shift";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  if (n_coil < 1 || n_coil > 64 || K < 0 || K > ((int64_t)1 << 26))
+    return fail(NFS_ESHAPE, "%s: n_coil %d or K %lld out of range", fn, n_coil, (long long)K);
+  if (sign != 1 && sign != -1) return fail(NFS_EINVAL, "%s: sign must be +1 or -1", fn);
+  if (K > 0 && (!m || !out || !theta)) return fail(NFS_EINVAL, "%s: NULL array", fn);
+  if (misaligned(m, 8) || misaligned(out, 8) || misaligned(theta, 8)) return fail(NFS_EINVAL, "%s: array misaligned", fn);
+  NFS_TRY(launch_phase_shift(reinterpret_cast<const float2*>(m), reinterpret_cast<float2*>(out), theta, n_coil, K,
+                             sign, (hipStream_t)stream),
+          fn);
+  return NFS_OK;
+}

@@ -450,4 +450,27 @@ hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, 
   return hipGetLastError();
 }
 
+// out[c][k] = m[c][k] * exp(i sign theta[k]): the per-sample phase offset
+// that a compressed phase basis moves out of the tile phase.  One thread
+// per sample; the rotation is evaluated in double precision once per sample
+// and applied to every coil (in place when out == m).
+__global__ __launch_bounds__(256) void phase_shift_kernel(const float2* m, float2* out, const double* __restrict__ theta,
+                                                          int G, int64_t K, int sign) {
+  const int64_t k = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (k >= K) return;
+  double sn, cs;
+  sincos((double)sign * theta[k], &sn, &cs);
+  for (int c = 0; c < G; ++c) {
+    const float2 v = m[(int64_t)c * K + k];
+    out[(int64_t)c * K + k] = make_float2((float)(cs * v.x - sn * v.y), (float)(sn * v.x + cs * v.y));
+  }
+}
+
+hipError_t launch_phase_shift(const float2* m, float2* out, const double* theta, int G, int64_t K, int sign,
+                              hipStream_t s) {
+  if (K == 0) return hipSuccess;
+  hipLaunchKernelGGL(phase_shift_kernel, dim3((unsigned)cdiv(K, 256)), dim3(256), 0, s, m, out, theta, G, K, sign);
+  return hipGetLastError();
+}
+
 }  // namespace nfs

@@ -221,6 +221,8 @@ hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s);
 // (from_rn) or st.r; partial r^H r -> part[1]
 hipError_t launch_cg_reorth_apply(const CgState& st, int nv, bool from_rn, hipStream_t s);
 hipError_t launch_cg_finish(const CgState& st, float2* rho, const float* icorr, int64_t L, hipStream_t s);
+hipError_t launch_phase_shift(const float2* m, float2* out, const double* theta, int G, int64_t K, int sign,
+                              hipStream_t s);
 
 
 // ---- map estimation (sensitivity and B0 maps from prescan data) ----

@@ -73,6 +73,9 @@ def lib():
             L.nfs_kspace_filter_mask.argtypes = [vp, ctypes.c_int64, i32, i32, i32, i32, vp,
                                                  ctypes.POINTER(ctypes.c_int64)]
             L.nfs_encode_backward.argtypes = [vp, pp, vp, vp, vp, vp, vp, i32, vp, sz, vp]
+            L.nfs_compress_basis.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int64, i32, dbl, vp, vp, vp,
+                                             vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
+            L.nfs_phase_shift.argtypes = [vp, vp, vp, i32, ctypes.c_int64, vp, i32, vp]
             L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
                                                i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]
@@ -326,6 +329,59 @@ def kspace_filter_mask(kpos, dims):
     _check(lib().nfs_kspace_filter_mask(k.ctypes.data_as(ctypes.c_void_p), k.shape[0], k.shape[1], nx, ny, nz,
                                         mask.ctypes.data_as(ctypes.c_void_p), ctypes.byref(cnt)))
     return mask.astype(np.float32)
+
+
+def compress_basis_host(fields, b0, kcoef, t, rel_tol: float = 0.0):
+    """The compressed phase basis of nfs_compress_basis from host arrays
+    fields [P][L], b0 [L], kcoef [K][P], t [K]: dict with fields [P'][L],
+    b0 [L], kcoef [K][P'], t [K] (float32), theta [K] (float64, rad),
+    n_basis P' and err_bound (rad).  Host computation."""
+    import numpy as np
+
+    f = np.ascontiguousarray(fields, dtype=np.float32)
+    b = np.ascontiguousarray(b0, dtype=np.float32)
+    kc = np.ascontiguousarray(kcoef, dtype=np.float32)
+    tt = np.ascontiguousarray(t, dtype=np.float32)
+    P, L = f.shape
+    K = tt.shape[0]
+    fo = np.zeros((P, L), dtype=np.float32)
+    bo = np.zeros(L, dtype=np.float32)
+    ko = np.zeros(K * P, dtype=np.float32)
+    to = np.zeros(K, dtype=np.float32)
+    th = np.zeros(K, dtype=np.float64)
+    pn, err = ctypes.c_int(), ctypes.c_double()
+    vp = lambda a: a.ctypes.data_as(ctypes.c_void_p)  # noqa: E731
+    _check(lib().nfs_compress_basis(vp(f), vp(b), vp(kc), vp(tt), L, K, P, float(rel_tol), vp(fo), vp(bo), vp(ko),
+                                    vp(to), vp(th), ctypes.byref(pn), ctypes.byref(err)))
+    n = pn.value
+    return dict(fields=fo[:n].copy(), b0=bo, kcoef=ko[:K * n].reshape(K, n).copy(), t=to, theta=th, n_basis=n,
+                err_bound=err.value)
+
+
+def compress_basis(prob: Problem, rel_tol: float = 0.0):
+    """(Problem with the compressed phase basis and prob's sens and icorr,
+    theta [K] float64 device tensor, info dict with n_basis and err_bound).
+    The basis is copied to the host, compressed there (nfs_compress_basis)
+    and the result copied back to prob's device."""
+    c = compress_basis_host(prob.fields.cpu().numpy(), prob.b0.cpu().numpy(), prob.kcoef.cpu().numpy(),
+                            prob.t.cpu().numpy(), rel_tol)
+    out = Problem(prob.sens, c["fields"], c["b0"], c["kcoef"], c["t"], prob.icorr, device=prob.device)
+    theta = torch.as_tensor(c["theta"], dtype=torch.float64, device=prob.device)
+    return out, theta, dict(n_basis=c["n_basis"], err_bound=c["err_bound"])
+
+
+def phase_shift(m, theta, sign: int, out=None):
+    """out[c][k] = m[c][k] exp(i sign theta[k]) on m's device (m [G][K]
+    complex64, theta [K] float64 device tensor); returns out."""
+    m = m if m.dtype == torch.complex64 and m.is_contiguous() else m.to(torch.complex64).contiguous()
+    if m.dim() != 2 or theta.dim() != 1 or theta.shape[0] != m.shape[1] or theta.dtype != torch.float64:
+        raise ValueError("m must be [G][K] and theta [K] float64")
+    o = out if out is not None else torch.empty_like(m)
+    dev = m.device
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    _check(lib().nfs_phase_shift(context(idx), _ptr(m), _ptr(o), m.shape[0], m.shape[1], _ptr(theta.contiguous()),
+                                 int(sign), ctypes.c_void_p(torch.cuda.current_stream(dev).cuda_stream)))
+    return o
 
 
 def apply_kspace_filter(rho, f, dims, device: int = 0):

@@ -1,0 +1,153 @@
+"""Host checks of the phase-basis compression (nfs_compress_basis, a host
+computation): the compressed phase theta[k] + t'[k] b0'[l] + sum_p
+kcoef'[k][p] fields'[p][l], evaluated here in float64 from the float32
+outputs, must equal the original phase t[k] b0[l] + sum_p kcoef[k][p]
+fields[p][l] to the reported residual bound plus the outputs' float32
+rounding, at every checked (sample, voxel) pair; the number of terms kept
+must be the rank the construction fixes."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import synth
+from paper_2604_09233_amd import nfs
+
+
+def phase(fields, b0, kcoef, t, ks, ls):
+    """phi[k, l] in float64, directly from the model's definition."""
+    f = np.asarray(fields, np.float64)[:, ls]
+    return (np.asarray(t, np.float64)[ks, None] * np.asarray(b0, np.float64)[None, ls]
+            + np.asarray(kcoef, np.float64)[ks] @ f)
+
+
+def check_phase(inp, out, ks, ls):
+    want = phase(inp["fields"], inp["b0"], inp["kcoef"], inp["t"], ks, ls)
+    got = out["theta"][ks, None] + phase(out["fields"], out["b0"], out["kcoef"], out["t"], ks, ls)
+    # float32 rounding of the outputs: each product a'_j h'_j is off by at
+    # most 2^-23 of max|a'_j| max|h'_j|, theta is double
+    terms = [np.abs(out["t"]).max() * np.abs(out["b0"]).max()]
+    terms += [np.abs(out["kcoef"][:, p]).max() * np.abs(out["fields"][p]).max() for p in range(out["n_basis"])]
+    slack = out["err_bound"] + 2.0 ** -22 * sum(terms)
+    dev = np.abs(got - want).max()
+    return dev, slack
+
+
+def basis_bound(inp):
+    P = inp["fields"].shape[0]
+    b = np.abs(inp["t"]).max() * np.abs(inp["b0"]).max()
+    return b + sum(np.abs(inp["kcoef"][:, p]).max() * np.abs(inp["fields"][p]).max() for p in range(P))
+
+
+def compress(inp, rel_tol=0.0):
+    return nfs.compress_basis_host(inp["fields"], inp["b0"], inp["kcoef"], inp["t"], rel_tol)
+
+
+def test_slice_of_solid_harmonics_keeps_ten_terms():
+    """On one slice (z constant) the 16 solid harmonics up to third order
+    span the 10 polynomials of degree <= 3 in x and y; without the constant
+    (moved into theta) that is 9, plus the B0 term: 10 terms, n_basis 9."""
+    d = synth.make_config("c2", with_noise=False)
+    out = compress(d)
+    assert out["n_basis"] == 9
+    assert out["err_bound"] <= 2.0 ** -24 * basis_bound(d)
+    rng = np.random.default_rng(0)
+    ks = rng.choice(d["K"], 400, replace=False)
+    ls = rng.choice(d["L"], 400, replace=False)
+    dev, slack = check_phase(d, out, ks, ls)
+    print(f"slice basis: max phase change {dev:.2e} rad (allowed {slack:.2e})")
+    assert dev <= slack
+
+
+def test_volume_of_solid_harmonics_loses_only_the_constant():
+    x, y, z = synth.grid_coords((12, 10, 8))
+    fields = synth.solid_harmonics(x, y, z, 16).astype(np.float32)
+    rng = np.random.default_rng(1)
+    K = 700
+    inp = dict(fields=fields, b0=(300 * rng.standard_normal(x.size)).astype(np.float32),
+               kcoef=(40 * rng.standard_normal((K, 16))).astype(np.float32),
+               t=np.linspace(0, 0.03, K).astype(np.float32))
+    out = compress(inp)
+    assert out["n_basis"] == 15
+    dev, slack = check_phase(inp, out, np.arange(K), np.arange(x.size))
+    assert dev <= slack
+
+
+def test_random_basis_is_kept_whole():
+    d = synth.random_problem(300, 500, 2, 6, seed=3)
+    out = compress(d)
+    assert out["n_basis"] == 6
+    dev, slack = check_phase(d, out, np.arange(500), np.arange(300))
+    assert dev <= slack
+
+
+@pytest.mark.parametrize("rank", [1, 3, 5])
+def test_fields_of_known_rank(rank):
+    """Field rows that are combinations of `rank` independent random rows
+    plus a constant, and an independent B0 row: rank + 1 terms remain."""
+    rng = np.random.default_rng(10 + rank)
+    L, K, P = 257, 333, 12
+    base = rng.standard_normal((rank, L))
+    mix = rng.standard_normal((P, rank))
+    offs = rng.standard_normal((P, 1))
+    inp = dict(fields=(mix @ base + offs).astype(np.float64),
+               b0=rng.standard_normal(L), kcoef=rng.standard_normal((K, P)), t=rng.standard_normal(K))
+    # the float32 rounding of the combined rows is itself a small residual:
+    # compare against the float32 inputs the library sees
+    inp = {k: np.asarray(v, np.float32) for k, v in inp.items()}
+    out = compress(inp, rel_tol=2.0 ** -20)
+    assert out["n_basis"] == rank
+    dev, slack = check_phase(inp, out, np.arange(K), np.arange(L))
+    assert dev <= slack
+
+
+def test_constant_term_goes_to_theta():
+    """A basis of one constant row: theta carries the whole phase and no
+    term is left (the (t, b0) slot is zero)."""
+    L, K = 50, 40
+    rng = np.random.default_rng(5)
+    inp = dict(fields=np.full((1, L), 0.5, np.float32), b0=np.zeros(L, np.float32),
+               kcoef=rng.standard_normal((K, 1)).astype(np.float32), t=np.zeros(K, np.float32))
+    out = compress(inp)
+    assert out["n_basis"] == 0
+    assert np.all(out["t"] == 0) and np.all(out["b0"] == 0)
+    assert np.allclose(out["theta"], 0.5 * inp["kcoef"][:, 0].astype(np.float64), rtol=1e-15, atol=0)
+
+
+def test_tolerance_trades_terms_for_phase_error():
+    """A looser bound drops more directions and reports a larger residual,
+    never above the bound asked for."""
+    d = synth.random_problem(400, 300, 2, 8, seed=9)
+    # make the last field terms weak: the phase is dominated by the first ones
+    d["kcoef"][:, 4:] *= 1e-4
+    full = compress(d)
+    loose = compress(d, rel_tol=1e-3)
+    assert loose["n_basis"] < full["n_basis"]
+    assert loose["err_bound"] <= 1e-3 * basis_bound(d)
+    dev, slack = check_phase(d, loose, np.arange(300), np.arange(400))
+    assert dev <= slack
+
+
+def test_degenerate_sizes_and_bad_arguments():
+    L = nfs.lib()
+    z = np.zeros(4, np.float32)
+    out = nfs.compress_basis_host(np.zeros((0, 4), np.float32), z, np.zeros((4, 0), np.float32), z)
+    assert out["n_basis"] == 0
+    out = nfs.compress_basis_host(np.zeros((3, 0), np.float32), np.zeros(0, np.float32),
+                                  np.ones((5, 3), np.float32), np.ones(5, np.float32))
+    assert out["n_basis"] == 0 and np.all(out["theta"] == 0)
+    vp = ctypes.c_void_p
+    buf = np.zeros(64, np.float64)
+    p = vp(buf.ctypes.data)
+    n = ctypes.c_int()
+    f = L.nfs_compress_basis
+    assert f(p, p, p, p, 4, 4, 1, -1.0, p, p, p, p, p, ctypes.byref(n), None) == nfs.NFS_EINVAL
+    assert f(p, p, p, p, 4, 4, 1, float("nan"), p, p, p, p, p, ctypes.byref(n), None) == nfs.NFS_EINVAL
+    assert f(p, None, p, p, 4, 4, 1, 0.0, p, p, p, p, p, ctypes.byref(n), None) == nfs.NFS_EINVAL
+    assert f(p, p, p, p, 4, 4, 1, 0.0, p, p, p, p, None, ctypes.byref(n), None) == nfs.NFS_EINVAL
+    assert f(p, p, p, p, 4, 4, 1, 0.0, p, p, p, p, p, None, None) == nfs.NFS_EINVAL
+    assert f(p, p, p, p, 4, 4, 32, 0.0, p, p, p, p, p, ctypes.byref(n), None) == nfs.NFS_ESHAPE
+    assert f(p, p, p, p, -1, 4, 1, 0.0, p, p, p, p, p, ctypes.byref(n), None) == nfs.NFS_ESHAPE
+    bad = np.array([1.0, np.inf, 0, 0], np.float32)
+    with pytest.raises(RuntimeError):
+        nfs.compress_basis_host(np.ones((1, 4), np.float32), bad, np.ones((4, 1), np.float32), np.ones(4, np.float32))
