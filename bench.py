@@ -189,28 +189,51 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
         sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
         ms.append(clean + sig * torch.from_numpy(d["noise"]).to(dev))
     n_iter = 30
+    # compressed phase bases (each slice: 16 solid harmonics on one slice ->
+    # 10 terms), the data rotations by exp(-i theta) inside the timed step
+    full_probs, thetas = probs, None
+    if not args.no_compress:
+        comp = [nfs.compress_basis(pr) for pr in probs]
+        probs = [c[0] for c in comp]
+        thetas = [c[1] for c in comp]
+    bufs = [torch.empty_like(m) for m in ms]
     if not args.no_tune:
         nfs.autotune_batched(probs, "bf16")
     work = sum((n_iter + 0.5) * d["L"] * d["K"] * d["n_coil"] for d in sl)
 
-    def timed(mode):
+    def timed(mode, prs):
+        rot = prs is not full_probs
+
+        def data():
+            if not rot:
+                return ms
+            return [nfs.phase_shift(m, th, -1, out=b) for m, th, b in zip(ms, thetas, bufs)]
+
         nfs.set_batch_mode(0, mode)
         nfs.set_graphs(0, True)
-        outs, hists, infos = nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True)
+        outs, hists, infos = nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True)
         torch.cuda.synchronize()
         ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         ev0.record()
         for _ in range(steps):
-            nfs.cg_solve_batched(probs, ms, n_iter, precision="bf16", reorth=True, outs=outs, hists=hists,
+            nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True, outs=outs, hists=hists,
                                  infos=infos)
         ev1.record()
         torch.cuda.synchronize()
         nfs.set_graphs(0, False)
         return ev0.elapsed_time(ev1) / steps, outs
 
-    t_p, out_p = timed("persistent")
-    t, out_s = timed("streams")
+    t_p, out_p = timed("persistent", probs)
+    t, out_s = timed("streams", probs)
     same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
+    full = None
+    if thetas is not None:
+        if not args.no_tune:
+            nfs.autotune_batched(full_probs, "bf16")
+        t_f, out_f = timed("streams", full_probs)
+        full = dict(ms_per_batch=t_f, value=work / (t_f * 1e-3),
+                    max_rel_diff_to_compressed=max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
+                                                   for a, b in zip(out_s, out_f)))
     return dict(workload="24 slices, 2D 96..160 square, 8..32 coils, 8000..30000 samples, 16 terms, per-slice B0, "
                          "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch (slices' solves "
                          "forked over 8 streams)",
@@ -219,6 +242,7 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
                                      form="lock-step; per iteration one persistent E and one persistent E^H launch "
                                           "per coil class over all slices"),
                 persistent_equals_streams=same,
+                phase_basis_terms=[pr.P + 1 for pr in probs], full_basis_form=full,
                 pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps, tuned=not args.no_tune)
 
 

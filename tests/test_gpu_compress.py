@@ -143,3 +143,34 @@ def test_compressed_c2_cg_vs_stored_oracle(nfs, c2, prec):
     print(f"compressed c2 CG reorth {prec}: iterate 10 rel {e10:.2e}, iterate 30 rel {e30:.2e}")
     assert info.cpu().tolist() == [30, 1]
     assert e30 < TOL[prec] and e10 < TOL[prec]
+
+
+# ------------------------------------------ batched slices on compressed bases
+@pytest.mark.parametrize("mode", ["streams", "persistent"])
+def test_compressed_batched_slices_match_oracle(nfs, mode):
+    """Uneven 2D slices, each compressed to 10 terms, solved in one batched
+    call on the rotated data; every slice against the oracle's solve of its
+    original problem."""
+    sl = synth.batched_slices(4, seed=5, n_range=(20, 36), g_range=(2, 10), k_range=(800, 2500))
+    probs, ms, refs = [], [], []
+    for d in sl:
+        cp, theta, _ = compressed(nfs, d)
+        assert cp.P == 9
+        clean = oracle.apply_E(d["rho_true"], *args(d))
+        sig = np.sqrt(np.mean(np.abs(clean) ** 2)) / (30 * np.sqrt(2))
+        m = (clean + sig * d["noise"]).astype(np.complex64)
+        probs.append(cp)
+        ms.append(nfs.phase_shift(torch.from_numpy(m).cuda(), theta, -1))
+        refs.append(oracle.cg_solve(m, *args(d), n_iter=10, reorth=True)["rho"])
+    nfs.set_batch_mode(0, mode)
+    try:
+        for prec in ("fp32", "fp16"):
+            rb, _, ib = nfs.cg_solve_batched(probs, ms, 10, precision=prec, reorth=True)
+            torch.cuda.synchronize()
+            for i in range(len(sl)):
+                err = rel(rb[i].cpu().numpy(), refs[i])
+                print(f"compressed batched {mode} {prec} slice {i}: rel {err:.2e}")
+                assert ib[i].cpu().tolist() == [10, 1]
+                assert err < TOL[prec]
+    finally:
+        nfs.set_batch_mode(0, "streams")
