@@ -114,10 +114,11 @@ def counters(out_md, precision, command, copy_bytes, *dirs):
     cwk = max(cw, key=lambda k: cw[k].get("WRITE_SIZE", 0.0))
     f_fac = copy_bytes / (cf[cfk]["FETCH_SIZE"] * 1024.0)
     w_fac = copy_bytes / (cw[cwk]["WRITE_SIZE"] * 1024.0)
-    lines = ["# Encode-kernel counters: CG solve, 2D 128x128 / 16 coils / 60000 samples / 16 terms, "
-             f"{precision.upper()} operands", "",
-             "encode_kernel<OP, PREC, NQ, NB, MT>: OP 0 = E, 1 = E^H; PREC 0 = fp32, 1 = bf16, 2 = fp16. The run "
-             "also holds the single FP32 E that generates the data.", "",
+    lines = ["# Encode-kernel counters: CG solve, 2D 128x128 / 16 coils / 60000 samples / 16 field terms "
+             f"(solved on the compressed 10-term phase basis), {precision.upper()} operands", "",
+             "encode_kernel<OP, PREC, NQ, NB, MT>: OP 0 = E, 1 = E^H; PREC 0 = fp32, 1 = bf16, 2 = fp16; NQ phase "
+             "instructions per tile (1 on the compressed basis). The run also holds the single FP32 E that "
+             "generates the data (full basis).", "",
              "Commands (from the repository root, one MI355X), one rocprofv3 run per counter set:", "",
              f"    {command} --pmc <counters> -- python3 bench.py --profile-run", "",
              "with these counter sets (one run each):", ""]
