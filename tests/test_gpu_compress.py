@@ -174,3 +174,42 @@ def test_compressed_batched_slices_match_oracle(nfs, mode):
                 assert err < TOL[prec]
     finally:
         nfs.set_batch_mode(0, "streams")
+
+
+# ------------------------------------------------------------- edge cases
+def test_basis_of_constants_leaves_only_the_offset(nfs):
+    """Field rows constant over the voxels and no B0: the compressed problem
+    has no term left (n_basis 0, zero (t, b0) slot), and E is the coil
+    weighting times exp(i theta) alone."""
+    rng = np.random.default_rng(8)
+    L, K, G, P = 200, 333, 3, 4
+    d = dict(sens=(rng.standard_normal((G, L)) + 1j * rng.standard_normal((G, L))).astype(np.complex64),
+             fields=np.repeat(rng.uniform(-1, 1, (P, 1)), L, axis=1).astype(np.float32),
+             b0=np.zeros(L, np.float32), kcoef=(5 * rng.standard_normal((K, P))).astype(np.float32),
+             t=np.linspace(0, 0.01, K).astype(np.float32))
+    cp, theta, info = compressed(nfs, d)
+    assert cp.P == 0 and info["err_bound"] < 1e-10  # rounding of the row means only
+    rho = (rng.standard_normal(L) + 1j * rng.standard_normal(L)).astype(np.complex64)
+    for prec in PRECS:
+        m = nfs.phase_shift(nfs.apply_E(cp, torch.from_numpy(rho), prec), theta, +1).cpu().numpy()
+        err = rel(m, oracle.apply_E(rho, *args(d)))
+        print(f"constant basis E {prec}: rel {err:.2e}")
+        assert err < TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp16"])
+def test_compressed_cg_with_intensity_correction(nfs, c1, prec):
+    """icorr travels with the compressed problem: the solve on rotated data
+    equals the oracle's corrected solve of the original problem."""
+    rng = np.random.default_rng(12)
+    j = rng.uniform(0.5, 1.5, c1["L"]).astype(np.float32)
+    full = nfs.Problem(*args(c1), icorr=j)
+    cp, theta, _ = nfs.compress_basis(full)
+    assert cp.icorr is not None and cp.P == 2
+    m = c1["m"]
+    rho, _, info = nfs.cg_solve(cp, nfs.phase_shift(torch.from_numpy(m).cuda(), theta, -1), 6, precision=prec,
+                                reorth=True)
+    ref = oracle.cg_solve(m, *args(c1), n_iter=6, icorr=j, reorth=True)["rho"]
+    err = rel(rho.cpu().numpy(), ref)
+    print(f"compressed CG with icorr {prec}: rel {err:.2e}")
+    assert info.cpu().tolist() == [6, 1] and err < TOL[prec]
