@@ -55,13 +55,8 @@ __device__ void direction_bound(const CgState& st, float mx, float* redf) {
 }
 
 __device__ __forceinline__ float2 sum_splits(const float2* hpart, int nsplit, int64_t stride, int64_t l, float u) {
-  float re = 0.f, im = 0.f;
-  for (int s = 0; s < nsplit; ++s) {
-    const float2 v = hpart[(size_t)s * stride + l];
-    re += v.x;
-    im += v.y;
-  }
-  return make_float2(re * u, im * u);
+  const float2 v = sum_strided(hpart + l, nsplit, stride);
+  return make_float2(v.x * u, v.y * u);
 }
 
 // smax[l] = max_c |S[c][l]|

@@ -321,24 +321,46 @@ __global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __
   const int N = nb * 16 + n;
   const int c = N >> 1, reim = N & 1;
   const int64_t ncol = (int64_t)NB * 16, pstride = HC16 * ncol;
-  float vals[8];
+  // the four items' split sums advance together, four splits at a time, so
+  // that sixteen loads are in flight; each sum is added in split order
+  const float2* src[4];
+  bool ok[4];
+  float2 v[4];
 #pragma unroll
   for (int j = 0; j < 4; ++j) {
     const int64_t item = ch * kChunk + g * 4 + j;
-    float2 v = make_float2(0.f, 0.f);
-    if (item < K && c < G) {
-      const float2* src = (const float2*)(epart + item * ncol + 2 * c);
-      for (int sp = 0; sp < nsplit; ++sp) {
-        const float2 w = src[sp * (pstride / 2)];
-        v.x += w.x;
-        v.y += w.y;
-      }
+    ok[j] = item < K && c < G;
+    src[j] = (const float2*)(epart + (ok[j] ? item : 0) * ncol + 2 * (ok[j] ? c : 0));
+    v[j] = make_float2(0.f, 0.f);
+  }
+  const int64_t st2 = pstride / 2;
+  for (int s0 = 0; s0 < nsplit; s0 += 4) {
+    float2 w[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        w[j][k] = ok[j] && s0 + k < nsplit ? src[j][(int64_t)(s0 + k) * st2] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (ok[j] && s0 + k < nsplit) {
+          v[j].x += w[j][k].x;
+          v[j].y += w[j][k].y;
+        }
+  }
+  float vals[8];
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    if (ok[j]) {
+      const int64_t item = ch * kChunk + g * 4 + j;
       const float w = wgt ? wgt[item] * wmul : wmul;
-      v.x *= scale * w;
-      v.y *= scale * w;
+      v[j].x *= scale * w;
+      v[j].y *= scale * w;
     }
-    vals[2 * j] = reim ? v.y : v.x;
-    vals[2 * j + 1] = reim ? -v.x : v.y;
+    vals[2 * j] = reim ? v[j].y : v[j].x;
+    vals[2 * j + 1] = reim ? -v[j].x : v[j].y;
   }
   store_fragment<PREC>(vals, out, ch, nb, NB, lane);
 }
@@ -788,28 +810,18 @@ __global__ void finish_E_to_m_kernel(const float* __restrict__ epart, int nsplit
   const int64_t k = i % K;
   const int64_t c = i / K;
   const int ncol = NB * 16;
-  float re = 0.f, im = 0.f;
-  for (int s = 0; s < nsplit; ++s) {
-    const float* row = epart + ((size_t)s * HC16 + k) * ncol;
-    re += row[2 * c];
-    im += row[2 * c + 1];
-  }
+  const float2 v = sum_strided((const float2*)(epart + k * ncol + 2 * c), nsplit, HC16 * ncol / 2);
   const float u = unscale ? *unscale : 1.f;
-  m[i] = make_float2(re * u, im * u);
+  m[i] = make_float2(v.x * u, v.y * u);
 }
 
 __global__ void finish_EH_kernel(const float2* __restrict__ hpart, int nsplit, int64_t HC16, int64_t L,
                                  const float* __restrict__ unscale, float2* __restrict__ x) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= L) return;
-  float re = 0.f, im = 0.f;
-  for (int s = 0; s < nsplit; ++s) {
-    const float2 v = hpart[(size_t)s * HC16 + l];
-    re += v.x;
-    im += v.y;
-  }
+  const float2 v = sum_strided(hpart + l, nsplit, HC16);
   const float u = unscale ? *unscale : 1.f;
-  x[l] = make_float2(re * u, im * u);
+  x[l] = make_float2(v.x * u, v.y * u);
 }
 
 // grad_b0[l] = Im(conj(rho[l]) x[l]), x = E^H (t o G) as split partials
@@ -818,15 +830,10 @@ __global__ void grad_b0_kernel(const float2* __restrict__ hpart, int nsplit, int
                                float* __restrict__ out) {
   const int64_t l = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (l >= L) return;
-  float re = 0.f, im = 0.f;
-  for (int s = 0; s < nsplit; ++s) {
-    const float2 v = hpart[(size_t)s * HC16 + l];
-    re += v.x;
-    im += v.y;
-  }
+  const float2 v = sum_strided(hpart + l, nsplit, HC16);
   const float u = unscale ? *unscale : 1.f;
   const float2 r = rho[l];
-  out[l] = (r.x * im - r.y * re) * u;
+  out[l] = (r.x * v.y - r.y * v.x) * u;
 }
 
 // grad_kcoef[k][b] = Im(sum_c G[c][k] conj(Z[k][c])), Z = E (h_b o rho) as E partials
@@ -838,14 +845,9 @@ __global__ void grad_kcoef_kernel(const float* __restrict__ epart, int nsplit, i
   const int ncol = NB * 16;
   float acc = 0.f;
   for (int c = 0; c < G; ++c) {
-    float zr = 0.f, zi = 0.f;
-    for (int s = 0; s < nsplit; ++s) {
-      const float* row = epart + ((size_t)s * HC16 + k) * ncol;
-      zr += row[2 * c];
-      zi += row[2 * c + 1];
-    }
+    const float2 z = sum_strided((const float2*)(epart + k * ncol + 2 * c), nsplit, HC16 * ncol / 2);
     const float2 g = grad_m[(int64_t)c * K + k];
-    acc += g.y * zr - g.x * zi;
+    acc += g.y * z.x - g.x * z.y;
   }
   out[k * P + b] = acc * (unscale ? *unscale : 1.f);
 }

@@ -37,6 +37,26 @@ constexpr float kRawPhaseBound = 128.f;
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
+// Sum of src[s * stride] over s = 0 .. n-1, added in that order (so rounded
+// as the plain loop rounds it), with the loads of eight consecutive terms
+// issued before their additions, so that they are in flight together
+// instead of one memory latency each.
+__device__ __forceinline__ float2 sum_strided(const float2* src, int n, int64_t stride) {
+  float re = 0.f, im = 0.f;
+  for (int s0 = 0; s0 < n; s0 += 8) {
+    float2 v[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) v[k] = s0 + k < n ? src[(int64_t)(s0 + k) * stride] : make_float2(0.f, 0.f);
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (s0 + k < n) {
+        re += v[k].x;
+        im += v[k].y;
+      }
+  }
+  return make_float2(re, im);
+}
+
 // phase MFMA instructions for P + 1 terms (t*b0 plus P field terms): three
 // split products per term, 32 k-slots per instruction (1, 2 or 3)
 inline int phase_instrs(int n_basis) { return (int)cdiv(3 * (n_basis + 1), 32); }
