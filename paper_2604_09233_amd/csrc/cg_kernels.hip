@@ -344,21 +344,36 @@ __global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv
   if (*st.stop) return;
   __shared__ double red[256];
   __shared__ double coef[2 * (kMaxReorth + 1)];
+  // (both loops issue the loads of several terms before using them in
+  // order, so the arithmetic is that of the plain loops)
   for (int i = threadIdx.x; i < 2 * nv; i += 256) {
     const double* pp = st.rpart + (size_t)i * kCgBlocks;
     double t = 0.0;
-    for (int b = 0; b < st.nblk; ++b) t += pp[b];
+    for (int b0 = 0; b0 < st.nblk; b0 += 8) {
+      double w[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) w[k] = b0 + k < st.nblk ? pp[b0 + k] : 0.0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k)
+        if (b0 + k < st.nblk) t += w[k];
+    }
     coef[i] = t;
   }
   __syncthreads();
   double a = 0.0;
   for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
     float2 r = from_rn ? st.rn[l] : st.r[l];
-    for (int j = 0; j < nv; ++j) {
-      const float cr = (float)coef[2 * j], ci = (float)coef[2 * j + 1];
-      const float2 v = st.V[(size_t)j * st.L + l];
-      r.x -= cr * v.x - ci * v.y;
-      r.y -= cr * v.y + ci * v.x;
+    for (int j0 = 0; j0 < nv; j0 += 4) {
+      float2 v[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v[k] = j0 + k < nv ? st.V[(size_t)(j0 + k) * st.L + l] : make_float2(0.f, 0.f);
+#pragma unroll
+      for (int k = 0; k < 4; ++k)
+        if (j0 + k < nv) {
+          const float cr = (float)coef[2 * (j0 + k)], ci = (float)coef[2 * (j0 + k) + 1];
+          r.x -= cr * v[k].x - ci * v[k].y;
+          r.y -= cr * v[k].y + ci * v[k].x;
+        }
     }
     st.r[l] = r;
     a += (double)r.x * r.x + (double)r.y * r.y;
