@@ -151,3 +151,21 @@ def test_degenerate_sizes_and_bad_arguments():
     bad = np.array([1.0, np.inf, 0, 0], np.float32)
     with pytest.raises(RuntimeError):
         nfs.compress_basis_host(np.ones((1, 4), np.float32), bad, np.ones((4, 1), np.float32), np.ones(4, np.float32))
+
+
+def test_largest_basis_is_handled():
+    """31 field terms plus B0 (the most a problem holds): a random basis keeps
+    every term, one with repeated rows loses the repeats."""
+    rng = np.random.default_rng(21)
+    L, K, P = 150, 120, 31
+    inp = dict(fields=rng.uniform(-1, 1, (P, L)).astype(np.float32), b0=rng.standard_normal(L).astype(np.float32),
+               kcoef=rng.standard_normal((K, P)).astype(np.float32), t=rng.standard_normal(K).astype(np.float32))
+    out = compress(inp)
+    assert out["n_basis"] == P
+    dev, slack = check_phase(inp, out, np.arange(K), np.arange(L))
+    assert dev <= slack
+    inp["fields"][16:] = inp["fields"][:15]  # rows 16..30 repeat rows 0..14
+    out = compress(inp)
+    assert out["n_basis"] == 16
+    dev, slack = check_phase(inp, out, np.arange(K), np.arange(L))
+    assert dev <= slack
