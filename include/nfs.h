@@ -246,7 +246,7 @@ int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int n
  * as many as make
  *   max_l sum_b |residual_b(l)| <= rel_tol * sum_b max|a_b| max|h_b|,
  * which bounds |phi' - phi| at every (k, l) by that fraction of the phase
- * bound.  rel_tol <= 0 selects 2^-24.  A basis evaluated on a lower-
+ * bound.  rel_tol 0 selects 2^-24.  A basis evaluated on a lower-
  * dimensional set (16 solid harmonics up to third order on one slice span
  * the 10 polynomials of degree <= 3 in two variables) loses its dependent
  * terms, so every tile phase takes fewer matrix-core products.
