@@ -493,12 +493,21 @@ __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, cons
       h8 ahi, alo;
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float ch = __uint_as_float(__float_as_uint(cs[r]) & 0xFFFFE000u);
-        const float sh = __uint_as_float(__float_as_uint(sn[r]) & 0xFFFFE000u);
-        ahi[2 * r] = (_Float16)ch;
-        ahi[2 * r + 1] = (_Float16)sh;
-        alo[2 * r] = (_Float16)(cs[r] - ch);
-        alo[2 * r + 1] = (_Float16)(sn[r] - sh);
+        // hi: both values rounded to f16 in one pack; lo = x - hi, formed
+        // exactly by one mixed-precision FMA per value that reads its half
+        // of the packed hi register, then rounded to f16
+        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+        h2 hp;
+        hp[0] = (_Float16)cs[r];
+        hp[1] = (_Float16)sn[r];
+        const unsigned hb = __builtin_bit_cast(unsigned, hp);
+        float lc, ls;
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lc) : "v"(hb), "v"(cs[r]));
+        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ls) : "v"(hb), "v"(sn[r]));
+        ahi[2 * r] = hp[0];
+        ahi[2 * r + 1] = hp[1];
+        alo[2 * r] = (_Float16)lc;
+        alo[2 * r + 1] = (_Float16)ls;
       }
 #pragma unroll
       for (int nb = 0; nb < NB; ++nb) {
