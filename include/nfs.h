@@ -299,7 +299,11 @@ int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, c
  * the first time they see a given set of pointers and parameters and
  * replay it (one hipGraphLaunch) on later identical calls.  Ignored while
  * the caller's stream is itself being captured and while kernel profiling
- * is on.  Graphs live until nfs_destroy.  Default off.                    */
+ * is on.  At most 32 graphs are kept per context: capturing a new one
+ * beyond that destroys the least recently used (after waiting for its last
+ * launch to finish), so callers that pass fresh buffers on every call do
+ * not grow the cache without bound.  The rest live until nfs_destroy.
+ * Default off.                                                            */
 int nfs_set_graphs(nfs_ctx* ctx, int on);
 
 /* How nfs_cg_solve_batched runs the slices (default NFS_BATCH_STREAMS).

@@ -23,7 +23,16 @@ struct nfs_ctx {
   bool profiling = false;
   bool graphs = false;
   int batch_mode = NFS_BATCH_STREAMS;
-  std::unordered_map<std::string, hipGraphExec_t> graph_cache;
+  // captured solves (nfs_set_graphs), at most kMaxGraphs; `done` is recorded
+  // after each launch so that an evicted graph is destroyed only once its
+  // last launch has finished
+  struct Graph {
+    hipGraphExec_t ex = nullptr;
+    hipEvent_t done = nullptr;
+    uint64_t last_use = 0;
+  };
+  std::unordered_map<std::string, Graph> graph_cache;
+  uint64_t graph_clock = 0;
   std::vector<hipStream_t> bstreams;  // batched solves: forked streams (default priority)
   std::vector<hipEvent_t> bevents;    // ... and their join events
   hipEvent_t fork_event = nullptr;
@@ -89,7 +98,11 @@ extern "C" int nfs_destroy(nfs_ctx* ctx) {
       (void)hipEventDestroy(pr.second);
     }
   for (auto e : ctx->pool) (void)hipEventDestroy(e);
-  for (auto& kv : ctx->graph_cache) (void)hipGraphExecDestroy(kv.second);
+  for (auto& kv : ctx->graph_cache) {
+    if (kv.second.done) (void)hipEventSynchronize(kv.second.done);
+    (void)hipGraphExecDestroy(kv.second.ex);
+    if (kv.second.done) (void)hipEventDestroy(kv.second.done);
+  }
   for (auto st : ctx->bstreams) (void)hipStreamDestroy(st);
   for (auto e : ctx->bevents) (void)hipEventDestroy(e);
   if (ctx->fork_event) (void)hipEventDestroy(ctx->fork_event);
@@ -659,6 +672,23 @@ static std::string graph_key(const nfs_ctx* ctx, const char* kind, const nfs_pro
 // Capture happens on a library-owned stream (the caller's stream may be the
 // legacy null stream, which cannot be captured); the instantiated graph is
 // then launched on the caller's stream, after the work already queued there.
+constexpr size_t kMaxGraphs = 32;
+
+// Drop the least recently used graph once the cache is full (callers that
+// pass fresh output buffers on every call would otherwise grow it without
+// bound); waits for that graph's last launch first.
+static int evict_graph(nfs_ctx* ctx) {
+  auto lru = ctx->graph_cache.begin();
+  for (auto it = ctx->graph_cache.begin(); it != ctx->graph_cache.end(); ++it)
+    if (it->second.last_use < lru->second.last_use) lru = it;
+  if (lru == ctx->graph_cache.end()) return NFS_OK;
+  if (lru->second.done) NFS_TRY(hipEventSynchronize(lru->second.done), "hipEventSynchronize");
+  NFS_TRY(hipGraphExecDestroy(lru->second.ex), "hipGraphExecDestroy");
+  if (lru->second.done) NFS_TRY(hipEventDestroy(lru->second.done), "hipEventDestroy");
+  ctx->graph_cache.erase(lru);
+  return NFS_OK;
+}
+
 template <class F>
 static int run_maybe_graph(nfs_ctx* ctx, const std::string& key, hipStream_t s, F&& enqueue) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
@@ -688,9 +718,25 @@ static int run_maybe_graph(nfs_ctx* ctx, const std::string& key, hipStream_t s, 
     const hipError_t e2 = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e2 != hipSuccess) return hip_fail(e2, "hipGraphInstantiate");
-    it = ctx->graph_cache.emplace(key, ex).first;
+    hipEvent_t done = nullptr;
+    const hipError_t e3 = hipEventCreateWithFlags(&done, hipEventDisableTiming);
+    if (e3 != hipSuccess) {
+      (void)hipGraphExecDestroy(ex);
+      return hip_fail(e3, "hipEventCreateWithFlags");
+    }
+    if (ctx->graph_cache.size() >= kMaxGraphs) {
+      const int rc2 = evict_graph(ctx);
+      if (rc2) {
+        (void)hipGraphExecDestroy(ex);
+        (void)hipEventDestroy(done);
+        return rc2;
+      }
+    }
+    it = ctx->graph_cache.emplace(key, nfs_ctx::Graph{ex, done, 0}).first;
   }
-  NFS_TRY(hipGraphLaunch(it->second, s), "hipGraphLaunch");
+  it->second.last_use = ++ctx->graph_clock;
+  NFS_TRY(hipGraphLaunch(it->second.ex, s), "hipGraphLaunch");
+  NFS_TRY(hipEventRecord(it->second.done, s), "hipEventRecord");
   return NFS_OK;
 }
 

@@ -16,4 +16,6 @@ from .inputs import (  # noqa: F401
     unit_noise,
     batched_slices,
     prescan,
+    reconstruction_mask,
+    restrict_voxels,
 )

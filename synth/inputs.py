@@ -121,7 +121,7 @@ def _smooth_waveforms(rng, n_wave: int, tau):
 def _trajectory(cfg, rng):
     """kcoef [K][P] (rad) and t [K] (s) for the spiral recipe of a config."""
     dims = cfg["dims"]
-    n = dims[0]
+    n = cfg.get("k_grid", dims[0])  # acquisition matrix (k_max); the grid may be coarser
     k_shot = cfg["k_shot"]
     shots = cfg["shots"]
     P = cfg["n_basis"]
@@ -257,6 +257,35 @@ def make_config(name: str, with_noise: bool = True):
     )
     if with_noise:
         out["noise"] = unit_noise(rs[4], (cfg["n_coil"], t.size))
+    return out
+
+
+def reconstruction_mask(d, dilate: int = 2):
+    """Reconstruction mask M_R of a synthetic workload: the voxels where the
+    phantom is non-zero, dilated by ``dilate`` voxels (grid connectivity 1
+    per step).  The paper reconstructs only inside M_R, the head region of
+    its prescan (Methods, "Computation of masks"); for the synthetic phantom
+    its support plays that part.  Returns bool [L] in voxel order."""
+    from scipy.ndimage import binary_dilation
+
+    shape = tuple(reversed(d["dims"]))
+    inside = (np.abs(d["rho_true"]) > 0).reshape(shape)
+    if dilate > 0:
+        inside = binary_dilation(inside, iterations=dilate)
+    return inside.ravel()
+
+
+def restrict_voxels(d, mask):
+    """The workload with its voxel set restricted to ``mask`` (bool [L]):
+    sens, fields, b0 and rho_true keep the masked voxels in voxel order;
+    the sample side (kcoef, t, noise) is unchanged.  Since rho_true is zero
+    outside its support, data built from it are the same for the full and
+    the restricted problem."""
+    mask = np.asarray(mask, dtype=bool)
+    out = dict(d)
+    out.update(sens=np.ascontiguousarray(d["sens"][:, mask]), fields=np.ascontiguousarray(d["fields"][:, mask]),
+               b0=np.ascontiguousarray(d["b0"][mask]), rho_true=np.ascontiguousarray(d["rho_true"][mask]),
+               L=int(mask.sum()), mask=mask, name=d.get("name", "") + "_masked")
     return out
 
 

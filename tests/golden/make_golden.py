@@ -1,23 +1,45 @@
 """Write the stored oracle results used by the full-size GPU checks.
 
-Calls only the FP64 oracle and the seeded input generators.  Output
-tests/golden/c2_cg.npz, for the 2D 128x128 / 16-coil / 60000-sample /
-16-term workload with data m = E rho_phantom + noise (SNR 30), 30 CG
-iterations, for the plain recurrences ("plain_*") and for the
-re-orthogonalised ones ("reorth_*"):
-  <kind>_rho        -- iterate 30 (complex64 copy of the FP64 result)
-  <kind>_it_<n>     -- iterate n for n in ``<kind>_iters`` (complex64 copies)
-  <kind>_hist       -- per-iteration ||r_n||, ||rho_n||, ||d_n||^2 (float64)
-  plain_vs_reorth   -- [30] relative L2 distance of plain iterate n from
-                       re-orthogonalised iterate n (FP64 both)
-  m_rms, sigma      -- data scale and noise level
-Run: python tests/golden/make_golden.py   (about 16 min on 8 cores)
+Calls only the FP64 oracle and the seeded input generators.  Every target
+builds its data as the tests do: m = E rho_phantom + noise at SNR 30, with
+E the oracle's.
+
+  c2      tests/golden/c2_cg.npz: the 2D 128x128 / 16-coil / 60000-sample /
+          16-term workload, 30 CG iterations, plain recurrences ("plain_*")
+          and re-orthogonalised ones ("reorth_*"):
+            <kind>_rho        iterate 30 (complex64 copy of the FP64 result)
+            <kind>_it_<n>     iterate n for n in <kind>_iters (complex64)
+            <kind>_hist       per-iteration ||r_n||, ||rho_n||, ||d_n||^2
+            plain_vs_reorth   [30] relative L2 distance of plain iterate n
+                              from re-orthogonalised iterate n (FP64 both)
+            m_rms, sigma      data scale and noise level          (~16 min)
+  c2mask  tests/golden/c2mask_cg.npz: the same workload restricted to its
+          reconstruction mask (phantom support dilated by 2 voxels), same
+          data; every plain iterate 1..30 (plain_its [30][Lm] complex64), the
+          re-orthogonalised iterates listed in reorth_iters, both histories,
+          plain_vs_reorth, mask (bool [L])                          (~4 min)
+  c3s     tests/golden/c3s_cg.npz: the scaled 3D workload (48x48x24, 8 coils,
+          4 x 8000 samples, 16 terms), 15 iterations, same keys as c2
+                                                                   (~10 min)
+  c3ehe   tests/golden/c3_ehe_sampled.npz: the 3D 96x96x48 / 32-coil /
+          572000-sample workload, q = E^H E p for p = the phantom, at
+          n_vox_sampled seeded voxels (vox [n], q [n] complex128); the full
+          E p is formed, so this is one full-size E                 (~35 min)
+  batch24 tests/golden/batch24_cg.npz: the 24-slice batched workload (full
+          phase bases), 30 re-orthogonalised iterations per slice; per slice
+          s: vox_<s> (sampled voxel indices), rho_<s> (complex128 at those
+          voxels), norm_<s> (||rho_30||)                            (~35 min)
+
+Run: python tests/golden/make_golden.py <target> [<target> ...]
 """
 import os
 import sys
 import time
 
-import numpy as np
+# the oracle parallelises over sample blocks itself; one BLAS thread per block
+os.environ.setdefault("OPENBLAS_NUM_THREADS", "1")
+
+import numpy as np  # noqa: E402
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
@@ -25,39 +47,113 @@ sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
 import oracle  # noqa: E402
 import synth  # noqa: E402
 
-ITERS = {"plain": [1, 2, 3], "reorth": [1, 5, 10, 20]}
-N_ITER = 30
+N_VOX_SAMPLED = 1536
+N_VOX_SLICE = 512
 
 
-def c2_data():
-    d = synth.make_config("c2")
-    a = (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
-    clean = oracle.apply_E(d["rho_true"], *a)
+def args_of(d):
+    return (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
+
+
+def noisy_data(d):
+    """m = E rho_phantom + complex Gaussian noise at SNR 30 (oracle E)."""
+    clean = oracle.apply_E(d["rho_true"], *args_of(d))
     rms = float(np.sqrt(np.mean(np.abs(clean) ** 2)))
     sigma = rms / (30 * np.sqrt(2))
-    m = (clean + sigma * d["noise"]).astype(np.complex64)
-    return d, a, m, rms, sigma
+    return (clean + sigma * d["noise"]).astype(np.complex64), rms, sigma
 
 
-def main():
-    t0 = time.time()
-    d, a, m, rms, sigma = c2_data()
-    out = dict(m_rms=rms, sigma=sigma, n_iter=N_ITER)
+def cg_pair(d, m, n_iter, iters, t0):
+    """Plain and re-orthogonalised oracle CG; the keys shared by c2 and c3s."""
+    out = {}
     runs = {}
     for kind, ro in (("plain", False), ("reorth", True)):
-        res = oracle.cg_solve(m, *a, n_iter=N_ITER, return_iterates=True, reorth=ro)
+        res = oracle.cg_solve(m, *args_of(d), n_iter=n_iter, return_iterates=True, reorth=ro)
         runs[kind] = res["iterates"]
         out[f"{kind}_rho"] = res["rho"].astype(np.complex64)
         out[f"{kind}_hist"] = res["hist"]
-        out[f"{kind}_iters"] = np.array(ITERS[kind])
-        for n in ITERS[kind]:
+        out[f"{kind}_iters"] = np.array(iters[kind])
+        for n in iters[kind]:
             out[f"{kind}_it_{n}"] = res["iterates"][n - 1].astype(np.complex64)
         print(f"{kind} done at {time.time() - t0:.0f} s, status {res['status']}", flush=True)
     out["plain_vs_reorth"] = np.array([np.linalg.norm(x - y) / np.linalg.norm(y)
                                        for x, y in zip(runs["plain"], runs["reorth"])])
-    print("plain vs reorth: " + " ".join(f"{v:.1e}" for v in out["plain_vs_reorth"]))
+    print("plain vs reorth: " + " ".join(f"{v:.1e}" for v in out["plain_vs_reorth"]), flush=True)
+    return out, runs
+
+
+def make_c2():
+    t0 = time.time()
+    d = synth.make_config("c2")
+    m, rms, sigma = noisy_data(d)
+    out, _ = cg_pair(d, m, 30, {"plain": [1, 2, 3], "reorth": [1, 5, 10, 20]}, t0)
+    out.update(m_rms=rms, sigma=sigma, n_iter=30)
     np.savez_compressed(os.path.join(HERE, "c2_cg.npz"), **out)
     print(f"c2 CG golden written in {time.time() - t0:.0f} s")
+
+
+def make_c2mask():
+    t0 = time.time()
+    d = synth.make_config("c2")
+    m, rms, sigma = noisy_data(d)  # rho_true vanishes outside the mask: same data
+    mask = synth.reconstruction_mask(d)
+    dm = synth.restrict_voxels(d, mask)
+    out, runs = cg_pair(dm, m, 30, {"plain": [], "reorth": [1, 5, 10, 20, 30]}, t0)
+    out["plain_its"] = np.stack(runs["plain"]).astype(np.complex64)
+    out.update(m_rms=rms, sigma=sigma, n_iter=30, mask=mask)
+    np.savez_compressed(os.path.join(HERE, "c2mask_cg.npz"), **out)
+    print(f"c2mask CG golden written in {time.time() - t0:.0f} s")
+
+
+def make_c3s():
+    t0 = time.time()
+    d = synth.make_config("c3s")
+    m, rms, sigma = noisy_data(d)
+    out, _ = cg_pair(d, m, 15, {"plain": [1, 2, 3, 5], "reorth": [1, 5, 10, 15]}, t0)
+    out.update(m_rms=rms, sigma=sigma, n_iter=15)
+    np.savez_compressed(os.path.join(HERE, "c3s_cg.npz"), **out)
+    print(f"c3s CG golden written in {time.time() - t0:.0f} s")
+
+
+def make_c3ehe():
+    t0 = time.time()
+    d = synth.make_config("c3", with_noise=False)
+    a = args_of(d)
+    vox = np.sort(np.random.default_rng(2024).choice(d["L"], N_VOX_SAMPLED, replace=False))
+    y = oracle.apply_E(d["rho_true"], *a, block=64)
+    print(f"full E done at {time.time() - t0:.0f} s", flush=True)
+    q = oracle.apply_EH(y, d["sens"][:, vox], d["fields"][:, vox], d["b0"][vox], d["kcoef"], d["t"], block=256)
+    np.savez_compressed(os.path.join(HERE, "c3_ehe_sampled.npz"), vox=vox, q=q, y_norm=np.linalg.norm(y))
+    print(f"c3 sampled E^H E golden written in {time.time() - t0:.0f} s")
+
+
+def make_batch24():
+    t0 = time.time()
+    sl = synth.batched_slices(24)
+    out = {}
+    for s, d in enumerate(sl):
+        m, _, _ = noisy_data(d)
+        res = oracle.cg_solve(m, *args_of(d), n_iter=30, reorth=True)
+        vox = np.sort(np.random.default_rng(500 + s).choice(d["L"], N_VOX_SLICE, replace=False))
+        out[f"vox_{s}"] = vox
+        out[f"rho_{s}"] = res["rho"][vox]
+        out[f"norm_{s}"] = np.linalg.norm(res["rho"])
+        print(f"slice {s} ({d['dims'][0]}^2, {d['n_coil']} coils, {d['K']} samples) done at "
+              f"{time.time() - t0:.0f} s, status {res['status']}", flush=True)
+    np.savez_compressed(os.path.join(HERE, "batch24_cg.npz"), **out)
+    print(f"batch24 CG golden written in {time.time() - t0:.0f} s")
+
+
+TARGETS = {"c2": make_c2, "c2mask": make_c2mask, "c3s": make_c3s, "c3ehe": make_c3ehe, "batch24": make_batch24}
+
+
+def main():
+    names = sys.argv[1:] or ["c2"]
+    for n in names:
+        if n not in TARGETS:
+            raise SystemExit(f"unknown target {n}; choose from {sorted(TARGETS)}")
+    for n in names:
+        TARGETS[n]()
 
 
 if __name__ == "__main__":

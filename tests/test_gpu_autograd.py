@@ -90,16 +90,27 @@ def test_autograd_finite_differences_float32(mods):
             fd = (loss_fn(kc, b0 + h * vb) - loss_fn(kc, b0 - h * vb)).item() / (2 * h)
             an = torch.sum(b0.grad * vb).item()
             assert abs(fd - an) < 2e-2 * abs(an) + 10 * floor, ("b0 dir", trial, fd, an)
+        # per-term gains g_b (kcoef[:, b] <- (1 + g_b) kcoef[:, b]): the gain
+        # direction of term b is scaled by c_b = max|kcoef[:, 1:4]| /
+        # max|kcoef[:, b]|, so that a step h moves every term's phase about as
+        # much as it moves the trajectory's (the small terms' raw gains sit
+        # below the quotient's noise floor); dL/dg_b = an / c_b.  A gain is
+        # checked when its scaled derivative stands 30x above the floor.
+        big = kc[:, 1:4].abs().max()
+        skipped = []
         for b in range(16):
+            c_b = (big / kc[:, b].abs().max()).item()
             e = torch.zeros_like(kc)
-            e[:, b] = kc[:, b]
+            e[:, b] = kc[:, b] * c_b
             an = torch.sum(kc.grad * e).item()
             if abs(an) < 30 * floor:
+                skipped.append(b)
                 continue
             fd = (loss_fn(kc + h * e, b0) - loss_fn(kc - h * e, b0)).item() / (2 * h)
             assert abs(fd - an) < 2e-2 * abs(an) + 10 * floor, ("gain", b, fd, an)
             checked += 1
-    assert checked >= 1
+    print(f"FD per-term gains: {checked} of 16 checked, skipped (derivative under 30x the noise floor): {skipped}")
+    assert checked >= 15, skipped
 
 
 @pytest.fixture(scope="module")

@@ -149,3 +149,71 @@ def test_persistent_batch_with_mixed_shapes_and_replacement(nfs):
         torch.cuda.synchronize()
         assert torch.equal(rb[i].cpu(), r1.cpu()), i
         assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
+
+
+def test_graph_cache_evicts_and_stays_correct(nfs, small_batch):
+    """Graph mode with fresh output buffers on every call: each call is a new
+    graph key, so after 32 captures the least recently used graphs are
+    destroyed; every result (including replays of graphs that survived and
+    re-captures of evicted ones) equals the eager solve."""
+    sl, probs, ms = small_batch
+    p, m = probs[2], torch.from_numpy(ms[2]).cuda()
+    nfs.set_graphs(0, False)
+    eager, _, _ = nfs.cg_solve(p, m, 6, precision="fp16", reorth=True)
+    eager = eager.cpu()
+    nfs.set_graphs(0, True)
+    try:
+        keep = []
+        for rep in range(40):
+            out, _, info = nfs.cg_solve(p, m, 6, precision="fp16", reorth=True)
+            keep.append(out)  # keeps every pointer distinct
+            torch.cuda.synchronize()
+            assert torch.equal(out.cpu(), eager), rep
+        # the first buffers' graphs were evicted: their calls capture again
+        for rep in range(3):
+            out, _, _ = nfs.cg_solve(p, m, 6, precision="fp16", reorth=True, out=keep[rep])
+            torch.cuda.synchronize()
+            assert torch.equal(out.cpu(), eager), rep
+    finally:
+        nfs.set_graphs(0, False)
+
+
+@pytest.fixture(scope="module")
+def batch24(nfs):
+    import os
+
+    g = np.load(os.path.join(os.path.dirname(__file__), "golden", "batch24_cg.npz"))
+    sl = synth.batched_slices(24)
+    probs, ms = [], []
+    for d in sl:
+        probs.append(nfs.Problem(*args(d)))
+        clean = oracle.apply_E(d["rho_true"], *args(d))
+        sig = np.sqrt(np.mean(np.abs(clean) ** 2)) / (30 * np.sqrt(2))
+        ms.append(torch.from_numpy((clean + sig * d["noise"]).astype(np.complex64)).cuda())
+    return sl, probs, ms, g
+
+
+@pytest.mark.parametrize("mode_name", ["streams", "persistent"])
+def test_full_batch_sampled_vs_stored_oracle(nfs, batch24, mode_name):
+    """The 24-slice workload (96..160 square, 8..32 coils, 8000..30000
+    samples, 16 terms, per-slice B0), all slices in one batched call with
+    BF16 operands and 30 re-orthogonalised iterations, against the stored
+    FP64 oracle solves (tests/golden/batch24_cg.npz) on 512 sampled voxels
+    per slice, both measures at the BF16 bar."""
+    from _parity import check
+
+    sl, probs, ms, g = batch24
+    nfs.set_batch_mode(0, mode_name)
+    try:
+        rb, hb, ib = nfs.cg_solve_batched(probs, ms, 30, precision="bf16", reorth=True)
+        torch.cuda.synchronize()
+    finally:
+        nfs.set_batch_mode(0, "streams")
+    worst = (0.0, 0.0)
+    for s in range(len(sl)):
+        assert ib[s].cpu().tolist() == [30, 1], s
+        x = rb[s].cpu().numpy()
+        e = check(x[g[f"vox_{s}"]], g[f"rho_{s}"], 2e-3, ("slice", s))
+        worst = max(worst, e)
+        assert abs(np.linalg.norm(x) - g[f"norm_{s}"]) < 2e-3 * g[f"norm_{s}"], s
+    print(f"24-slice batch ({mode_name}), BF16, sampled voxels vs oracle: worst rel {worst[0]:.2e} max {worst[1]:.2e}")

@@ -376,3 +376,54 @@ def test_c2_cg_plain_vs_stored_oracle(nfs, c2, c2_golden, prec):
         err = rel(rho.cpu().numpy(), g[f"plain_it_{n}"])
         print(f"c2 CG plain {prec}: iterate {n} rel {err:.2e}")
         assert err < TOL[prec]
+
+
+# ------------------------------------------ phases beyond the raw sin/cos range
+@pytest.fixture(scope="module")
+def big_phase(nfs):
+    """A problem whose phase bound sum_b max|a_b| max|h_b| / 2pi exceeds the
+    128 revolutions up to which the kernels feed the phase straight to the
+    hardware sine/cosine: above it they reduce it with v_fract first (the
+    paper's 219 x 219 field of view at Nyquist with +-150 Hz off-resonance
+    comes close to that bound)."""
+    d = synth.random_problem(1000, 1500, 5, 7, seed=41, phase_scale=380.0, b0_hz=300.0)
+    tb = np.max(np.abs(d["t"].astype(np.float64))) * np.max(np.abs(d["b0"].astype(np.float64)))
+    bound = (tb + sum(np.max(np.abs(d["kcoef"][:, b].astype(np.float64))) * np.max(np.abs(d["fields"][b]))
+                      for b in range(d["n_basis"]))) / (2 * np.pi)
+    assert 160 < bound < 256, bound  # v_fract branch taken; hardware range 256
+    d["bound"] = bound
+    d["gp"] = gpu_problem(nfs, d)
+    d["E_ref"] = oracle.apply_E(d["rho"], *args(d))
+    d["EH_ref"] = oracle.apply_EH(d["m"], *args(d))
+    d["EHE_ref"] = oracle.apply_EHE(d["rho"], *args(d))
+    d["cg_ref"] = oracle.cg_solve(d["m"], *args(d), n_iter=6)
+    return d
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_phase_beyond_raw_range(nfs, big_phase, prec):
+    from _parity import check
+
+    d = big_phase
+    gp = d["gp"]
+    m = nfs.apply_E(gp, torch.from_numpy(d["rho"]), prec).cpu().numpy()
+    x = nfs.apply_EH(gp, torch.from_numpy(d["m"]), prec).cpu().numpy()
+    q = nfs.apply_EHE(gp, torch.from_numpy(d["rho"]), prec).cpu().numpy()
+    rho, _, info = nfs.cg_solve(gp, torch.from_numpy(d["m"]), 6, precision=prec)
+    e = [check(m, d["E_ref"], TOL[prec], "E"), check(x, d["EH_ref"], TOL[prec], "EH"),
+         check(q, d["EHE_ref"], TOL[prec], "EHE"), check(rho.cpu().numpy(), d["cg_ref"]["rho"], TOL[prec], "CG")]
+    assert info.cpu().tolist() == [6, 1]
+    print(f"phase bound {d['bound']:.0f} rev, {prec}: " + " ".join(f"{a:.1e}/{b:.1e}" for a, b in e))
+
+
+def test_phase_beyond_raw_range_resident(nfs, big_phase):
+    """The resident-P build takes the same v_fract branch."""
+    from _parity import check
+
+    d = big_phase
+    rho_r, _, info = nfs.cg_solve_resident(d["gp"], torch.from_numpy(d["m"]), 6)
+    rho_s, _, _ = nfs.cg_solve(d["gp"], torch.from_numpy(d["m"]), 6, precision="fp16")
+    assert info.cpu().tolist() == [6, 1]
+    e = check(rho_r.cpu().numpy(), d["cg_ref"]["rho"], TOL["fp16"], "resident CG")
+    print(f"phase bound {d['bound']:.0f} rev, resident fp16 CG: {e[0]:.1e}/{e[1]:.1e}; "
+          f"split vs resident {rel(rho_r.cpu().numpy(), rho_s.cpu().numpy()):.1e}")

@@ -102,6 +102,32 @@ def test_single_voxel_closed_form():
     np.testing.assert_allclose(m2[0], [cmath.exp(-1j), cmath.exp(0.5j), 1.0], rtol=1e-12, atol=1e-12)
 
 
+def test_phase_hand_evaluated_and_consistent_with_E():
+    """oracle.phase (the exponent K R) on the numbers of the single-voxel
+    pin, evaluated by hand: row k, column l is sum_b kcoef[k, b] h_b(l) +
+    t[k] b0[l].  Two basis terms (h = x and h = 1) so that a transposed or
+    dropped term shows.  Then exp(i phase) column l, weighted by S_c(l), is
+    E applied to the unit vector at l (a sign slip in either fails)."""
+    fields = np.array([[0.5, -0.25], [1.0, 1.0]], dtype=np.float32)
+    b0 = np.array([2 * np.pi * 100.0, 0.0], dtype=np.float32)
+    kcoef = np.array([[4.0, 0.25], [-2.0, 0.0], [0.0, -1.5]], dtype=np.float32)
+    t = np.array([0.0, 1e-3, 2e-3], dtype=np.float32)
+    ph = oracle.phase(kcoef, t, fields, b0)
+    b0_32 = float(np.float32(2 * np.pi * 100.0))
+    t1, t2 = float(np.float32(1e-3)), float(np.float32(2e-3))
+    want = np.array([[2.0 + 0.25, -1.0 + 0.25],
+                     [-1.0 + t1 * b0_32, 0.5],
+                     [-1.5 + t2 * b0_32, -1.5]])
+    np.testing.assert_allclose(ph, want, rtol=0, atol=1e-15)
+    sens = np.array([[0.5 + 0.5j, 1.0], [2.0j, -1.0]], dtype=np.complex64)
+    for l in range(2):
+        e = np.zeros(2)
+        e[l] = 1.0
+        m = oracle.apply_E(e, sens, fields, b0, kcoef, t)
+        np.testing.assert_allclose(m, sens[:, l:l + 1].astype(np.complex128) * np.exp(1j * ph[:, l])[None, :],
+                                   rtol=1e-13, atol=1e-13)
+
+
 def test_E_is_linear(rng):
     d = synth.random_problem(40, 50, 3, 5, seed=2)
     a = _args(d)
