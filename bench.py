@@ -2,26 +2,35 @@
 """Benchmark of the non-Fourier SENSE hot path on one MI355X.
 
 One step = one full CG solve (setup, E^H m, n_iter iterations of E^H E with
-the FP64 scalar updates and residual re-orthogonalisation) on the 2D
-128x128 / 16-coil / 4 x 15000-sample / 16-field-term workload (30
-iterations), inputs resident in HBM.
-
-Solves are replayed from a captured hipGraph (the library's graph mode; the
-pass that times the encode kernel alone runs eagerly, since per-launch HIP
-events cannot live inside a graph).  Encode-kernel shapes are autotuned
-before timing.
+the FP64 scalar updates and residual re-orthogonalisation) on the 3D
+96x96x48 / 32-coil / 16 x 35750-sample / 16-field-term workload (15
+iterations; the largest configuration), inputs resident in HBM, replayed
+from a captured hipGraph (the library's graph mode).  Encode-kernel shapes
+are autotuned before timing.
 
 Reported value: E^H E voxel*sample*coil per second over the solve, i.e.
 (n_iter + 1/2) * L * K * G / (solve time), the initial E^H m counting as half
-an application.  ms_per_step is the CG solve time.  The result is checked
-against the stored FP64 oracle solve of the same workload.
+an application.  ms_per_step is the CG solve time.
 
-Also reported: the same for the FP32 operand form, one E^H E application
-timed alone, the fused encode kernel's average duration (HIP events on its
-launch stream, over the timed region) with its roofline, and the FP64 CPU
-oracle timed on a bounded sample of the workload on this host, and the
-map-estimation step (initial sensitivities, sensitivity and B0 smoothing) on
-the paper's prescan geometry.
+Accuracy.  A full FP64 oracle CG of the 3D workload takes many hours on the
+host, so rel_err_vs_oracle is null when no stored full solve exists; beside
+it go the errors against stored FP64 oracle values that the tests also use:
+the scaled 3D case's CG iterate (48x48x24, 8 coils, 4 x 8000 samples, 15
+iterations; tests/golden/c3s_cg.npz) and E^H E of the phantom at 1536 voxels
+of the full workload (tests/golden/c3_ehe_sampled.npz).
+
+Roofline: the fused encode kernel (phase tile, sin/cos, complex contraction),
+its average launch duration from HIP events on its launch stream over an
+eager pass of the same solve, against the transcendental peak (one sin and
+one cos per voxel-sample pair), with its matrix-pipe time fraction and the
+HBM traffic per launch from the committed counter summary.
+
+Side measurements: the BF16 and FP32 operand forms; one E^H E alone; the 2D
+128x128 workload (all forms, the compressed phase basis with its setup
+charged, the resident-P form, the plain recurrences, the stopping-criteria
+study, the k-space filter); the 24-slice batch; the map estimation on the
+paper's prescan geometry; the FP64 CPU oracle on a bounded sample of the
+headline workload.
 """
 from __future__ import annotations
 
@@ -43,6 +52,14 @@ HBM_PEAK_GBS = 8000.0
 MFMA_PEAK_TFLOPS = {"fp16": 2500.0, "bf16": 2500.0, "fp32": 157.3}
 N_CU, SIMD_PER_CU, TRANS_LANES_PER_SIMD, CLOCK_GHZ = 256, 4, 8, 2.4
 TRANS_PEAK = N_CU * SIMD_PER_CU * TRANS_LANES_PER_SIMD * CLOCK_GHZ * 1e9
+GOLDEN = os.path.join(ROOT, "tests", "golden")
+
+WORKLOADS = {
+    "c3": "c3: 3D 96x96x48, 32 coils, 16 x 35750-sample tilted spiral shots (R~7), 16 field terms, B0 +-150 Hz, "
+          "15 CG iterations, re-orthogonalised (one step = one CG solve)",
+    "c2": "c2: 2D 128x128, 16 coils, 4 x 15000-sample R=4 spiral, 16 field terms, B0 +-100 Hz, 30 CG iterations, "
+          "re-orthogonalised (one step = one CG solve)",
+}
 
 
 def progress(msg):
@@ -57,20 +74,16 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--precision", default="fp16", choices=["fp16", "bf16", "fp32"])
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-fp32-form", action="store_true")
+    ap.add_argument("--no-forms", action="store_true", help="skip the other operand forms of the headline")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 2D 128x128 side measurements")
     ap.add_argument("--no-batched", action="store_true", help="skip the 24-slice batched-solve measurement")
-    ap.add_argument("--no-3d", action="store_true", help="skip the 3D 96x96x48 / 32-coil solve measurement")
     ap.add_argument("--no-tune", action="store_true", help="use the default encode shapes instead of autotuned ones")
-    ap.add_argument("--no-resident", action="store_true", help="skip the resident-P (non-split) solve measurement")
-    ap.add_argument("--no-stopping", action="store_true", help="skip the 250-iteration L-curve / SSIM run")
-    ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--no-maps", action="store_true", help="skip the sensitivity / B0 map-estimation measurement")
+    ap.add_argument("--plain", action="store_true", help="plain CG recurrences (no re-orthogonalisation)")
     ap.add_argument("--profile-run", action="store_true",
-                    help="one solve only (no side measurements, no CPU baseline), for counter collection")
-    ap.add_argument("--no-compress", action="store_true",
-                    help="solve with the full phase basis instead of its compressed form (nfs_compress_basis)")
+                    help="one solve of the headline workload only, for counter collection")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every solve eagerly instead of replaying it from a captured hipGraph")
     return ap.parse_args()
@@ -82,12 +95,23 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def cpu_baseline(d):
-    """FP64 oracle E^H E on every 8th sample (all voxels, all coils), repeated
-    for at least 10 s of wall time; returns v*s*c/s."""
+def max_rel(a, b):
+    a = np.asarray(a, dtype=np.complex128)
+    b = np.asarray(b, dtype=np.complex128)
+    return float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+
+
+def golden(name):
+    p = os.path.join(GOLDEN, name)
+    return np.load(p) if os.path.exists(p) else None
+
+
+def cpu_baseline(d, stride):
+    """FP64 oracle E^H E on every `stride`-th sample (all voxels, all coils),
+    repeated for at least 10 s of wall time; returns v*s*c/s."""
     import oracle
 
-    ks = np.arange(0, d["K"], 8)
+    ks = np.arange(0, d["K"], stride)
     a = (d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
     x = d["rho_true"]
     work = 0.0
@@ -99,81 +123,288 @@ def cpu_baseline(d):
         if el >= 10.0:
             break
     return dict(value=work / el, unit="voxel*sample*coil/s", cores=os.cpu_count(), kind="oracle",
-                sample=f"FP64 E^H E on every 8th sample ({len(ks)} of {d['K']}) x {d['L']} voxels x "
-                       f"{d['n_coil']} coils, repeated {work / (d['L'] * len(ks) * d['n_coil']):.0f}x "
-                       f"in {el:.1f} s, numpy with {os.cpu_count()} threads")
+                sample=f"FP64 E^H E on every {stride}th sample ({len(ks)} of {d['K']}) x {d['L']} voxels x "
+                       f"{d['n_coil']} coils of the headline workload, repeated "
+                       f"{work / (d['L'] * len(ks) * d['n_coil']):.0f}x in {el:.1f} s, numpy with "
+                       f"{os.cpu_count()} threads")
 
 
-def threed_run(nfs, synth, torch, dev, args):
-    """The 3D workload (96x96x48, 32 coils, 16 x 35750 samples, 16 terms,
-    B0 +-150 Hz, 15 CG iterations): one warm-up and one timed solve at the
-    benchmark's precision, re-orthogonalised; E checked against the FP64
-    oracle on 48 sampled k-space rows (all voxels, all coils)."""
-    import oracle
+class Solver:
+    """One workload on the GPU: problem, synthetic data (E rho_phantom with
+    the library's FP32 E, plus complex noise at SNR 30) and timed solves."""
 
-    d = synth.make_config("c3")
-    L, K, G, n_iter = d["L"], d["K"], d["n_coil"], d["n_iter"]
-    prob = nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev)
-    rho_t = torch.from_numpy(d["rho_true"]).to(dev)
-    clean = nfs.apply_E(prob, rho_t, "fp32")
-    sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
-    m = clean + sig * torch.from_numpy(d["noise"]).to(dev)
-    del clean
-    if not args.no_tune:
-        nfs.autotune(prob, args.precision)
-    ks = np.sort(np.random.default_rng(3).choice(K, 48, replace=False))
-    e_gpu = nfs.apply_E(prob, rho_t, args.precision).cpu().numpy()[:, ks]
-    e_ref = oracle.apply_E(d["rho_true"], d["sens"], d["fields"], d["b0"], d["kcoef"][ks], d["t"][ks])
-    out = torch.empty(L, dtype=torch.complex64, device=dev)
-    hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
-    info = torch.zeros(2, dtype=torch.int32, device=dev)
-    nfs.cg_solve(prob, m, n_iter, precision=args.precision, reorth=True, out=out, hist=hist, info=info)
-    torch.cuda.synchronize()
-    nfs.profile_enable(0, True)
-    nfs.profile_read(0, "E")
-    nfs.profile_read(0, "EH")
-    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    nfs.cg_solve(prob, m, n_iter, precision=args.precision, reorth=True, out=out, hist=hist, info=info)
-    ev1.record()
-    torch.cuda.synchronize()
-    kt = {k: nfs.profile_read(0, k) for k in ("E", "EH")}
-    nfs.profile_enable(0, False)
-    ms = ev0.elapsed_time(ev1)
-    # the paper's k-space filter on the 3D reconstruction: bins inside the
-    # 3D hull of the first-order k positions (x, y, z terms)
+    def __init__(self, nfs, torch, dev, d, reorth):
+        self.nfs, self.torch, self.dev, self.d, self.reorth = nfs, torch, dev, d, reorth
+        self.prob = nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev)
+        clean = nfs.apply_E(self.prob, torch.from_numpy(d["rho_true"]).to(dev), "fp32")
+        sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
+        self.m = clean + sig * torch.from_numpy(d["noise"]).to(dev)
+        del clean
+        torch.cuda.synchronize()
+        self.L, self.K, self.G, self.n_iter = d["L"], d["K"], d["n_coil"], d["n_iter"]
+
+    def buffers(self, n_iter=None):
+        torch, dev = self.torch, self.dev
+        n = self.n_iter if n_iter is None else n_iter
+        return (torch.empty(self.L, dtype=torch.complex64, device=dev),
+                torch.full((n + 1, 3), float("nan"), dtype=torch.float64, device=dev),
+                torch.zeros(2, dtype=torch.int32, device=dev))
+
+    def time_solves(self, prec, steps, warmup, graphs=True, prob=None, data=None, reorth=None):
+        """Mean ms per solve over `steps` after `warmup`; data(): the CG
+        right-hand side, called inside the timed region."""
+        nfs, torch = self.nfs, self.torch
+        prob = self.prob if prob is None else prob
+        data = (lambda: self.m) if data is None else data
+        reorth = self.reorth if reorth is None else reorth
+        out, hist, info = self.buffers()
+        nfs.set_graphs(0, graphs)
+        try:
+            for _ in range(warmup):
+                nfs.cg_solve(prob, data(), self.n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            t0 = time.perf_counter()
+            ev0.record()
+            for _ in range(steps):
+                nfs.cg_solve(prob, data(), self.n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
+            ev1.record()
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+        finally:
+            nfs.set_graphs(0, False)
+        return out, hist, info, ev0.elapsed_time(ev1) / steps, wall
+
+    def kernel_times(self, prec, solves=1, prob=None):
+        """Encode-kernel launch durations (HIP events on the launch stream,
+        the library's profiling hook) over eager solves."""
+        nfs, torch = self.nfs, self.torch
+        prob = self.prob if prob is None else prob
+        out, hist, info = self.buffers()
+        nfs.cg_solve(prob, self.m, self.n_iter, precision=prec, reorth=self.reorth, out=out, hist=hist, info=info)
+        torch.cuda.synchronize()
+        nfs.profile_enable(0, True)
+        nfs.profile_read(0, "E")
+        nfs.profile_read(0, "EH")
+        for _ in range(solves):
+            nfs.cg_solve(prob, self.m, self.n_iter, precision=prec, reorth=self.reorth, out=out, hist=hist, info=info)
+        torch.cuda.synchronize()
+        kt = {k: nfs.profile_read(0, k) for k in ("E", "EH")}
+        nfs.profile_enable(0, False)
+        return kt
+
+    def ehe_alone(self, prec, reps):
+        nfs, torch = self.nfs, self.torch
+        p = torch.from_numpy(self.d["rho_true"]).to(self.dev)
+        q = torch.empty_like(p)
+        for _ in range(2):
+            nfs.apply_EHE(self.prob, p, prec, out=q)
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nfs.apply_EHE(self.prob, p, prec, out=q)
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        return float(np.median(times)), q
+
+
+def phase_instrs(P):
+    return -(-3 * (P + 1) // 32)
+
+
+def col_blocks(G):
+    return {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
+
+
+def roofline(kt, L, K, G, P, prec, counters_md):
+    """Roofline object of the dominant encode launch (E or E^H)."""
+    from paper_2604_09233_amd.profile_summary import read_traffic
+
+    n_e, ms_e = kt["E"]
+    n_h, ms_h = kt["EH"]
+    kname, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
+    avg_ms = ms_k / max(n_k, 1)
+    pairs = L * K  # voxel-sample pairs per launch
+    achieved = 2 * pairs / (avg_ms * 1e-3)  # one sin and one cos per pair
+    # matrix-pipe time of the MFMA instructions the kernel issues, at the
+    # published dense peak, as a fraction of the measured launch time: per
+    # 16 x 16 tile (256 pairs) ceil(3 (P+1) / 32) f16 16x16x32 phase
+    # instructions, and per 16-column block of the 2G real columns one f16
+    # (fp16), two bf16 (bf16: hi and lo data parts) or three f16 (fp32: split
+    # operands) 16x16x32 contraction instructions
+    tiles = pairs / 256.0
+    flops = tiles * 16384 * (phase_instrs(P) + col_blocks(G) * {"fp16": 1, "bf16": 2, "fp32": 3}[prec])
+    tr = read_traffic(os.path.join(ROOT, "profiles", counters_md))
+    return dict(bound="alu", achieved=achieved / 1e12, peak=TRANS_PEAK / 1e12, unit="Tsincos-ops/s",
+                frac=achieved / TRANS_PEAK, traffic=(tr or {}).get(kname), traffic_unit="bytes per launch",
+                kernel=f"encode_kernel ({kname})", avg_launch_ms=avg_ms, launches=n_k,
+                mfma_pipe_frac=flops / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) / (avg_ms * 1e-3),
+                encode_kernel_ms={"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)})
+
+
+def c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth):
+    """Errors against the stored FP64 oracle values of the 3D workloads: E^H E
+    of the phantom at the stored voxels of the full workload, and the CG
+    iterates of the scaled 3D case (data from the library's FP32 E, which
+    differs from the oracle-built data by ~1e-6 relative)."""
+    out = {}
+    g = golden("c3_ehe_sampled.npz")
+    if g is not None:
+        _, q = sv.ehe_alone(prec, 1)
+        q = q.cpu().numpy()[g["vox"]]
+        out["c3_EHE_sampled"] = dict(voxels=int(len(g["vox"])), rel=rel(q, g["q"]), max_rel=max_rel(q, g["q"]))
+    g = golden("c3s_cg.npz")
+    if g is not None:
+        s = Solver(nfs, torch, dev, synth.make_config("c3s"), reorth)
+        kind = "reorth" if reorth else "plain"
+        n = int(g["n_iter"])
+        rho, _, _ = nfs.cg_solve(s.prob, s.m, n, precision=prec, reorth=reorth)
+        ref = g[f"{kind}_rho"]
+        out["c3s_cg"] = dict(workload="3D 48x48x24, 8 coils, 4 x 8000 samples, 16 terms, 15 iterations",
+                             iterate=n, rel=rel(rho.cpu().numpy(), ref), max_rel=max_rel(rho.cpu().numpy(), ref))
+    return out
+
+
+def threed_kspace_filter(nfs, torch, dev, d, rho):
+    """The paper's k-space filter on the 3D reconstruction: bins inside the
+    hull of the first-order k positions (x, y, z terms)."""
     t0 = time.perf_counter()
     f = nfs.kspace_filter_mask(d["kcoef"][:, 1:4].astype(np.float64) / np.pi, d["dims"])
     ms_mask = (time.perf_counter() - t0) * 1e3
     f_dev = torch.from_numpy(f).to(dev)
-    nfs.apply_kspace_filter(out, f_dev, d["dims"])
+    nfs.apply_kspace_filter(rho, f_dev, d["dims"])
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record()
-    out_f = nfs.apply_kspace_filter(out, f_dev, d["dims"])
+    out_f = nfs.apply_kspace_filter(rho, f_dev, d["dims"])
     e1.record()
     torch.cuda.synchronize()
     ref_img = torch.from_numpy(d["rho_true"])
-    kf3 = dict(bins_inside=int(f.sum()), bins=int(f.size), ms_mask_host=ms_mask, ms_apply=e0.elapsed_time(e1),
-               ssim_vs_phantom_before=float(nfs.ssim(out, ref_img, d["dims"]).cpu()[0]),
-               ssim_vs_phantom_after=float(nfs.ssim(out_f, ref_img, d["dims"]).cpu()[0]))
-    del out_f, f_dev
-    pairs = L * K
-    enc = {k: v[1] / max(v[0], 1) for k, v in kt.items()}
-    # MFMA instructions issued per 16 x 16 tile: the phase (f16) and the
-    # contraction (one f16, two bf16 or three f16 per 16-column block)
-    nq = -(-3 * (d["n_basis"] + 1) // 32)
-    nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
-    flops = pairs / 256.0 * 16384 * (nq + nb * {"fp16": 1, "bf16": 2, "fp32": 3}[args.precision])
-    return dict(workload="3D 96x96x48, 32 coils, 16 x 35750-sample spiral shots, 16 field terms, B0 +-150 Hz, "
-                         "15 CG iterations, re-orthogonalised",
-                precision=args.precision, ms_per_solve=ms, value=(n_iter + 0.5) * pairs * G / (ms * 1e-3),
-                unit="voxel*sample*coil/s", encode_kernel_ms=enc,
-                sincos_frac_of_peak={k: 2 * pairs / (v * 1e-3) / TRANS_PEAK for k, v in enc.items()},
-                mfma_frac_of_peak={k: flops / (v * 1e-3) / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) for k, v in enc.items()},
-                rel_err_E_sampled=rel(e_gpu, e_ref), sampled_rows=len(ks),
-                held_tiles_nsplit=nfs.tuned_shape(prob, args.precision),
-                cg_info=info.cpu().tolist(), kspace_filter=kf3)
+    return dict(bins_inside=int(f.sum()), bins=int(f.size), ms_mask_host=ms_mask, ms_apply=e0.elapsed_time(e1),
+                ssim_vs_phantom_before=float(nfs.ssim(rho, ref_img, d["dims"]).cpu()[0]),
+                ssim_vs_phantom_after=float(nfs.ssim(out_f, ref_img, d["dims"]).cpu()[0]))
+
+
+def twod_run(nfs, synth, torch, dev, args):
+    """The 2D 128x128 workload: the 30-iteration solve in each operand form
+    against the stored FP64 oracle solves, the compressed phase basis with
+    its setup (host compression, data rotation) charged, the resident-P
+    (non-split) form, the plain recurrences, the 250-iteration stopping
+    study and the k-space filter."""
+    reorth = not args.plain
+    kind = "reorth" if reorth else "plain"
+    d = synth.make_config("c2")
+    sv = Solver(nfs, torch, dev, d, reorth)
+    L, K, G, n_iter = sv.L, sv.K, sv.G, sv.n_iter
+    vsc = L * K * G
+    g = golden("c2_cg.npz")
+    steps = max(2, args.steps // 2)
+    precs = [args.precision] + [p for p in ("fp32", "bf16") if p != args.precision]
+    forms = {}
+    rho_main = None
+    for prec in precs:
+        if not args.no_tune:
+            nfs.autotune(sv.prob, prec)
+        rho, _, info, ms, _ = sv.time_solves(prec, steps, 1, graphs=not args.no_graphs)
+        forms[prec] = dict(ms_per_step=ms, value=(n_iter + 0.5) * vsc / (ms * 1e-3),
+                           rel_err_vs_oracle=rel(rho.cpu().numpy(), g[f"{kind}_rho"]) if g is not None else None,
+                           cg_info=info.cpu().tolist())
+        if prec == args.precision:
+            rho_main = rho.clone()
+    kt = sv.kernel_times(args.precision)
+    roof = roofline(kt, L, K, G, d["n_basis"], args.precision, f"encode_kernel_c2_{args.precision}_counters.md")
+
+    # compressed phase basis: 16 solid harmonics on one slice span 10
+    # functions; the compression is redone per geometry (kcoef is measured
+    # per scan), so its host time is charged to an end-to-end figure
+    t_c = time.perf_counter()
+    cprob, theta, cinfo = nfs.compress_basis(sv.prob)
+    torch.cuda.synchronize()
+    t_c = (time.perf_counter() - t_c) * 1e3
+    if not args.no_tune:
+        nfs.autotune(cprob, args.precision)
+    mbuf = torch.empty_like(sv.m)
+    rho_c, _, _, ms_c, _ = sv.time_solves(args.precision, steps, 1, graphs=not args.no_graphs, prob=cprob,
+                                          data=lambda: nfs.phase_shift(sv.m, theta, -1, out=mbuf))
+    compressed = dict(terms=d["n_basis"] + 1, compressed_terms=cprob.P + 1, err_bound_rad=cinfo["err_bound"],
+                      ms_solve=ms_c, ms_setup_host=t_c, ms_end_to_end=ms_c + t_c,
+                      rel_err_vs_oracle=rel(rho_c.cpu().numpy(), g[f"{kind}_rho"]) if g is not None else None,
+                      note="solve on the compressed basis with the data rotation by exp(-i theta) inside the step; "
+                           "ms_setup_host = nfs_compress_basis (host copies, FP64 compression, device copies)")
+    del rho_c
+
+    # non-split form: P built once per solve (2 K L x 4 bytes), streamed by every E and E^H
+    resident = None
+    if args.precision == "fp16":
+        def t_res(n):
+            o, h, f = sv.buffers(n)
+            nfs.cg_solve_resident(sv.prob, sv.m, n, reorth=reorth, out=o, hist=h, info=f)
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            nfs.cg_solve_resident(sv.prob, sv.m, n, reorth=reorth, out=o, hist=h, info=f)
+            e1.record()
+            torch.cuda.synchronize()
+            return o, e0.elapsed_time(e1)
+        if not args.no_tune:
+            nfs.autotune(sv.prob, "fp16")
+        rr, ms_r = t_res(n_iter)
+        _, ms_r1 = t_res(1)
+        resident = dict(ms_per_step=ms_r, ms_per_iteration=(ms_r - ms_r1) / (n_iter - 1),
+                        ms_build_and_first_iteration=ms_r1, P_bytes=2 * L * K * 4,
+                        identical_to_split=bool(torch.equal(rr.cpu(), rho_main.cpu())),
+                        rel_err_vs_oracle=rel(rr.cpu().numpy(), g[f"{kind}_rho"]) if g is not None else None)
+        del rr
+        sv.prob._ws.pop(("CG_RESIDENT", "fp16", n_iter, reorth), None)
+        sv.prob._ws.pop(("CG_RESIDENT", "fp16", 1, reorth), None)
+        torch.cuda.empty_cache()
+
+    plain = None
+    if reorth:
+        rhop, _, _, msp, _ = sv.time_solves(args.precision, steps, 1, graphs=not args.no_graphs, reorth=False)
+        plain = dict(ms_per_step=msp,
+                     rel_err_vs_oracle_plain=rel(rhop.cpu().numpy(), g["plain_rho"]) if g is not None else None,
+                     oracle_plain_vs_reorth=float(g["plain_vs_reorth"][-1]) if g is not None else None)
+
+    # the paper's stopping-criteria study: 250 iterations, L-curve corner and
+    # SSIM of every iterate against the phantom
+    n_long = 250
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    ev[0].record()
+    _, h_long, i_long, its = nfs.cg_solve_traced(sv.prob, sv.m, n_long, precision=args.precision, reorth=reorth)
+    ev[1].record()
+    ss = nfs.ssim(its[1:], torch.from_numpy(d["rho_true"]), d["dims"])
+    ev[2].record()
+    torch.cuda.synchronize()
+    ss = ss.cpu().numpy()
+    corner, _ = nfs.lcurve_corner(h_long)
+    stopping = dict(iterations=n_long, ms_solve=ev[0].elapsed_time(ev[1]), ms_ssim_all=ev[1].elapsed_time(ev[2]),
+                    peak_ssim=float(ss.max()), peak_ssim_iteration=int(np.argmax(ss)) + 1,
+                    ssim_at=dict((str(k), float(ss[k - 1])) for k in (5, 10, 30, 100, 250)),
+                    lcurve_corner_iteration=corner, cg_info=i_long.cpu().tolist())
+    del its
+
+    # the paper's k-space filter: bins inside the hull of the first-order k
+    # positions (linear x, y terms; kcoef / pi in cycles per FOV)
+    f = nfs.kspace_filter_mask(d["kcoef"][:, 1:3].astype(np.float64) / np.pi, d["dims"])
+    f_dev = torch.from_numpy(f).to(dev)
+    nfs.apply_kspace_filter(rho_main, f_dev, d["dims"])
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    rho_f = nfs.apply_kspace_filter(rho_main, f_dev, d["dims"])
+    e1.record()
+    torch.cuda.synchronize()
+    ref_img = torch.from_numpy(d["rho_true"])
+    kf = dict(bins_inside=int(f.sum()), bins=int(f.size), ms_apply=e0.elapsed_time(e1),
+              ssim_vs_phantom_before=float(nfs.ssim(rho_main, ref_img, d["dims"]).cpu()[0]),
+              ssim_vs_phantom_after=float(nfs.ssim(rho_f, ref_img, d["dims"]).cpu()[0]))
+    return dict(workload=WORKLOADS["c2"], L=L, K=K, G=G, n_iter=n_iter, forms=forms, roofline=roof,
+                encode_shapes=nfs.tuned_shape(sv.prob, args.precision), compressed_basis=compressed,
+                resident_P=resident, plain_recurrences=plain, stopping_criteria=stopping, kspace_filter=kf)
 
 
 def batched_run(nfs, synth, torch, dev, args, steps=2):
@@ -189,20 +420,20 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
         sig = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2))) / (30 * np.sqrt(2))
         ms.append(clean + sig * torch.from_numpy(d["noise"]).to(dev))
     n_iter = 30
-    # compressed phase bases (each slice: 16 solid harmonics on one slice ->
-    # 10 terms), the data rotations by exp(-i theta) inside the timed step
-    full_probs, thetas = probs, None
-    if not args.no_compress:
-        comp = [nfs.compress_basis(pr) for pr in probs]
-        probs = [c[0] for c in comp]
-        thetas = [c[1] for c in comp]
-    bufs = [torch.empty_like(m) for m in ms]
-    if not args.no_tune:
-        nfs.autotune_batched(probs, "bf16")
     work = sum((n_iter + 0.5) * d["L"] * d["K"] * d["n_coil"] for d in sl)
+    # compressed phase bases (each slice: 16 solid harmonics on one slice ->
+    # 10 terms), the data rotations by exp(-i theta) inside the timed step;
+    # the compression's host time per batch is reported beside it
+    t_c = time.perf_counter()
+    comp = [nfs.compress_basis(pr) for pr in probs]
+    torch.cuda.synchronize()
+    t_c = (time.perf_counter() - t_c) * 1e3
+    cprobs = [c[0] for c in comp]
+    thetas = [c[1] for c in comp]
+    bufs = [torch.empty_like(m) for m in ms]
 
     def timed(mode, prs):
-        rot = prs is not full_probs
+        rot = prs is cprobs
 
         def data():
             if not rot:
@@ -210,39 +441,46 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
             return [nfs.phase_shift(m, th, -1, out=b) for m, th, b in zip(ms, thetas, bufs)]
 
         nfs.set_batch_mode(0, mode)
-        nfs.set_graphs(0, True)
-        outs, hists, infos = nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True)
-        torch.cuda.synchronize()
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        ev0.record()
-        for _ in range(steps):
-            nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True, outs=outs, hists=hists,
-                                 infos=infos)
-        ev1.record()
-        torch.cuda.synchronize()
-        nfs.set_graphs(0, False)
+        nfs.set_graphs(0, not args.no_graphs)
+        try:
+            outs, hists, infos = nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True)
+            torch.cuda.synchronize()
+            ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            ev0.record()
+            for _ in range(steps):
+                nfs.cg_solve_batched(prs, data(), n_iter, precision="bf16", reorth=True, outs=outs, hists=hists,
+                                     infos=infos)
+            ev1.record()
+            torch.cuda.synchronize()
+        finally:
+            nfs.set_graphs(0, False)
+            nfs.set_batch_mode(0, "streams")
         return ev0.elapsed_time(ev1) / steps, outs
 
-    t_p, out_p = timed("persistent", probs)
-    t, out_s = timed("streams", probs)
-    same = all(torch.equal(a, b) for a, b in zip(out_s, out_p))
-    full = None
-    if thetas is not None:
-        if not args.no_tune:
-            nfs.autotune_batched(full_probs, "bf16")
-        t_f, out_f = timed("streams", full_probs)
-        full = dict(ms_per_batch=t_f, value=work / (t_f * 1e-3),
-                    max_rel_diff_to_compressed=max(float(torch.linalg.vector_norm(a - b) / torch.linalg.vector_norm(b))
-                                                   for a, b in zip(out_s, out_f)))
+    if not args.no_tune:
+        nfs.autotune_batched(probs, "bf16")
+    t_f, out_f = timed("streams", probs)
+    t_fp, out_fp = timed("persistent", probs)
+    if not args.no_tune:
+        nfs.autotune_batched(cprobs, "bf16")
+    t_c_s, out_c = timed("streams", cprobs)
+    t_c_p, out_cp = timed("persistent", cprobs)
+    same = all(torch.equal(a, b) for a, b in zip(out_f, out_fp)) and all(
+        torch.equal(a, b) for a, b in zip(out_c, out_cp))
     return dict(workload="24 slices, 2D 96..160 square, 8..32 coils, 8000..30000 samples, 16 terms, per-slice B0, "
-                         "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch (slices' solves "
-                         "forked over 8 streams)",
-                ms_per_batch=t, value=work / (t * 1e-3), unit="voxel*sample*coil/s",
-                persistent_form=dict(ms_per_batch=t_p, value=work / (t_p * 1e-3),
+                         "30 CG iterations each, BF16 operands, re-orthogonalised, one graph launch per batch",
+                ms_per_batch=t_f, value=work / (t_f * 1e-3), unit="voxel*sample*coil/s",
+                form="per-slice solves forked over 8 streams, full phase bases",
+                persistent_form=dict(ms_per_batch=t_fp, value=work / (t_fp * 1e-3),
                                      form="lock-step; per iteration one persistent E and one persistent E^H launch "
                                           "per coil class over all slices"),
+                compressed_bases=dict(ms_per_batch_streams=t_c_s, ms_per_batch_persistent=t_c_p,
+                                      ms_setup_host=t_c, ms_end_to_end_streams=t_c_s + t_c,
+                                      terms=[pr.P + 1 for pr in cprobs],
+                                      max_rel_diff_to_full=max(float(torch.linalg.vector_norm(a - b)
+                                                                     / torch.linalg.vector_norm(b))
+                                                               for a, b in zip(out_c, out_f))),
                 persistent_equals_streams=same,
-                phase_basis_terms=[pr.P + 1 for pr in probs], full_basis_form=full,
                 pairs_per_EHE=sum(d["L"] * d["K"] for d in sl), steps=steps, tuned=not args.no_tune)
 
 
@@ -354,250 +592,69 @@ def main():
     from paper_2604_09233_amd import nfs
 
     dev = torch.device("cuda:0")
+    reorth = not args.plain
+    progress(f"headline workload {args.config}: inputs")
     d = synth.make_config(args.config)
-    L, K, G, n_iter = d["L"], d["K"], d["n_coil"], d["n_iter"]
-    prob = nfs.Problem(d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"], device=dev)
-    # synthetic data: m = E rho_phantom + complex noise at SNR 30
-    clean = nfs.apply_E(prob, torch.from_numpy(d["rho_true"]), "fp32")
-    rms = float(torch.sqrt(torch.mean(torch.abs(clean) ** 2)))
-    sigma = rms / (30 * np.sqrt(2))
-    m = clean + sigma * torch.from_numpy(d["noise"]).to(dev)
-    torch.cuda.synchronize()
-
-    # Phase-basis compression, once per geometry (like the shape tuning):
-    # the 16 solid harmonics on one slice span 10 functions, and the
-    # per-sample offset theta cancels in E^H E.  The solve then runs on the
-    # compressed problem with data exp(-i theta) m, the rotation inside the
-    # timed step.
-    prob_full = prob
-    theta, basis = None, None
-    if not args.no_compress:
-        t_c = time.perf_counter()
-        prob, theta, cinfo = nfs.compress_basis(prob_full)
-        t_c = time.perf_counter() - t_c
-        basis = dict(terms=d["n_basis"] + 1, compressed_terms=prob.P + 1, err_bound_rad=cinfo["err_bound"],
-                     untimed_setup_s=t_c, setup="once per geometry (host copies of the basis, host compression, "
-                                                "device copies back), like the shape tuning; not in ms_per_step")
-    m_solve = m if theta is None else nfs.phase_shift(m, theta, -1)
-    m_buf = torch.empty_like(m)
-    torch.cuda.synchronize()
-
-    progress("autotune and the c2 solve")
-    tuned = {}
-    if not args.no_tune:
-        for prec in {args.precision, "fp32", "bf16"}:
-            tuned[prec] = nfs.autotune(prob, prec)
-
-    def solve(prec, out, hist, info, reorth, p=None):
-        p = prob if p is None else p
-        data = m
-        if p is not prob_full:
-            data = nfs.phase_shift(m, theta, -1, out=m_buf)
-        return nfs.cg_solve(p, data, n_iter, precision=prec, reorth=reorth, out=out, hist=hist, info=info)
-
-    def time_solves(prec, steps, warmup, profile=False, reorth=not args.plain, p=None):
-        out = torch.empty(L, dtype=torch.complex64, device=dev)
-        hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=dev)
-        info = torch.zeros(2, dtype=torch.int32, device=dev)
-        for _ in range(warmup):
-            solve(prec, out, hist, info, reorth, p)
-        torch.cuda.synchronize()
-        if profile:
-            nfs.profile_enable(0, True)
-            nfs.profile_read(0, "E")
-            nfs.profile_read(0, "EH")
-        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        t0 = time.perf_counter()
-        ev0.record()
-        for _ in range(steps):
-            solve(prec, out, hist, info, reorth, p)
-        ev1.record()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        ms = ev0.elapsed_time(ev1) / steps
-        kt = None
-        if profile:
-            kt = {k: nfs.profile_read(0, k) for k in ("E", "EH")}
-            nfs.profile_enable(0, False)
-        return out, hist, info, ms, wall, kt
-
+    sv = Solver(nfs, torch, dev, d, reorth)
+    L, K, G, n_iter = sv.L, sv.K, sv.G, sv.n_iter
     if args.profile_run:
-        time_solves(args.precision, 1, 0, profile=False)
+        out, hist, info = sv.buffers()
+        nfs.cg_solve(sv.prob, sv.m, n_iter, precision=args.precision, reorth=reorth, out=out, hist=hist, info=info)
         torch.cuda.synchronize()
-        print(json.dumps({"profile_run": "done"}))
+        print(json.dumps({"profile_run": "done", "config": args.config, "cg_info": info.cpu().tolist()}))
         return
-    if not args.no_graphs:
-        nfs.set_graphs(0, True)
-        rho, hist, info, ms, wall, _ = time_solves(args.precision, args.steps, args.warmup)
-        nfs.set_graphs(0, False)
-        # kernel timing (HIP events around every encode launch) on eager solves
-        _, _, _, _, _, kt = time_solves(args.precision, max(1, args.steps // 2), 0, profile=True)
-    else:
-        rho, hist, info, ms, wall, kt = time_solves(args.precision, args.steps, args.warmup, profile=True)
+
+    progress("autotune and the timed solves")
+    if not args.no_tune:
+        nfs.autotune(sv.prob, args.precision)
+    rho, hist, info, ms, wall = sv.time_solves(args.precision, args.steps, args.warmup, graphs=not args.no_graphs)
+    rho = rho.clone()
     vsc = L * K * G
     value = (n_iter + 0.5) * vsc / (ms * 1e-3)
+    st = info.cpu().tolist()
 
-    # accuracy against the stored FP64 oracle solve of this workload
-    err = None
-    kind = "plain" if args.plain else "reorth"
-    gpath = os.path.join(ROOT, "tests", "golden", f"{args.config}_cg.npz")
-    if os.path.exists(gpath):
-        g = np.load(gpath)
+    progress("encode-kernel timing, E^H E alone, oracle checks")
+    kt = sv.kernel_times(args.precision)
+    roof = roofline(kt, L, K, G, d["n_basis"], args.precision, f"encode_kernel_{args.config}_{args.precision}_counters.md")
+    ehe_ms, _ = sv.ehe_alone(args.precision, 10)
+    err, checks = None, {}
+    kind = "reorth" if reorth else "plain"
+    g = golden(f"{args.config}_cg.npz")
+    if g is not None:
         err = rel(rho.cpu().numpy(), g[f"{kind}_rho"])
+    if args.config == "c3":
+        checks = c3_oracle_checks(nfs, synth, torch, dev, args.precision, sv, reorth)
 
-    # one E^H E application alone (median of 20 after 3 warm-ups)
-    p = torch.from_numpy(d["rho_true"]).to(dev)
-    q = torch.empty_like(p)
-    for _ in range(3):
-        nfs.apply_EHE(prob, p, args.precision, out=q)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(20):
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        nfs.apply_EHE(prob, p, args.precision, out=q)
-        e1.record()
-        torch.cuda.synchronize()
-        times.append(e0.elapsed_time(e1))
-    ehe_ms = float(np.median(times))
+    forms = {}
+    if not args.no_forms:
+        progress("other operand forms")
+        for prec in ("bf16", "fp32"):
+            if prec == args.precision:
+                continue
+            if not args.no_tune:
+                nfs.autotune(sv.prob, prec)
+            rf, _, inf, msf, _ = sv.time_solves(prec, 1, 1, graphs=not args.no_graphs)
+            forms[prec] = dict(ms_per_step=msf, value=(n_iter + 0.5) * vsc / (msf * 1e-3), cg_info=inf.cpu().tolist(),
+                               rel_diff_to_headline=rel(rf.cpu().numpy(), rho.cpu().numpy()))
+            if args.config == "c3":
+                forms[prec].update(c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth))
+            del rf
+    kf3 = threed_kspace_filter(nfs, torch, dev, d, rho) if len(d["dims"]) == 3 else None
+    shapes = nfs.tuned_shape(sv.prob, args.precision)
+    cpu_d = d
+    del sv, rho
+    torch.cuda.empty_cache()
 
-    # FP32 and BF16 operand forms for comparison (same workload, same solve)
-    def form(prec):
-        rho_f, _, _, ms_f, _, _ = time_solves(prec, max(1, args.steps // 2), 1)
-        return dict(ms_per_step=ms_f, value=(n_iter + 0.5) * vsc / (ms_f * 1e-3),
-                    rel_err_vs_oracle=rel(rho_f.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
-
-    full_basis = None
-    if basis is not None:
-        # the same solve on the uncompressed basis (17 terms: two phase
-        # instructions per tile)
-        if not args.no_tune:
-            nfs.autotune(prob_full, args.precision)
-        rho_u, _, _, ms_u, _, _ = time_solves(args.precision, max(1, args.steps // 2), 1, p=prob_full)
-        full_basis = dict(ms_per_step=ms_u, value=(n_iter + 0.5) * vsc / (ms_u * 1e-3),
-                          rel_err_vs_oracle=rel(rho_u.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
-        basis["full_basis_form"] = full_basis
-        del rho_u
-    fp32 = form("fp32") if not args.no_fp32_form and args.precision != "fp32" else None
-    bf16 = form("bf16") if not args.no_fp32_form and args.precision != "bf16" else None
-    # plain recurrences, same precision, for reference
-    plain = None
-    if not args.plain:
-        rhop, _, _, msp, _, _ = time_solves(args.precision, max(1, args.steps // 2), 1, reorth=False)
-        plain = dict(ms_per_step=msp,
-                     rel_err_vs_oracle_plain=rel(rhop.cpu().numpy(), g["plain_rho"]) if err is not None else None,
-                     oracle_plain_vs_reorth=float(g["plain_vs_reorth"][-1]) if err is not None else None)
-
-    # roofline of the dominant kernel (the fused encode kernel, E or E^H)
-    n_e, ms_e = kt["E"]
-    n_h, ms_h = kt["EH"]
-    kname, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
-    avg_ms = ms_k / max(n_k, 1)
-    pairs = L * K  # voxel-sample pairs per launch
-    # ALU bound: one sin and one cos per voxel-sample pair on the transcendental unit
-    trans_peak = TRANS_PEAK  # ops/s
-    achieved = 2 * pairs / (avg_ms * 1e-3)
-    # matrix-pipe time of the MFMA instructions the kernel issues, at the
-    # published dense peaks, as a fraction of the measured launch time: per
-    # 16 x 16 tile (256 pairs) ceil(3 (P+1) / 32) f16 16x16x32 phase
-    # instructions, and per 16-column block of the 2G real columns one f16
-    # 16x16x32 (fp16), two bf16 16x16x32 (bf16: hi and lo data parts) or
-    # three f16 16x16x32 (fp32: split operands) contraction instructions
-    P = prob.P  # terms of the basis the solve runs on
-    nq = -(-3 * (P + 1) // 32)
-    nb = {1: 1, 2: 2, 3: 4, 4: 4}.get(-(-2 * G // 16), 8)
-    tiles = pairs / 256.0
-    flops_phase = tiles * nq * 16384
-    flops_con = tiles * nb * {"fp16": 16384, "bf16": 2 * 16384, "fp32": 3 * 16384}[args.precision]
-    t_mfma = (flops_phase + flops_con) / (MFMA_PEAK_TFLOPS["fp16"] * 1e12)
-    # HBM bytes per launch from the committed counter summary (FETCH_SIZE +
-    # WRITE_SIZE, copy-calibrated), only while the kernel sources match the
-    # ones the counters were taken on
-    from paper_2604_09233_amd.profile_summary import read_traffic
-    tr = read_traffic(os.path.join(ROOT, "profiles", f"encode_kernel_{args.config}_{args.precision}_counters.md"))
-    traffic = tr.get(kname) if tr else None
-    roofline = dict(bound="alu", achieved=achieved / 1e12, peak=trans_peak / 1e12, unit="Tsincos-ops/s",
-                    frac=achieved / trans_peak, traffic=traffic, traffic_unit="bytes per launch",
-                    kernel=f"encode_kernel ({kname})",
-                    avg_launch_ms=avg_ms, launches=n_k,
-                    mfma_pipe_frac=t_mfma / (avg_ms * 1e-3))
-
-    resident = None
-    if not args.no_resident and args.precision == "fp16":
-        # non-split form: P built once per solve (2 K L x 4 bytes), streamed by every E and E^H
-        def t_res(n):
-            o = torch.empty(L, dtype=torch.complex64, device=dev)
-            h = torch.full((n + 1, 3), float("nan"), dtype=torch.float64, device=dev)
-            f = torch.zeros(2, dtype=torch.int32, device=dev)
-            nfs.cg_solve_resident(prob, m_solve, n, reorth=not args.plain, out=o, hist=h, info=f)
-            torch.cuda.synchronize()
-            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-            e0.record()
-            nfs.cg_solve_resident(prob, m_solve, n, reorth=not args.plain, out=o, hist=h, info=f)
-            e1.record()
-            torch.cuda.synchronize()
-            return o, e0.elapsed_time(e1)
-        rr, ms_r = t_res(n_iter)
-        _, ms_r1 = t_res(1)
-        resident = dict(ms_per_step=ms_r, ms_per_iteration=(ms_r - ms_r1) / (n_iter - 1),
-                        ms_build_and_first_iteration=ms_r1, P_bytes=2 * L * K * 4,
-                        identical_to_split=bool(torch.equal(rr.cpu(), rho.cpu())),
-                        rel_err_vs_oracle=rel(rr.cpu().numpy(), g[f"{kind}_rho"]) if err is not None else None)
-        del rr
-        prob._ws.pop(("CG_RESIDENT", args.precision, n_iter, not args.plain), None)
-        prob._ws.pop(("CG_RESIDENT", args.precision, 1, not args.plain), None)
+    twod = None
+    if not args.no_2d and args.config != "c2":
+        progress("2D 128x128 leg")
+        twod = twod_run(nfs, synth, torch, dev, args)
         torch.cuda.empty_cache()
-
-    stopping = None
-    if not args.no_stopping:
-        # the paper's stopping-criteria study: 250 iterations, L-curve corner
-        # and SSIM of every iterate against the phantom
-        n_long = 250
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
-        ev[0].record()
-        _, h_long, i_long, its = nfs.cg_solve_traced(prob, m_solve, n_long, precision=args.precision,
-                                                     reorth=not args.plain)
-        ev[1].record()
-        ss = nfs.ssim(its[1:], torch.from_numpy(d["rho_true"]), d["dims"])
-        ev[2].record()
-        torch.cuda.synchronize()
-        ss = ss.cpu().numpy()
-        corner, _ = nfs.lcurve_corner(h_long)
-        stopping = dict(iterations=n_long, ms_solve=ev[0].elapsed_time(ev[1]), ms_ssim_all=ev[1].elapsed_time(ev[2]),
-                        peak_ssim=float(ss.max()), peak_ssim_iteration=int(np.argmax(ss)) + 1,
-                        ssim_at=dict((str(k), float(ss[k - 1])) for k in (5, 10, 30, 100, 250)),
-                        lcurve_corner_iteration=corner, cg_info=i_long.cpu().tolist())
-        del its
-
-    progress("operand forms, stopping study, k-space filter")
-    # the paper's k-space filter on the reconstruction: bins inside the hull
-    # of the first-order k positions (linear x, y terms; kcoef / pi in
-    # cycles per FOV for the normalised coordinates), IFFT(FFT(rho) o f)
-    kf = None
-    if len(d["dims"]) == 2:
-        f = nfs.kspace_filter_mask(d["kcoef"][:, 1:3].astype(np.float64) / np.pi, d["dims"])
-        f_dev = torch.from_numpy(f).to(dev)
-        nfs.apply_kspace_filter(rho, f_dev, d["dims"])
-        torch.cuda.synchronize()
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        rho_f = nfs.apply_kspace_filter(rho, f_dev, d["dims"])
-        e1.record()
-        torch.cuda.synchronize()
-        ref_img = torch.from_numpy(d["rho_true"])
-        s_before = float(nfs.ssim(rho, ref_img, d["dims"]).cpu()[0])
-        s_after = float(nfs.ssim(rho_f, ref_img, d["dims"]).cpu()[0])
-        kf = dict(bins_inside=int(f.sum()), bins=int(f.size), ms_apply=e0.elapsed_time(e1),
-                  ssim_vs_phantom_before=s_before, ssim_vs_phantom_after=s_after)
-
     progress("batched leg")
     batched = None if args.no_batched else batched_run(nfs, synth, torch, dev, args)
-    progress("3D leg")
-    threed = None if args.no_3d else threed_run(nfs, synth, torch, dev, args)
     progress("maps leg")
     maps = None if args.no_maps else maps_run(nfs, synth, torch, dev)
 
-    st = info.cpu().tolist()
     out = {
         "metric": "E^H·E voxel·sample·coil/s (over the CG solve); CG solve time at rel.err <=2e-3 vs FP64 oracle",
         "value": value,
@@ -611,32 +668,28 @@ def main():
         "vs_baseline": None,
         "dtype": args.precision,
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: 2D 128x128, 16 coils, 4x15000-sample R=4 spiral, 16 field terms, "
-                               f"B0 +-100 Hz, {n_iter} CG iterations (one step = one CG solve)",
-                   "L": L, "K": K, "G": G, "n_iter": n_iter, "precision": args.precision,
-                   "cg": "plain" if args.plain else "re-orthogonalised", "hip_graphs": not args.no_graphs,
-                   "phase_basis": basis, "phase_instructions_per_tile": nq},
+        "config": {"workload": WORKLOADS[args.config], "L": L, "K": K, "G": G, "n_iter": n_iter,
+                   "precision": args.precision, "cg": "re-orthogonalised" if reorth else "plain",
+                   "hip_graphs": not args.no_graphs, "phase_basis_terms": d["n_basis"] + 1,
+                   "phase_instructions_per_tile": phase_instrs(d["n_basis"])},
         "rel_err_vs_oracle": err,
-        "encode_shapes": {"tuned": not args.no_tune,
-                          "held_tiles_nsplit": nfs.tuned_shape(prob, args.precision)},
+        "rel_err_vs_oracle_note": None if err is not None else
+            "no stored full-size FP64 oracle solve of this workload (many hours on the host); see oracle_checks",
+        "oracle_checks": checks,
+        "encode_shapes": {"tuned": not args.no_tune, "held_tiles_nsplit": shapes},
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
-        "fp32_form": fp32,
-        "bf16_form": bf16,
-        "plain_recurrences": plain,
-        "encode_kernel_ms": {"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)},
-        "roofline": roofline,
-        "resident_P": resident,
-        "stopping_criteria": stopping,
-        "kspace_filter": kf,
+        "forms": forms,
+        "roofline": roof,
+        "kspace_filter_3d": kf3,
+        "2d": twod,
         "batched": batched,
-        "3d": threed,
         "maps": maps,
         "wall_s_timed": wall,
     }
     if not args.no_cpu_baseline:
         progress("CPU oracle baseline")
-        out["cpu_baseline"] = cpu_baseline(d)
+        out["cpu_baseline"] = cpu_baseline(cpu_d, 512 if args.config == "c3" else 8)
     print(json.dumps(out))
 
 

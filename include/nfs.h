@@ -213,11 +213,13 @@ int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, double* kappa
  * both reconstruction listings): rho_f = IFFT(FFT(rho) o f) on an image grid
  * nx x ny x nz (voxel index x + nx (y + ny z)), f real [L] in the same index
  * order, bin (u, v, w) standing for the signed frequency u (if u < ceil(nx/2),
- * else u - nx) and so on, in cycles per field of view.  Applied on the GPU as
- * (1/L) E^H diag(f) E rho with E the DFT of the grid, built from the
- * library's own encoding operator (FP32-grade operands); rho, out: device
- * [L] complex; f: device float [L].  Workspace:
- * nfs_kspace_filter_workspace_bytes.                                      */
+ * else u - nx) and so on, in cycles per field of view.  The DFT is applied
+ * one axis at a time (float32 sums, twiddles from double precision): forward
+ * passes, then f and 1/L, then inverse passes, L (nx + ny + nz) complex
+ * multiply-adds per direction.  rho, out: device [L] complex (must not
+ * alias); f: device float [L].  Each axis at most 2048 long (NFS_ESHAPE
+ * otherwise).  Workspace: nfs_kspace_filter_workspace_bytes (L complex,
+ * rounded up to 256 bytes; ctx is not read).                              */
 int nfs_kspace_filter_workspace_bytes(const nfs_ctx* ctx, int nx, int ny, int nz, size_t* bytes);
 int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* out, int nx, int ny, int nz, const float* f,
                             void* ws, size_t ws_bytes, void* stream);
@@ -266,6 +268,25 @@ int nfs_kspace_filter_mask(const double* kpos, int64_t K, int dim, int nx, int n
 int nfs_compress_basis(const float* fields, const float* b0, const float* kcoef, const float* t, int64_t L,
                        int64_t K, int P, double rel_tol, float* fields_out, float* b0_out, float* kcoef_out,
                        float* t_out, double* theta, int* n_basis_out, double* err_bound);
+
+/* The same compression on the GPU, from the problem's DEVICE arrays
+ * (prob->fields, b0, kcoef, t; sens and icorr are not read) into DEVICE
+ * outputs, so that a new geometry (the field coefficients are measured per
+ * scan) costs a few launches instead of host copies: identical steps in
+ * double precision, sums over voxels formed per workgroup and added in
+ * workgroup order, so results match nfs_compress_basis up to the order of
+ * those sums.  Outputs sized for the largest P' = P: fields_out [P][L]
+ * (rows 0..P'-1 written), kcoef_out [K][P] (the first K P' entries written,
+ * as [K][P']), b0_out [L], t_out [K], theta [K] double; n_basis_out: device
+ * int receiving P'; err_bound: device double or NULL.  P' is known on the
+ * host only after synchronising (one int to read back before building the
+ * compressed nfs_problem).  Non-finite inputs give undefined outputs (the
+ * host call rejects them).  Workspace: nfs_compress_workspace_bytes
+ * (256-byte aligned).  Asynchronous on `stream`.                          */
+int nfs_compress_workspace_bytes(const nfs_problem* prob, size_t* bytes);
+int nfs_compress_basis_device(nfs_ctx* ctx, const nfs_problem* prob, double rel_tol, float* fields_out,
+                              float* b0_out, float* kcoef_out, float* t_out, double* theta, int* n_basis_out,
+                              double* err_bound, void* ws, size_t ws_bytes, void* stream);
 
 /* out[c][k] = m[c][k] exp(i sign theta[k]) for sign = +1 or -1 (the
  * per-sample offset of nfs_compress_basis), rotation in double precision.

@@ -19,7 +19,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD_DIR = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnfs.so")
 SOURCES = ["encode_kernels.hip", "cg_kernels.hip", "quality_kernels.hip", "postproc_kernels.hip", "maps_kernels.hip",
-           "capi.hip"]
+           "compress_kernels.hip", "capi.hip"]
 # The encode kernels keep MFMA accumulators in ordinary VGPRs (no AGPR
 # round trips between the phase tile and the sine/cosine that consume it).
 SOURCE_FLAGS = {"encode_kernels.hip": ["-mllvm", "-amdgpu-mfma-vgpr-form"]}

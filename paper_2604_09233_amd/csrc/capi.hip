@@ -878,50 +878,25 @@ extern "C" int nfs_lcurve_corner(const double* hist, int n_rows, int* corner, do
 }
 
 // ---------------------------------------------------------------------------
-// k-space filter: rho_f = (1 / L) E^H diag(f) E rho on the DFT problem of the
-// image grid (written into the workspace), FP32-grade operands.
-struct FilterLayout {
-  nfs_problem pr;
-  size_t o_sens, o_fields, o_b0, o_kcoef, o_t, o_enc, total;
-  Layout y;
-};
-
-static FilterLayout filter_layout(const nfs_ctx* ctx, int nx, int ny, int nz, void* ws) {
-  FilterLayout f{};
-  const int64_t L = (int64_t)nx * ny * nz;
-  const int P = nz > 1 ? 3 : 2;
-  size_t o = 0;
-  auto take = [&](size_t bytes) {
-    const size_t at = o;
-    o += al(bytes);
-    return at;
-  };
-  f.o_sens = take((size_t)L * 8);
-  f.o_fields = take((size_t)P * L * 4);
-  f.o_b0 = take((size_t)L * 4);
-  f.o_kcoef = take((size_t)L * P * 4);
-  f.o_t = take((size_t)L * 4);
-  f.o_enc = o;
-  char* b = static_cast<char*>(ws);
-  f.pr = nfs_problem{L, L, 1, P, (const float*)(b + f.o_sens), (const float*)(b + f.o_fields),
-                     (const float*)(b + f.o_b0), (const float*)(b + f.o_kcoef), (const float*)(b + f.o_t), nullptr};
-  f.y = make_layout(ctx, &f.pr, NFS_OP_EHE, NFS_FP32, 0, 0);
-  f.total = f.o_enc + f.y.total;
-  return f;
-}
-
+// k-space filter: rho_f = IFFT(FFT(rho) o f), one DFT pass per axis and
+// direction (axes of length 1 skipped), the filter and 1/L applied with the
+// last forward pass; the passes alternate between the workspace ([L]
+// complex) and `out`, so that the last one writes `out`.
 static int check_filter_dims(int nx, int ny, int nz, const char* fn) {
   if (nx < 1 || ny < 1 || nz < 1) return fail(NFS_ESHAPE, "%s: grid %d x %d x %d", fn, nx, ny, nz);
+  if (nx > kMaxDftAxis || ny > kMaxDftAxis || nz > kMaxDftAxis)
+    return fail(NFS_ESHAPE, "%s: grid %d x %d x %d has an axis longer than %d", fn, nx, ny, nz, kMaxDftAxis);
   if ((int64_t)nx * ny * nz > ((int64_t)1 << 26)) return fail(NFS_ESHAPE, "%s: grid too large", fn);
   return NFS_OK;
 }
 
 extern "C" int nfs_kspace_filter_workspace_bytes(const nfs_ctx* ctx, int nx, int ny, int nz, size_t* bytes) {
   const char* fn = "nfs_kspace_filter_workspace_bytes";
+  (void)ctx;
   if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
   int rc = check_filter_dims(nx, ny, nz, fn);
   if (rc) return rc;
-  *bytes = filter_layout(ctx, nx, ny, nz, nullptr).total;
+  *bytes = al((size_t)nx * ny * nz * 8);
   return NFS_OK;
 }
 
@@ -938,20 +913,37 @@ extern "C" int nfs_apply_kspace_filter(nfs_ctx* ctx, const float* rho, float* ou
   if (misaligned(f, 4)) return fail(NFS_EINVAL, "%s: f not 4-byte aligned", fn);
   if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
   if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
-  const FilterLayout fl = filter_layout(ctx, nx, ny, nz, ws);
-  if (ws_bytes < fl.total) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, fl.total);
+  if (ws_bytes < al((size_t)L * 8))
+    return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, al((size_t)L * 8));
   hipStream_t s = (hipStream_t)stream;
-  char* b = static_cast<char*>(ws);
-  NFS_TRY(launch_dft_problem(nx, ny, nz, (float2*)(b + fl.o_sens), (float*)(b + fl.o_fields), (float*)(b + fl.o_b0),
-                             (float*)(b + fl.o_kcoef), (float*)(b + fl.o_t), s),
-          "dft_problem");
-  void* enc = b + fl.o_enc;
-  Ctx c{ctx, fl.y, &fl.pr, reinterpret_cast<const float2*>(fl.pr.sens), enc, s, nullptr};
-  if ((rc = seq_pack_coefs(c, true, true))) return rc;
-  if ((rc = seq_EHE(c, reinterpret_cast<const float2*>(rho), false, f, (float)(1.0 / (double)L)))) return rc;
-  NFS_TRY(launch_finish_EH(at<float2>(enc, fl.y.o_hpart), fl.y.shH.nsplit, fl.y.LC * 16, L, unscale_slot(c, 1),
-                           reinterpret_cast<float2*>(out), s),
-          "finish_EH");
+  // axes as [outer][n][inner] views: x (contiguous), y, z
+  struct Axis {
+    int n;
+    int64_t outer, inner;
+  };
+  std::vector<Axis> axes;
+  if (nx > 1) axes.push_back({nx, (int64_t)ny * nz, 1});
+  if (ny > 1) axes.push_back({ny, (int64_t)nz, (int64_t)nx});
+  if (nz > 1) axes.push_back({nz, 1, (int64_t)nx * ny});
+  const float inv_l = (float)(1.0 / (double)L);
+  const float2* src = reinterpret_cast<const float2*>(rho);
+  float2* dst_out = reinterpret_cast<float2*>(out);
+  float2* dst_ws = static_cast<float2*>(ws);
+  if (axes.empty()) {
+    NFS_TRY(launch_filter_scale(src, dst_out, f, inv_l, L, s), "filter_scale");
+    return NFS_OK;
+  }
+  const int passes = 2 * (int)axes.size();
+  for (int i = 0; i < passes; ++i) {
+    const bool fwd = i < (int)axes.size();
+    const Axis& ax = fwd ? axes[i] : axes[passes - 1 - i];
+    const bool last_fwd = i + 1 == (int)axes.size();
+    float2* dst = (passes - 1 - i) % 2 == 0 ? dst_out : dst_ws;
+    NFS_TRY(launch_dft_axis(src, dst, ax.outer, ax.n, ax.inner, fwd ? -1 : +1, last_fwd ? inv_l : 1.f,
+                            last_fwd ? f : nullptr, s),
+            "dft_axis");
+    src = dst;
+  }
   return NFS_OK;
 }
 
@@ -2486,6 +2478,55 @@ extern "C" int nfs_compress_basis(const float* fields, const float* b0, const fl
   }
   *n_basis_out = Pn;
   if (err_bound) *err_bound = err;
+  return NFS_OK;
+}
+
+// The same compression on the device (compress_kernels.hip): term maxima,
+// then the launches of launch_compress_basis; the workspace holds the term
+// maxima and the double-precision scratch.
+static size_t compress_ws_bytes(int64_t L, int P) {
+  return al(2 * kMaxTerms * 4) + al(compress_workspace_doubles(L, P) * 8);
+}
+
+extern "C" int nfs_compress_workspace_bytes(const nfs_problem* prob, size_t* bytes) {
+  const char* fn = "nfs_compress_workspace_bytes";
+  if (!bytes) return fail(NFS_EINVAL, "%s: bytes is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  *bytes = compress_ws_bytes(prob->n_vox, prob->n_basis);
+  return NFS_OK;
+}
+
+extern "C" int nfs_compress_basis_device(nfs_ctx* ctx, const nfs_problem* prob, double rel_tol, float* fields_out,
+                                         float* b0_out, float* kcoef_out, float* t_out, double* theta,
+                                         int* n_basis_out, double* err_bound, void* ws, size_t ws_bytes,
+                                         void* stream) {
+  const char* fn = "nfs_compress_basis_device";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  if (!(rel_tol >= 0.0) || !std::isfinite(rel_tol)) return fail(NFS_EINVAL, "%s: rel_tol must be finite and >= 0", fn);
+  const int64_t L = prob->n_vox, K = prob->n_samp;
+  const int P = prob->n_basis;
+  if ((L > 0 && (!prob->b0 || !b0_out)) || (K > 0 && (!prob->t || !t_out || !theta)) || !n_basis_out ||
+      (P > 0 && L > 0 && (!prob->fields || !fields_out)) || (P > 0 && K > 0 && (!prob->kcoef || !kcoef_out)))
+    return fail(NFS_EINVAL, "%s: NULL array", fn);
+  if (misaligned(prob->fields, 4) || misaligned(prob->b0, 4) || misaligned(prob->kcoef, 4) || misaligned(prob->t, 4) ||
+      misaligned(fields_out, 4) || misaligned(b0_out, 4) || misaligned(kcoef_out, 4) || misaligned(t_out, 4) ||
+      misaligned(theta, 8) || misaligned(n_basis_out, 4) || misaligned(err_bound, 8))
+    return fail(NFS_EINVAL, "%s: array misaligned", fn);
+  if (!ws) return fail(NFS_EWORKSPACE, "%s: workspace is NULL", fn);
+  if ((uintptr_t)ws % 256) return fail(NFS_EWORKSPACE, "%s: workspace not 256-byte aligned", fn);
+  const size_t need = compress_ws_bytes(L, P);
+  if (ws_bytes < need) return fail(NFS_EWORKSPACE, "%s: workspace has %zu bytes, needs %zu", fn, ws_bytes, need);
+  hipStream_t s = (hipStream_t)stream;
+  unsigned* tmax = static_cast<unsigned*>(ws);
+  double* dws = reinterpret_cast<double*>(static_cast<char*>(ws) + al(2 * kMaxTerms * 4));
+  NFS_TRY(launch_term_absmax(prob->t, prob->kcoef, K, prob->b0, prob->fields, L, P, tmax, s), "term_absmax");
+  NFS_TRY(launch_compress_basis(prob->fields, prob->b0, prob->kcoef, prob->t, L, K, P,
+                                rel_tol > 0.0 ? rel_tol : std::ldexp(1.0, -24), tmax, dws, fields_out, b0_out,
+                                kcoef_out, t_out, theta, n_basis_out, err_bound, s),
+          "compress_basis");
   return NFS_OK;
 }
 

@@ -185,14 +185,24 @@ hipError_t launch_ssim(const float2* imgs, int n_img, const float2* ref, int nx,
                        hipStream_t s);
 
 // ---- k-space filter (postproc_kernels.hip) ------------------------------------
-// The DFT of an nx x ny x nz grid as an encoding problem: voxel l and sample
-// k index the same grid (x fastest); fields[d][l] = centred pixel index
-// (index - n_d / 2) along axis d, kcoef[k][d] = -2 pi (signed frequency of
-// bin k along d) / n_d, t = b0 = 0, sens = 1 (one coil); P = 2 (nz == 1) or
-// 3.  Then E rho = FFT(rho) up to a sign per bin, and E^H diag(w) E rho =
-// L IFFT(w o FFT(rho)).
-hipError_t launch_dft_problem(int nx, int ny, int nz, float2* sens, float* fields, float* b0, float* kcoef, float* t,
-                              hipStream_t s);
+// One DFT along one axis of an [outer][n][inner] complex array:
+// out = scale * g * DFT_sign(in) with g = f (per element, in the array's
+// index order; NULL for 1); n <= kMaxDftAxis.
+constexpr int kMaxDftAxis = 2048;
+hipError_t launch_dft_axis(const float2* in, float2* out, int64_t outer, int n, int64_t inner, int sign, float scale,
+                           const float* f, hipStream_t s);
+hipError_t launch_filter_scale(const float2* in, float2* out, const float* f, float scale, int64_t L, hipStream_t s);
+
+// ---- phase-basis compression on the device (compress_kernels.hip) ----------
+constexpr int kCmpBlocks = 256;  // workgroups of its voxel reductions
+// doubles of scratch for launch_compress_basis (partials, eigenvectors, r*)
+size_t compress_workspace_doubles(int64_t L, int P);
+// the host compression's arithmetic on device arrays; tmax: term maxima of
+// launch_term_absmax; ws: compress_workspace_doubles(L, P) doubles
+hipError_t launch_compress_basis(const float* fields, const float* b0, const float* kcoef, const float* t, int64_t L,
+                                 int64_t K, int P, double rel_tol, const unsigned* tmax, double* ws,
+                                 float* fields_out, float* b0_out, float* kcoef_out, float* t_out, double* theta,
+                                 int* n_basis_out, double* err_bound, hipStream_t s);
 
 // ---- CG (cg_kernels.hip) -----------------------------------------------------
 struct CgState {

@@ -76,6 +76,8 @@ def lib():
             L.nfs_compress_basis.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int64, i32, dbl, vp, vp, vp,
                                              vp, vp, ctypes.POINTER(i32), ctypes.POINTER(dbl)]
             L.nfs_phase_shift.argtypes = [vp, vp, vp, i32, ctypes.c_int64, vp, i32, vp]
+            L.nfs_compress_workspace_bytes.argtypes = [pp, ctypes.POINTER(sz)]
+            L.nfs_compress_basis_device.argtypes = [vp, pp, dbl, vp, vp, vp, vp, vp, vp, vp, vp, sz, vp]
             L.nfs_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_cg_solve_batched.argtypes = [vp, i32, pp, ctypes.POINTER(vp), ctypes.POINTER(vp), i32, dbl, i32,
                                                i32, i32, ctypes.POINTER(vp), ctypes.POINTER(vp), vp, sz, vp]
@@ -358,11 +360,32 @@ def compress_basis_host(fields, b0, kcoef, t, rel_tol: float = 0.0):
                 err_bound=err.value)
 
 
-def compress_basis(prob: Problem, rel_tol: float = 0.0):
+def compress_basis(prob: Problem, rel_tol: float = 0.0, on_device: bool = True):
     """(Problem with the compressed phase basis and prob's sens and icorr,
     theta [K] float64 device tensor, info dict with n_basis and err_bound).
-    The basis is copied to the host, compressed there (nfs_compress_basis)
-    and the result copied back to prob's device."""
+    on_device: computed on the GPU (nfs_compress_basis_device; one
+    synchronisation to read the new term count); else the basis is copied to
+    the host, compressed there (nfs_compress_basis) and copied back."""
+    if on_device:
+        dev, L, K, P = prob.device, prob.L, prob.K, prob.P
+        nbytes = ctypes.c_size_t()
+        _check(lib().nfs_compress_workspace_bytes(ctypes.byref(prob.st), ctypes.byref(nbytes)))
+        ws = torch.empty(nbytes.value + 256, dtype=torch.uint8, device=dev)
+        off = (-ws.data_ptr()) % 256
+        fo = torch.empty((max(P, 1), L), dtype=torch.float32, device=dev)
+        bo = torch.empty(L, dtype=torch.float32, device=dev)
+        ko = torch.empty(max(K * P, 1), dtype=torch.float32, device=dev)
+        to = torch.empty(K, dtype=torch.float32, device=dev)
+        theta = torch.empty(K, dtype=torch.float64, device=dev)
+        sc = torch.zeros(2, dtype=torch.float64, device=dev)  # [P' (int bits), err_bound]
+        _check(lib().nfs_compress_basis_device(context(prob.index), ctypes.byref(prob.st), float(rel_tol), _ptr(fo),
+                                               _ptr(bo), _ptr(ko), _ptr(to), _ptr(theta), _ptr(sc),
+                                               ctypes.c_void_p(sc.data_ptr() + 8), ctypes.c_void_p(ws.data_ptr() + off),
+                                               nbytes.value, prob._stream()))
+        host = sc.cpu()
+        n = int(host[:1].view(torch.int32)[0])
+        out = Problem(prob.sens, fo[:n], bo, ko[:K * n].view(K, n), to, prob.icorr, device=dev)
+        return out, theta, dict(n_basis=n, err_bound=float(host[1]))
     c = compress_basis_host(prob.fields.cpu().numpy(), prob.b0.cpu().numpy(), prob.kcoef.cpu().numpy(),
                             prob.t.cpu().numpy(), rel_tol)
     out = Problem(prob.sens, c["fields"], c["b0"], c["kcoef"], c["t"], prob.icorr, device=prob.device)
@@ -385,8 +408,8 @@ def phase_shift(m, theta, sign: int, out=None):
 
 
 def apply_kspace_filter(rho, f, dims, device: int = 0):
-    """IFFT(FFT(rho) o f) on the image grid dims (x fastest), on the GPU
-    through the library's encoding operator (see include/nfs.h)."""
+    """IFFT(FFT(rho) o f) on the image grid dims (x fastest), on the GPU,
+    one DFT pass per axis and direction (see include/nfs.h)."""
     dev = torch.device("cuda", device)
     rho = _c64(rho, dev)
     f = f.to(device=dev, dtype=torch.float32).contiguous() if torch.is_tensor(f) else \

@@ -3,8 +3,8 @@ profiles/.
 
   python -m paper_2604_09233_amd.profile_summary stats <kernel_stats.csv> <title> <command> [note]
       per-kernel durations from `--kernel-trace --stats`
-  python -m paper_2604_09233_amd.profile_summary counters <out.md> <precision> <command-prefix> <copy-bytes> \
-      <sq_dir> [<sq_dir> ...] <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
+  python -m paper_2604_09233_amd.profile_summary counters <out.md> <precision> <workload> <bench-args> \
+      <command-prefix> <copy-bytes> <sq_dir> [<sq_dir> ...] <fetch_dir> <write_dir> <copy_fetch_dir> <copy_write_dir>
       per-dispatch counter averages of the encode kernels from `--pmc` runs
       (each *_dir holds run_counter_collection.csv and run_kernel_trace.csv),
       the HBM traffic per launch from FETCH_SIZE / WRITE_SIZE scaled by what
@@ -96,7 +96,7 @@ def _per_dispatch(d, match=None):
 PREC_ARG = {"fp32": "0", "bf16": "1", "fp16": "2"}
 
 
-def counters(out_md, precision, command, copy_bytes, *dirs):
+def counters(out_md, precision, workload, bench_args, command, copy_bytes, *dirs):
     sq_dirs, (fetch_dir, write_dir, cfetch_dir, cwrite_dir) = dirs[:-4], dirs[-4:]
     copy_bytes = float(copy_bytes)
     merged, durs = defaultdict(dict), defaultdict(list)
@@ -114,13 +114,12 @@ def counters(out_md, precision, command, copy_bytes, *dirs):
     cwk = max(cw, key=lambda k: cw[k].get("WRITE_SIZE", 0.0))
     f_fac = copy_bytes / (cf[cfk]["FETCH_SIZE"] * 1024.0)
     w_fac = copy_bytes / (cw[cwk]["WRITE_SIZE"] * 1024.0)
-    lines = ["# Encode-kernel counters: CG solve, 2D 128x128 / 16 coils / 60000 samples / 16 field terms "
-             f"(solved on the compressed 10-term phase basis), {precision.upper()} operands", "",
+    lines = [f"# Encode-kernel counters: CG solve, {workload}, {precision.upper()} operands", "",
              "encode_kernel<OP, PREC, NQ, NB, MT>: OP 0 = E, 1 = E^H; PREC 0 = fp32, 1 = bf16, 2 = fp16; NQ phase "
-             "instructions per tile (1 on the compressed basis). The run also holds the single FP32 E that "
-             "generates the data (full basis).", "",
+             "instructions per tile, NB column blocks, MT held tiles per wave. The run also holds the single "
+             "FP32 E that generates the data.", "",
              "Commands (from the repository root, one MI355X), one rocprofv3 run per counter set:", "",
-             f"    {command} --pmc <counters> -- python3 bench.py --profile-run", "",
+             f"    {command} --pmc <counters> -- python3 bench.py {bench_args}", "",
              "with these counter sets (one run each):", ""]
     for i, d in enumerate(list(sq_dirs) + [fetch_dir, write_dir]):
         names = sorted({r["Counter_Name"] for r in csv.DictReader(open(os.path.join(d, "run_counter_collection.csv")))})

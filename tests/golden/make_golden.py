@@ -17,7 +17,11 @@ E the oracle's.
           reconstruction mask (phantom support dilated by 2 voxels), same
           data; every plain iterate 1..30 (plain_its [30][Lm] complex64), the
           re-orthogonalised iterates listed in reorth_iters, both histories,
-          plain_vs_reorth, mask (bool [L])                          (~4 min)
+          plain_vs_reorth, mask (bool [L]), and the plain trajectory's
+          rounding sensitivity (probe_deltas, probe_dev [delta][iterate]:
+          distance from the plain iterates when every E^H E p is perturbed
+          by relative noise delta; probe_hist [delta]: those runs' histories)
+                                                                   (~12 min)
   c3s     tests/golden/c3s_cg.npz: the scaled 3D workload (48x48x24, 8 coils,
           4 x 8000 samples, 16 terms), 15 iterations, same keys as c2
                                                                    (~10 min)
@@ -48,6 +52,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 N_VOX_SAMPLED = 1536
+PROBE_DELTAS = [1e-6, 1e-5, 1e-4, 3e-4, 1e-3]
 N_VOX_SLICE = 512
 
 
@@ -100,6 +105,18 @@ def make_c2mask():
     dm = synth.restrict_voxels(d, mask)
     out, runs = cg_pair(dm, m, 30, {"plain": [], "reorth": [1, 5, 10, 20, 30]}, t0)
     out["plain_its"] = np.stack(runs["plain"]).astype(np.complex64)
+    # sensitivity of the plain trajectory to rounding: every E^H E p
+    # perturbed by relative noise delta (the oracle's probe); probe_dev[i][n]
+    # = distance of perturbed iterate n+1 from the plain one for PROBE_DELTAS[i]
+    dev, hists = [], []
+    for delta in PROBE_DELTAS:
+        pr = oracle.cg_solve(m, *args_of(dm), n_iter=30, return_iterates=True, perturb=(delta, 7))
+        dev.append([np.linalg.norm(x - y) / np.linalg.norm(y) for x, y in zip(pr["iterates"], runs["plain"])])
+        hists.append(pr["hist"])
+        print(f"probe {delta:.0e}: " + " ".join(f"{v:.1e}" for v in dev[-1]), flush=True)
+    out["probe_deltas"] = np.array(PROBE_DELTAS)
+    out["probe_dev"] = np.array(dev)
+    out["probe_hist"] = np.array(hists)
     out.update(m_rms=rms, sigma=sigma, n_iter=30, mask=mask)
     np.savez_compressed(os.path.join(HERE, "c2mask_cg.npz"), **out)
     print(f"c2mask CG golden written in {time.time() - t0:.0f} s")

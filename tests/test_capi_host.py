@@ -469,3 +469,19 @@ def test_kspace_filter_mask_3d_full_trajectory_sampled():
     clear = np.abs(dist) > 1e-6
     assert np.array_equal(f[idx][clear].astype(bool), dist[clear] < 0)
     assert 0.3 < f.mean() < 0.9
+
+
+def test_kspace_filter_workspace_and_limits(L):
+    n = ctypes.c_size_t()
+    assert L.nfs_kspace_filter_workspace_bytes(None, 96, 96, 48, ctypes.byref(n)) == 0
+    assert n.value == 96 * 96 * 48 * 8  # one complex grid, already a multiple of 256
+    assert L.nfs_kspace_filter_workspace_bytes(None, 5, 3, 1, ctypes.byref(n)) == 0
+    assert n.value == 256  # 120 bytes rounded up to the 256-byte segment
+    assert L.nfs_kspace_filter_workspace_bytes(None, 2049, 2, 1, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    assert L.nfs_kspace_filter_workspace_bytes(None, 2048, 2048, 1, ctypes.byref(n)) == 0
+    assert L.nfs_kspace_filter_workspace_bytes(None, 0, 2, 1, ctypes.byref(n)) == nfs.NFS_ESHAPE
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    # too-long axis, then a short workspace: refused before any launch
+    assert L.nfs_apply_kspace_filter(c, A, A + 4096, 4096, 1, 1, A, A, 1 << 20, None) == nfs.NFS_ESHAPE
+    assert L.nfs_apply_kspace_filter(c, A, A + 4096, 16, 16, 1, A, A, 255, None) == nfs.NFS_EWORKSPACE
+    assert L.nfs_apply_kspace_filter(c, A, A + 4096, 16, 16, 1, None, A, 1 << 20, None) == nfs.NFS_EINVAL

@@ -86,17 +86,25 @@ def test_c3s_cg_reorth_every_stored_iterate(nfs, c3s, prec):
 
 @pytest.mark.parametrize("prec", PRECS)
 def test_c3s_cg_plain_stored_iterates(nfs, c3s, prec):
-    """The recurrences as printed, on the unmasked 3D grid: the stored early
-    iterates, where the FP64 plain and re-orthogonalised trajectories still
-    agree far below the bar (plain_vs_reorth in the golden file)."""
+    """The recurrences as printed, on the scaled 3D problem.  Its FP64 plain
+    and re-orthogonalised trajectories agree to rounding (plain_vs_reorth in
+    the golden file, ~1e-15 up to iterate 15), so every stored iterate of
+    either kind is a reference for the plain GPU solve there; those where the
+    two stay 20x below the bar are checked, through iterate 15."""
     g = c3s["g"]
-    its_ok = [int(k) for k in g["plain_iters"] if g["plain_vs_reorth"][int(k) - 1] < TOL[prec] / 20]
-    assert its_ok and its_ok[0] == 1
-    n = max(its_ok)
-    _, _, _, its = nfs.cg_solve_traced(c3s["gp"], torch.from_numpy(c3s["m"]), n, precision=prec)
+    n = int(g["n_iter"])
+    refs = {}
+    for k in g["reorth_iters"]:
+        refs[int(k)] = g[f"reorth_it_{int(k)}"]
+    for k in g["plain_iters"]:
+        refs[int(k)] = g[f"plain_it_{int(k)}"]
+    ks = sorted(k for k in refs if g["plain_vs_reorth"][k - 1] < TOL[prec] / 20)
+    assert ks and ks[0] == 1
+    _, _, info, its = nfs.cg_solve_traced(c3s["gp"], torch.from_numpy(c3s["m"]), max(ks), precision=prec)
     its = its.cpu().numpy()
-    errs = [check(its[k], g[f"plain_it_{k}"], TOL[prec], ("c3s plain", prec, k)) for k in its_ok]
-    print(f"c3s CG plain {prec}: iterates {its_ok}: " + " ".join(f"{a:.1e}/{b:.1e}" for a, b in errs))
+    errs = [check(its[k], refs[k], TOL[prec], ("c3s plain", prec, k)) for k in ks]
+    print(f"c3s CG plain {prec}: iterates {ks}: " + " ".join(f"{a:.1e}/{b:.1e}" for a, b in errs))
+    assert max(ks) == n or g["plain_vs_reorth"][n - 1] >= TOL[prec] / 20
 
 
 # ------------------------------------------------------------- full-size 3D
