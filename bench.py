@@ -21,9 +21,11 @@ of the full workload (tests/golden/c3_ehe_sampled.npz).
 
 Roofline: the fused encode kernel (phase tile, sin/cos, complex contraction),
 its average launch duration from HIP events on its launch stream over an
-eager pass of the same solve, against the transcendental peak (one sin and
-one cos per voxel-sample pair), with its matrix-pipe time fraction and the
-HBM traffic per launch from the committed counter summary.
+eager pass of the same solve, against the peak of whichever pipe it keeps
+busier (the matrix cores for the 3D workload, whose 32 coils make four
+contraction instructions per tile; see roofline()), with both pipes'
+fractions and the HBM traffic per launch from the committed counter
+summary.
 
 Side measurements: the BF16 and FP32 operand forms; one E^H E alone; the 2D
 128x128 workload (all forms, the compressed phase basis with its setup
@@ -86,7 +88,17 @@ def parse():
                     help="one solve of the headline workload only, for counter collection")
     ap.add_argument("--no-graphs", action="store_true",
                     help="launch every solve eagerly instead of replaying it from a captured hipGraph")
+    ap.add_argument("--shapes", default=None,
+                    help="encode shapes of the headline workload at --precision instead of autotuning, "
+                         "'E:<held tiles>:<splits>,EH:<held tiles>:<splits>' (as the autotuner reports them)")
     return ap.parse_args()
+
+
+def apply_shapes(nfs, prob, precision, spec):
+    """Pin the encode shapes given as 'E:4:2,EH:4:3'."""
+    for part in spec.split(","):
+        op, mt, ns = part.split(":")
+        nfs.set_shape(prob, precision, op, int(mt), int(ns))
 
 
 def rel(a, b):
@@ -220,29 +232,46 @@ def col_blocks(G):
 
 
 def roofline(kt, L, K, G, P, prec, counters_md):
-    """Roofline object of the dominant encode launch (E or E^H)."""
+    """Roofline object of the dominant encode launch (E or E^H).  The kernel
+    keeps two pipes busy: the matrix cores (phase tile and contraction) and
+    the transcendental unit (one sin and one cos per voxel-sample pair).
+    The bound is the pipe with the larger busy fraction: the matrix cores'
+    time for the MFMA instructions the kernel issues at the published dense
+    peak, against the transcendentals' time at their peak.  `achieved` is
+    algorithmic work per launch over the launch's mean duration: for "mfma"
+    the flops of the contraction (8 G per pair) and of the phase (2 (P + 1)
+    per pair) against the 2.5 PFLOP/s dense f16 peak; for "alu" the 2 sin/cos
+    per pair against the transcendental peak."""
     from paper_2604_09233_amd.profile_summary import read_traffic
 
     n_e, ms_e = kt["E"]
     n_h, ms_h = kt["EH"]
     kname, n_k, ms_k = ("EH", n_h, ms_h) if ms_h >= ms_e else ("E", n_e, ms_e)
     avg_ms = ms_k / max(n_k, 1)
+    t = avg_ms * 1e-3
     pairs = L * K  # voxel-sample pairs per launch
-    achieved = 2 * pairs / (avg_ms * 1e-3)  # one sin and one cos per pair
-    # matrix-pipe time of the MFMA instructions the kernel issues, at the
-    # published dense peak, as a fraction of the measured launch time: per
-    # 16 x 16 tile (256 pairs) ceil(3 (P+1) / 32) f16 16x16x32 phase
-    # instructions, and per 16-column block of the 2G real columns one f16
-    # (fp16), two bf16 (bf16: hi and lo data parts) or three f16 (fp32: split
-    # operands) 16x16x32 contraction instructions
+    trans = 2 * pairs / t
+    # MFMA instructions issued per 16 x 16 tile (256 pairs): ceil(3 (P+1) /
+    # 32) f16 16x16x32 phase instructions, and per 16-column block of the 2G
+    # real columns one f16 (fp16), two bf16 (bf16: hi and lo data parts) or
+    # three f16 (fp32: split operands) 16x16x32 contraction instructions
     tiles = pairs / 256.0
-    flops = tiles * 16384 * (phase_instrs(P) + col_blocks(G) * {"fp16": 1, "bf16": 2, "fp32": 3}[prec])
+    exec_flops = tiles * 16384 * (phase_instrs(P) + col_blocks(G) * {"fp16": 1, "bf16": 2, "fp32": 3}[prec])
+    mfma_peak = MFMA_PEAK_TFLOPS["fp16"] * 1e12
+    algo_flops = pairs * (8 * G + 2 * (P + 1))
+    trans_frac = trans / TRANS_PEAK
+    mfma_busy = exec_flops / mfma_peak / t
     tr = read_traffic(os.path.join(ROOT, "profiles", counters_md))
-    return dict(bound="alu", achieved=achieved / 1e12, peak=TRANS_PEAK / 1e12, unit="Tsincos-ops/s",
-                frac=achieved / TRANS_PEAK, traffic=(tr or {}).get(kname), traffic_unit="bytes per launch",
-                kernel=f"encode_kernel ({kname})", avg_launch_ms=avg_ms, launches=n_k,
-                mfma_pipe_frac=flops / (MFMA_PEAK_TFLOPS["fp16"] * 1e12) / (avg_ms * 1e-3),
-                encode_kernel_ms={"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)})
+    out = dict(traffic=(tr or {}).get(kname), traffic_unit="bytes per launch", kernel=f"encode_kernel ({kname})",
+               avg_launch_ms=avg_ms, launches=n_k, mfma_pipe_frac=mfma_busy, transcendental_frac=trans_frac,
+               algorithmic_flops_per_launch=algo_flops, executed_mfma_flops_per_launch=exec_flops,
+               encode_kernel_ms={"E": ms_e / max(n_e, 1), "EH": ms_h / max(n_h, 1)})
+    if mfma_busy >= trans_frac:
+        out.update(bound="mfma", achieved=algo_flops / t / 1e12, peak=mfma_peak / 1e12, unit="TFLOP/s",
+                   frac=algo_flops / t / mfma_peak)
+    else:
+        out.update(bound="alu", achieved=trans / 1e12, peak=TRANS_PEAK / 1e12, unit="Tsincos-ops/s", frac=trans_frac)
+    return out
 
 
 def c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth):
@@ -320,6 +349,8 @@ def twod_run(nfs, synth, torch, dev, args):
     # compressed phase basis: 16 solid harmonics on one slice span 10
     # functions; the compression is redone per geometry (kcoef is measured
     # per scan), so its host time is charged to an end-to-end figure
+    nfs.compress_basis(sv.prob)  # first call: loads the kernels
+    torch.cuda.synchronize()
     t_c = time.perf_counter()
     cprob, theta, cinfo = nfs.compress_basis(sv.prob)
     torch.cuda.synchronize()
@@ -333,7 +364,8 @@ def twod_run(nfs, synth, torch, dev, args):
                       ms_solve=ms_c, ms_setup_host=t_c, ms_end_to_end=ms_c + t_c,
                       rel_err_vs_oracle=rel(rho_c.cpu().numpy(), g[f"{kind}_rho"]) if g is not None else None,
                       note="solve on the compressed basis with the data rotation by exp(-i theta) inside the step; "
-                           "ms_setup_host = nfs_compress_basis (host copies, FP64 compression, device copies)")
+                           "ms_setup_host = wall time of nfs_compress_basis_device (FP64 on the GPU) including "
+                           "the one synchronisation that reads the kept term count back")
     del rho_c
 
     # non-split form: P built once per solve (2 K L x 4 bytes), streamed by every E and E^H
@@ -424,6 +456,8 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
     # compressed phase bases (each slice: 16 solid harmonics on one slice ->
     # 10 terms), the data rotations by exp(-i theta) inside the timed step;
     # the compression's host time per batch is reported beside it
+    nfs.compress_basis(probs[0])  # first call: loads the kernels
+    torch.cuda.synchronize()
     t_c = time.perf_counter()
     comp = [nfs.compress_basis(pr) for pr in probs]
     torch.cuda.synchronize()
@@ -597,6 +631,8 @@ def main():
     d = synth.make_config(args.config)
     sv = Solver(nfs, torch, dev, d, reorth)
     L, K, G, n_iter = sv.L, sv.K, sv.G, sv.n_iter
+    if args.shapes:
+        apply_shapes(nfs, sv.prob, args.precision, args.shapes)
     if args.profile_run:
         out, hist, info = sv.buffers()
         nfs.cg_solve(sv.prob, sv.m, n_iter, precision=args.precision, reorth=reorth, out=out, hist=hist, info=info)
@@ -605,7 +641,7 @@ def main():
         return
 
     progress("autotune and the timed solves")
-    if not args.no_tune:
+    if not args.no_tune and not args.shapes:
         nfs.autotune(sv.prob, args.precision)
     rho, hist, info, ms, wall = sv.time_solves(args.precision, args.steps, args.warmup, graphs=not args.no_graphs)
     rho = rho.clone()
@@ -676,7 +712,8 @@ def main():
         "rel_err_vs_oracle_note": None if err is not None else
             "no stored full-size FP64 oracle solve of this workload (many hours on the host); see oracle_checks",
         "oracle_checks": checks,
-        "encode_shapes": {"tuned": not args.no_tune, "held_tiles_nsplit": shapes},
+        "encode_shapes": {"tuned": not args.no_tune and not args.shapes, "pinned": args.shapes,
+                          "held_tiles_nsplit": shapes},
         "cg_info": {"iterations": st[0], "status": nfs.CG_STATUS.get(st[1], st[1])},
         "ehe_alone": {"ms": ehe_ms, "value": vsc / (ehe_ms * 1e-3)},
         "forms": forms,

@@ -377,6 +377,13 @@ int nfs_autotune_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, i
  * held tiles per wave and split count (tuned, else the default choice).    */
 int nfs_tuned_shape(const nfs_ctx* ctx, const nfs_problem* prob, int precision, int op, int* held_tiles,
                     int* nsplit);
+/* Pin the encode shape of `op` (NFS_OP_E or NFS_OP_EH) for this problem's
+ * shape class, as if the autotuner had chosen it (for instance a shape found
+ * by an earlier nfs_autotune and stored by the caller): held tiles per wave
+ * (2, or 4 for up to four 16-column blocks, i.e. up to 32 coils) and split
+ * count 1..64.  NFS_EINVAL for other values.  Results differ from another
+ * shape's only in the order of the split sums.  Host-only.               */
+int nfs_set_shape(nfs_ctx* ctx, const nfs_problem* prob, int precision, int op, int held_tiles, int nsplit);
 
 /* Backward of m = E rho for a real loss L, for field-map and trajectory
  * refinement.  grad_m is dL/dm in PyTorch's convention for complex tensors

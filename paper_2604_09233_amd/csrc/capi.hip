@@ -2098,6 +2098,23 @@ extern "C" int nfs_tuned_shape(const nfs_ctx* ctx, const nfs_problem* prob, int 
   return NFS_OK;
 }
 
+extern "C" int nfs_set_shape(nfs_ctx* ctx, const nfs_problem* prob, int precision, int op, int held_tiles,
+                             int nsplit) {
+  const char* fn = "nfs_set_shape";
+  if (!ctx) return fail(NFS_EINVAL, "%s: ctx is NULL", fn);
+  int rc = check_sizes(prob, fn);
+  if (rc) return rc;
+  if ((rc = check_prec(precision, fn))) return rc;
+  if (op != NFS_OP_E && op != NFS_OP_EH) return fail(NFS_EINVAL, "%s: op must be NFS_OP_E or NFS_OP_EH", fn);
+  const int nb = col_blocks(prob->n_coil);
+  if (!valid_held_tiles(nb, held_tiles))
+    return fail(NFS_EINVAL, "%s: %d held tiles not built for %d column blocks", fn, held_tiles, nb);
+  if (nsplit < 1 || nsplit > 64) return fail(NFS_EINVAL, "%s: nsplit %d outside [1, 64]", fn, nsplit);
+  ctx->tune[tune_key(op == NFS_OP_E ? OP_E : OP_EH, precision, prob)] = {held_tiles, nsplit};
+  ++ctx->tune_generation;
+  return NFS_OK;
+}
+
 // ---------------------------------------------------------------------------
 // map estimation (sensitivity and B0 maps from multi-echo prescan data)
 

@@ -441,84 +441,140 @@ __device__ __forceinline__ void stage_chunk(const u4* __restrict__ strmcoef, con
   }
 }
 
-// One (streamed chunk) x (MT held tiles) step: phase tile, sin/cos, complex
+// The A operand of the contraction for one tile: the (cos, sin) pairs the
+// lane holds, as FP16 (one part), BF16 (one part) or FP16 (two parts, for
+// the FP32 form).
+template <int PREC>
+struct TileOperand {
+  u4 hi, lo;  // lo used by the FP32 form only
+};
+
+// Phase tile on the f16 matrix cores: NQ chained 16x16x32 products.
+template <int NQ>
+__device__ __forceinline__ f4 phase_tile(const u4 (&ph)[NQ], const u4 (&hc)[NQ]) {
+  f4 p = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    p = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, ph[q]), __builtin_bit_cast(h8, hc[q]), p, 0,
+                                               0, 0);
+  return p;
+}
+
+// sin/cos of a phase tile (revolutions; v_fract first when FRACT) and its
+// conversion to the contraction operand.
+template <int PREC, bool FRACT>
+__device__ __forceinline__ TileOperand<PREC> tile_operand(f4 ph) {
+  float cs[4], sn[4];
+#pragma unroll
+  for (int r = 0; r < 4; ++r) {
+    const float x = FRACT ? __builtin_amdgcn_fractf(ph[r]) : ph[r];
+    sn[r] = __builtin_amdgcn_sinf(x);
+    cs[r] = __builtin_amdgcn_cosf(x);
+  }
+  TileOperand<PREC> op;
+  if (PREC == PREC_FP16) {
+    h8 a;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[2 * r] = (_Float16)cs[r];
+      a[2 * r + 1] = (_Float16)sn[r];
+    }
+    op.hi = __builtin_bit_cast(u4, a);
+    op.lo = u4{0, 0, 0, 0};
+  } else if (PREC == PREC_BF16) {
+    b8 a;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      a[2 * r] = (__bf16)cs[r];
+      a[2 * r + 1] = (__bf16)sn[r];
+    }
+    op.hi = __builtin_bit_cast(u4, a);
+    op.lo = u4{0, 0, 0, 0};
+  } else {
+    // (cos, sin) split: hi = both values rounded to f16 in one pack; lo =
+    // x - hi, formed exactly by one mixed-precision FMA per value that reads
+    // its half of the packed hi register, then rounded to f16
+    h8 ahi, alo;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+      h2 hp;
+      hp[0] = (_Float16)cs[r];
+      hp[1] = (_Float16)sn[r];
+      const unsigned hb = __builtin_bit_cast(unsigned, hp);
+      float lc, ls;
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lc) : "v"(hb), "v"(cs[r]));
+      asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ls) : "v"(hb), "v"(sn[r]));
+      ahi[2 * r] = hp[0];
+      ahi[2 * r + 1] = hp[1];
+      alo[2 * r] = (_Float16)lc;
+      alo[2 * r + 1] = (_Float16)ls;
+    }
+    op.hi = __builtin_bit_cast(u4, ahi);
+    op.lo = __builtin_bit_cast(u4, alo);
+  }
+  return op;
+}
+
+// The complex contraction of one tile against the streamed chunk's data
+// operand: one 16x16x32 product per column block (FP16), two (BF16: hi and
+// lo data parts), or three (FP32: lo.hi, hi.lo, hi.hi of two-part f16
+// operands, summed from zero and added once on the VALU).
+template <int PREC, int NB, int NQ>
+__device__ __forceinline__ void contract_tile(const TileOperand<PREC>& op, const Stream<PREC, NB, NQ>& cur,
+                                              f4 (&acc)[NB]) {
+#pragma unroll
+  for (int nb = 0; nb < NB; ++nb) {
+    if (PREC == PREC_FP16) {
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, op.hi), __builtin_bit_cast(h8, cur.d[nb]),
+                                                       acc[nb], 0, 0, 0);
+    } else if (PREC == PREC_BF16) {
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, op.hi),
+                                                        __builtin_bit_cast(b8, cur.d[2 * nb]), acc[nb], 0, 0, 0);
+      acc[nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(b8, op.hi),
+                                                        __builtin_bit_cast(b8, cur.d[2 * nb + 1]), acc[nb], 0, 0, 0);
+    } else {
+      const h8 dhi = __builtin_bit_cast(h8, cur.d[2 * nb]), dlo = __builtin_bit_cast(h8, cur.d[2 * nb + 1]);
+      f4 t = {0.f, 0.f, 0.f, 0.f};
+      t = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, op.lo), dhi, t, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, op.hi), dlo, t, 0, 0, 0);
+      t = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, op.hi), dhi, t, 0, 0, 0);
+      acc[nb] += t;
+    }
+  }
+}
+
+// One (streamed chunk) x (MT held tiles) step: phase tiles, sin/cos, complex
 // contraction into acc (see the kernel comment).
+// FP16 and FP32 operands: software-pipelined across the held tiles: the
+// phase products of all MT tiles are issued first, and the sin/cos of tile
+// mt + 1 are formed before the contraction of tile mt, so that each tile's
+// transcendentals can run on the VALU while the matrix cores work through
+// the previous tile's contraction, and the phase results are long done by
+// the time they are read (measured on the 3D and 2D workloads: 2-6 % less
+// time per launch).  BF16 operands keep the tile-by-tile order, which
+// measured faster for their two contraction products per column block.
 // FRACT: reduce the phase with v_fract before the hardware sine/cosine
 // (needed only when the phase may leave the +-256 revolution input range).
 template <int PREC, int NB, int NQ, int MT, bool FRACT>
 __device__ __forceinline__ void chunk_step(const Stream<PREC, NB, NQ>& cur, const u4 (&hc)[MT][NQ],
                                            f4 (&acc)[MT][NB]) {
+  if (PREC == PREC_BF16) {
+#pragma unroll
+    for (int mt = 0; mt < MT; ++mt)
+      contract_tile<PREC, NB, NQ>(tile_operand<PREC, FRACT>(phase_tile<NQ>(cur.ph, hc[mt])), cur, acc[mt]);
+    return;
+  }
+  f4 ph[MT];
+#pragma unroll
+  for (int mt = 0; mt < MT; ++mt) ph[mt] = phase_tile<NQ>(cur.ph, hc[mt]);
+  TileOperand<PREC> op = tile_operand<PREC, FRACT>(ph[0]);
 #pragma unroll
   for (int mt = 0; mt < MT; ++mt) {
-    f4 ph = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int q = 0; q < NQ; ++q)
-      ph = __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, cur.ph[q]), __builtin_bit_cast(h8, hc[mt][q]),
-                                                  ph, 0, 0, 0);
-    float cs[4], sn[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      const float x = FRACT ? __builtin_amdgcn_fractf(ph[r]) : ph[r];
-      sn[r] = __builtin_amdgcn_sinf(x);
-      cs[r] = __builtin_amdgcn_cosf(x);
-    }
-    if (PREC == PREC_FP16) {
-      h8 a;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[2 * r] = (_Float16)cs[r];
-        a[2 * r + 1] = (_Float16)sn[r];
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb)
-        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a, __builtin_bit_cast(h8, cur.d[nb]), acc[mt][nb], 0, 0, 0);
-    } else if (PREC == PREC_BF16) {
-      b8 a;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        a[2 * r] = (__bf16)cs[r];
-        a[2 * r + 1] = (__bf16)sn[r];
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, cur.d[2 * nb]), acc[mt][nb], 0,
-                                                              0, 0);
-        acc[mt][nb] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(b8, cur.d[2 * nb + 1]), acc[mt][nb],
-                                                              0, 0, 0);
-      }
-    } else {
-      // (cos, sin) split: hi keeps the leading 11 significant bits (exact in
-      // f16 for normal values), lo = x - hi is exact in float32 and rounded
-      // once to f16
-      h8 ahi, alo;
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        // hi: both values rounded to f16 in one pack; lo = x - hi, formed
-        // exactly by one mixed-precision FMA per value that reads its half
-        // of the packed hi register, then rounded to f16
-        typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-        h2 hp;
-        hp[0] = (_Float16)cs[r];
-        hp[1] = (_Float16)sn[r];
-        const unsigned hb = __builtin_bit_cast(unsigned, hp);
-        float lc, ls;
-        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel_hi:[1,0,0]" : "=v"(lc) : "v"(hb), "v"(cs[r]));
-        asm("v_fma_mix_f32 %0, -%1, 1.0, %2 op_sel:[1,0,0] op_sel_hi:[1,0,0]" : "=v"(ls) : "v"(hb), "v"(sn[r]));
-        ahi[2 * r] = hp[0];
-        ahi[2 * r + 1] = hp[1];
-        alo[2 * r] = (_Float16)lc;
-        alo[2 * r + 1] = (_Float16)ls;
-      }
-#pragma unroll
-      for (int nb = 0; nb < NB; ++nb) {
-        const h8 dhi = __builtin_bit_cast(h8, cur.d[2 * nb]), dlo = __builtin_bit_cast(h8, cur.d[2 * nb + 1]);
-        f4 t = {0.f, 0.f, 0.f, 0.f};
-        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(alo, dhi, t, 0, 0, 0);
-        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi, dlo, t, 0, 0, 0);
-        t = __builtin_amdgcn_mfma_f32_16x16x32_f16(ahi, dhi, t, 0, 0, 0);
-        acc[mt][nb] += t;
-      }
-    }
+    TileOperand<PREC> next;
+    if (mt + 1 < MT) next = tile_operand<PREC, FRACT>(ph[mt + 1]);
+    contract_tile<PREC, NB, NQ>(op, cur, acc[mt]);
+    if (mt + 1 < MT) op = next;
   }
 }
 

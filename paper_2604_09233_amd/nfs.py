@@ -86,6 +86,7 @@ def lib():
             L.nfs_tune_workspace_bytes.argtypes = [vp, pp, i32, ctypes.POINTER(sz)]
             L.nfs_autotune.argtypes = [vp, pp, i32, vp, sz, vp]
             L.nfs_tuned_shape.argtypes = [vp, pp, i32, i32, ctypes.POINTER(i32), ctypes.POINTER(i32)]
+            L.nfs_set_shape.argtypes = [vp, pp, i32, i32, i32, i32]
             L.nfs_tune_workspace_bytes_batched.argtypes = [vp, i32, pp, i32, ctypes.POINTER(sz)]
             L.nfs_autotune_batched.argtypes = [vp, i32, pp, i32, vp, sz, vp]
             L.nfs_profile_enable.argtypes = [vp, i32]
@@ -488,6 +489,13 @@ def tuned_shape(prob: Problem, precision: str = "fp16"):
                                      ctypes.byref(mt), ctypes.byref(ns)))
         out[name] = (mt.value, ns.value)
     return out
+
+
+def set_shape(prob: Problem, precision: str, op: str, held_tiles: int, nsplit: int):
+    """Pin the encode shape of op ("E" or "EH") for prob's shape class
+    (see include/nfs.h)."""
+    _check(lib().nfs_set_shape(context(prob.index), ctypes.byref(prob.st), PRECISIONS[precision], OPS[op],
+                               int(held_tiles), int(nsplit)))
 
 
 def set_graphs(device: int, on: bool = True):

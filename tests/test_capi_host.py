@@ -485,3 +485,17 @@ def test_kspace_filter_workspace_and_limits(L):
     assert L.nfs_apply_kspace_filter(c, A, A + 4096, 4096, 1, 1, A, A, 1 << 20, None) == nfs.NFS_ESHAPE
     assert L.nfs_apply_kspace_filter(c, A, A + 4096, 16, 16, 1, A, A, 255, None) == nfs.NFS_EWORKSPACE
     assert L.nfs_apply_kspace_filter(c, A, A + 4096, 16, 16, 1, None, A, 1 << 20, None) == nfs.NFS_EINVAL
+
+
+def test_set_shape_rejects_bad_shapes(L):
+    c = ctypes.cast(FAKE_CTX, ctypes.c_void_p)
+    pr = prob(G=32)  # four column blocks
+    assert L.nfs_set_shape(None, ctypes.byref(pr), 2, 0, 4, 2) == nfs.NFS_EINVAL
+    assert L.nfs_set_shape(c, ctypes.byref(pr), 7, 0, 4, 2) == nfs.NFS_EINVAL
+    assert L.nfs_set_shape(c, ctypes.byref(pr), 2, 2, 4, 2) == nfs.NFS_EINVAL  # only E and E^H
+    assert L.nfs_set_shape(c, ctypes.byref(pr), 2, 0, 3, 2) == nfs.NFS_EINVAL
+    assert L.nfs_set_shape(c, ctypes.byref(pr), 2, 0, 2, 0) == nfs.NFS_EINVAL
+    assert L.nfs_set_shape(c, ctypes.byref(pr), 2, 1, 2, 65) == nfs.NFS_EINVAL
+    pr8 = prob(G=64)  # eight column blocks: four held tiles are not built
+    assert L.nfs_set_shape(c, ctypes.byref(pr8), 2, 0, 4, 2) == nfs.NFS_EINVAL
+    assert b"held tiles" in L.nfs_last_error()

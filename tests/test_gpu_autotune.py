@@ -101,3 +101,23 @@ def test_autotune_batched_then_batched_solve(nfs):
     # a single solve of a slice uses the same tuned shapes: bit-identical
     r1, _, _ = nfs.cg_solve(probs[1], torch.from_numpy(ms[1]), 8, precision="fp32", reorth=True)
     assert torch.equal(r1.cpu(), rb[1].cpu())
+
+
+@pytest.mark.parametrize("shape", [(2, 1), (4, 3), (2, 64)])
+def test_pinned_shape_is_used_and_matches_oracle(nfs, shape):
+    """nfs_set_shape: the pinned shape is the one later calls report and use
+    (a split count above the streamed chunk count leaves empty splits), and
+    the operators still match the oracle."""
+    d = synth.random_problem(700, 1300, 6, 9, seed=79, phase_scale=8.0)
+    a = (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
+    gp = nfs.Problem(*a)
+    mt, ns = shape
+    for op in ("E", "EH"):
+        nfs.set_shape(gp, "fp16", op, mt, ns)
+    assert nfs.tuned_shape(gp, "fp16") == {"E": shape, "EH": shape}
+    e1 = rel(nfs.apply_E(gp, torch.from_numpy(d["rho"]), "fp16").cpu().numpy(), oracle.apply_E(d["rho"], *a))
+    e2 = rel(nfs.apply_EHE(gp, torch.from_numpy(d["rho"]), "fp16").cpu().numpy(), oracle.apply_EHE(d["rho"], *a))
+    print(f"pinned shape {shape}: E {e1:.1e}, EHE {e2:.1e}")
+    assert max(e1, e2) < TOL["fp16"]
+    with pytest.raises(nfs.NfsError):
+        nfs.set_shape(gp, "fp16", "E", 3, 2)
