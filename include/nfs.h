@@ -160,6 +160,24 @@ int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* r
                  int n_iter, double tol, int replace_every, int reorth, int precision,
                  double* hist, int* info, void* ws, size_t ws_bytes, void* stream);
 
+/* The same solve for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * no workspace argument; the scratch lives in a device array of the library
+ * (NFS_SCRATCH_BYTES per GPU, held from library load until the process
+ * ends; its address per device is looked up once, by nfs_create).  Same
+ * arguments, results and rules as nfs_cg_solve, which it shares its kernels
+ * with (results are bit-identical to nfs_cg_solve with the same encode
+ * shapes).  Allocates nothing: NFS_EWORKSPACE if the solve needs more than
+ * NFS_SCRATCH_BYTES (nfs_workspace_bytes with NFS_OP_CG gives the need;
+ * the 2D 128x128 / 16-coil / 60000-sample workload takes about 140 MB at
+ * its tuned shapes).  Every call on one GPU uses that GPU's one scratch
+ * array and leaves it in an undefined state; calls that overlap on one GPU
+ * (different streams or host threads without ordering) race and give
+ * undefined results.                                                      */
+#define NFS_SCRATCH_BYTES (256u * 1024u * 1024u)
+int nfs_cg_solve_noalloc(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter, double tol,
+                         int replace_every, int reorth, int precision, double* hist, int* info, void* stream);
+
 /* The same solve in the non-split form of the reconstruction figure (left
  * column): the phase factors P = exp(i phi) are built once per solve, as the
  * float16 (cos, sin) operand of the FP16 contraction (2 K L x 4 bytes of

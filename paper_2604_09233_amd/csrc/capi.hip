@@ -8,6 +8,7 @@
 #include <algorithm>
 #include <array>
 #include <map>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -42,6 +43,7 @@ struct nfs_ctx {
   // autotuned encode shapes: key (op, precision, L, K, G, P) -> (MT, nsplit)
   std::map<std::string, std::pair<int, int>> tune;
   unsigned tune_generation = 0;  // bumped by every autotune (part of graph keys)
+  void* scratch = nullptr;       // this device's copy of `scratch` (nfs_cg_solve_noalloc)
 };
 
 static std::string tune_key(int op, int prec, const nfs_problem* pr) {
@@ -71,6 +73,38 @@ static int hip_fail(hipError_t e, const char* where) {
 extern "C" const char* nfs_last_error(void) { return g_err.c_str(); }
 extern "C" int nfs_version(void) { return 100; }
 
+// Device scratch of nfs_cg_solve_noalloc: a file-scope device array, so
+// that the call needs no allocation at all.  Its name is only a host-side
+// stand-in; the device address of each GPU's copy comes from
+// hipGetSymbolAddress (with that device current) and is kept per device.
+constexpr size_t kScratchBytes = (size_t)NFS_SCRATCH_BYTES;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+static std::mutex g_scratch_mu;
+static std::unordered_map<int, void*> g_scratch_ptr;
+
+static int scratch_address(int device, void** out) {
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  auto it = g_scratch_ptr.find(device);
+  if (it != g_scratch_ptr.end()) {
+    *out = it->second;
+    return NFS_OK;
+  }
+  int cur = 0;
+  hipError_t e = hipGetDevice(&cur);
+  if (e != hipSuccess) return hip_fail(e, "nfs_create: hipGetDevice");
+  e = hipSetDevice(device);
+  if (e != hipSuccess) return hip_fail(e, "nfs_create: hipSetDevice");
+  void* p = nullptr;
+  e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  const hipError_t e2 = hipSetDevice(cur);
+  if (e != hipSuccess) return hip_fail(e, "nfs_create: hipGetSymbolAddress(scratch)");
+  if (e2 != hipSuccess) return hip_fail(e2, "nfs_create: hipSetDevice");
+  if (!p || (uintptr_t)p % 256) return fail(NFS_EHIP, "nfs_create: scratch address %p not 256-byte aligned", p);
+  g_scratch_ptr.emplace(device, p);
+  *out = p;
+  return NFS_OK;
+}
+
 extern "C" int nfs_create(nfs_ctx** ctx, int device) {
   if (!ctx) return fail(NFS_EINVAL, "nfs_create: ctx is NULL");
   *ctx = nullptr;
@@ -83,9 +117,13 @@ extern "C" int nfs_create(nfs_ctx** ctx, int device) {
   if (e != hipSuccess) return hip_fail(e, "nfs_create: hipGetDeviceProperties");
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(NFS_EUNSUPPORTED, "nfs_create: device %d is %s, not gfx950", device, prop.gcnArchName);
+  void* sp = nullptr;
+  const int rc = scratch_address(device, &sp);
+  if (rc) return rc;
   nfs_ctx* c = new nfs_ctx;
   c->device = device;
   c->n_cu = prop.multiProcessorCount > 0 ? prop.multiProcessorCount : 256;
+  c->scratch = sp;
   *ctx = c;
   return NFS_OK;
 }
@@ -760,6 +798,26 @@ extern "C" int nfs_cg_solve(nfs_ctx* ctx, const nfs_problem* prob, const float* 
       graph_key(ctx, "cg", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision, ws, ws_bytes, stream);
   return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
     return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ws, st);
+  });
+}
+
+extern "C" int nfs_cg_solve_noalloc(nfs_ctx* ctx, const nfs_problem* prob, const float* m, float* rho, int n_iter,
+                                    double tol, int replace_every, int reorth, int precision, double* hist, int* info,
+                                    void* stream) {
+  const char* fn = "nfs_cg_solve_noalloc";
+  int rc = check_cg_args(ctx, prob, m, rho, n_iter, tol, replace_every, reorth, precision, hist, info, fn);
+  if (rc) return rc;
+  const Layout y = make_layout(ctx, prob, NFS_OP_CG, precision, n_iter, reorth);
+  if (y.total > kScratchBytes)
+    return fail(NFS_EWORKSPACE, "%s: the solve needs %zu bytes of scratch, more than the %zu the library holds", fn,
+                y.total, kScratchBytes);
+  if (!ctx->scratch) return fail(NFS_EHIP, "%s: no scratch address for device %d", fn, ctx->device);
+  hipStream_t s = (hipStream_t)stream;
+  const void* ptrs[4] = {m, rho, hist, info};
+  const std::string key = graph_key(ctx, "cgn", prob, 1, ptrs, 4, n_iter, tol, replace_every, reorth, precision,
+                                    ctx->scratch, kScratchBytes, stream);
+  return run_maybe_graph(ctx, key, s, [&](hipStream_t st) {
+    return run_cg(ctx, prob, y, m, rho, n_iter, tol, replace_every, reorth, hist, info, ctx->scratch, st);
   });
 }
 

@@ -64,6 +64,7 @@ def lib():
                 getattr(L, name).argtypes = [vp, pp, vp, vp, i32, vp, sz, vp]
             L.nfs_cg_solve.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
             L.nfs_cg_solve_resident.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, sz, vp]
+            L.nfs_cg_solve_noalloc.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp]
             L.nfs_cg_solve_traced.argtypes = [vp, pp, vp, vp, i32, dbl, i32, i32, i32, vp, vp, vp, vp, sz, vp]
             L.nfs_ssim_workspace_bytes.argtypes = [i32, i32, i32, i32, ctypes.POINTER(sz)]
             L.nfs_ssim.argtypes = [vp, vp, i32, vp, i32, i32, i32, vp, vp, sz, vp]
@@ -243,6 +244,22 @@ def cg_solve(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int
     _check(lib().nfs_cg_solve(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
                               float(tol), int(replace_every), int(reorth), PRECISIONS[precision], _ptr(hist),
                               _ptr(info), _ptr(ws), ws.numel(), prob._stream()))
+    return rho, hist, info
+
+
+def cg_solve_noalloc(prob: Problem, m, n_iter: int, tol: float = 0.0, replace_every: int = 0,
+                     precision: str = "fp32", reorth: bool = False, out=None, hist=None, info=None):
+    """cg_solve on the library's own device scratch (no workspace; for
+    callers that cannot allocate, see include/nfs.h).  Same returns."""
+    m = _c64(m, prob.device)
+    rho = out if out is not None else torch.empty(prob.L, dtype=torch.complex64, device=prob.device)
+    if hist is None:
+        hist = torch.full((n_iter + 1, 3), float("nan"), dtype=torch.float64, device=prob.device)
+    if info is None:
+        info = torch.zeros(2, dtype=torch.int32, device=prob.device)
+    _check(lib().nfs_cg_solve_noalloc(context(prob.index), ctypes.byref(prob.st), _ptr(m), _ptr(rho), int(n_iter),
+                                      float(tol), int(replace_every), int(reorth), PRECISIONS[precision],
+                                      _ptr(hist), _ptr(info), prob._stream()))
     return rho, hist, info
 
 
