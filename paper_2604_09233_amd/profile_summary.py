@@ -20,16 +20,25 @@ import sys
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCES = [os.path.join(HERE, "csrc", "encode_kernels.hip"), os.path.join(HERE, "csrc", "nfs_internal.h"),
-                  os.path.join(HERE, "build.py")]
 TRAFFIC_TAG = "encode-kernel traffic per launch (bytes):"
+# what the encode kernels' machine code depends on: their source file, the
+# part of the shared header before the launcher declarations (constants,
+# shape and work-list structs, the split-sum helper), and the compiler flags
+# they are built with
+_HEADER_END = "// ---- launchers (encode_kernels.hip)"
 
 
 def kernel_source_hash() -> str:
+    from . import build
+
     h = hashlib.sha256()
-    for p in KERNEL_SOURCES:
-        with open(p, "rb") as f:
-            h.update(f.read())
+    with open(os.path.join(HERE, "csrc", "encode_kernels.hip"), "rb") as f:
+        h.update(f.read())
+    with open(os.path.join(HERE, "csrc", "nfs_internal.h")) as f:
+        hdr = f.read()
+    h.update(hdr[:hdr.index(_HEADER_END)].encode())
+    flags = build.COMMON + build.DEVICE_FLAGS + build.SOURCE_FLAGS.get("encode_kernels.hip", [])
+    h.update(" ".join(f for f in flags if not f.startswith("/")).encode())
     return h.hexdigest()
 
 
