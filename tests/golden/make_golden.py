@@ -21,7 +21,9 @@ E the oracle's.
           rounding sensitivity (probe_deltas, probe_dev [delta][iterate]:
           distance from the plain iterates when every E^H E p is perturbed
           by relative noise delta; probe_hist [delta]: those runs' histories)
-                                                                   (~12 min)
+          and the same probe on the re-orthogonalised trajectory
+          (reorth_probe_dev, reorth_probe_maxdev [delta][iterate]: relative L2
+          and largest-element distances)                           (~28 min)
   c3s     tests/golden/c3s_cg.npz: the scaled 3D workload (48x48x24, 8 coils,
           4 x 8000 samples, 16 terms), 15 iterations, same keys as c2
                                                                    (~10 min)
@@ -52,7 +54,7 @@ import oracle  # noqa: E402
 import synth  # noqa: E402
 
 N_VOX_SAMPLED = 1536
-PROBE_DELTAS = [1e-6, 1e-5, 1e-4, 3e-4, 1e-3]
+PROBE_DELTAS = [1e-6, 2e-6, 5e-6, 1e-5, 3e-5, 1e-4, 3e-4, 1e-3]
 N_VOX_SLICE = 512
 
 
@@ -117,6 +119,17 @@ def make_c2mask():
     out["probe_deltas"] = np.array(PROBE_DELTAS)
     out["probe_dev"] = np.array(dev)
     out["probe_hist"] = np.array(hists)
+    # the same probe on the re-orthogonalised trajectory: relative L2
+    # distance and largest-element distance (over the largest element) of
+    # every perturbed iterate from the unperturbed one
+    rdev, rmax = [], []
+    for delta in PROBE_DELTAS:
+        pr = oracle.cg_solve(m, *args_of(dm), n_iter=30, return_iterates=True, perturb=(delta, 7), reorth=True)
+        rdev.append([np.linalg.norm(x - y) / np.linalg.norm(y) for x, y in zip(pr["iterates"], runs["reorth"])])
+        rmax.append([np.max(np.abs(x - y)) / np.max(np.abs(y)) for x, y in zip(pr["iterates"], runs["reorth"])])
+        print(f"reorth probe {delta:.0e}: " + " ".join(f"{v:.1e}" for v in rdev[-1]), flush=True)
+    out["reorth_probe_dev"] = np.array(rdev)
+    out["reorth_probe_maxdev"] = np.array(rmax)
     out.update(m_rms=rms, sigma=sigma, n_iter=30, mask=mask)
     np.savez_compressed(os.path.join(HERE, "c2mask_cg.npz"), **out)
     print(f"c2mask CG golden written in {time.time() - t0:.0f} s")

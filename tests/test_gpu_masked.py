@@ -12,10 +12,17 @@ iterate the probe keeps within a quarter of the bar.  Past the horizon the
 iterates depend on rounding at any precision (the FP64 plain solve itself
 leaves the exact-arithmetic trajectory, see plain_vs_reorth), so they are
 held to the spread that rounding of that size gives in the oracle: at every
-iterate the distance from the FP64 plain iterate, and the data-residual and
-solution-norm histories, within four times the probe's own deviation (plus
-the bar).  The re-orthogonalised solve is compared at every stored iterate.
-Both parity measures of tests/_parity.py.
+iterate the distance from the FP64 plain iterate within four times the
+probe's own deviation (its running maximum over iterates) plus the bar,
+the solution-norm history within the same relative bound, and the
+data-residual history within four times the probe's running-maximum
+deviation plus the bar.  The re-orthogonalised solve is compared at every
+stored iterate the same way, against the same probe run on the
+re-orthogonalised trajectory (on a problem this ill-conditioned, kappa ~
+1e14, even the exact-arithmetic trajectory moves under operator rounding
+once the Krylov space reaches the small singular values): at the bar where
+that probe stays within a quarter of it, else within four times the
+probe's deviation plus the bar.  Both parity measures of tests/_parity.py.
 """
 import os
 
@@ -25,7 +32,7 @@ import torch
 
 import oracle
 import synth
-from _parity import PRECS, TOL, check, rel
+from _parity import PRECS, TOL, check, max_rel, rel
 
 pytestmark = pytest.mark.gpu
 
@@ -75,12 +82,17 @@ def horizon(g, i, tol):
     return hz
 
 
+def operator_probe(nfs, c2mask, prec):
+    """(twice the GPU's relative E^H E error here, index of the probe for it)"""
+    q = nfs.apply_EHE(c2mask["gp"], torch.from_numpy(c2mask["p"]), prec).cpu().numpy()
+    delta = 2 * rel(q, c2mask["ehe_ref"])
+    return delta, probe_index(c2mask["g"], delta)
+
+
 @pytest.mark.parametrize("prec", PRECS)
 def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     g, gp = c2mask["g"], c2mask["gp"]
-    q = nfs.apply_EHE(gp, torch.from_numpy(c2mask["p"]), prec).cpu().numpy()
-    delta = 2 * rel(q, c2mask["ehe_ref"])
-    i = probe_index(g, delta)
+    delta, i = operator_probe(nfs, c2mask, prec)
     hz = horizon(g, i, TOL[prec])
     n = int(g["n_iter"])
     _, hist, info, its = nfs.cg_solve_traced(gp, torch.from_numpy(c2mask["m"]), n, precision=prec)
@@ -88,21 +100,26 @@ def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     assert info.cpu().tolist() == [n, 1]
     errs = [check(its[k], g["plain_its"][k - 1], TOL[prec], ("c2mask plain", prec, k)) for k in range(1, hz + 1)]
     # past the horizon: within the spread the oracle's probe shows for
-    # rounding of this size (iterates, data residual, solution norm)
-    dev = g["probe_dev"][i]
+    # rounding of this size, taken as the running maximum over iterates
+    # (one probe run's deviation at a single iterate can dip by chance):
+    # iterates, and the history's solution norm (bounded by the iterate
+    # bound through the triangle inequality) and data residual
+    dev = np.maximum.accumulate(g["probe_dev"][i])
+    bound = 4 * dev + TOL[prec]
     for k in range(hz + 1, n + 1):
         e = rel(its[k], g["plain_its"][k - 1])
-        assert e <= 4 * dev[k - 1] + TOL[prec], ("c2mask plain spread", prec, k, e, dev[k - 1])
+        assert e <= bound[k - 1], ("c2mask plain spread", prec, k, e, dev[k - 1])
     h = hist.cpu().numpy()
     ref, ph = g["plain_hist"], g["probe_hist"][i]
-    for col in (1, 2):
-        spread = np.abs(ph[1:, col] - ref[1:, col])
-        assert np.all(np.abs(h[1:, col] - ref[1:, col]) <= 4 * spread + TOL[prec] * ref[1:, col]), col
-    last = rel(its[n], g["plain_its"][n - 1])
+    assert np.all(np.abs(h[1:, 1] - ref[1:, 1]) <= bound * ref[1:, 1]), "solution norm"
+    dspread = np.maximum.accumulate(np.abs(ph[1:, 2] - ref[1:, 2]))
+    assert np.all(np.abs(h[1:, 2] - ref[1:, 2]) <= 4 * dspread + TOL[prec] * ref[1:, 2]), "data residual"
+    later = ", ".join(f"{k}: {rel(its[k], g['plain_its'][k - 1]):.1e} (probe {dev[k - 1]:.1e})"
+                      for k in (5, 10, 15, 20, 30) if k <= n)
     print(f"c2mask plain {prec}: E^H E error {delta / 2:.1e}, probe delta {g['probe_deltas'][i]:.0e}, horizon {hz} "
           f"of {n}; worst rel/max up to it "
-          f"{max((e[0] for e in errs), default=0):.1e}/{max((e[1] for e in errs), default=0):.1e}; iterate {n} "
-          f"rel {last:.1e} (FP64 plain vs exact arithmetic there {g['plain_vs_reorth'][n - 1]:.1e})")
+          f"{max((e[0] for e in errs), default=0):.1e}/{max((e[1] for e in errs), default=0):.1e}; iterates {later} "
+          f"(FP64 plain vs exact arithmetic at {n}: {g['plain_vs_reorth'][n - 1]:.1e})")
     assert hz >= 1, hz
 
 
@@ -110,12 +127,28 @@ def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
 def test_c2mask_reorth_cg_every_stored_iterate(nfs, c2mask, prec):
     g = c2mask["g"]
     n = int(g["n_iter"])
+    delta, i = operator_probe(nfs, c2mask, prec)
+    rd = np.maximum.accumulate(g["reorth_probe_dev"][i])
+    rm = np.maximum.accumulate(g["reorth_probe_maxdev"][i])
     _, hist, info, its = nfs.cg_solve_traced(c2mask["gp"], torch.from_numpy(c2mask["m"]), n, precision=prec,
                                              reorth=True)
     its = its.cpu().numpy()
     assert info.cpu().tolist() == [n, 1]
-    errs = [check(its[int(k)], g[f"reorth_it_{int(k)}"], TOL[prec], ("c2mask reorth", prec, int(k)))
-            for k in g["reorth_iters"]]
+    tol = TOL[prec]
+    out = []
+    for k in (int(k) for k in g["reorth_iters"]):
+        ref = g[f"reorth_it_{k}"]
+        if rd[k - 1] <= tol / 4 and rm[k - 1] <= tol / 4:
+            e = check(its[k], ref, tol, ("c2mask reorth", prec, k))
+            out.append(f"{k}: {e[0]:.1e}/{e[1]:.1e}")
+        else:
+            e, em = rel(its[k], ref), max_rel(its[k], ref)
+            assert e <= 4 * rd[k - 1] + tol and em <= 4 * rm[k - 1] + tol, ("c2mask reorth spread", prec, k, e, em,
+                                                                         rd[k - 1], rm[k - 1])
+            out.append(f"{k}: {e:.1e}/{em:.1e} (probe spread {rd[k - 1]:.1e}/{rm[k - 1]:.1e})")
     h = hist.cpu().numpy()
-    assert np.max(np.abs(h[:, 2] - g["reorth_hist"][:, 2])) < TOL[prec] * g["reorth_hist"][0, 2]
-    print(f"c2mask reorth {prec}: " + " ".join(f"{a:.1e}/{b:.1e}" for a, b in errs))
+    assert np.max(np.abs(h[:, 2] - g["reorth_hist"][:, 2])) < tol * g["reorth_hist"][0, 2]
+    print(f"c2mask reorth {prec}: E^H E error {delta / 2:.1e}, probe delta {g['probe_deltas'][i]:.0e}; "
+          + ", ".join(out))
+    # the first stored iterates are inside the probe's horizon at every precision
+    assert rd[0] <= tol / 4 and rm[0] <= tol / 4
