@@ -152,6 +152,27 @@ def test_persistent_batch_with_mixed_shapes_and_replacement(nfs):
         assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
 
 
+def test_persistent_mode_falls_back_for_shapes_it_does_not_take(nfs):
+    """A batch holding a slice of 32 phase terms (three phase instructions
+    per tile, which the persistent kernel is not built for) runs as the
+    streams form under NFS_BATCH_PERSISTENT: every slice still equals its
+    single solve bit for bit."""
+    sl = [synth.random_problem(300, 900, 12, 31, seed=51), synth.random_problem(350, 800, 64, 9, seed=52)]
+    probs = [nfs.Problem(*args(d)) for d in sl]
+    ms = [torch.from_numpy(d["m"]) for d in sl]
+    nfs.set_batch_mode(0, "persistent")
+    try:
+        rb, _, ib = nfs.cg_solve_batched(probs, ms, 5, precision="fp16", reorth=True)
+        torch.cuda.synchronize()
+    finally:
+        nfs.set_batch_mode(0, "streams")
+    for i, (p, m) in enumerate(zip(probs, ms)):
+        r1, _, i1 = nfs.cg_solve(p, m, 5, precision="fp16", reorth=True)
+        torch.cuda.synchronize()
+        assert ib[i].cpu().tolist() == [5, 1], i
+        assert torch.equal(rb[i].cpu(), r1.cpu()), i
+
+
 def test_graph_cache_evicts_and_stays_correct(nfs, small_batch):
     """Graph mode with fresh output buffers on every call: each call is a new
     graph key, so after 32 captures the least recently used graphs are

@@ -74,6 +74,7 @@ SHAPES = [
     (300, 500, 33, 20),    # NB=8 (66 real columns), NT=8
     (2048, 3000, 32, 16),  # several tiles, NB=4
     (16, 4096, 3, 4),      # one held tile for E^H, long stream
+    (500, 700, 64, 31),    # the largest coil and term counts: NB=8, 32 terms (NQ=3)
 ]
 
 
@@ -91,6 +92,27 @@ def test_ragged_shapes(nfs, shape, prec):
     q = nfs.apply_EHE(gp, torch.from_numpy(d["rho"]), prec).cpu().numpy()
     e3 = check(q, oracle.apply_EHE(d["rho"], *a), TOL[prec], ("EHE", shape))
     print(f"shape {shape} {prec}: E {e1[0]:.2e}/{e1[1]:.2e} EH {e2[0]:.2e}/{e2[1]:.2e} EHE {e3[0]:.2e}/{e3[1]:.2e}")
+
+
+@pytest.mark.parametrize("prec", PRECS)
+def test_cg_at_the_largest_coil_and_term_counts(nfs, prec):
+    """64 coils (8 column blocks) and 31 field terms (32 phase terms, three
+    phase instructions per tile), the most the library takes: the
+    re-orthogonalised CG against the oracle at every iterate, and the
+    resident form (FP16) bit-identical to the split solve."""
+    d = synth.random_problem(400, 600, 64, 31, seed=37)
+    a = args(d)
+    gp = gpu_problem(nfs, d)
+    ref = oracle.cg_solve(d["m"], *a, n_iter=6, reorth=True, return_iterates=True)
+    _, _, info, its = nfs.cg_solve_traced(gp, torch.from_numpy(d["m"]), 6, precision=prec, reorth=True)
+    its = its.cpu().numpy()
+    assert info.cpu().tolist() == [6, 1]
+    errs = [check(its[k], ref["iterates"][k - 1], TOL[prec], ("CG max sizes", prec, k)) for k in range(1, 7)]
+    print(f"64 coils, 32 terms, {prec}: " + " ".join(f"{e[0]:.1e}/{e[1]:.1e}" for e in errs))
+    if prec == "fp16":
+        rs, _, _ = nfs.cg_solve(gp, torch.from_numpy(d["m"]), 6, precision="fp16", reorth=True)
+        rr, _, _ = nfs.cg_solve_resident(gp, torch.from_numpy(d["m"]), 6, precision="fp16", reorth=True)
+        assert torch.equal(rs.cpu(), rr.cpu())
 
 
 @pytest.mark.parametrize("prec", PRECS)
