@@ -134,6 +134,100 @@ def apply_EHE(p, sens, fields, b0, kcoef, t, block=_DEF_BLOCK, threads=None):
     return np.conj(np.sum(acc * S_T, axis=0))
 
 
+# ---------------------------------------------------------------------------
+# Operand-rounding probe (not part of the method).  E^H E evaluated with the
+# matrix-core operands rounded as a reduced-precision operand form rounds
+# them, everything else in FP64: models how far a working precision moves
+# the CG trajectory of a particular problem.  Rounding is round-to-nearest-
+# even, from the IEEE formats' definitions:
+#   "fp16": cos and sin rounded to float16; each data operand (S o p, the E
+#           output, the coil data) scaled by a power of two that puts its
+#           largest real or imaginary part just below 2^14 (the E output by
+#           2^-(ceil(log2 L) + 1) relative to the E operand's scale) and
+#           rounded to float16;
+#   "bf16": cos and sin rounded to bfloat16 (float32 with its low 16 bits
+#           rounded off); each data operand split into a bfloat16 high part
+#           and the bfloat16 rounding of the remainder.
+
+def _bf16(x):
+    """Round float64 values to bfloat16 (via float32; nearest, ties to even)."""
+    f = np.ascontiguousarray(x, dtype=np.float32)
+    b = f.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def _round_parts(z, fn):
+    return fn(np.real(z)) + 1j * fn(np.imag(z))
+
+
+def _pow2_scale(z):
+    """2^(14 - e) with max(|re|, |im|) < 2^e (1 for an all-zero operand)."""
+    mx = max(float(np.max(np.abs(np.real(z)), initial=0.0)), float(np.max(np.abs(np.imag(z)), initial=0.0)))
+    if not mx > 0.0:
+        return 1.0
+    _, e = np.frexp(mx)
+    return float(np.ldexp(1.0, 14 - int(e)))
+
+
+def _round_exp(phi, fmt):
+    c, s = np.cos(phi), np.sin(phi)
+    fn = (lambda v: v.astype(np.float16).astype(np.float64)) if fmt == "fp16" else _bf16
+    return fn(c) + 1j * fn(s)
+
+
+def _round_data(z, fmt, scale):
+    """Data operand z as the operand form holds it (z * scale rounded), unscaled."""
+    if fmt == "fp16":
+        return _round_parts(z * scale, lambda v: v.astype(np.float16).astype(np.float64)) / scale
+    hi = _round_parts(z, _bf16)
+    return hi + _round_parts(z - hi, _bf16)
+
+
+def apply_EH_rounded(m, sens, fields, b0, kcoef, t, fmt, block=_DEF_BLOCK, threads=None):
+    """E^H sigma with operand rounding ``fmt`` (probe; see above)."""
+    R = _spatial_basis(fields, b0)
+    Kt = _temporal_basis(kcoef, t)
+    m = np.asarray(m, dtype=np.complex128)
+    sig = _round_data(m, fmt, _pow2_scale(m))
+    blocks = _blocks(Kt.shape[0], block)
+
+    def work(se):
+        s, e = se
+        return np.conj(sig[:, s:e]) @ _round_exp(Kt[s:e] @ R, fmt)
+
+    acc = np.zeros((sig.shape[0], R.shape[1]), dtype=np.complex128)
+    with ThreadPoolExecutor(_threads(threads or len(blocks))) as ex:
+        for part in ex.map(work, blocks):
+            acc += part
+    return np.conj(np.sum(acc * np.asarray(sens, dtype=np.complex128), axis=0))
+
+
+def apply_EHE_rounded(p, sens, fields, b0, kcoef, t, fmt, block=_DEF_BLOCK, threads=None):
+    """E^H E p with operand rounding ``fmt`` (probe; see above)."""
+    R = _spatial_basis(fields, b0)
+    Kt = _temporal_basis(kcoef, t)
+    S_T = np.asarray(sens, dtype=np.complex128)
+    L = S_T.shape[1]
+    Q = S_T.T * np.asarray(p, dtype=np.complex128)[:, None]
+    sq = _pow2_scale(Q)
+    Q = _round_data(Q, fmt, sq)
+    sy = sq * float(np.ldexp(1.0, -(int(np.ceil(np.log2(L))) + 1))) if L > 1 else sq * 0.5
+    blocks = _blocks(Kt.shape[0], block)
+
+    def work(se):
+        s, e = se
+        Pb = _round_exp(Kt[s:e] @ R, fmt)
+        y = _round_data(Pb @ Q, fmt, sy)
+        return np.conj(y).T @ Pb
+
+    acc = np.zeros_like(S_T)
+    with ThreadPoolExecutor(_threads(threads or len(blocks))) as ex:
+        for part in ex.map(work, blocks):
+            acc += part
+    return np.conj(np.sum(acc * S_T, axis=0))
+
+
 def dense_E(sens, fields, b0, kcoef, t):
     """The explicit (Gamma*K) x L encoding matrix, built column by column by
     applying E to unit vectors (tiny problems only)."""
@@ -148,7 +242,7 @@ def dense_E(sens, fields, b0, kcoef, t):
 
 def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
              return_iterates=False, explicit_residual=False, block=_DEF_BLOCK, threads=None,
-             perturb=None, reorth=False):
+             perturb=None, reorth=False, operands=None):
     """CG on E^H E rho = E^H sigma, as in the reconstruction figure.
 
     Steps: optional intensity correction S <- S o (j 1^T); p = E^H sigma;
@@ -177,7 +271,10 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
     xi complex Gaussian (seeded), which models a working precision whose
     relative rounding error is about delta.  Comparing such a run with the
     unperturbed one measures how far the iterates of this particular problem
-    can move under rounding at that level.
+    can move under rounding at that level.  ``operands = "fp16" | "bf16"``
+    is the other probe: E^H sigma and every E^H E p with the matrix-core
+    operands rounded as that operand form rounds them (apply_EH_rounded,
+    apply_EHE_rounded), the CG arithmetic itself in FP64.
 
     Returns dict(rho, iters, status, hist[iters+1][3], iterates?, dres?)
     where hist row n holds (||r_n||, ||rho_n||, ||d_n||^2 from the
@@ -189,7 +286,7 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
     args = (sens, fields, b0, kcoef, t)
     kw = dict(block=block, threads=threads)
     m = np.asarray(m, dtype=np.complex128)
-    p = apply_EH(m, *args, **kw)
+    p = apply_EH(m, *args, **kw) if operands is None else apply_EH_rounded(m, *args, operands, **kw)
     r = p.copy()
     rho = np.zeros_like(p)
     alpha = float(np.real(np.vdot(r, r)))
@@ -206,7 +303,7 @@ def cg_solve(m, sens, fields, b0, kcoef, t, n_iter, icorr=None, tol=0.0,
         status = "exact"
     else:
         while n < n_iter:
-            q = apply_EHE(p, *args, **kw)
+            q = apply_EHE(p, *args, **kw) if operands is None else apply_EHE_rounded(p, *args, operands, **kw)
             if prng is not None:
                 xi = prng.standard_normal(q.shape) + 1j * prng.standard_normal(q.shape)
                 q = q * (1.0 + perturb[0] * xi / np.sqrt(2.0))

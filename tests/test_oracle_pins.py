@@ -361,3 +361,62 @@ def test_reorth_keeps_residuals_orthogonal_on_the_2d_spiral_config():
     U = np.stack([r / np.linalg.norm(r) for r in rs], axis=1)
     G = U.conj().T @ U
     assert np.max(np.abs(G - np.eye(len(rs)))) < 1e-6
+
+
+# ---------------------------------------------------------------- rounding probe
+def test_bf16_rounding_definition():
+    """bfloat16 = float32 with the low 16 bits rounded off, nearest, ties to
+    even: representable values stay, halfway cases go to the even neighbour,
+    and every result is within half a unit in the last place."""
+    from oracle.nfs_oracle import _bf16
+
+    exact = np.array([1.0, -2.5, 0.0078125, 3.140625, 65280.0])
+    assert np.array_equal(_bf16(exact), exact)
+    ulp1 = 2.0 ** -7
+    ties = np.array([1 + ulp1 / 2, 1 + 3 * ulp1 / 2, -(1 + ulp1 / 2)])
+    assert np.array_equal(_bf16(ties), np.array([1.0, 1 + 2 * ulp1, -1.0]))
+    x = np.random.default_rng(0).standard_normal(10000) * 10.0 ** np.random.default_rng(1).uniform(-3, 3, 10000)
+    y = _bf16(x)
+    assert np.all(y.astype(np.float32).view(np.uint32) & 0xFFFF == 0)
+    assert np.all(np.abs(y - x) <= 2.0 ** -8 * np.abs(x) * (1 + 1e-12))
+
+
+def test_rounding_probe_is_exact_on_representable_operands():
+    """Phases on multiples of pi/2 (cos, sin in {0, +-1}) and small integer
+    data: every operand the probe rounds is representable, so E^H E and
+    E^H sigma with fp16 or bf16 operand rounding equal the FP64 values."""
+    from oracle import nfs_oracle as o
+
+    rng = np.random.default_rng(4)
+    L, K, G = 40, 64, 3
+    fields = rng.integers(0, 4, size=(1, L)).astype(np.float64)
+    kcoef = (np.pi / 2) * rng.integers(0, 2, size=(K, 1)).astype(np.float64)
+    b0, t = np.zeros(L), np.zeros(K)
+    sens = rng.integers(-2, 3, size=(G, L)) + 1j * rng.integers(-2, 3, size=(G, L))
+    p = rng.integers(-3, 4, size=L) + 1j * rng.integers(-3, 4, size=L)
+    m = rng.integers(-5, 6, size=(G, K)) + 1j * rng.integers(-5, 6, size=(G, K))
+    a = (sens, fields, b0, kcoef, t)
+    for fmt in ("fp16", "bf16"):
+        q, qr = o.apply_EHE(p, *a), o.apply_EHE_rounded(p, *a, fmt)
+        x, xr = o.apply_EH(m, *a), o.apply_EH_rounded(m, *a, fmt)
+        assert np.max(np.abs(qr - q)) <= 1e-12 * np.max(np.abs(q)), fmt
+        assert np.max(np.abs(xr - x)) <= 1e-12 * np.max(np.abs(x)), fmt
+
+
+def test_rounding_probe_error_is_at_the_format_unit():
+    """On a random problem the rounded E^H E differs from the FP64 one by the
+    order of the format's unit roundoff (fp16 2^-11, bf16 2^-8 on the cos and
+    sin operands), and the fp16 data scale puts the largest part in
+    [2^13, 2^14)."""
+    from oracle import nfs_oracle as o
+
+    d = synth.random_problem(200, 400, 5, 6, seed=8)
+    a = (d["sens"], d["fields"], d["b0"], d["kcoef"], d["t"])
+    q = o.apply_EHE(d["rho"], *a)
+    for fmt, lo, hi in (("fp16", 2.0 ** -16, 2.0 ** -10), ("bf16", 2.0 ** -13, 2.0 ** -7)):
+        e = np.linalg.norm(o.apply_EHE_rounded(d["rho"], *a, fmt) - q) / np.linalg.norm(q)
+        assert lo < e < hi, (fmt, e)
+    z = d["m"] * 37.0
+    sc = o._pow2_scale(z)
+    top = max(np.max(np.abs(z.real)), np.max(np.abs(z.imag))) * sc
+    assert 2.0 ** 13 <= top < 2.0 ** 14
