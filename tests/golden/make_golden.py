@@ -23,7 +23,9 @@ E the oracle's.
           by relative noise delta; probe_hist [delta]: those runs' histories)
           and the same probe on the re-orthogonalised trajectory
           (reorth_probe_dev, reorth_probe_maxdev [delta][iterate]: relative L2
-          and largest-element distances)                           (~28 min)
+          and largest-element distances); and both solves with the FP16 and
+          BF16 forms' operand rounding (emul_<fmt>_<kind>_dev, _maxdev
+          [iterate], _hist)                                         (~45 min)
   c3s     tests/golden/c3s_cg.npz: the scaled 3D workload (48x48x24, 8 coils,
           4 x 8000 samples, 16 terms), 15 iterations, same keys as c2
                                                                    (~10 min)
@@ -130,6 +132,19 @@ def make_c2mask():
         print(f"reorth probe {delta:.0e}: " + " ".join(f"{v:.1e}" for v in rdev[-1]), flush=True)
     out["reorth_probe_dev"] = np.array(rdev)
     out["reorth_probe_maxdev"] = np.array(rmax)
+    # the operand-rounding probe: the same solves with the matrix-core
+    # operands rounded as the FP16 and BF16 operand forms round them
+    for fmt in ("fp16", "bf16"):
+        for kind, ro in (("plain", False), ("reorth", True)):
+            pr = oracle.cg_solve(m, *args_of(dm), n_iter=30, return_iterates=True, operands=fmt, reorth=ro)
+            ref = runs[kind]
+            out[f"emul_{fmt}_{kind}_dev"] = np.array([np.linalg.norm(x - y) / np.linalg.norm(y)
+                                                       for x, y in zip(pr["iterates"], ref)])
+            out[f"emul_{fmt}_{kind}_maxdev"] = np.array([np.max(np.abs(x - y)) / np.max(np.abs(y))
+                                                          for x, y in zip(pr["iterates"], ref)])
+            out[f"emul_{fmt}_{kind}_hist"] = pr["hist"]
+            print(f"{fmt} operands, {kind}: " + " ".join(f"{v:.1e}" for v in out[f"emul_{fmt}_{kind}_dev"]),
+                  flush=True)
     out.update(m_rms=rms, sigma=sigma, n_iter=30, mask=mask)
     np.savez_compressed(os.path.join(HERE, "c2mask_cg.npz"), **out)
     print(f"c2mask CG golden written in {time.time() - t0:.0f} s")

@@ -4,14 +4,18 @@ paper solves for), through the C ABI, against the stored FP64 oracle solves
 
 The recurrences as printed (plain CG) are compared with the FP64 plain
 solve at every iterate up to the horizon where that trajectory is stable
-under the GPU's rounding: the golden file holds the oracle's sensitivity
-probe (every E^H E p perturbed by relative noise delta) for several delta;
-the test measures the GPU's E^H E error on this problem and takes the
-horizon of the smallest stored delta at least twice that error, as the last
-iterate the probe keeps within a quarter of the bar.  Past the horizon the
-iterates depend on rounding at any precision (the FP64 plain solve itself
-leaves the exact-arithmetic trajectory, see plain_vs_reorth), so they are
-held to the spread that rounding of that size gives in the oracle: at every
+under the GPU's rounding, the last iterate that the oracle's probe of the
+operand form keeps within a quarter of the bar.  The golden file holds two
+kinds of probe: the solves with every E^H E p perturbed by relative noise
+delta at several levels (every form takes the smallest stored level at
+least twice the GPU's measured E^H E error on this problem; the model of
+the FP32 form, whose split operands round to ~2^-22), and the FP64 solves
+with the matrix-core operands rounded as the FP16 and BF16 forms round
+them (the model of those forms).  Past the horizon, where both apply, the
+larger deviation counts.
+Past the horizon the iterates depend on rounding at any precision (the
+FP64 plain solve itself leaves the exact-arithmetic trajectory, see
+plain_vs_reorth), so they are held to the spread the probe shows: at every
 iterate the distance from the FP64 plain iterate within four times the
 probe's own deviation (its running maximum over iterates) plus the bar,
 the solution-norm history within the same relative bound, and the
@@ -73,51 +77,81 @@ def probe_index(g, delta):
     return idx[0]
 
 
-def horizon(g, i, tol):
-    """Last iterate probe i keeps within tol / 4."""
-    dev = g["probe_dev"][i]
+def operator_error(nfs, c2mask, prec):
+    """The GPU's relative E^H E error on this problem (random vector)."""
+    q = nfs.apply_EHE(c2mask["gp"], torch.from_numpy(c2mask["p"]), prec).cpu().numpy()
+    return rel(q, c2mask["ehe_ref"])
+
+
+def probe(nfs, c2mask, prec, kind):
+    """The oracle's probes of this operand form's rounding on the `kind`
+    ("plain" / "reorth") trajectory: (description, relative L2 deviation per
+    iterate, largest-element deviation per iterate or None, data-residual
+    history deviation per iterate or None), each the largest over the
+    probes that apply, and (L2, largest-element) deviations of the probe
+    that models the form, for its horizon.  The probes: relative noise at
+    the smallest stored level at least twice the measured E^H E error (all
+    forms) and, for FP16 and BF16, the oracle solve with the operands
+    rounded as that form rounds them (the model for those forms)."""
+    g = c2mask["g"]
+    err = operator_error(nfs, c2mask, prec)
+    i = probe_index(g, 2 * err)
+    ref_hist = g[f"{kind}_hist"]
+    if kind == "plain":
+        devs, maxdevs, hists = [g["probe_dev"][i]], None, [g["probe_hist"][i]]
+    else:
+        devs, maxdevs, hists = [g["reorth_probe_dev"][i]], [g["reorth_probe_maxdev"][i]], []
+    label = f"noise {g['probe_deltas'][i]:.0e}"
+    if prec in ("fp16", "bf16"):
+        devs.append(g[f"emul_{prec}_{kind}_dev"])
+        if maxdevs is not None:
+            maxdevs.append(g[f"emul_{prec}_{kind}_maxdev"])
+        hists.append(g[f"emul_{prec}_{kind}_hist"])
+        label += f" and {prec} operand rounding"
+    d2 = np.max([np.abs(h[1:, 2] - ref_hist[1:, 2]) for h in hists], axis=0) if hists else None
+    # the horizon comes from the probe that models the form: operand
+    # rounding for FP16 / BF16, noise for FP32 (split operands, ~2^-22)
+    model = devs[-1], (None if maxdevs is None else maxdevs[-1])
+    return (f"{label} (E^H E error {err:.1e})", np.max(devs, axis=0),
+            None if maxdevs is None else np.max(maxdevs, axis=0), d2, model)
+
+
+def horizon(dev, tol):
+    """Last iterate the probe keeps within tol / 4 (from iterate 1 on)."""
     hz = 0
     while hz < len(dev) and dev[hz] <= tol / 4:
         hz += 1
     return hz
 
 
-def operator_probe(nfs, c2mask, prec):
-    """(twice the GPU's relative E^H E error here, index of the probe for it)"""
-    q = nfs.apply_EHE(c2mask["gp"], torch.from_numpy(c2mask["p"]), prec).cpu().numpy()
-    delta = 2 * rel(q, c2mask["ehe_ref"])
-    return delta, probe_index(c2mask["g"], delta)
-
-
 @pytest.mark.parametrize("prec", PRECS)
 def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     g, gp = c2mask["g"], c2mask["gp"]
-    delta, i = operator_probe(nfs, c2mask, prec)
-    hz = horizon(g, i, TOL[prec])
+    label, dev0, _, d2, (model, _) = probe(nfs, c2mask, prec, "plain")
+    hz = horizon(model, TOL[prec])
     n = int(g["n_iter"])
     _, hist, info, its = nfs.cg_solve_traced(gp, torch.from_numpy(c2mask["m"]), n, precision=prec)
     its = its.cpu().numpy()
     assert info.cpu().tolist() == [n, 1]
     errs = [check(its[k], g["plain_its"][k - 1], TOL[prec], ("c2mask plain", prec, k)) for k in range(1, hz + 1)]
-    # past the horizon: within the spread the oracle's probe shows for
-    # rounding of this size, taken as the running maximum over iterates
-    # (one probe run's deviation at a single iterate can dip by chance):
-    # iterates, and the history's solution norm (bounded by the iterate
-    # bound through the triangle inequality) and data residual
-    dev = np.maximum.accumulate(g["probe_dev"][i])
+    # past the horizon: within the spread the probe shows, taken as the
+    # running maximum over iterates (one probe run's deviation at a single
+    # iterate can dip by chance): iterates, and the history's solution norm
+    # (bounded by the iterate bound through the triangle inequality) and
+    # data residual
+    dev = np.maximum.accumulate(dev0)
     bound = 4 * dev + TOL[prec]
     for k in range(hz + 1, n + 1):
         e = rel(its[k], g["plain_its"][k - 1])
         assert e <= bound[k - 1], ("c2mask plain spread", prec, k, e, dev[k - 1])
     h = hist.cpu().numpy()
-    ref, ph = g["plain_hist"], g["probe_hist"][i]
+    ref = g["plain_hist"]
     assert np.all(np.abs(h[1:, 1] - ref[1:, 1]) <= bound * ref[1:, 1]), "solution norm"
-    dspread = np.maximum.accumulate(np.abs(ph[1:, 2] - ref[1:, 2]))
+    dspread = np.maximum.accumulate(d2)
     assert np.all(np.abs(h[1:, 2] - ref[1:, 2]) <= 4 * dspread + TOL[prec] * ref[1:, 2]), "data residual"
-    later = ", ".join(f"{k}: {rel(its[k], g['plain_its'][k - 1]):.1e} (probe {dev[k - 1]:.1e})"
+    later = ", ".join(f"{k}: {rel(its[k], g['plain_its'][k - 1]):.1e} (probe {dev0[k - 1]:.1e})"
                       for k in (5, 10, 15, 20, 30) if k <= n)
-    print(f"c2mask plain {prec}: E^H E error {delta / 2:.1e}, probe delta {g['probe_deltas'][i]:.0e}, horizon {hz} "
-          f"of {n}; worst rel/max up to it "
+    print(f"c2mask plain {prec}: probe {label}, horizon {hz} of {n}; worst rel/max up to it "
           f"{max((e[0] for e in errs), default=0):.1e}/{max((e[1] for e in errs), default=0):.1e}; iterates {later} "
           f"(FP64 plain vs exact arithmetic at {n}: {g['plain_vs_reorth'][n - 1]:.1e})")
     assert hz >= 1, hz
@@ -127,9 +161,11 @@ def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
 def test_c2mask_reorth_cg_every_stored_iterate(nfs, c2mask, prec):
     g = c2mask["g"]
     n = int(g["n_iter"])
-    delta, i = operator_probe(nfs, c2mask, prec)
-    rd = np.maximum.accumulate(g["reorth_probe_dev"][i])
-    rm = np.maximum.accumulate(g["reorth_probe_maxdev"][i])
+    label, rd0, rm0, _, (md, mm) = probe(nfs, c2mask, prec, "reorth")
+    rd = np.maximum.accumulate(rd0)
+    rm = np.maximum.accumulate(rm0)
+    md = np.maximum.accumulate(md)
+    mm = np.maximum.accumulate(mm)
     _, hist, info, its = nfs.cg_solve_traced(c2mask["gp"], torch.from_numpy(c2mask["m"]), n, precision=prec,
                                              reorth=True)
     its = its.cpu().numpy()
@@ -138,7 +174,7 @@ def test_c2mask_reorth_cg_every_stored_iterate(nfs, c2mask, prec):
     out = []
     for k in (int(k) for k in g["reorth_iters"]):
         ref = g[f"reorth_it_{k}"]
-        if rd[k - 1] <= tol / 4 and rm[k - 1] <= tol / 4:
+        if md[k - 1] <= tol / 4 and mm[k - 1] <= tol / 4:
             e = check(its[k], ref, tol, ("c2mask reorth", prec, k))
             out.append(f"{k}: {e[0]:.1e}/{e[1]:.1e}")
         else:
@@ -148,7 +184,6 @@ def test_c2mask_reorth_cg_every_stored_iterate(nfs, c2mask, prec):
             out.append(f"{k}: {e:.1e}/{em:.1e} (probe spread {rd[k - 1]:.1e}/{rm[k - 1]:.1e})")
     h = hist.cpu().numpy()
     assert np.max(np.abs(h[:, 2] - g["reorth_hist"][:, 2])) < tol * g["reorth_hist"][0, 2]
-    print(f"c2mask reorth {prec}: E^H E error {delta / 2:.1e}, probe delta {g['probe_deltas'][i]:.0e}; "
-          + ", ".join(out))
+    print(f"c2mask reorth {prec}: probe {label}; " + ", ".join(out))
     # the first stored iterates are inside the probe's horizon at every precision
-    assert rd[0] <= tol / 4 and rm[0] <= tol / 4
+    assert md[0] <= tol / 4 and mm[0] <= tol / 4
