@@ -30,3 +30,23 @@ def check(a, b, tol, what=""):
     e, em = rel(a, b), max_rel(a, b)
     assert e < tol and em < tol, (what, e, em, tol)
     return e, em
+
+
+def horizon(dev, tol, lookahead=2):
+    """Rounding horizon of a CG trajectory from a probe's deviation per
+    iterate (dev[k - 1] for iterate k): the last iterate k such that the
+    probe stays within tol / 4 at every iterate up to k + lookahead.  The
+    lookahead keeps the horizon off the iterates where the trajectory starts
+    to depend on rounding: there one rounding pattern can leave it an
+    iterate or two before another."""
+    n = len(dev)
+    first_out = next((j for j in range(n) if dev[j] > tol / 4), n)  # 0-based index of the first iterate beyond
+    return n if first_out == n else max(0, first_out - lookahead)
+
+
+def spread(dev, lookahead=2):
+    """A probe's deviation as a bound past the horizon: at iterate k the
+    largest deviation up to iterate k + lookahead (the same allowance for a
+    trajectory that leaves an iterate or two earlier than the probe's)."""
+    dev = np.asarray(dev, dtype=np.float64)
+    return np.array([dev[:min(len(dev), k + 1 + lookahead)].max() for k in range(len(dev))])

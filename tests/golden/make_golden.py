@@ -12,7 +12,14 @@ E the oracle's.
             <kind>_hist       per-iteration ||r_n||, ||rho_n||, ||d_n||^2
             plain_vs_reorth   [30] relative L2 distance of plain iterate n
                               from re-orthogonalised iterate n (FP64 both)
-            m_rms, sigma      data scale and noise level          (~16 min)
+            plain_its         every plain iterate 1..30 (complex64)
+            probe_deltas, probe_dev [delta][iterate], probe_hist: the plain
+                              trajectory under relative noise delta on every
+                              E^H E p (distance from the plain iterates,
+                              histories)
+            emul_<fmt>_plain_dev, _hist: the same under the FP16 / BF16
+                              forms' operand rounding
+            m_rms, sigma      data scale and noise level          (~80 min)
   c2mask  tests/golden/c2mask_cg.npz: the same workload restricted to its
           reconstruction mask (phantom support dilated by 2 voxels), same
           data; every plain iterate 1..30 (plain_its [30][Lm] complex64), the
@@ -91,11 +98,34 @@ def cg_pair(d, m, n_iter, iters, t0):
     return out, runs
 
 
+def plain_probes(out, d, m, plain_its, levels, t0):
+    """The plain trajectory's probes: relative noise at `levels` (seed 7) and
+    the FP16 / BF16 operand rounding; deviations per iterate and histories."""
+    dev, hists = [], []
+    for delta in levels:
+        pr = oracle.cg_solve(m, *args_of(d), n_iter=len(plain_its), return_iterates=True, perturb=(delta, 7))
+        dev.append([np.linalg.norm(x - y) / np.linalg.norm(y) for x, y in zip(pr["iterates"], plain_its)])
+        hists.append(pr["hist"])
+        print(f"probe {delta:.0e} at {time.time() - t0:.0f} s: " + " ".join(f"{v:.1e}" for v in dev[-1]), flush=True)
+    out["probe_deltas"] = np.array(levels)
+    out["probe_dev"] = np.array(dev)
+    out["probe_hist"] = np.array(hists)
+    for fmt in ("fp16", "bf16"):
+        pr = oracle.cg_solve(m, *args_of(d), n_iter=len(plain_its), return_iterates=True, operands=fmt)
+        out[f"emul_{fmt}_plain_dev"] = np.array([np.linalg.norm(x - y) / np.linalg.norm(y)
+                                                  for x, y in zip(pr["iterates"], plain_its)])
+        out[f"emul_{fmt}_plain_hist"] = pr["hist"]
+        print(f"{fmt} operands at {time.time() - t0:.0f} s: "
+              + " ".join(f"{v:.1e}" for v in out[f"emul_{fmt}_plain_dev"]), flush=True)
+
+
 def make_c2():
     t0 = time.time()
     d = synth.make_config("c2")
     m, rms, sigma = noisy_data(d)
-    out, _ = cg_pair(d, m, 30, {"plain": [1, 2, 3], "reorth": [1, 5, 10, 20]}, t0)
+    out, runs = cg_pair(d, m, 30, {"plain": [1, 2, 3], "reorth": [1, 5, 10, 20]}, t0)
+    out["plain_its"] = np.stack(runs["plain"]).astype(np.complex64)
+    plain_probes(out, d, m, runs["plain"], [1e-6, 2e-6, 5e-6], t0)
     out.update(m_rms=rms, sigma=sigma, n_iter=30)
     np.savez_compressed(os.path.join(HERE, "c2_cg.npz"), **out)
     print(f"c2 CG golden written in {time.time() - t0:.0f} s")

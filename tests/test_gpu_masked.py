@@ -4,8 +4,9 @@ paper solves for), through the C ABI, against the stored FP64 oracle solves
 
 The recurrences as printed (plain CG) are compared with the FP64 plain
 solve at every iterate up to the horizon where that trajectory is stable
-under the GPU's rounding, the last iterate that the oracle's probe of the
-operand form keeps within a quarter of the bar.  The golden file holds two
+under the GPU's rounding: two iterates before the first one that the
+oracle's probe of the operand form takes beyond a quarter of the bar
+(tests/_parity.py: horizon).  The golden file holds two
 kinds of probe: the solves with every E^H E p perturbed by relative noise
 delta at several levels (every form takes the smallest stored level at
 least twice the GPU's measured E^H E error on this problem; the model of
@@ -17,10 +18,10 @@ Past the horizon the iterates depend on rounding at any precision (the
 FP64 plain solve itself leaves the exact-arithmetic trajectory, see
 plain_vs_reorth), so they are held to the spread the probe shows: at every
 iterate the distance from the FP64 plain iterate within four times the
-probe's own deviation (its running maximum over iterates) plus the bar,
-the solution-norm history within the same relative bound, and the
-data-residual history within four times the probe's running-maximum
-deviation plus the bar.  The re-orthogonalised solve is compared at every
+probes' deviation (the largest up to two iterates ahead) plus the bar, the
+solution-norm history within the same relative bound, and the
+data-residual history within four times the probes' deviation (likewise)
+plus the bar.  The re-orthogonalised solve is compared at every
 stored iterate the same way, against the same probe run on the
 re-orthogonalised trajectory (on a problem this ill-conditioned, kappa ~
 1e14, even the exact-arithmetic trajectory moves under operator rounding
@@ -36,7 +37,7 @@ import torch
 
 import oracle
 import synth
-from _parity import PRECS, TOL, check, max_rel, rel
+from _parity import PRECS, TOL, check, horizon, max_rel, rel, spread
 
 pytestmark = pytest.mark.gpu
 
@@ -116,14 +117,6 @@ def probe(nfs, c2mask, prec, kind):
             None if maxdevs is None else np.max(maxdevs, axis=0), d2, model)
 
 
-def horizon(dev, tol):
-    """Last iterate the probe keeps within tol / 4 (from iterate 1 on)."""
-    hz = 0
-    while hz < len(dev) and dev[hz] <= tol / 4:
-        hz += 1
-    return hz
-
-
 @pytest.mark.parametrize("prec", PRECS)
 def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     g, gp = c2mask["g"], c2mask["gp"]
@@ -134,12 +127,12 @@ def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     its = its.cpu().numpy()
     assert info.cpu().tolist() == [n, 1]
     errs = [check(its[k], g["plain_its"][k - 1], TOL[prec], ("c2mask plain", prec, k)) for k in range(1, hz + 1)]
-    # past the horizon: within the spread the probe shows, taken as the
-    # running maximum over iterates (one probe run's deviation at a single
-    # iterate can dip by chance): iterates, and the history's solution norm
-    # (bounded by the iterate bound through the triangle inequality) and
-    # data residual
-    dev = np.maximum.accumulate(dev0)
+    # past the horizon: within the spread the probes show, taken up to two
+    # iterates ahead (one probe run's deviation at a single iterate can dip
+    # by chance, and a trajectory can leave an iterate or two earlier):
+    # iterates, and the history's solution norm (bounded by the iterate
+    # bound through the triangle inequality) and data residual
+    dev = spread(dev0)
     bound = 4 * dev + TOL[prec]
     for k in range(hz + 1, n + 1):
         e = rel(its[k], g["plain_its"][k - 1])
@@ -147,7 +140,7 @@ def test_c2mask_plain_cg_every_iterate_to_horizon(nfs, c2mask, prec):
     h = hist.cpu().numpy()
     ref = g["plain_hist"]
     assert np.all(np.abs(h[1:, 1] - ref[1:, 1]) <= bound * ref[1:, 1]), "solution norm"
-    dspread = np.maximum.accumulate(d2)
+    dspread = spread(d2)
     assert np.all(np.abs(h[1:, 2] - ref[1:, 2]) <= 4 * dspread + TOL[prec] * ref[1:, 2]), "data residual"
     later = ", ".join(f"{k}: {rel(its[k], g['plain_its'][k - 1]):.1e} (probe {dev0[k - 1]:.1e})"
                       for k in (5, 10, 15, 20, 30) if k <= n)
@@ -162,8 +155,8 @@ def test_c2mask_reorth_cg_every_stored_iterate(nfs, c2mask, prec):
     g = c2mask["g"]
     n = int(g["n_iter"])
     label, rd0, rm0, _, (md, mm) = probe(nfs, c2mask, prec, "reorth")
-    rd = np.maximum.accumulate(rd0)
-    rm = np.maximum.accumulate(rm0)
+    rd = spread(rd0)
+    rm = spread(rm0)
     md = np.maximum.accumulate(md)
     mm = np.maximum.accumulate(mm)
     _, hist, info, its = nfs.cg_solve_traced(c2mask["gp"], torch.from_numpy(c2mask["m"]), n, precision=prec,
