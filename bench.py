@@ -12,12 +12,14 @@ Reported value: E^H E voxel*sample*coil per second over the solve, i.e.
 (n_iter + 1/2) * L * K * G / (solve time), the initial E^H m counting as half
 an application.  ms_per_step is the CG solve time.
 
-Accuracy.  A full FP64 oracle CG of the 3D workload takes many hours on the
-host, so rel_err_vs_oracle is null when no stored full solve exists; beside
-it go the errors against stored FP64 oracle values that the tests also use:
-the scaled 3D case's CG iterate (48x48x24, 8 coils, 4 x 8000 samples, 15
-iterations; tests/golden/c3s_cg.npz) and E^H E of the phantom at 1536 voxels
-of the full workload (tests/golden/c3_ehe_sampled.npz).
+Accuracy.  A full 15-iteration FP64 oracle CG of the 3D workload takes many
+hours on the host, so rel_err_vs_oracle is null; beside it go the errors
+against stored FP64 oracle values that the tests also use: the scaled 3D
+case's CG iterate (48x48x24, 8 coils, 4 x 8000 samples, 15 iterations;
+tests/golden/c3s_cg.npz), E^H E of the phantom at 1536 voxels of the full
+workload (tests/golden/c3_ehe_sampled.npz), and the third iterate of the
+full-size CG with the workload's unit coil noise as data, at every voxel
+(tests/golden/c3_cg.npz).
 
 Roofline: the fused encode kernel (phase tile, sin/cos, complex contraction),
 its average launch duration from HIP events on its launch stream over an
@@ -279,9 +281,10 @@ def roofline(kt, L, K, G, P, prec, counters_md):
 
 def c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth):
     """Errors against the stored FP64 oracle values of the 3D workloads: E^H E
-    of the phantom at the stored voxels of the full workload, and the CG
-    iterates of the scaled 3D case (data from the library's FP32 E, which
-    differs from the oracle-built data by ~1e-6 relative)."""
+    of the phantom at the stored voxels of the full workload, the CG iterates
+    of the scaled 3D case (data from the library's FP32 E, which differs from
+    the oracle-built data by ~1e-6 relative), and the first iterates of the
+    full-size CG with the workload's unit coil noise as data."""
     out = {}
     g = golden("c3_ehe_sampled.npz")
     if g is not None:
@@ -297,6 +300,15 @@ def c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth):
         ref = g[f"{kind}_rho"]
         out["c3s_cg"] = dict(workload="3D 48x48x24, 8 coils, 4 x 8000 samples, 16 terms, 15 iterations",
                              iterate=n, rel=rel(rho.cpu().numpy(), ref), max_rel=max_rel(rho.cpu().numpy(), ref))
+    g = golden("c3_cg.npz")
+    if g is not None:
+        # the full-size re-orthogonalised CG with the workload's unit coil
+        # noise as data, at the last stored iterate, every voxel
+        n = int(g["n_iter"])
+        rho, _, _ = nfs.cg_solve(sv.prob, torch.from_numpy(sv.d["noise"]).to(dev), n, precision=prec, reorth=True)
+        x = rho.cpu().numpy()
+        out["c3_cg_full_size"] = dict(data="unit coil noise", iterate=n, voxels=int(len(x)), rel=rel(x, g["rho"]),
+                                      max_rel=max_rel(x, g["rho"]))
     return out
 
 
