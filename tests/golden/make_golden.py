@@ -40,6 +40,10 @@ E the oracle's.
           572000-sample workload, q = E^H E p for p = the phantom, at
           n_vox_sampled seeded voxels (vox [n], q [n] complex128); the full
           E p is formed, so this is one full-size E                 (~35 min)
+  c3cg    tests/golden/c3_cg.npz: the same workload's re-orthogonalised FP64
+          CG on E^H E rho = E^H m with m = its unit coil noise, 3 iterations:
+          it_<k> (iterate k at the seeded voxels vox), norms [k] (||rho_k||),
+          rho (iterate 3, all voxels, complex64), hist          (~2-3 hours)
   batch24 tests/golden/batch24_cg.npz: the 24-slice batched workload (full
           phase bases), 30 re-orthogonalised iterations per slice; per slice
           s: vox_<s> (sampled voxel indices), rho_<s> (complex128 at those
@@ -202,6 +206,26 @@ def make_c3ehe():
     print(f"c3 sampled E^H E golden written in {time.time() - t0:.0f} s")
 
 
+N_C3_ITERS = 3
+N_VOX_C3 = 4096
+
+
+def make_c3cg():
+    """The full-size 3D CG: the re-orthogonalised FP64 solve of
+    E^H E rho = E^H m with m the workload's unit coil noise (no E needed for
+    the data), its first iterates."""
+    t0 = time.time()
+    d = synth.make_config("c3")
+    res = oracle.cg_solve(d["noise"], *args_of(d), n_iter=N_C3_ITERS, return_iterates=True, reorth=True, block=128)
+    vox = np.sort(np.random.default_rng(2025).choice(d["L"], N_VOX_C3, replace=False))
+    out = dict(n_iter=N_C3_ITERS, vox=vox, hist=res["hist"], rho=res["rho"].astype(np.complex64),
+               norms=np.array([np.linalg.norm(x) for x in res["iterates"]]))
+    for k, x in enumerate(res["iterates"], 1):
+        out[f"it_{k}"] = x[vox].astype(np.complex64)
+    np.savez_compressed(os.path.join(HERE, "c3_cg.npz"), **out)
+    print(f"c3 CG golden written in {time.time() - t0:.0f} s, status {res['status']}")
+
+
 def make_batch24():
     t0 = time.time()
     sl = synth.batched_slices(24)
@@ -219,7 +243,8 @@ def make_batch24():
     print(f"batch24 CG golden written in {time.time() - t0:.0f} s")
 
 
-TARGETS = {"c2": make_c2, "c2mask": make_c2mask, "c3s": make_c3s, "c3ehe": make_c3ehe, "batch24": make_batch24}
+TARGETS = {"c2": make_c2, "c2mask": make_c2mask, "c3s": make_c3s, "c3ehe": make_c3ehe, "c3cg": make_c3cg,
+           "batch24": make_batch24}
 
 
 def main():
