@@ -19,7 +19,7 @@ case's CG iterate (48x48x24, 8 coils, 4 x 8000 samples, 15 iterations;
 tests/golden/c3s_cg.npz), E^H E of the phantom at 1536 voxels of the full
 workload (tests/golden/c3_ehe_sampled.npz), and the third iterate of the
 full-size CG with the workload's unit coil noise as data, at every voxel
-(tests/golden/c3_cg.npz).
+(tests/golden/c3_cg_noise.npz).
 
 Roofline: the fused encode kernel (phase tile, sin/cos, complex contraction),
 its average launch duration from HIP events on its launch stream over an
@@ -300,7 +300,7 @@ def c3_oracle_checks(nfs, synth, torch, dev, prec, sv, reorth):
         ref = g[f"{kind}_rho"]
         out["c3s_cg"] = dict(workload="3D 48x48x24, 8 coils, 4 x 8000 samples, 16 terms, 15 iterations",
                              iterate=n, rel=rel(rho.cpu().numpy(), ref), max_rel=max_rel(rho.cpu().numpy(), ref))
-    g = golden("c3_cg.npz")
+    g = golden("c3_cg_noise.npz")
     if g is not None:
         # the full-size re-orthogonalised CG with the workload's unit coil
         # noise as data, at the last stored iterate, every voxel

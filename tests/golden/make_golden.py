@@ -40,7 +40,7 @@ E the oracle's.
           572000-sample workload, q = E^H E p for p = the phantom, at
           n_vox_sampled seeded voxels (vox [n], q [n] complex128); the full
           E p is formed, so this is one full-size E                 (~35 min)
-  c3cg    tests/golden/c3_cg.npz: the same workload's re-orthogonalised FP64
+  c3cg    tests/golden/c3_cg_noise.npz: the same workload's re-orthogonalised FP64
           CG on E^H E rho = E^H m with m = its unit coil noise, 3 iterations:
           it_<k> (iterate k at the seeded voxels vox), norms [k] (||rho_k||),
           rho (iterate 3, all voxels, complex64), hist          (~2-3 hours)
@@ -222,7 +222,7 @@ def make_c3cg():
                norms=np.array([np.linalg.norm(x) for x in res["iterates"]]))
     for k, x in enumerate(res["iterates"], 1):
         out[f"it_{k}"] = x[vox].astype(np.complex64)
-    np.savez_compressed(os.path.join(HERE, "c3_cg.npz"), **out)
+    np.savez_compressed(os.path.join(HERE, "c3_cg_noise.npz"), **out)
     print(f"c3 CG golden written in {time.time() - t0:.0f} s, status {res['status']}")
 
 

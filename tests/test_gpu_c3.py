@@ -9,7 +9,7 @@
   evaluated on those rows and voxels, E^H E p at 1536 sampled voxels against
   the stored oracle values (tests/golden/c3_ehe_sampled.npz: one full-size
   oracle E), the first three iterates of the full-size re-orthogonalised CG
-  against a stored FP64 oracle solve (tests/golden/c3_cg.npz: data = the
+  against a stored FP64 oracle solve (tests/golden/c3_cg_noise.npz: data = the
   workload's unit coil noise, so that no oracle E is needed for it), and
   the full 15-iteration solve through properties that hold at any size:
   its recursive residual and data-residual histories against explicit
@@ -171,7 +171,7 @@ def test_c3_EHE_sampled_vs_stored_oracle(nfs, c3, prec):
 def test_c3_cg_full_size_vs_stored_oracle(nfs, c3, prec):
     """The full-size re-orthogonalised CG on E^H E rho = E^H m with m the
     workload's unit coil noise, against the stored FP64 oracle solve
-    (tests/golden/c3_cg.npz): every stored iterate at its 4096 seeded
+    (tests/golden/c3_cg_noise.npz): every stored iterate at its 4096 seeded
     voxels, the last one at every voxel, the iterate norms and the residual
     history.  FP32 and FP16 are held to both parity measures at the bar.
     BF16 is held to the bar in relative L2 (the bar stated for that form)
@@ -182,7 +182,7 @@ def test_c3_cg_full_size_vs_stored_oracle(nfs, c3, prec):
     (1.6e-3 and 2.1e-3 at iterate 3 at the stored voxels), with no room left
     below the bar; a localised fault would show as orders of magnitude
     more."""
-    g = np.load(os.path.join(GOLDEN, "c3_cg.npz"))
+    g = np.load(os.path.join(GOLDEN, "c3_cg_noise.npz"))
     n = int(g["n_iter"])
     vox = g["vox"]
     _, hist, info, its = nfs.cg_solve_traced(c3["gp"], torch.from_numpy(c3["noise"]), n, precision=prec,
