@@ -241,8 +241,8 @@ def roofline(kt, L, K, G, P, prec, counters_md):
     launch's work is the larger: the matrix cores for the MFMA instructions
     the kernel issues, at the dense f16 peak, or the transcendental unit for
     its 2 sin/cos per pair (the matrix cores at 32 coils, where a 16 x 16
-    tile takes six matrix-core instructions; the transcendentals at 16
-    coils, four).  For "mfma", achieved = the algorithmic contraction and
+    tile takes six matrix-core instructions; at 16 coils, four, the two
+    times are within 1 % and the matrix cores' is the larger).  For "mfma", achieved = the algorithmic contraction and
     phase flops (8 G + 2 (P + 1) per pair) over the launch's mean duration
     against the 2.5 PFLOP/s dense peak; for "alu", the 2 sin/cos per pair
     against the transcendental peak.  Both pipes' fractions are reported."""
