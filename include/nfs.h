@@ -323,9 +323,11 @@ int nfs_phase_shift(nfs_ctx* ctx, const float* m, float* out, int n_coil, int64_
  * nfs_cg_solve); hist, info: host arrays of device pointers, or NULL (and
  * individual entries may be NULL).  The workspace (256-byte aligned, at
  * least nfs_workspace_bytes_batched bytes) is split into one CG workspace
- * per slice (each nfs_workspace_bytes of that slice, rounded up to 256) and
- * a 1 KiB block of work-list counters for the persistent form; 0 bytes for
- * n_slices 0, which returns NFS_OK without work.                          */
+ * per slice (each nfs_workspace_bytes of that slice, rounded up to 256), a
+ * 1 KiB block of work-list counters for the persistent form and that
+ * form's per-slice launch arguments (192 * n_slices bytes, then twice
+ * 128 * n_slices bytes, each rounded up to 256); 0 bytes for n_slices 0,
+ * which returns NFS_OK without work.                                      */
 int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
                                 int n_iter, int reorth, size_t* bytes);
 int nfs_cg_solve_batched(nfs_ctx* ctx, int n_slices, const nfs_problem* probs, const float* const* m,
@@ -354,10 +356,13 @@ int nfs_set_graphs(nfs_ctx* ctx, int on);
  *      persistent launch per shape class (column blocks, held tiles),
  *      whose fixed grid walks a work list of all its slices' tile blocks
  *      (slices of different L and K in the same launch; the classes run
- *      side by side on the library streams); the per-slice packing and CG
- *      vector kernels between them are forked over the streams.  Used when
- *      every slice has FP16 or BF16 operands, at most 20 field terms and
- *      at most 32 coils; otherwise the call runs as NFS_BATCH_STREAMS.
+ *      side by side on the library streams); between them the operand
+ *      packing and each CG vector step of all slices are one batched launch
+ *      (each slice's workgroups and arithmetic as in its own solve; the
+ *      setup and residual replacements fork per-slice kernels over the
+ *      streams instead).  Used when every slice has FP16 or BF16 operands,
+ *      at most 20 field terms and at most 32 coils; otherwise the call runs
+ *      as NFS_BATCH_STREAMS.
  * Either way each slice's result is bit-identical to its nfs_cg_solve.     */
 enum nfs_batch_mode { NFS_BATCH_STREAMS = 0, NFS_BATCH_PERSISTENT = 1 };
 int nfs_set_batch_mode(nfs_ctx* ctx, int mode);

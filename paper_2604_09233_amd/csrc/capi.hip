@@ -1407,6 +1407,9 @@ static std::vector<std::vector<int>> assign_lanes(int n_slices, const nfs_proble
 // Slices' layouts one after another, then kBatchCounters work-list counters
 // of the persistent launches (the last offset in offs).
 constexpr int kBatchCounters = 256;
+// and the per-slice arguments of the lock-step form's batched vector and
+// packing launches (CgSlice[n], then two PackSlice[n])
+static size_t slice_args_bytes(int n) { return al(n * sizeof(CgSlice)) + 2 * al(n * sizeof(PackSlice)); }
 static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs, int precision, int n_iter, int reorth,
                             std::vector<Layout>* ys, std::vector<size_t>* offs) {
   size_t tot = 0;
@@ -1417,7 +1420,7 @@ static size_t batch_layouts(const nfs_ctx* ctx, int n, const nfs_problem* probs,
     if (ys) ys->push_back(y);
   }
   if (offs) offs->push_back(tot);
-  return n ? tot + al(kBatchCounters * sizeof(int)) : 0;
+  return n ? tot + al(kBatchCounters * sizeof(int)) + slice_args_bytes(n) : 0;
 }
 
 extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, const nfs_problem* probs, int precision,
@@ -1438,8 +1441,10 @@ extern "C" int nfs_workspace_bytes_batched(const nfs_ctx* ctx, int n_slices, con
 // ---------------------------------------------------------------------------
 // Lock-step batched CG: every slice runs the nfs_cg_solve sequence, but the
 // E and E^H contractions of all slices go into one persistent encode launch
-// each (launch_encode_persistent), between which the per-slice packing and
-// CG vector kernels are forked over the library streams and joined.
+// each (launch_encode_persistent), and between them the operand packing and
+// the CG vector steps of all slices are one batched launch per step (the
+// setup and the residual replacements fork per-slice kernels over the
+// library streams instead).
 struct SliceRun {
   const nfs_problem* pr;
   const Layout* y;
@@ -1612,10 +1617,67 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
     return Ctx{ctx, *r.y, r.pr, r.sens, r.ws, sk, r.st.stop};
   };
   auto hs = [](const SliceRun& r) { return r.y->LC * 16; };
+  // the batched launches' per-slice arguments (the single-slice launches'
+  // arguments of pre_E for the direction, mid_EHE, cg_beta ... cg_direction)
+  char* argbase = static_cast<char*>(ws) + offs[n] + al(kBatchCounters * sizeof(int));
+  CgSlice* d_cg = reinterpret_cast<CgSlice*>(argbase);
+  PackSlice* d_pe = reinterpret_cast<PackSlice*>(argbase + al(n * sizeof(CgSlice)));
+  PackSlice* d_ph = reinterpret_cast<PackSlice*>(argbase + al(n * sizeof(CgSlice)) + al(n * sizeof(PackSlice)));
+  std::vector<CgSlice> h_cg(n);
+  std::vector<PackSlice> h_pe(n), h_ph(n);
+  int max_nblk = 1;
+  int64_t max_pe = 0, max_ph = 0;
+  for (int i = 0; i < n; ++i) {
+    const SliceRun& r = runs[i];
+    const Layout& y = *r.y;
+    float* us = scaled_prec(y.prec) ? at<float>(r.ws, y.o_unscale) : nullptr;
+    CgSlice& cg = h_cg[i];
+    cg = CgSlice{};
+    cg.st = r.st;
+    cg.hpart = at<float2>(r.ws, y.o_hpart);
+    cg.unscale = us ? us + 1 : nullptr;
+    cg.rho = r.x;
+    cg.stride = hs(r);
+    cg.nsplit = y.shH.nsplit;
+    max_nblk = std::max(max_nblk, r.st.nblk);
+    PackSlice& pe = h_pe[i];  // pre_E of the direction (bound already formed by the CG step)
+    pe = PackSlice{};
+    pe.src = r.st.p;
+    pe.mul = r.sens;
+    pe.out = at<void>(r.ws, y.o_dataE);
+    pe.bmax = at<float>(r.ws, y.o_bmax);
+    pe.unscale = at<float>(r.ws, y.o_unscale);
+    pe.stop = r.st.stop;
+    pe.n_items = y.L;
+    pe.is = 1;
+    pe.cs = 0;
+    pe.nchunks = y.LC;
+    pe.G = y.G;
+    pe.NB = y.NB;
+    max_pe = std::max(max_pe, cdiv(y.LC * y.NB * 64, 256));
+    PackSlice& ph = h_ph[i];  // mid_EHE
+    ph = PackSlice{};
+    ph.src = at<float>(r.ws, y.o_epart);
+    ph.out = at<void>(r.ws, y.o_dataH);
+    ph.unscale_in = at<float>(r.ws, y.o_unscale);
+    ph.unscale = at<float>(r.ws, y.o_unscale) + 1;
+    ph.stop = r.st.stop;
+    ph.n_items = y.K;
+    ph.nchunks = y.KC;
+    ph.HC16 = y.KC * 16;
+    ph.scale = epart_pack_scale(y.prec, y.L);
+    ph.wmul = 1.f;
+    ph.G = y.G;
+    ph.NB = y.NB;
+    ph.nsplit = y.shE.nsplit;
+    max_ph = std::max(max_ph, cdiv(y.KC * y.NB * 64, 256));
+  }
   int rc;
   // setup and the E^H packing of the data
   rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
     const Layout& y = *r.y;
+    const int i = (int)(&r - runs.data());
+    NFS_TRY(launch_store_slice_args(h_cg[i], h_pe[i], h_ph[i], d_cg + i, d_pe + i, d_ph + i, sk), "store_slice_args");
     if (r.pr->icorr)
       NFS_TRY(launch_scale_sens(reinterpret_cast<const float2*>(r.pr->sens), r.pr->icorr, y.G, y.L,
                                 const_cast<float2*>(r.sens), sk),
@@ -1648,11 +1710,11 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
   });
   if (rc) return rc;
   // E (operand already packed), E^H packing, E^H
+  const int prec = ys[0].prec;
   auto ehe_rest = [&]() -> int {
     int e = persistent_encode(ctx, runs, OP_E, counters, s);
     if (e) return e;
-    e = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int { return mid_EHE(ctx_of(r, sk)); });
-    if (e) return e;
+    NFS_TRY(launch_pack_EH_from_epart_batched(prec, d_ph, n, max_ph, s), "pack_EH_from_epart(batched)");
     return persistent_encode(ctx, runs, OP_EH, counters, s);
   };
   for (int it = 0; it < n_iter; ++it) {
@@ -1674,11 +1736,11 @@ static int run_cg_lockstep(nfs_ctx* ctx, int n, const nfs_problem* probs, const 
       return more ? pre_E_dir(r, sk) : NFS_OK;
     };
     if (!replace) {
-      rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {
-        const int e = beta_update(r, sk);
-        return e ? e : finish_iteration(r, sk);
-      });
-      if (rc) return rc;
+      NFS_TRY(launch_cg_beta_batched(d_cg, n, max_nblk, s), "cg_beta(batched)");
+      NFS_TRY(launch_cg_update_batched(d_cg, n, max_nblk, it, nv, s), "cg_update(batched)");
+      if (reorth) NFS_TRY(launch_cg_reorth_apply_batched(d_cg, n, max_nblk, nv, true, s), "cg_reorth_apply(batched)");
+      NFS_TRY(launch_cg_direction_batched(d_cg, n, max_nblk, it, n_iter, tol, s), "cg_direction(batched)");
+      if (more) NFS_TRY(launch_pack_data_E_batched(prec, d_pe, n, max_pe, s), "pack_data(E, batched)");
       continue;
     }
     rc = fork_join(ctx, lanes, runs, s, [&](SliceRun& r, hipStream_t sk) -> int {

@@ -18,6 +18,17 @@ namespace nfs {
 
 enum { CG_MAXITER = 1, CG_TOL = 2, CG_EXACT = 3, CG_BREAKDOWN = 4 };
 
+// A workgroup's place in the grid of one solve's vector kernel: column x,
+// row y, and the grid's width nx (the solve's nblk).  A single-solve launch
+// takes its own blockIdx and gridDim; a batched launch takes the slice from
+// blockIdx.z and runs, for each slice, exactly the workgroups of that
+// slice's own single-solve grid, so every slice's arithmetic and every
+// fixed-order sum is that of its single solve.
+struct Blk {
+  int x, y, nx;
+};
+__device__ __forceinline__ Blk own_blk() { return Blk{(int)blockIdx.x, (int)blockIdx.y, (int)gridDim.x}; }
+
 // Sum of v over the workgroup (256 threads), fixed order; result in all threads.
 __device__ double block_sum(double v, double* red) {
   red[threadIdx.x] = v;
@@ -38,19 +49,20 @@ __device__ double sum_partials(const double* part, int nblk, double* red) {
 
 // Bound on the FP16 E operand entries S[c][l] p[l] of the new direction:
 // workgroup maximum of smax[l] |p[l]| (smax[l] = max_c |S[c][l]|) into
-// bmax[blockIdx.x], the entries past the CG grid cleared by workgroup 0, so
+// bmax[bx] (bx: the workgroup's column), the entries past the CG grid
+// cleared by workgroup 0, so
 // that the E operand packing (which reads all kBmaxBlocks entries) needs no
 // pass of its own.  The bound is at most sqrt(2) above the largest |re| or
 // |im|, which only moves the power-of-two scale.
-__device__ void direction_bound(const CgState& st, float mx, float* redf) {
+__device__ void direction_bound(const CgState& st, float mx, float* redf, int bx) {
   redf[threadIdx.x] = mx;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if ((int)threadIdx.x < w) redf[threadIdx.x] = fmaxf(redf[threadIdx.x], redf[threadIdx.x + w]);
     __syncthreads();
   }
-  if (threadIdx.x == 0) st.bmax[blockIdx.x] = redf[0];
-  if (blockIdx.x == 0)
+  if (threadIdx.x == 0) st.bmax[bx] = redf[0];
+  if (bx == 0)
     for (int i = st.nblk + threadIdx.x; i < kBmaxBlocks; i += 256) st.bmax[i] = 0.f;
 }
 
@@ -110,7 +122,7 @@ __global__ __launch_bounds__(256) void cg_init_kernel(CgState st, const float2* 
   }
   a = block_sum(a, red);
   if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
-  if (st.smax) direction_bound(st, mx, redf);
+  if (st.smax) direction_bound(st, mx, redf, blockIdx.x);
 }
 
 // alpha_0, ||m||^2, hist row 0, early exit when E^H m == 0
@@ -136,35 +148,40 @@ __global__ __launch_bounds__(256) void cg_start_kernel(CgState st, int nblk_m, i
 }
 
 // q = E^H E p (sum of split partials), partial Re p^H q -> part[0]
-__global__ __launch_bounds__(256) void cg_beta_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
-                                                      int64_t stride, const float* __restrict__ unscale,
-                                                      int64_t L) {
+__device__ __forceinline__ void cg_beta_body(const CgState& st, const float2* __restrict__ hpart, int nsplit,
+                                             int64_t stride, const float* __restrict__ unscale, int64_t L, Blk b) {
   if (*st.stop) return;
   __shared__ double red[256];
   const float u = unscale ? *unscale : 1.f;
   double a = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+  for (int64_t l = (int64_t)b.x * 256 + threadIdx.x; l < L; l += (int64_t)b.nx * 256) {
     const float2 q = sum_splits(hpart, nsplit, stride, l, u);
     const float2 p = st.p[l];
     st.q[l] = q;
     a += (double)p.x * q.x + (double)p.y * q.y;
   }
   a = block_sum(a, red);
-  if (threadIdx.x == 0) st.part[blockIdx.x] = a;
+  if (threadIdx.x == 0) st.part[b.x] = a;
 }
 
-// Partial sums, over the elements of workgroup column blockIdx.x, of
+__global__ __launch_bounds__(256) void cg_beta_kernel(CgState st, const float2* __restrict__ hpart, int nsplit,
+                                                      int64_t stride, const float* __restrict__ unscale,
+                                                      int64_t L) {
+  cg_beta_body(st, hpart, nsplit, stride, unscale, L, own_blk());
+}
+
+// Partial sums, over the elements of workgroup column b.x, of
 // conj(v_j) r for the stored residuals v_j, j in [j0, j1) (re-orthogonal-
 // isation), into rpart.  r[l] is given by rfun(l).  Wave w takes j = j0 + w,
 // j0 + w + 4, ...: each lane accumulates in float64 over its elements (in
 // element order) and the wave reduces with a fixed xor-shuffle tree.
 template <class RF>
-__device__ void reorth_dots(const CgState& st, int j0, int j1, RF&& rfun) {
+__device__ void reorth_dots(const CgState& st, int j0, int j1, Blk b, RF&& rfun) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   for (int j = j0 + wave; j < j1; j += kWaves) {
     const float2* v = st.V + (size_t)j * st.L;
     double re = 0.0, im = 0.0;
-    for (int64_t base = (int64_t)blockIdx.x * 256; base < st.L; base += (int64_t)gridDim.x * 256)
+    for (int64_t base = (int64_t)b.x * 256; base < st.L; base += (int64_t)b.nx * 256)
       for (int k = lane; k < 256; k += 64) {
         const int64_t l = base + k;
         if (l >= st.L) break;
@@ -177,8 +194,8 @@ __device__ void reorth_dots(const CgState& st, int j0, int j1, RF&& rfun) {
       im += __shfl_xor(im, off);
     }
     if (lane == 0) {
-      st.rpart[(2 * (size_t)j) * kCgBlocks + blockIdx.x] = re;
-      st.rpart[(2 * (size_t)j + 1) * kCgBlocks + blockIdx.x] = im;
+      st.rpart[(2 * (size_t)j) * kCgBlocks + b.x] = re;
+      st.rpart[(2 * (size_t)j + 1) * kCgBlocks + b.x] = im;
     }
   }
 }
@@ -190,14 +207,14 @@ __device__ void reorth_dots(const CgState& st, int j0, int j1, RF&& rfun) {
 // nv > 0 every workgroup (x, y) also forms the partial dot products of the
 // new r with v_j, j in [4y, 4y + 4), recomputing the new r of its elements
 // from the unmodified r and q with the same arithmetic.
-__global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __restrict__ rho, int64_t L, int n,
-                                                        int nv) {
+__device__ __forceinline__ void cg_update_body(const CgState& st, float2* __restrict__ rho, int64_t L, int n, int nv,
+                                               Blk b) {
   if (*st.stop) return;
   __shared__ double red[256];
   const double beta = sum_partials(st.part, st.nblk, red);
   const double alpha = st.alpha[n];
   if (!(beta > 0.0) || !isfinite(beta)) {
-    if (blockIdx.x == 0 && blockIdx.y == 0 && threadIdx.x == 0) {
+    if (b.x == 0 && b.y == 0 && threadIdx.x == 0) {
       st.info[1] = CG_BREAKDOWN;
       *st.stop = 1;
     }
@@ -205,10 +222,10 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
   }
   const double gamma = alpha / beta;
   const float gf = (float)gamma;
-  if (blockIdx.y == 0) {
+  if (b.y == 0) {
     float2* rout = nv > 0 ? st.rn : st.r;
     double a = 0.0, xx = 0.0;
-    for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+    for (int64_t l = (int64_t)b.x * 256 + threadIdx.x; l < L; l += (int64_t)b.nx * 256) {
       const float2 p = st.p[l], q = st.q[l];
       float2 x = rho[l], r = st.r[l];
       x.x = fmaf(gf, p.x, x.x);
@@ -227,14 +244,14 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
     a = block_sum(a, red);
     xx = block_sum(xx, red);
     if (threadIdx.x == 0) {
-      st.part[kCgBlocks + blockIdx.x] = a;
-      st.part[2 * kCgBlocks + blockIdx.x] = xx;
-      if (blockIdx.x == 0) st.scal[0] = beta;
+      st.part[kCgBlocks + b.x] = a;
+      st.part[2 * kCgBlocks + b.x] = xx;
+      if (b.x == 0) st.scal[0] = beta;
     }
   }
   if (nv > 0) {
-    const int j0 = 4 * blockIdx.y, j1 = j0 + 4 < nv ? j0 + 4 : nv;
-    reorth_dots(st, j0, j1, [&](int64_t l) {
+    const int j0 = 4 * b.y, j1 = j0 + 4 < nv ? j0 + 4 : nv;
+    reorth_dots(st, j0, j1, b, [&](int64_t l) {
       const float2 q = st.q[l];
       float2 r = st.r[l];
       r.x = fmaf(-gf, q.x, r.x);
@@ -242,6 +259,11 @@ __global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __re
       return r;
     });
   }
+}
+
+__global__ __launch_bounds__(256) void cg_update_kernel(CgState st, float2* __restrict__ rho, int64_t L, int n,
+                                                        int nv) {
+  cg_update_body(st, rho, L, n, nv, own_blk());
 }
 
 // residual replacement: r = b - (E^H E rho); partial r^H r -> part[1]
@@ -264,7 +286,7 @@ __global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float
   if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
   if (nv > 0) {
     __syncthreads();  // this workgroup's r writes are visible to all its waves
-    reorth_dots(st, 0, nv, [&](int64_t l) { return st.r[l]; });
+    reorth_dots(st, 0, nv, own_blk(), [&](int64_t l) { return st.r[l]; });
   }
 }
 
@@ -274,7 +296,7 @@ __global__ __launch_bounds__(256) void cg_replace_kernel(CgState st, const float
 // takes the stop decision.  It raises the stop flag itself: a workgroup of
 // this launch that starts after that skips its share of the p and V
 // updates, which is harmless because neither is read once the loop stops.
-__global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L, int n, int n_iter, double tol) {
+__device__ __forceinline__ void cg_direction_body(const CgState& st, int64_t L, int n, int n_iter, double tol, Blk b) {
   if (*st.stop) return;
   __shared__ double red[256];
   const double anew = sum_partials(st.part + kCgBlocks, st.nblk, red);
@@ -284,7 +306,7 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L
   const float inv = store ? (float)(1.0 / sqrt(anew)) : 0.f;
   float2* v = store ? st.V + (size_t)(n + 1) * L : nullptr;
   float mx = 0.f;
-  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < L; l += (int64_t)gridDim.x * 256) {
+  for (int64_t l = (int64_t)b.x * 256 + threadIdx.x; l < L; l += (int64_t)b.nx * 256) {
     const float2 r = st.r[l];
     float2 p = st.p[l];
     p.x = fmaf(bf, p.x, r.x);
@@ -295,9 +317,9 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L
   }
   if (st.smax) {
     __shared__ float redf[256];
-    direction_bound(st, mx, redf);
+    direction_bound(st, mx, redf, b.x);
   }
-  if (blockIdx.x != 0) return;
+  if (b.x != 0) return;
   const double xx = sum_partials(st.part + 2 * kCgBlocks, st.nblk, red);
   if (threadIdx.x != 0) return;
   const double beta = st.scal[0];
@@ -320,6 +342,10 @@ __global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L
   }
 }
 
+__global__ __launch_bounds__(256) void cg_direction_kernel(CgState st, int64_t L, int n, int n_iter, double tol) {
+  cg_direction_body(st, L, n, n_iter, tol, own_blk());
+}
+
 // ---------------------------------------------------------------------------
 // Re-orthogonalisation of the residual against the stored normalised
 // residuals v_j (classical Gram-Schmidt with float64 dot products).
@@ -340,7 +366,7 @@ __global__ __launch_bounds__(256) void cg_store_v_kernel(CgState st, int j) {
 // partials of each v_j^H src itself (thread i takes sum i, partials in
 // workgroup order), so all workgroups use bit-identical coefficients;
 // partial r^H r -> part[1].
-__global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv, int from_rn) {
+__device__ __forceinline__ void cg_reorth_apply_body(const CgState& st, int nv, int from_rn, Blk b) {
   if (*st.stop) return;
   __shared__ double red[256];
   __shared__ double coef[2 * (kMaxReorth + 1)];
@@ -361,7 +387,7 @@ __global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv
   }
   __syncthreads();
   double a = 0.0;
-  for (int64_t l = (int64_t)blockIdx.x * 256 + threadIdx.x; l < st.L; l += (int64_t)gridDim.x * 256) {
+  for (int64_t l = (int64_t)b.x * 256 + threadIdx.x; l < st.L; l += (int64_t)b.nx * 256) {
     float2 r = from_rn ? st.rn[l] : st.r[l];
     for (int j0 = 0; j0 < nv; j0 += 4) {
       float2 v[4];
@@ -379,7 +405,55 @@ __global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv
     a += (double)r.x * r.x + (double)r.y * r.y;
   }
   a = block_sum(a, red);
-  if (threadIdx.x == 0) st.part[kCgBlocks + blockIdx.x] = a;
+  if (threadIdx.x == 0) st.part[kCgBlocks + b.x] = a;
+}
+
+__global__ __launch_bounds__(256) void cg_reorth_apply_kernel(CgState st, int nv, int from_rn) {
+  cg_reorth_apply_body(st, nv, from_rn, own_blk());
+}
+
+// ---------------------------------------------------------------------------
+// Batched forms for the lock-step batched solve: one launch runs a step for
+// every slice.  Grid (max nblk, rows, slices); the slice's arguments are
+// read from the device array sl (written once per solve), and the
+// workgroups past the slice's own nblk return at once.
+__device__ __forceinline__ bool slice_blk(const CgSlice* __restrict__ sl, CgSlice& a, Blk& b) {
+  a = sl[blockIdx.z];
+  b = Blk{(int)blockIdx.x, (int)blockIdx.y, a.st.nblk};
+  return b.x < b.nx;
+}
+
+__global__ __launch_bounds__(256) void cg_beta_batched_kernel(const CgSlice* __restrict__ sl) {
+  CgSlice a;
+  Blk b;
+  if (slice_blk(sl, a, b)) cg_beta_body(a.st, a.hpart, a.nsplit, a.stride, a.unscale, a.st.L, b);
+}
+
+__global__ __launch_bounds__(256) void cg_update_batched_kernel(const CgSlice* __restrict__ sl, int n, int nv) {
+  CgSlice a;
+  Blk b;
+  if (slice_blk(sl, a, b)) cg_update_body(a.st, a.rho, a.st.L, n, nv, b);
+}
+
+__global__ __launch_bounds__(256) void cg_reorth_apply_batched_kernel(const CgSlice* __restrict__ sl, int nv,
+                                                                      int from_rn) {
+  CgSlice a;
+  Blk b;
+  if (slice_blk(sl, a, b)) cg_reorth_apply_body(a.st, nv, from_rn, b);
+}
+
+__global__ __launch_bounds__(256) void cg_direction_batched_kernel(const CgSlice* __restrict__ sl, int n, int n_iter,
+                                                                   double tol) {
+  CgSlice a;
+  Blk b;
+  if (slice_blk(sl, a, b)) cg_direction_body(a.st, a.st.L, n, n_iter, tol, b);
+}
+
+__global__ void store_slice_args_kernel(CgSlice cg, PackSlice pe, PackSlice ph, CgSlice* cg_out, PackSlice* pe_out,
+                                        PackSlice* ph_out) {
+  *cg_out = cg;
+  *pe_out = pe;
+  *ph_out = ph;
 }
 
 __global__ void cg_finish_kernel(float2* __restrict__ rho, const float* __restrict__ icorr, int64_t L) {
@@ -450,6 +524,39 @@ hipError_t launch_cg_store_v(const CgState& st, int j, hipStream_t s) {
 
 hipError_t launch_cg_reorth_apply(const CgState& st, int nv, bool from_rn, hipStream_t s) {
   hipLaunchKernelGGL(cg_reorth_apply_kernel, dim3(st.nblk), dim3(256), 0, s, st, nv, (int)from_rn);
+  return hipGetLastError();
+}
+
+hipError_t launch_store_slice_args(const CgSlice& cg, const PackSlice& pe, const PackSlice& ph, CgSlice* cg_out,
+                                   PackSlice* pe_out, PackSlice* ph_out, hipStream_t s) {
+  hipLaunchKernelGGL(store_slice_args_kernel, dim3(1), dim3(1), 0, s, cg, pe, ph, cg_out, pe_out, ph_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_beta_batched(const CgSlice* sl, int n, int max_nblk, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cg_beta_batched_kernel, dim3(max_nblk, 1, n), dim3(256), 0, s, sl);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_update_batched(const CgSlice* sl, int n, int max_nblk, int it, int nv, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const unsigned ny = nv > 0 ? (unsigned)cdiv(nv, 4) : 1u;
+  hipLaunchKernelGGL(cg_update_batched_kernel, dim3(max_nblk, ny, n), dim3(256), 0, s, sl, it, nv);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_reorth_apply_batched(const CgSlice* sl, int n, int max_nblk, int nv, bool from_rn,
+                                          hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cg_reorth_apply_batched_kernel, dim3(max_nblk, 1, n), dim3(256), 0, s, sl, nv, (int)from_rn);
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_direction_batched(const CgSlice* sl, int n, int max_nblk, int it, int n_iter, double tol,
+                                       hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(cg_direction_batched_kernel, dim3(max_nblk, 1, n), dim3(256), 0, s, sl, it, n_iter, tol);
   return hipGetLastError();
 }
 

@@ -231,11 +231,13 @@ __device__ __forceinline__ void store_fragment(const float (&vals)[8], void* __r
 // magnitude lands just below 2^14; 1/scale is stored in *unscale.
 // An optional real per-item weight wgt multiplies every value (used by the
 // backward pass: t o G for the B0 gradient, h_b o rho for the field terms).
+// bx: the workgroup's index in the single-slice grid (its blockIdx.x).
 template <int PREC, int OP>
-__global__ __launch_bounds__(256) void pack_data_kernel(
-    const float2* __restrict__ src, const float2* __restrict__ mul, const float* __restrict__ wgt, int64_t n_items,
-    int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* __restrict__ out, const float* __restrict__ bmax,
-    float* __restrict__ unscale, const int* stop) {
+__device__ __forceinline__ void pack_data_body(const float2* __restrict__ src, const float2* __restrict__ mul,
+                                               const float* __restrict__ wgt, int64_t n_items, int64_t is, int64_t cs,
+                                               int G, int NB, int64_t nchunks, void* __restrict__ out,
+                                               const float* __restrict__ bmax, float* __restrict__ unscale,
+                                               const int* stop, int64_t bx) {
   if (stop && *stop) return;
   float scale = 1.f;
   if (PREC != PREC_BF16) {
@@ -254,9 +256,9 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
       sh = sh > 100 ? 100 : (sh < -100 ? -100 : sh);
       scale = ldexpf(1.f, sh);
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) *unscale = 1.f / scale;
+    if (bx == 0 && threadIdx.x == 0) *unscale = 1.f / scale;
   }
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  const int64_t i = bx * 256 + threadIdx.x;
   if (i >= nchunks * NB * 64) return;
   const int lane = (int)(i & 63);
   const int64_t q = i >> 6;
@@ -291,6 +293,24 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
   store_fragment<PREC>(vals, out, ch, nb, NB, lane);
 }
 
+template <int PREC, int OP>
+__global__ __launch_bounds__(256) void pack_data_kernel(
+    const float2* __restrict__ src, const float2* __restrict__ mul, const float* __restrict__ wgt, int64_t n_items,
+    int64_t is, int64_t cs, int G, int NB, int64_t nchunks, void* __restrict__ out, const float* __restrict__ bmax,
+    float* __restrict__ unscale, const int* stop) {
+  pack_data_body<PREC, OP>(src, mul, wgt, n_items, is, cs, G, NB, nchunks, out, bmax, unscale, stop, blockIdx.x);
+}
+
+// The E-operand packing of the lock-step batched solve: slice blockIdx.y of
+// sl, workgroups past that slice's own grid return at once.
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_data_E_batched_kernel(const PackSlice* __restrict__ sl) {
+  const PackSlice a = sl[blockIdx.y];
+  if ((int64_t)blockIdx.x * 256 >= a.nchunks * a.NB * 64) return;
+  pack_data_body<PREC, OP_E>((const float2*)a.src, a.mul, a.wgt, a.n_items, a.is, a.cs, a.G, a.NB, a.nchunks, a.out,
+                             a.bmax, a.unscale, a.stop, blockIdx.x);
+}
+
 // E^H data operand straight from the E partials (the E^H E chain): the
 // streamed items are the samples, with value(k, c) = sum over splits, in
 // split order, of epart[s][k][2c] + i epart[s][k][2c + 1], times `scale`.
@@ -303,15 +323,15 @@ __global__ __launch_bounds__(256) void pack_data_kernel(
 // An optional real weight per sample, times wmul, multiplies the E output
 // first (|weight * wmul| <= 1 keeps the scale bound).
 template <int PREC>
-__global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __restrict__ epart, int nsplit,
-                                                                 int64_t HC16, int NB, int64_t K, int G, float scale,
-                                                                 const float* __restrict__ wgt, float wmul,
-                                                                 const float* __restrict__ unscale_in,
-                                                                 float* __restrict__ unscale_out, int64_t nchunks,
-                                                                 void* __restrict__ out, const int* stop) {
+__device__ __forceinline__ void pack_EH_from_epart_body(const float* __restrict__ epart, int nsplit, int64_t HC16,
+                                                        int NB, int64_t K, int G, float scale,
+                                                        const float* __restrict__ wgt, float wmul,
+                                                        const float* __restrict__ unscale_in,
+                                                        float* __restrict__ unscale_out, int64_t nchunks,
+                                                        void* __restrict__ out, const int* stop, int64_t bx) {
   if (stop && *stop) return;
-  if (PREC != PREC_BF16 && blockIdx.x == 0 && threadIdx.x == 0) *unscale_out = *unscale_in / scale;
-  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (PREC != PREC_BF16 && bx == 0 && threadIdx.x == 0) *unscale_out = *unscale_in / scale;
+  const int64_t i = bx * 256 + threadIdx.x;
   if (i >= nchunks * NB * 64) return;
   const int lane = (int)(i & 63);
   const int64_t q = i >> 6;
@@ -363,6 +383,27 @@ __global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __
     vals[2 * j + 1] = reim ? -v[j].x : v[j].y;
   }
   store_fragment<PREC>(vals, out, ch, nb, NB, lane);
+}
+
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_EH_from_epart_kernel(const float* __restrict__ epart, int nsplit,
+                                                                 int64_t HC16, int NB, int64_t K, int G, float scale,
+                                                                 const float* __restrict__ wgt, float wmul,
+                                                                 const float* __restrict__ unscale_in,
+                                                                 float* __restrict__ unscale_out, int64_t nchunks,
+                                                                 void* __restrict__ out, const int* stop) {
+  pack_EH_from_epart_body<PREC>(epart, nsplit, HC16, NB, K, G, scale, wgt, wmul, unscale_in, unscale_out, nchunks,
+                                out, stop, blockIdx.x);
+}
+
+// The E^H-operand packing of E^H E in the lock-step batched solve (slice
+// blockIdx.y of sl, as pack_data_E_batched_kernel).
+template <int PREC>
+__global__ __launch_bounds__(256) void pack_EH_from_epart_batched_kernel(const PackSlice* __restrict__ sl) {
+  const PackSlice a = sl[blockIdx.y];
+  if ((int64_t)blockIdx.x * 256 >= a.nchunks * a.NB * 64) return;
+  pack_EH_from_epart_body<PREC>((const float*)a.src, a.nsplit, a.HC16, a.NB, a.n_items, a.G, a.scale, a.wgt, a.wmul,
+                                a.unscale_in, a.unscale, a.nchunks, a.out, a.stop, blockIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -1139,14 +1180,18 @@ hipError_t launch_finish_E_to_m(const float* epart, int nsplit, int64_t HC16, in
   return hipGetLastError();
 }
 
+float epart_pack_scale(int prec, int64_t L) {
+  int lg = 0;
+  while (((int64_t)1 << lg) < L) ++lg;
+  return prec != PREC_BF16 ? ldexpf(1.f, -(lg + 1)) : 1.f;
+}
+
 hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, int64_t HC16, int NB, int64_t K, int G,
                                      int64_t L, const float* wgt, float wmul, const float* unscale_in,
                                      float* unscale_out, int64_t nchunks, void* out, const int* stop, hipStream_t s) {
   const int64_t total = nchunks * NB * 64;
   if (total == 0) return hipSuccess;
-  int lg = 0;
-  while (((int64_t)1 << lg) < L) ++lg;
-  const float scale = prec != PREC_BF16 ? ldexpf(1.f, -(lg + 1)) : 1.f;
+  const float scale = epart_pack_scale(prec, L);
   const dim3 gr = grid1(total), bl(256);
 #define NFS_PACKH(P_)                                                                                           \
   hipLaunchKernelGGL(pack_EH_from_epart_kernel<P_>, gr, bl, 0, s, epart, nsplit, HC16, NB, K, G, scale, wgt, wmul, \
@@ -1155,6 +1200,25 @@ hipError_t launch_pack_EH_from_epart(int prec, const float* epart, int nsplit, i
   else if (prec == PREC_BF16) NFS_PACKH(PREC_BF16);
   else NFS_PACKH(PREC_FP16);
 #undef NFS_PACKH
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_EH_from_epart_batched(int prec, const PackSlice* sl, int n, int64_t max_blocks,
+                                             hipStream_t s) {
+  if (n == 0 || max_blocks == 0) return hipSuccess;
+  const dim3 gr((unsigned)max_blocks, (unsigned)n), bl(256);
+  if (prec == PREC_FP32) hipLaunchKernelGGL(pack_EH_from_epart_batched_kernel<PREC_FP32>, gr, bl, 0, s, sl);
+  else if (prec == PREC_BF16) hipLaunchKernelGGL(pack_EH_from_epart_batched_kernel<PREC_BF16>, gr, bl, 0, s, sl);
+  else hipLaunchKernelGGL(pack_EH_from_epart_batched_kernel<PREC_FP16>, gr, bl, 0, s, sl);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_data_E_batched(int prec, const PackSlice* sl, int n, int64_t max_blocks, hipStream_t s) {
+  if (n == 0 || max_blocks == 0) return hipSuccess;
+  const dim3 gr((unsigned)max_blocks, (unsigned)n), bl(256);
+  if (prec == PREC_FP32) hipLaunchKernelGGL(pack_data_E_batched_kernel<PREC_FP32>, gr, bl, 0, s, sl);
+  else if (prec == PREC_BF16) hipLaunchKernelGGL(pack_data_E_batched_kernel<PREC_BF16>, gr, bl, 0, s, sl);
+  else hipLaunchKernelGGL(pack_data_E_batched_kernel<PREC_FP16>, gr, bl, 0, s, sl);
   return hipGetLastError();
 }
 

@@ -227,6 +227,51 @@ struct CgState {
   int nblk;         // CG workgroups
 };
 constexpr int kMaxReorth = 2048;
+
+// One slice of the lock-step batched solve as its batched vector kernels
+// read it (device memory, written once per solve): the CG state and the
+// arguments its single-slice launches take.
+struct CgSlice {
+  CgState st;
+  const float2* hpart;    // E^H partials [nsplit][stride]
+  const float* unscale;   // their 1/scale
+  float2* rho;            // the iterate
+  int64_t stride;
+  int nsplit;
+};
+// One slice's operand packing in the batched solve: the arguments of
+// pack_data (E operand) or of pack_EH_from_epart (E^H operand of E^H E).
+struct PackSlice {
+  const void* src;          // pack_data: float2 items; pack_EH_from_epart: the E partials (float)
+  const float2* mul;        // pack_data: per (coil, item) factor or NULL
+  const float* wgt;         // per-item weight or NULL
+  void* out;                // packed operand
+  const float* bmax;        // pack_data: [kBmaxBlocks] magnitude bound (scaled precisions)
+  const float* unscale_in;  // pack_EH_from_epart: 1/scale of the E operand
+  float* unscale;           // 1/scale of the packed operand
+  const int* stop;
+  int64_t n_items, is, cs;  // pack_data: items and strides; pack_EH_from_epart: samples (n_items)
+  int64_t nchunks, HC16;
+  float scale, wmul;        // pack_EH_from_epart
+  int G, NB, nsplit;
+};
+hipError_t launch_store_slice_args(const CgSlice& cg, const PackSlice& pe, const PackSlice& ph, CgSlice* cg_out,
+                                   PackSlice* pe_out, PackSlice* ph_out, hipStream_t s);
+// the vector steps of one iteration for the n slices of sl at once (grid
+// (max_nblk, rows, n)); arithmetic and sums as the single-slice launches
+hipError_t launch_cg_beta_batched(const CgSlice* sl, int n, int max_nblk, hipStream_t s);
+hipError_t launch_cg_update_batched(const CgSlice* sl, int n, int max_nblk, int it, int nv, hipStream_t s);
+hipError_t launch_cg_reorth_apply_batched(const CgSlice* sl, int n, int max_nblk, int nv, bool from_rn,
+                                          hipStream_t s);
+hipError_t launch_cg_direction_batched(const CgSlice* sl, int n, int max_nblk, int it, int n_iter, double tol,
+                                       hipStream_t s);
+// pack_data (op OP_E) / pack_EH_from_epart for the n slices of sl at once
+// (grid (max_blocks, n), max_blocks: the largest single-slice grid)
+hipError_t launch_pack_data_E_batched(int prec, const PackSlice* sl, int n, int64_t max_blocks, hipStream_t s);
+hipError_t launch_pack_EH_from_epart_batched(int prec, const PackSlice* sl, int n, int64_t max_blocks,
+                                             hipStream_t s);
+// the E^H-operand scale of pack_EH_from_epart for L voxels
+float epart_pack_scale(int prec, int64_t L);
 hipError_t launch_cg_reset(const CgState& st, hipStream_t s);
 // smax[l] = max_c |S[c][l]|
 hipError_t launch_sens_absmax(const float2* sens, int G, int64_t L, float* smax, hipStream_t s);

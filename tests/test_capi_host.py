@@ -177,7 +177,8 @@ def test_batched_validation(L):
     two = ctypes.c_size_t()
     L.nfs_workspace_bytes(None, ctypes.byref(ok[1]), 3, 2, 30, 1, ctypes.byref(two))
     al = lambda b: (b + 255) // 256 * 256
-    assert n.value == al(one.value) + al(two.value) + 1024  # per-slice workspaces, then the work-list counters
+    # per-slice workspaces, the work-list counters, the persistent form's per-slice launch arguments
+    assert n.value == al(one.value) + al(two.value) + 1024 + al(192 * 2) + 2 * al(128 * 2)
     z = ctypes.c_size_t(7)
     assert L.nfs_workspace_bytes_batched(None, 0, None, 2, 30, 1, ctypes.byref(z)) == 0 and z.value == 0
     assert L.nfs_set_graphs(None, 1) == nfs.NFS_EINVAL
