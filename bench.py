@@ -397,8 +397,8 @@ def twod_run(nfs, synth, torch, dev, args):
             e1.record()
             torch.cuda.synchronize()
             return o, e0.elapsed_time(e1)
-        if not args.no_tune:
-            nfs.autotune(sv.prob, "fp16")
+        # the shapes tuned for the split solve above (same shape class), so
+        # that the two forms sum the same splits in the same order
         rr, ms_r = t_res(n_iter)
         _, ms_r1 = t_res(1)
         resident = dict(ms_per_step=ms_r, ms_per_iteration=(ms_r - ms_r1) / (n_iter - 1),
