@@ -546,7 +546,8 @@ def batched_run(nfs, synth, torch, dev, args, steps=2):
                 form="per-slice solves forked over 8 streams, full phase bases",
                 persistent_form=dict(ms_per_batch=t_fp, value=work / (t_fp * 1e-3),
                                      form="lock-step; per iteration one persistent E and one persistent E^H launch "
-                                          "per coil class over all slices"),
+                                          "per coil class over all slices, the packing and CG vector steps "
+                                          "between them one batched launch each"),
                 compressed_bases=dict(ms_per_batch_streams=t_c_s, ms_per_batch_persistent=t_c_p,
                                       ms_setup_host=t_c, ms_end_to_end_streams=t_c_s + t_c,
                                       terms=[pr.P + 1 for pr in cprobs],
