@@ -152,6 +152,31 @@ def test_persistent_batch_with_mixed_shapes_and_replacement(nfs):
         assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
 
 
+def test_persistent_batch_of_more_than_24_slices(nfs):
+    """30 slices of 2 to 8 coils (one column block: one launch class, more
+    slices than one persistent launch takes, so the class is cut into two
+    launches), FP16 operands with their per-slice scale bounds, plain
+    recurrences: the batched packing and vector launches cover every slice,
+    and each slice equals its single solve bit for bit."""
+    sl = synth.batched_slices(30, seed=17, n_range=(16, 40), g_range=(2, 8), k_range=(500, 2000))
+    probs, ms = [], []
+    for d in sl:
+        probs.append(nfs.Problem(*args(d)))
+        ms.append(torch.from_numpy((d["noise"] * 0.1).astype(np.complex64)))
+    nfs.set_batch_mode(0, "persistent")
+    try:
+        rb, hb, ib = nfs.cg_solve_batched(probs, ms, 7, precision="fp16", reorth=False)
+        torch.cuda.synchronize()
+    finally:
+        nfs.set_batch_mode(0, "streams")
+    for i, (p, m) in enumerate(zip(probs, ms)):
+        r1, h1, i1 = nfs.cg_solve(p, m, 7, precision="fp16", reorth=False)
+        torch.cuda.synchronize()
+        assert torch.equal(ib[i].cpu(), i1.cpu()), i
+        assert torch.equal(rb[i].cpu(), r1.cpu()), i
+        assert np.array_equal(hb[i].cpu().numpy(), h1.cpu().numpy(), equal_nan=True), i
+
+
 def test_persistent_mode_falls_back_for_shapes_it_does_not_take(nfs):
     """A batch holding a slice of 32 phase terms (three phase instructions
     per tile, which the persistent kernel is not built for) runs as the
