@@ -211,7 +211,7 @@ class Solver:
         nfs, torch = self.nfs, self.torch
         p = torch.from_numpy(self.d["rho_true"]).to(self.dev)
         q = torch.empty_like(p)
-        for _ in range(2):
+        for _ in range(3):
             nfs.apply_EHE(self.prob, p, prec, out=q)
         torch.cuda.synchronize()
         times = []
@@ -692,7 +692,7 @@ def main():
     progress("encode-kernel timing, E^H E alone, oracle checks")
     kt = sv.kernel_times(args.precision)
     roof = roofline(kt, L, K, G, d["n_basis"], args.precision, f"encode_kernel_{args.config}_{args.precision}_counters.md")
-    ehe_ms, _ = sv.ehe_alone(args.precision, 10)
+    ehe_ms, _ = sv.ehe_alone(args.precision, 20)  # median of 20 after 3 warm-ups
     err, checks = None, {}
     kind = "reorth" if reorth else "plain"
     g = golden(f"{args.config}_cg.npz")
