@@ -373,7 +373,7 @@ int nfs_set_batch_mode(nfs_ctx* ctx, int mode);
  * `precision`) it times every candidate shape on the caller's stream, with
  * the problem's own phase coefficients and realistic operands (E of
  * rho = 1 + i, then E^H of that output): held tiles per wave (2 or 4) and the
- * split count of the streamed range (targets of 2..16 workgroups per CU).
+ * split count of the streamed range (targets of 1..48 workgroups per CU).
  * The fastest shape per direction is kept in `ctx` and used by every later
  * call on a problem of the same shape class; nfs_workspace_bytes then
  * reflects it, so query workspace sizes after tuning.  Results of a tuned

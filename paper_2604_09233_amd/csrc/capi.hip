@@ -1890,7 +1890,10 @@ static std::vector<TuneCand> tune_candidates(const nfs_ctx* ctx, int NB, int64_t
     if (!valid_held_tiles(NB, MT)) continue;
     const int64_t gx = std::max<int64_t>(1, cdiv(HC, (int64_t)kWaves * MT));
     std::vector<int> seen;
-    for (int per_cu : {1, 2, 3, 4, 5, 6, 8, 12, 16}) {  // target workgroups per CU
+    // target workgroups per CU; the large targets give problems with many
+    // held blocks (the 3D workload's 1728-2235 per split) split counts of
+    // 3-8, where the last partial round of resident workgroups is small
+    for (int per_cu : {1, 2, 3, 4, 5, 6, 8, 12, 16, 24, 32, 48}) {
       const int ns = (int)std::min(std::max<int64_t>(cdiv((int64_t)per_cu * ctx->n_cu, gx), 1), maxs);
       if (std::find(seen.begin(), seen.end(), ns) == seen.end()) {
         seen.push_back(ns);
